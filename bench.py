@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Benchmark of the Bloch-simulation hot path on one MI355X.
+
+A step is one whole simulation of the 2D single-shot EPI workload
+(256 x 256 head-like phantom, 65,536 spins; 128 x 128 EPI at dt = 4 us,
+20,374 intervals, 16,384 ADC samples) through ``koma_simulate``: host
+packing of the sequence into the event program, its upload, every kernel
+(excitation, block ends, sample sums, cross-workgroup reduction), with the
+phantom and the signal in HBM. ``value`` is grid spin-steps per second
+(spins x intervals / time) of the mixed-precision form; the all-FP64 form,
+NRMSE against the FP64 oracle, the other workloads, serving latency, the
+roofline of the dominant kernel and the oracle's CPU rate are reported
+beside it in the same JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "G spin-steps/s (mixed vs FP64 GPU) + serving p50/p99 latency at NRMSE<=1e-4"
+PEAK_FP32 = 157.3  # TFLOP/s, MI355X FP32 vector (published)
+PEAK_HBM = 8000.0  # GB/s
+# Algorithmic work of one (spin, sample) term of a precession block summed by
+# the sample-parallel kernel: one complex multiply (rotation and decay by the
+# per-sample factor, 6 FLOP) and one complex add into the sample (2 FLOP).
+FLOP_PER_TERM = 8
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("komahip_kernels.hip", "komahip_internal.h"):
+        with open(os.path.join(ROOT, "paper_2301_02702_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def nrmse(got, ref):
+    return float(np.sqrt(np.mean(np.abs(got - ref) ** 2)) / np.max(np.abs(ref)))
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def run_workload(K, ctx, torch, sc, ph, seq, prec, steps, warmup, profile=False):
+    """Time `steps` device-resident simulations; return (seconds per step, signal, kernel stats)."""
+    ctx.set_config(prec)
+    dph = K.device_phantom(ph)
+    sig = torch.zeros((ph.n_groups, seq.n_adc, 2), dtype=torch.float64, device="cuda:0")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        ctx.simulate(sc, dph, seq, where="device", sig=sig, stream=stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    if profile:
+        ctx.profile(True)
+    t = time_steps(step, steps, 0, torch)
+    stats = {k: ctx.kernel_stats(k) for k in ("seq", "par", "reduce", "aux")} if profile else None
+    if profile:
+        ctx.profile(False)
+    s = sig.cpu().numpy()
+    return t, s[..., 0] + 1j * s[..., 1], stats
+
+
+def cpu_baseline(sc, ph, seq):
+    import oracle
+    th = oracle.default_threads()
+    t0 = time.perf_counter()
+    ref = oracle.simulate(sc, ph, seq, mode=oracle.MODE_STEP, threads=th)
+    dt = time.perf_counter() - t0
+    return ref, {"value": ph.n * seq.n_int / dt / 1e9, "unit": "G spin-steps/s", "cores": th,
+                 "kind": "oracle", "wall_s": round(dt, 3),
+                 "sample": f"the whole workload ({ph.n} spins x {seq.n_int} intervals), "
+                           "per-interval splitting in FP64, one signal matrix per thread"}
+
+
+def load_traffic(khash):
+    p = os.path.join(ROOT, "profiles", "traffic_k_par_epi256.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_hash") != khash:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-extra", action="store_true", help="headline workload only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2301_02702_amd import komahip as K
+    from paper_2301_02702_amd import workloads as W
+
+    K.lib()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ctx = K.Context(0, "mixed")
+    sc, ph, seq = W.config(2)
+    spin_steps = ph.n * seq.n_int
+    log(f"[bench] workload epi256: {ph.n} spins x {seq.n_int} intervals, {seq.n_adc} ADC")
+
+    # headline: mixed precision, live HIP-event timing of every launch
+    t_mix, s_mix, st_mix = run_workload(K, ctx, torch, sc, ph, seq, "mixed", args.steps, args.warmup, True)
+    log(f"[bench] mixed: {t_mix * 1e3:.3f} ms/step")
+    t_64, s_64, st_64 = run_workload(K, ctx, torch, sc, ph, seq, "fp64", args.steps, args.warmup, True)
+    log(f"[bench] fp64:  {t_64 * 1e3:.3f} ms/step")
+
+    info = K.koma_plan_info(sc, ph, seq, K.make_config("mixed"))
+    n_terms = ph.n * info["n_deferred_adc"]
+    par = st_mix["par"]
+    par_ms = par["total_ms"] / max(par["launches"], 1)
+    achieved = FLOP_PER_TERM * n_terms / (par_ms * 1e-3) / 1e12 / (par["launches"] / args.steps)
+    khash = kernel_source_hash()
+    traffic = load_traffic(khash)
+    roofline = {"bound": "alu", "kernel": "k_par<Mixed> (sample-parallel block sums)",
+                "achieved": round(achieved, 3), "peak": PEAK_FP32, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32, 4), "traffic": traffic,
+                "avg_launch_ms": round(par_ms, 5), "launches_per_step": par["launches"] / args.steps,
+                "flop_per_unit": FLOP_PER_TERM, "units_per_step": n_terms,
+                "unit_def": "one (spin, ADC sample) term of a precession block",
+                "kernel_hash": khash}
+
+    out = {
+        "metric": METRIC, "value": round(spin_steps / t_mix / 1e9, 3), "unit": "G spin-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t_mix * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "epi256_mixed: 256x256 head phantom (65536 spins, 3 tissue classes, "
+                               "50 Hz smooth off-resonance), 128x128 single-shot EPI, dt 4 us, "
+                               f"{seq.n_int} intervals, {seq.n_adc} ADC samples",
+                   "spins": ph.n, "intervals": seq.n_int, "adc": seq.n_adc, "spin_steps": spin_steps,
+                   "phantom_in": "HBM", "signal_out": "HBM", "sequence_packing": "host, every step"},
+        "fp64": {"value": round(spin_steps / t_64 / 1e9, 3), "ms_per_step": round(t_64 * 1e3, 4)},
+        "mixed_over_fp64": round(t_64 / t_mix, 3),
+        "kernel_ms_per_step": {p: {k: round(v["total_ms"] / args.steps, 4) for k, v in st.items()}
+                               for p, st in (("mixed", st_mix), ("fp64", st_64))},
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu:
+        log("[bench] oracle CPU baseline (whole workload, per-interval FP64) ...")
+        ref, cpu = cpu_baseline(sc, ph, seq)
+        out["cpu_baseline"] = cpu
+        out["nrmse_vs_oracle"] = {"mixed": nrmse(s_mix[0], ref[0]), "fp64": nrmse(s_64[0], ref[0])}
+        log(f"[bench] oracle {cpu['wall_s']} s on {cpu['cores']} threads; NRMSE {out['nrmse_vs_oracle']}")
+    else:
+        out["cpu_baseline"] = None
+        out["nrmse_vs_oracle"] = None
+    out["nrmse_mixed_vs_fp64"] = nrmse(s_mix[0], s_64[0])
+
+    if not args.no_extra:
+        extra = {}
+        for k in (1, 4, 5):
+            sck, phk, seqk = W.config(k)
+            ss = phk.n * seqk.n_int
+            rep = 3 if k != 5 else 2
+            tm, sm, _ = run_workload(K, ctx, torch, sck, phk, seqk, "mixed", rep, 1)
+            t6, s6, _ = run_workload(K, ctx, torch, sck, phk, seqk, "fp64", rep, 1)
+            e = np.sqrt(np.mean(np.abs(sm - s6) ** 2, axis=1)) / np.max(np.abs(s6), axis=1)
+            extra[W.WORKLOAD_NAMES[k].split(" ")[0]] = {
+                "spins": phk.n, "intervals": seqk.n_int, "spin_steps": ss,
+                "mixed_gsps": round(ss / tm / 1e9, 3), "fp64_gsps": round(ss / t6 / 1e9, 3),
+                "mixed_ms": round(tm * 1e3, 3), "fp64_ms": round(t6 * 1e3, 3),
+                "nrmse_mixed_vs_fp64_max": float(np.max(e))}
+            log(f"[bench] {W.WORKLOAD_NAMES[k]}: mixed {ss / tm / 1e9:.2f}, fp64 {ss / t6 / 1e9:.2f} G spin-steps/s")
+            del phk
+        out["workloads"] = extra
+
+    if not args.no_serving:
+        from paper_2301_02702_amd import serve
+        log(f"[bench] serving: {args.serving_requests} requests ...")
+        out["serving"] = serve.benchmark(ctx_device=0, n_requests=args.serving_requests, rho=0.8,
+                                         log=log)
+
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = 2 * a.numel() * 4
+
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

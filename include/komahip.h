@@ -1,0 +1,203 @@
+/*
+ * komahip: MI355X (gfx950) Bloch-simulation hot path of the KomaMRI method
+ * (Castillo-Passi et al., arXiv 2301.02702).
+ *
+ * The library integrates the Bloch equation in the rotating frame
+ * (section "Physical and Mathematical Background", Eq. Bloch with the
+ * effective field of Eq. B-def) for every spin of a phantom over a
+ * discretised sequence, with the paper's first-order operator splitting
+ * (rotation, then relaxation, per interval), the spinor rotation of
+ * Eq. Rot_exc in the excitation regime, the integral (trapezoidal) phase of
+ * precession blocks (section "Simulation blocks, Regime Switching, and
+ * Sequence-Aware Time Stepping") and the relaxation update, and returns the
+ * acquired signal: at every ADC sample, the sum of the transverse
+ * magnetisation Mxy = Mx + i My over the spins of each signal group
+ * (Figure 3, the simulation pipeline).
+ *
+ * Conventions
+ *   - SI units: m, s, T/m, T, rad/s, rad/(s T).
+ *   - A spin starts at thermal equilibrium (Mxy = 0, Mz = M0) at t[0].
+ *   - B1 is constant on each interval (piecewise constant), G is linear
+ *     between grid points (piecewise linear), x and dw are constant.
+ *   - Interval n is in the excitation regime iff b1_re[n] != 0 or
+ *     b1_im[n] != 0 (exact test); otherwise it is in the precession regime.
+ *   - An ADC index k samples the state at t[k]; k = 0 samples the initial
+ *     state.
+ *   - The signal is the plain sum of Mxy over a group's spins (no
+ *     normalisation, no coil weighting, no noise).
+ *
+ * Threading: a context is used by one host thread at a time. Requests are
+ * independent objects but share their context's device and allocator.
+ * Every entry point returns a koma_status; no C++ exception crosses the ABI.
+ * On error, outputs are left untouched and koma_last_error() describes the
+ * failure. A device (HIP) failure poisons the context: every later call on
+ * it returns KOMA_E_DEVICE.
+ */
+#ifndef KOMAHIP_H
+#define KOMAHIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KOMA_OK = 0,
+    KOMA_E_ARG = -1,       /* NULL pointer, bad size, bad configuration value */
+    KOMA_E_PHANTOM = -2,   /* non-finite value, PD < 0, T1/T2 <= 0 or NaN, bad group offsets */
+    KOMA_E_SEQUENCE = -3,  /* n_t < 2, non-finite value, t not strictly increasing,
+                              ADC indices out of [0, n_t) or not strictly increasing */
+    KOMA_E_NOMEM = -4,     /* device allocation failed */
+    KOMA_E_BUDGET = -5,    /* the request's device footprint exceeds hbm_budget */
+    KOMA_E_DEVICE = -6,    /* a HIP call failed; the context is poisoned */
+    KOMA_E_CANCELLED = -7, /* the request was cancelled */
+    KOMA_E_STATE = -8      /* call not valid in the object's current state */
+} koma_status;
+
+/* Arithmetic of the kernels. KOMA_FP64: everything in FP64.
+ * KOMA_MIXED: rotations, precession factors and relaxation in FP32; the
+ * cumulative gradient/off-resonance phase of precession blocks in FP64
+ * (reduced to [0, 1) turns before the FP32 sine/cosine); the sum over the
+ * lanes of a wavefront in FP32 and every sum beyond the wavefront in FP64. */
+typedef enum { KOMA_FP64 = 0, KOMA_MIXED = 1 } koma_precision;
+
+/* Where the caller's phantom, signal and m_final pointers live. Sequence
+ * arrays are always host memory (they are packed on the host). */
+typedef enum { KOMA_HOST = 0, KOMA_DEVICE = 1 } koma_mem;
+
+typedef struct {
+    double b0;    /* T, > 0; validated, no role in rotating-frame dynamics */
+    double gamma; /* rad/(s T), > 0 (proton: 2.6752218744e8) */
+} koma_scanner;
+
+/* Phantom: structure of arrays, n spins, float32 (canonical precision of the
+ * inputs: every path reads exactly these values). */
+typedef struct {
+    int64_t n;                /* spins, >= 1 */
+    const float *x, *y, *z;   /* m, finite */
+    const float *pd;          /* M0, >= 0, finite */
+    const float *t1, *t2;     /* s, > 0; +INFINITY means no relaxation */
+    const float *dw;          /* off-resonance, rad/s, finite */
+    int64_t n_groups;         /* >= 1 */
+    const int64_t *group_off; /* host memory always: n_groups + 1 non-decreasing offsets
+                                 from 0 to n; NULL means one group */
+} koma_phantom;
+
+/* Discretised sequence (host memory). */
+typedef struct {
+    int64_t n_t;                  /* time points, >= 2 */
+    const double *t;              /* s, strictly increasing, finite */
+    const double *gx, *gy, *gz;   /* T/m at the time points */
+    const double *b1_re, *b1_im;  /* T, per interval [n_t - 1] */
+    int64_t n_adc;                /* >= 0 */
+    const int64_t *adc_idx;       /* strictly increasing indices in [0, n_t) */
+} koma_sequence;
+
+typedef struct {
+    koma_precision precision;
+    int spins_per_lane;    /* spins summed per lane in the sample-parallel kernel: 0 = auto, or 1, 2, 4, 8 */
+    int wg_size;           /* 256 (reserved: other values are rejected) */
+    int64_t chunk_events;  /* events per launch of the spin-sequential kernel for requests; >= 1 */
+    size_t hbm_budget;     /* bytes a request may hold on the device; 0 = no limit */
+    size_t partial_budget; /* bytes for cross-workgroup signal partials per launch; >= 1 MiB */
+    int defer_min_adc;     /* precession blocks with at least this many ADC samples are
+                              summed by the sample-parallel kernel; < 0 disables it */
+    int stretch_max;       /* longest run of evenly spaced samples evaluated by recurrence
+                              after one exact FP64 anchor; 1..128 */
+} koma_config;
+
+typedef struct koma_ctx koma_ctx;
+typedef struct koma_req koma_req;
+
+/* Defaults: KOMA_MIXED, auto spins per lane, 256, 4096 events, no budget,
+ * 1 GiB partials, defer_min_adc 32, stretch_max 128. */
+void koma_config_default(koma_config *cfg);
+
+/* Create a context on HIP device `device` (sets it current). The context
+ * owns a HIP stream used when callers pass a NULL stream. */
+koma_status koma_ctx_create(int device, const koma_config *cfg, koma_ctx **out);
+void koma_ctx_destroy(koma_ctx *ctx);
+
+/* Message of the last error on this context (empty string if none). The
+ * pointer stays valid until the next call on the context. ctx may be NULL
+ * (message of the last failed koma_ctx_create on this thread). */
+const char *koma_last_error(const koma_ctx *ctx);
+
+/* Replace the context configuration (validated as in koma_ctx_create). */
+koma_status koma_ctx_set_config(koma_ctx *ctx, const koma_config *cfg);
+
+/* Device bytes a request for this phantom and sequence would hold (inputs
+ * copied to the device, spin state, snapshots, partials, packed sequence).
+ * Validates the sequence (host) and the phantom sizes. */
+koma_status koma_footprint(const koma_phantom *ph, const koma_sequence *seq,
+                           const koma_config *cfg, size_t *bytes);
+
+/* One whole simulation, synchronous on `hip_stream` (NULL: the context's
+ * stream). Phantom arrays, sig and m_final live where `where` says (device
+ * pointers must be on the context's device and stay valid until return).
+ *   sig:     [n_groups][n_adc][2] doubles (re, im), caller-owned, overwritten.
+ *   m_final: NULL or [n][3] doubles (Mx, My, Mz) after the last interval.
+ * Nothing is kept after return. */
+koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phantom *ph,
+                          const koma_sequence *seq, koma_mem where, void *hip_stream,
+                          double *sig, double *m_final);
+
+/* ---- chunked execution with device-resident state (serving) ------------
+ * koma_req_open copies the phantom (host or device memory per `where`) and
+ * the packed sequence into request-owned device buffers and initialises the
+ * spin state; nothing of the caller's is kept. koma_req_advance enqueues the
+ * next chunk of at most `max_events` events (<= 0: the configured
+ * chunk_events) on `hip_stream` without waiting; the signal of every
+ * precession block finished so far is summed at the same time. koma_req_done
+ * reports whether all events have been enqueued. koma_req_result enqueues
+ * the final cross-workgroup sums and copies the signal ([n_groups][n_adc][2]
+ * doubles, host memory) back, synchronising `hip_stream`. Requests are
+ * independent: one request's result does not depend on which other requests
+ * run at the same time. All calls on one request use one stream (or the caller
+ * orders them); koma_req_close waits for that stream only, and the request's
+ * device blocks go back to the context's cache for later requests. */
+koma_status koma_req_open(koma_ctx *ctx, const koma_scanner *sc, const koma_phantom *ph,
+                          const koma_sequence *seq, koma_mem where, koma_req **out);
+koma_status koma_req_advance(koma_req *req, int64_t max_events, void *hip_stream);
+koma_status koma_req_done(const koma_req *req, int *done);
+koma_status koma_req_result(koma_req *req, double *sig, void *hip_stream);
+/* Checkpoint: the spin state, the signal accumulated so far and the event
+ * cursor, as an opaque host byte string. Call with host_buf NULL to get the
+ * size. The request must be idle (its last advance synchronised). */
+koma_status koma_req_save(const koma_req *req, void *host_buf, size_t *bytes);
+/* Restore a checkpoint taken from a request opened with the same inputs. */
+koma_status koma_req_load(koma_req *req, const void *host_buf, size_t bytes);
+void koma_req_close(koma_req *req);
+
+typedef struct {
+    int64_t n_spins, n_tiles, n_groups, n_adc;
+    int64_t n_events, n_rf, n_runs, n_inline_adc, n_deferred_adc, n_stretches, n_snapshots;
+    int64_t n_blocks, spins_per_lane, n_chunks;
+    int64_t events_done;
+    size_t footprint;
+} koma_req_info;
+koma_status koma_req_info_get(const koma_req *req, koma_req_info *info);
+/* The same figures for a plan built on the host only (no device work);
+ * footprint is what koma_req_open would hold. */
+koma_status koma_plan_info(const koma_scanner *sc, const koma_phantom *ph, const koma_sequence *seq,
+                           const koma_config *cfg, koma_req_info *info);
+
+/* ---- measurement ---------------------------------------------------------
+ * With profiling on, every kernel launch of the context is bracketed by HIP
+ * events recorded on the stream it is launched on; koma_ctx_kernel_stats
+ * synchronises those streams and returns per-kernel totals:
+ *   kind 0: spin-sequential kernel (excitation, block ends, inline samples)
+ *   kind 1: sample-parallel kernel (samples of long precession blocks)
+ *   kind 2: cross-workgroup reduction into the signal
+ *   kind 3: state initialisation / export
+ * Totals are reset by koma_ctx_profile(ctx, 1). */
+koma_status koma_ctx_profile(koma_ctx *ctx, int on);
+koma_status koma_ctx_kernel_stats(koma_ctx *ctx, int kind, double *total_ms, int64_t *launches,
+                                  int64_t *work_units);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KOMAHIP_H */

@@ -1,0 +1,1257 @@
+// Host side of the komahip C-ABI: validation, sequence packing into the
+// event program, spin tiling, launch planning, contexts and requests.
+//
+// Sequence packing (paper: section "Simulation blocks, Regime Switching, and
+// Sequence-Aware Time Stepping"): intervals with B1 != 0 are excitation
+// intervals (one EV_RF each); every maximal run of B1 = 0 intervals is one
+// precession block. For a block the spin-independent integral of the gradient
+// K(t) = gamma_bar * sum((G_n + G_{n+1})/2 dt_n) (cycles/m, trapezoidal, exact
+// for piecewise-linear G) and the elapsed time tau(t) are accumulated in FP64
+// from the block start; a spin's block phase at t is -2 pi (x.K(t) + f tau(t))
+// with f = dw / 2 pi, and its relaxation over the block is the relaxation
+// update over tau.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "komahip.h"
+#include "komahip_internal.h"
+
+using namespace koma;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr double kTwoPi = 6.28318530717958647692;
+// Samples are merged into one evenly spaced stretch only when every sample of
+// it lies within these bounds of the straight line through the stretch: the
+// induced phase error is below 2e-9 turns per metre of |x| and 1e-12 s times
+// |f| (about the rounding of the time grid itself, ~1e-16 relative).
+constexpr double kStretchTolK = 2e-9;   // cycles/m
+constexpr double kStretchTolT = 1e-12;  // s
+
+struct Chunk {
+    int64_t s0, s1;   // stretch range
+    int64_t c0, c1;   // deferred sample range (columns)
+    int64_t ready;    // event index after which all of its snapshots exist
+};
+
+struct Plan {
+    // sequence program
+    std::vector<Event> ev;
+    std::vector<Stretch> st;
+    std::vector<int32_t> inl_k, def_k;  // inline / deferred column -> ADC index
+    int64_t n_slots = 0, n_rf = 0, n_runs = 0;
+    std::vector<int64_t> snap_event;  // slot -> event index of its EV_SNAP
+    // spin layout
+    int64_t n_spins = 0, n_groups = 1, n_tiles = 0, n_adc = 0;
+    std::vector<Tile> tiles;
+    std::vector<int32_t> tile_off;  // [n_groups + 1]
+    std::vector<Block> blocks;
+    std::vector<int32_t> blk_off;   // [n_groups + 1]
+    int spl = 1;
+    int64_t per_wg = 1;
+    std::vector<Chunk> chunks;
+    int64_t max_cols = 0;
+    double gamma = 0;
+};
+
+struct DevMem {  // request-owned or context-scratch device allocation
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+enum { K_SEQ = 0, K_PAR = 1, K_RED = 2, K_AUX = 3, K_KINDS = 4 };
+
+struct ProfRec {
+    hipEvent_t a, b;
+    int kind;
+    int64_t work;
+};
+
+}  // namespace
+
+struct koma_ctx {
+    int device = 0;
+    koma_config cfg{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    bool poisoned = false;
+    bool prof = false;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> ev_free;
+    double tot_ms[K_KINDS] = {0, 0, 0, 0};
+    int64_t n_launch[K_KINDS] = {0, 0, 0, 0};
+    int64_t work[K_KINDS] = {0, 0, 0, 0};
+    // device blocks released by closed requests, reused by later ones (by size)
+    std::multimap<size_t, void *> pool;
+    size_t pool_bytes = 0;
+    // scratch reused by koma_simulate (grow-only)
+    DevMem s_ev, s_st, s_tiles, s_blocks, s_toff, s_boff, s_inl, s_def, s_snap, s_pa, s_pb, s_sig,
+        s_mxy, s_mz, s_flags, s_mf, s_ph[7];
+};
+
+struct koma_req {
+    koma_ctx *ctx = nullptr;
+    Plan plan;
+    bool fp64 = false;
+    // request-owned device memory
+    DevMem ph[7], ev, st, tiles, blocks, toff, boff, inl, def, snap, pa, pb, sig, mxy, mz;
+    hipStream_t last_stream = nullptr;  // stream of the last enqueued work
+    int64_t cursor = 0;
+    size_t next_chunk = 0;
+    bool finished = false;   // all events enqueued and all sums launched
+    bool cancelled = false;
+    size_t footprint = 0;
+};
+
+// ---------------------------------------------------------------- helpers
+
+static koma_status fail(koma_ctx *ctx, koma_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) {
+        ctx->err = buf;
+        if (st == KOMA_E_DEVICE) ctx->poisoned = true;
+    } else {
+        g_create_error = buf;
+    }
+    return st;
+}
+
+#define HIPCHK(ctx, call)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? KOMA_E_NOMEM : KOMA_E_DEVICE,      \
+                        "%s failed: %s", #call, hipGetErrorString(e_));                       \
+    } while (0)
+
+static koma_status dev_reserve(koma_ctx *ctx, DevMem &m, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (m.cap >= bytes) return KOMA_OK;
+    if (m.p) {
+        hipError_t e = hipFree(m.p);
+        m.p = nullptr;
+        m.cap = 0;
+        if (e != hipSuccess) return fail(ctx, KOMA_E_DEVICE, "hipFree failed: %s", hipGetErrorString(e));
+    }
+    hipError_t e = hipMalloc(&m.p, bytes);
+    if (e != hipSuccess) {
+        m.p = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, KOMA_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    m.cap = bytes;
+    return KOMA_OK;
+}
+
+static void dev_free(DevMem &m) {
+    if (m.p) (void)hipFree(m.p);
+    m.p = nullptr;
+    m.cap = 0;
+}
+
+// Caching allocator for request buffers: hipFree can synchronise the whole
+// device, which would stall every other request in flight, so blocks of
+// closed requests are kept and reused (smallest fit within 2x), and only
+// released when an allocation fails or the context is destroyed.
+static void pool_trim(koma_ctx *ctx) {
+    for (auto &kv : ctx->pool) (void)hipFree(kv.second);
+    ctx->pool.clear();
+    ctx->pool_bytes = 0;
+}
+
+static koma_status pool_get(koma_ctx *ctx, DevMem &m, size_t bytes) {
+    bytes = (std::max<size_t>(bytes, 16) + 255) & ~(size_t)255;
+    auto it = ctx->pool.lower_bound(bytes);
+    if (it != ctx->pool.end() && it->first <= 2 * bytes) {
+        m.p = it->second;
+        m.cap = it->first;
+        ctx->pool_bytes -= it->first;
+        ctx->pool.erase(it);
+        return KOMA_OK;
+    }
+    hipError_t e = hipMalloc(&m.p, bytes);
+    if (e == hipErrorOutOfMemory && !ctx->pool.empty()) {
+        (void)hipGetLastError();
+        pool_trim(ctx);
+        e = hipMalloc(&m.p, bytes);
+    }
+    if (e != hipSuccess) {
+        m.p = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, KOMA_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    m.cap = bytes;
+    return KOMA_OK;
+}
+
+static void pool_put(koma_ctx *ctx, DevMem &m) {
+    if (m.p) {
+        ctx->pool.insert({m.cap, m.p});
+        ctx->pool_bytes += m.cap;
+    }
+    m.p = nullptr;
+    m.cap = 0;
+}
+
+template <class T>
+static koma_status pool_upload(koma_ctx *ctx, DevMem &m, const std::vector<T> &v, hipStream_t s) {
+    koma_status st = pool_get(ctx, m, v.size() * sizeof(T));
+    if (st != KOMA_OK) return st;
+    if (!v.empty()) HIPCHK(ctx, hipMemcpyAsync(m.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return KOMA_OK;
+}
+
+template <class T>
+static koma_status upload(koma_ctx *ctx, DevMem &m, const std::vector<T> &v, hipStream_t s) {
+    koma_status st = dev_reserve(ctx, m, v.size() * sizeof(T));
+    if (st != KOMA_OK) return st;
+    if (!v.empty()) HIPCHK(ctx, hipMemcpyAsync(m.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return KOMA_OK;
+}
+
+static bool finite_d(double v) { return std::isfinite(v); }
+
+// ---------------------------------------------------------------- validation
+
+static koma_status check_config(koma_ctx *ctx, const koma_config *c) {
+    if (!c) return fail(ctx, KOMA_E_ARG, "config is NULL");
+    if (c->precision != KOMA_FP64 && c->precision != KOMA_MIXED)
+        return fail(ctx, KOMA_E_ARG, "precision must be KOMA_FP64 or KOMA_MIXED");
+    if (!(c->spins_per_lane == 0 || c->spins_per_lane == 1 || c->spins_per_lane == 2 ||
+          c->spins_per_lane == 4 || c->spins_per_lane == 8))
+        return fail(ctx, KOMA_E_ARG, "spins_per_lane must be 0, 1, 2, 4 or 8");
+    if (c->wg_size != 256) return fail(ctx, KOMA_E_ARG, "wg_size must be 256");
+    if (c->chunk_events < 1) return fail(ctx, KOMA_E_ARG, "chunk_events must be >= 1");
+    if (c->partial_budget < ((size_t)1 << 20)) return fail(ctx, KOMA_E_ARG, "partial_budget must be >= 1 MiB");
+    if (c->stretch_max < 1 || c->stretch_max > kStretchMax)
+        return fail(ctx, KOMA_E_ARG, "stretch_max must be in [1, %d]", kStretchMax);
+    return KOMA_OK;
+}
+
+static koma_status check_scanner(koma_ctx *ctx, const koma_scanner *sc) {
+    if (!sc) return fail(ctx, KOMA_E_ARG, "scanner is NULL");
+    if (!(finite_d(sc->gamma) && sc->gamma > 0)) return fail(ctx, KOMA_E_ARG, "gamma must be finite and > 0");
+    if (!(finite_d(sc->b0) && sc->b0 > 0)) return fail(ctx, KOMA_E_ARG, "b0 must be finite and > 0");
+    return KOMA_OK;
+}
+
+static koma_status check_sequence(koma_ctx *ctx, const koma_sequence *q) {
+    if (!q) return fail(ctx, KOMA_E_ARG, "sequence is NULL");
+    if (q->n_t < 2) return fail(ctx, KOMA_E_SEQUENCE, "n_t must be >= 2 (got %lld)", (long long)q->n_t);
+    if (q->n_t > ((int64_t)1 << 31) - 2) return fail(ctx, KOMA_E_SEQUENCE, "n_t too large");
+    if (!q->t || !q->gx || !q->gy || !q->gz || !q->b1_re || !q->b1_im)
+        return fail(ctx, KOMA_E_ARG, "sequence array is NULL");
+    if (q->n_adc < 0) return fail(ctx, KOMA_E_SEQUENCE, "n_adc must be >= 0");
+    if (q->n_adc > 0 && !q->adc_idx) return fail(ctx, KOMA_E_ARG, "adc_idx is NULL");
+    for (int64_t i = 0; i < q->n_t; ++i) {
+        if (!finite_d(q->t[i]) || !finite_d(q->gx[i]) || !finite_d(q->gy[i]) || !finite_d(q->gz[i]))
+            return fail(ctx, KOMA_E_SEQUENCE, "non-finite time or gradient at point %lld", (long long)i);
+        if (i > 0 && !(q->t[i] > q->t[i - 1]))
+            return fail(ctx, KOMA_E_SEQUENCE, "t not strictly increasing at point %lld", (long long)i);
+    }
+    for (int64_t i = 0; i + 1 < q->n_t; ++i)
+        if (!finite_d(q->b1_re[i]) || !finite_d(q->b1_im[i]))
+            return fail(ctx, KOMA_E_SEQUENCE, "non-finite B1 on interval %lld", (long long)i);
+    for (int64_t k = 0; k < q->n_adc; ++k) {
+        if (q->adc_idx[k] < 0 || q->adc_idx[k] >= q->n_t)
+            return fail(ctx, KOMA_E_SEQUENCE, "adc_idx[%lld] = %lld out of [0, n_t)", (long long)k,
+                        (long long)q->adc_idx[k]);
+        if (k > 0 && q->adc_idx[k] <= q->adc_idx[k - 1])
+            return fail(ctx, KOMA_E_SEQUENCE, "adc_idx not strictly increasing at %lld", (long long)k);
+    }
+    return KOMA_OK;
+}
+
+static koma_status check_phantom_shape(koma_ctx *ctx, const koma_phantom *p) {
+    if (!p) return fail(ctx, KOMA_E_ARG, "phantom is NULL");
+    if (p->n < 1) return fail(ctx, KOMA_E_PHANTOM, "phantom needs n >= 1 spins");
+    if (!p->x || !p->y || !p->z || !p->pd || !p->t1 || !p->t2 || !p->dw)
+        return fail(ctx, KOMA_E_ARG, "phantom array is NULL");
+    if (p->n_groups < 1) return fail(ctx, KOMA_E_PHANTOM, "n_groups must be >= 1");
+    if (!p->group_off) {
+        if (p->n_groups != 1) return fail(ctx, KOMA_E_PHANTOM, "group_off is NULL but n_groups != 1");
+    } else {
+        if (p->group_off[0] != 0 || p->group_off[p->n_groups] != p->n)
+            return fail(ctx, KOMA_E_PHANTOM, "group_off must run from 0 to n");
+        for (int64_t g = 0; g < p->n_groups; ++g)
+            if (p->group_off[g + 1] < p->group_off[g])
+                return fail(ctx, KOMA_E_PHANTOM, "group_off decreases at group %lld", (long long)g);
+    }
+    return KOMA_OK;
+}
+
+static koma_status check_phantom_values_host(koma_ctx *ctx, const koma_phantom *p) {
+    for (int64_t i = 0; i < p->n; ++i) {
+        if (!std::isfinite(p->x[i]) || !std::isfinite(p->y[i]) || !std::isfinite(p->z[i]) ||
+            !std::isfinite(p->dw[i]) || !std::isfinite(p->pd[i]))
+            return fail(ctx, KOMA_E_PHANTOM, "non-finite position, dw or PD at spin %lld", (long long)i);
+        if (p->pd[i] < 0) return fail(ctx, KOMA_E_PHANTOM, "PD < 0 at spin %lld", (long long)i);
+        if (!(p->t1[i] > 0) || !(p->t2[i] > 0))
+            return fail(ctx, KOMA_E_PHANTOM, "T1/T2 must be > 0 (or +inf) at spin %lld", (long long)i);
+    }
+    return KOMA_OK;
+}
+
+// ---------------------------------------------------------------- planning
+
+namespace {
+
+struct Sample {
+    int32_t k;
+    double v[4];  // kx, ky, kz, tau
+};
+
+// Split the samples of one block into evenly spaced stretches.
+template <class Emit>
+void make_stretches(const std::vector<Sample> &s, int max_len, Emit emit) {
+    const size_t m = s.size();
+    size_t i = 0;
+    while (i < m) {
+        size_t len = 1;
+        double inc[4] = {0, 0, 0, 0};
+        if (i + 1 < m && max_len > 1) {
+            // greedy: extend while the next sample stays on the line of the first step
+            size_t j = i + 1;
+            double d0[4];
+            for (int c = 0; c < 4; ++c) d0[c] = s[i + 1].v[c] - s[i].v[c];
+            while (j < m && (j - i + 1) <= (size_t)max_len) {
+                bool ok = true;
+                const double n = (double)(j - i);
+                for (int c = 0; c < 4 && ok; ++c) {
+                    const double tol = (c < 3 ? kStretchTolK : kStretchTolT) * (1.0 + n);
+                    ok = std::fabs(s[j].v[c] - (s[i].v[c] + n * d0[c])) <= tol;
+                }
+                if (!ok) break;
+                ++j;
+            }
+            len = j - i;
+            // verify against the line through the first and last sample; shrink if needed
+            while (len > 1) {
+                for (int c = 0; c < 4; ++c) inc[c] = (s[i + len - 1].v[c] - s[i].v[c]) / (double)(len - 1);
+                bool ok = true;
+                for (size_t q = 1; q < len && ok; ++q)
+                    for (int c = 0; c < 4 && ok; ++c) {
+                        const double tol = c < 3 ? kStretchTolK : kStretchTolT;
+                        ok = std::fabs(s[i + q].v[c] - (s[i].v[c] + (double)q * inc[c])) <= tol;
+                    }
+                if (ok) break;
+                len = len / 2;
+            }
+            if (len == 1) inc[0] = inc[1] = inc[2] = inc[3] = 0;
+        }
+        emit(i, len, inc);
+        i += len;
+    }
+}
+
+}  // namespace
+
+static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamma, const koma_phantom *ph,
+                              const koma_sequence *q, Plan &P) {
+    P = Plan();
+    P.gamma = gamma;
+    P.n_spins = ph->n;
+    P.n_groups = ph->n_groups;
+    P.n_adc = q->n_adc;
+    const double gbar = gamma / kTwoPi;
+    const int64_t n_t = q->n_t, n_int = n_t - 1;
+
+    // ---- spin tiles: 64-spin slots that never straddle a signal group
+    P.tile_off.assign(P.n_groups + 1, 0);
+    for (int64_t g = 0; g < P.n_groups; ++g) {
+        const int64_t a = ph->group_off ? ph->group_off[g] : 0;
+        const int64_t b = ph->group_off ? ph->group_off[g + 1] : ph->n;
+        P.tile_off[g] = (int32_t)P.tiles.size();
+        for (int64_t s = a; s < b; s += kWave) {
+            Tile t;
+            t.spin0 = s;
+            t.count = (int32_t)std::min<int64_t>(kWave, b - s);
+            t.group = (int32_t)g;
+            P.tiles.push_back(t);
+            if (P.tiles.size() >= (size_t)1 << 30) return fail(ctx, KOMA_E_PHANTOM, "too many spins");
+        }
+    }
+    P.tile_off[P.n_groups] = (int32_t)P.tiles.size();
+    P.n_tiles = (int64_t)P.tiles.size();
+
+    // ---- event program
+    std::vector<uint8_t> is_adc(n_t, 0);
+    for (int64_t k = 0; k < q->n_adc; ++k) is_adc[q->adc_idx[k]] = 1;
+    std::vector<int32_t> adc_pos(n_t, -1);
+    for (int64_t k = 0; k < q->n_adc; ++k) adc_pos[q->adc_idx[k]] = (int32_t)k;
+    auto is_rf = [&](int64_t n) { return q->b1_re[n] != 0.0 || q->b1_im[n] != 0.0; };
+    const int defer_min = cfg.defer_min_adc;
+
+    int64_t a = 0;
+    std::vector<Sample> samples;
+    for (;;) {
+        // precession block [a, b]
+        int64_t b = a;
+        while (b < n_int && !is_rf(b)) ++b;
+        samples.clear();
+        double K[3] = {0, 0, 0};
+        for (int64_t p = a; p <= b; ++p) {
+            if (is_adc[p]) {
+                Sample s;
+                s.k = adc_pos[p];
+                s.v[0] = K[0];
+                s.v[1] = K[1];
+                s.v[2] = K[2];
+                s.v[3] = q->t[p] - q->t[a];
+                samples.push_back(s);
+            }
+            if (p < b) {
+                const double dt = q->t[p + 1] - q->t[p];
+                K[0] += gbar * 0.5 * (q->gx[p] + q->gx[p + 1]) * dt;
+                K[1] += gbar * 0.5 * (q->gy[p] + q->gy[p + 1]) * dt;
+                K[2] += gbar * 0.5 * (q->gz[p] + q->gz[p + 1]) * dt;
+            }
+        }
+        const bool defer = defer_min >= 0 && b > a && (int64_t)samples.size() >= std::max(1, defer_min);
+        if (!samples.empty()) {
+            if (defer) {
+                const int32_t slot = (int32_t)P.n_slots++;
+                Event e{};
+                e.kind = EV_SNAP;
+                e.a0 = slot;
+                P.snap_event.push_back((int64_t)P.ev.size());
+                P.ev.push_back(e);
+                make_stretches(samples, cfg.stretch_max, [&](size_t i, size_t len, const double *inc) {
+                    Stretch s{};
+                    s.slot = slot;
+                    s.d0 = (int32_t)P.def_k.size();
+                    s.count = (int32_t)len;
+                    for (int c = 0; c < 4; ++c) {
+                        s.k0[c] = samples[i].v[c];
+                        s.dk[c] = inc[c];
+                    }
+                    for (size_t j = 0; j < len; ++j) P.def_k.push_back(samples[i + j].k);
+                    P.st.push_back(s);
+                });
+            } else {
+                make_stretches(samples, cfg.stretch_max, [&](size_t i, size_t len, const double *inc) {
+                    Event e{};
+                    e.kind = EV_ADC;
+                    e.a0 = (int32_t)P.inl_k.size();
+                    e.count = (int32_t)len;
+                    for (int c = 0; c < 4; ++c) {
+                        e.d[c] = samples[i].v[c];
+                        e.d[4 + c] = inc[c];
+                    }
+                    for (size_t j = 0; j < len; ++j) P.inl_k.push_back(samples[i + j].k);
+                    P.ev.push_back(e);
+                });
+            }
+        }
+        if (b > a) {
+            Event e{};
+            e.kind = EV_END;
+            e.d[0] = K[0];
+            e.d[1] = K[1];
+            e.d[2] = K[2];
+            e.d[3] = q->t[b] - q->t[a];
+            P.ev.push_back(e);
+            ++P.n_runs;
+        }
+        if (b == n_int) break;
+        // excitation interval b
+        {
+            const double dt = q->t[b + 1] - q->t[b];
+            const double v[8] = {0.5 * (q->gx[b] + q->gx[b + 1]),
+                                 0.5 * (q->gy[b] + q->gy[b + 1]),
+                                 0.5 * (q->gz[b] + q->gz[b + 1]),
+                                 q->b1_re[b],
+                                 q->b1_im[b],
+                                 q->b1_re[b] * q->b1_re[b] + q->b1_im[b] * q->b1_im[b],
+                                 -gamma * dt / (2.0 * kTwoPi),
+                                 dt};
+            Event e{};
+            e.kind = EV_RF;
+            for (int c = 0; c < 8; ++c) {
+                e.d[c] = v[c];
+                e.f[c] = (float)v[c];
+            }
+            P.ev.push_back(e);
+            ++P.n_rf;
+        }
+        a = b + 1;
+        if ((int64_t)P.ev.size() >= ((int64_t)1 << 31) - 4) return fail(ctx, KOMA_E_SEQUENCE, "sequence too long");
+    }
+    if ((int64_t)P.inl_k.size() + (int64_t)P.def_k.size() != q->n_adc)
+        return fail(ctx, KOMA_E_SEQUENCE, "internal: ADC samples lost in packing");
+
+    // ---- sample-parallel layout: blocks of 4*S tiles of one group
+    const int64_t n_st = (int64_t)P.st.size();
+    int spl = cfg.spins_per_lane;
+    if (spl == 0) {
+        spl = 1;
+        for (int cand : {4, 2}) {  // largest S that still gives >= 8 workgroups per CU
+            int64_t nb = 0;
+            for (int64_t g = 0; g < P.n_groups; ++g) {
+                const int64_t nt = P.tile_off[g + 1] - P.tile_off[g];
+                nb += (nt + 4 * cand - 1) / (4 * cand);
+            }
+            if (nb * std::max<int64_t>(n_st, 1) >= 2048) {
+                spl = cand;
+                break;
+            }
+        }
+    }
+    P.spl = spl;
+    P.blk_off.assign(P.n_groups + 1, 0);
+    for (int64_t g = 0; g < P.n_groups; ++g) {
+        P.blk_off[g] = (int32_t)P.blocks.size();
+        for (int32_t t = P.tile_off[g]; t < P.tile_off[g + 1]; t += 4 * spl) {
+            Block bl{};
+            bl.tile0 = t;
+            bl.ntiles = std::min<int32_t>(4 * spl, P.tile_off[g + 1] - t);
+            bl.group = (int32_t)g;
+            P.blocks.push_back(bl);
+        }
+    }
+    P.blk_off[P.n_groups] = (int32_t)P.blocks.size();
+    const int64_t n_blocks = (int64_t)P.blocks.size();
+    // stretches per workgroup: keep >= ~16 workgroups per CU, share spin loads beyond that
+    P.per_wg = 1;
+    if (n_st > 0) {
+        const int64_t target = 4096;
+        const int64_t wgs = n_blocks * n_st;
+        P.per_wg = std::max<int64_t>(1, std::min<int64_t>(16, wgs / target));
+    }
+
+    // ---- deferred sample chunks, sized by the partial budget
+    if (n_st > 0) {
+        const int64_t cap_cols = std::max<int64_t>(
+            kStretchMax, (int64_t)(cfg.partial_budget / (size_t)(std::max<int64_t>(n_blocks, 1) * 16)));
+        int64_t s = 0;
+        while (s < n_st) {
+            Chunk c;
+            c.s0 = s;
+            c.c0 = P.st[s].d0;
+            int64_t cols = 0;
+            while (s < n_st && (cols + P.st[s].count <= cap_cols || cols == 0)) {
+                cols += P.st[s].count;
+                ++s;
+            }
+            c.s1 = s;
+            c.c1 = c.c0 + cols;
+            c.ready = P.snap_event[P.st[s - 1].slot] + 1;  // slots are increasing with the stretch order
+            P.chunks.push_back(c);
+            P.max_cols = std::max(P.max_cols, cols);
+        }
+    }
+    return KOMA_OK;
+}
+
+static size_t plan_footprint(const Plan &P, bool fp64, bool with_state, bool with_phantom) {
+    const size_t r = fp64 ? 8 : 4;
+    const size_t n_pad = (size_t)P.n_tiles * kWave;
+    size_t b = 0;
+    b += P.ev.size() * sizeof(Event) + P.st.size() * sizeof(Stretch);
+    b += P.tiles.size() * sizeof(Tile) + P.blocks.size() * sizeof(Block);
+    b += (P.tile_off.size() + P.blk_off.size() + P.inl_k.size() + P.def_k.size()) * 4;
+    b += (size_t)P.n_slots * n_pad * 2 * r;                       // snapshots
+    b += (size_t)P.n_tiles * P.inl_k.size() * 2 * r;              // inline partials
+    b += (size_t)P.blocks.size() * (size_t)P.max_cols * 16;       // cross-workgroup partials
+    b += (size_t)P.n_groups * (size_t)P.n_adc * 16;               // signal
+    if (with_state) b += n_pad * 3 * r;
+    if (with_phantom) b += (size_t)P.n_spins * 7 * 4;
+    return b;
+}
+
+// ---------------------------------------------------------------- profiling
+
+static koma_status prof_begin(koma_ctx *ctx, hipStream_t s, hipEvent_t *out) {
+    *out = nullptr;
+    if (!ctx->prof) return KOMA_OK;
+    hipEvent_t e;
+    if (!ctx->ev_free.empty()) {
+        e = ctx->ev_free.back();
+        ctx->ev_free.pop_back();
+    } else {
+        HIPCHK(ctx, hipEventCreate(&e));
+    }
+    HIPCHK(ctx, hipEventRecord(e, s));
+    *out = e;
+    return KOMA_OK;
+}
+
+static koma_status prof_end(koma_ctx *ctx, hipStream_t s, hipEvent_t a, int kind, int64_t work) {
+    if (!ctx->prof || !a) return KOMA_OK;
+    hipEvent_t e;
+    if (!ctx->ev_free.empty()) {
+        e = ctx->ev_free.back();
+        ctx->ev_free.pop_back();
+    } else {
+        HIPCHK(ctx, hipEventCreate(&e));
+    }
+    HIPCHK(ctx, hipEventRecord(e, s));
+    ctx->recs.push_back({a, e, kind, work});
+    return KOMA_OK;
+}
+
+// ---------------------------------------------------------------- execution
+
+namespace {
+
+struct Bufs {  // device views used by the launch sequence
+    PhantomDev ph;
+    const Event *ev;
+    const Stretch *st;
+    const Tile *tiles;
+    const Block *blocks;
+    const int32_t *toff, *boff, *inl, *def;
+    void *snap, *pa;
+    double *pb;
+    double *sig;
+    void *mxy, *mz;
+};
+
+}  // namespace
+
+#define LAUNCH(ctx, kind, work, s, expr)                                                  \
+    do {                                                                                  \
+        hipEvent_t pa_;                                                                   \
+        koma_status st_ = prof_begin((ctx), (s), &pa_);                                   \
+        if (st_ != KOMA_OK) return st_;                                                   \
+        if ((expr) != 0) return fail((ctx), KOMA_E_DEVICE, "kernel launch failed: %s", \
+                                     hipGetErrorString(hipGetLastError()));               \
+        st_ = prof_end((ctx), (s), pa_, (kind), (work));                                  \
+        if (st_ != KOMA_OK) return st_;                                                   \
+    } while (0)
+
+static koma_status run_seq(koma_ctx *ctx, const Plan &P, bool fp64, const Bufs &B, int64_t e0, int64_t e1,
+                           bool init, bool store, hipStream_t s) {
+    if (e1 <= e0) return KOMA_OK;
+    SeqArgs a{};
+    a.ph = B.ph;
+    a.tiles = B.tiles;
+    a.n_tiles = P.n_tiles;
+    a.ev = B.ev;
+    a.e0 = e0;
+    a.e1 = e1;
+    a.inv_gamma = 1.0 / P.gamma;
+    a.init = init ? 1 : 0;
+    a.store = store ? 1 : 0;
+    a.mxy = B.mxy;
+    a.mz = B.mz;
+    a.snap = B.snap;
+    a.pa = B.pa;
+    a.n_inline = (int64_t)P.inl_k.size();
+    LAUNCH(ctx, K_SEQ, P.n_tiles * kWave * (e1 - e0), s, launch_seq(fp64, a, s));
+    return KOMA_OK;
+}
+
+static koma_status run_chunk(koma_ctx *ctx, const Plan &P, bool fp64, const Bufs &B, const Chunk &c,
+                             hipStream_t s) {
+    ParArgs a{};
+    a.ph = B.ph;
+    a.tiles = B.tiles;
+    a.n_tiles = P.n_tiles;
+    a.blocks = B.blocks;
+    a.n_blocks = (int64_t)P.blocks.size();
+    a.st = B.st;
+    a.per_wg = P.per_wg;
+    a.snap = B.snap;
+    a.pb = B.pb;
+    a.col0 = c.c0;
+    a.cols = c.c1 - c.c0;
+    const int64_t max_st = 65535 * P.per_wg;  // grid.y limit
+    for (int64_t s0 = c.s0; s0 < c.s1; s0 += max_st) {
+        a.s0 = s0;
+        a.s1 = std::min(c.s1, s0 + max_st);
+        int64_t cols = 0;
+        for (int64_t i = a.s0; i < a.s1; ++i) cols += P.st[i].count;
+        LAUNCH(ctx, K_PAR, P.n_tiles * kWave * cols, s, launch_par(fp64, P.spl, a, s));
+    }
+    ReduceArgs r{};
+    r.part = B.pb;
+    r.cols = c.c1 - c.c0;
+    r.row_off = B.boff;
+    r.n_groups = P.n_groups;
+    r.col_to_adc = B.def + c.c0;
+    r.sig = B.sig;
+    r.n_adc = P.n_adc;
+    LAUNCH(ctx, K_RED, (int64_t)P.blocks.size() * (c.c1 - c.c0) * 16, s, launch_reduce(true, r, s));
+    return KOMA_OK;
+}
+
+static koma_status run_inline_reduce(koma_ctx *ctx, const Plan &P, bool fp64, const Bufs &B, hipStream_t s) {
+    if (P.inl_k.empty()) return KOMA_OK;
+    ReduceArgs r{};
+    r.part = B.pa;
+    r.cols = (int64_t)P.inl_k.size();
+    r.row_off = B.toff;
+    r.n_groups = P.n_groups;
+    r.col_to_adc = B.inl;
+    r.sig = B.sig;
+    r.n_adc = P.n_adc;
+    LAUNCH(ctx, K_RED, P.n_tiles * r.cols * (fp64 ? 16 : 8), s, launch_reduce(fp64, r, s));
+    return KOMA_OK;
+}
+
+static koma_status validate_device_phantom(koma_ctx *ctx, const PhantomDev &ph, int64_t n, DevMem &flags,
+                                           hipStream_t s) {
+    const int64_t nwg = (n + kWG - 1) / kWG;
+    koma_status st = dev_reserve(ctx, flags, (size_t)nwg * 4);
+    if (st != KOMA_OK) return st;
+    LAUNCH(ctx, K_AUX, n, s, launch_validate(ph, n, (int32_t *)flags.p, s));
+    std::vector<int32_t> h((size_t)nwg);
+    HIPCHK(ctx, hipMemcpyAsync(h.data(), flags.p, h.size() * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    int32_t bad = 0;
+    for (int32_t v : h) bad |= v;
+    if (bad & 1) return fail(ctx, KOMA_E_PHANTOM, "non-finite position, dw or PD in the phantom");
+    if (bad & 2) return fail(ctx, KOMA_E_PHANTOM, "PD < 0 in the phantom");
+    if (bad & 4) return fail(ctx, KOMA_E_PHANTOM, "T1/T2 must be > 0 (or +inf)");
+    return KOMA_OK;
+}
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" {
+
+void koma_config_default(koma_config *cfg) {
+    if (!cfg) return;
+    cfg->precision = KOMA_MIXED;
+    cfg->spins_per_lane = 0;
+    cfg->wg_size = 256;
+    cfg->chunk_events = 4096;
+    cfg->hbm_budget = 0;
+    cfg->partial_budget = (size_t)1 << 30;
+    cfg->defer_min_adc = 32;
+    cfg->stretch_max = 128;
+}
+
+koma_status koma_ctx_create(int device, const koma_config *cfg, koma_ctx **out) {
+    if (!out) return fail(nullptr, KOMA_E_ARG, "out is NULL");
+    *out = nullptr;
+    koma_config c;
+    if (cfg)
+        c = *cfg;
+    else
+        koma_config_default(&c);
+    if (check_config(nullptr, &c) != KOMA_OK) return KOMA_E_ARG;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) return fail(nullptr, KOMA_E_DEVICE, "no HIP device available");
+    if (device < 0 || device >= n) return fail(nullptr, KOMA_E_ARG, "device %d out of range", device);
+    if ((e = hipSetDevice(device)) != hipSuccess)
+        return fail(nullptr, KOMA_E_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+    koma_ctx *ctx = new (std::nothrow) koma_ctx();
+    if (!ctx) return fail(nullptr, KOMA_E_NOMEM, "out of host memory");
+    ctx->device = device;
+    ctx->cfg = c;
+    if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess) {
+        delete ctx;
+        return fail(nullptr, KOMA_E_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+    *out = ctx;
+    return KOMA_OK;
+}
+
+void koma_ctx_destroy(koma_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    DevMem *all[] = {&ctx->s_ev, &ctx->s_st, &ctx->s_tiles, &ctx->s_blocks, &ctx->s_toff, &ctx->s_boff,
+                     &ctx->s_inl, &ctx->s_def, &ctx->s_snap, &ctx->s_pa, &ctx->s_pb, &ctx->s_sig,
+                     &ctx->s_mxy, &ctx->s_mz, &ctx->s_flags, &ctx->s_mf};
+    for (DevMem *m : all) dev_free(*m);
+    for (DevMem &m : ctx->s_ph) dev_free(m);
+    pool_trim(ctx);
+    for (auto &r : ctx->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : ctx->ev_free) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char *koma_last_error(const koma_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+koma_status koma_ctx_set_config(koma_ctx *ctx, const koma_config *cfg) {
+    if (!ctx) return KOMA_E_ARG;
+    koma_status st = check_config(ctx, cfg);
+    if (st != KOMA_OK) return st;
+    ctx->cfg = *cfg;
+    return KOMA_OK;
+}
+
+koma_status koma_footprint(const koma_phantom *ph, const koma_sequence *seq, const koma_config *cfg,
+                           size_t *bytes) {
+    koma_ctx tmp;
+    if (!bytes) return KOMA_E_ARG;
+    koma_config c;
+    if (cfg)
+        c = *cfg;
+    else
+        koma_config_default(&c);
+    koma_status st;
+    if ((st = check_config(&tmp, &c)) != KOMA_OK) return st;
+    if ((st = check_phantom_shape(&tmp, ph)) != KOMA_OK) return st;
+    if ((st = check_sequence(&tmp, seq)) != KOMA_OK) return st;
+    Plan P;
+    if ((st = build_plan(&tmp, c, 2.6752218744e8, ph, seq, P)) != KOMA_OK) return st;
+    *bytes = plan_footprint(P, c.precision == KOMA_FP64, true, true);
+    return KOMA_OK;
+}
+
+koma_status koma_ctx_profile(koma_ctx *ctx, int on) {
+    if (!ctx) return KOMA_E_ARG;
+    for (auto &r : ctx->recs) {
+        ctx->ev_free.push_back(r.a);
+        ctx->ev_free.push_back(r.b);
+    }
+    ctx->recs.clear();
+    for (int k = 0; k < K_KINDS; ++k) {
+        ctx->tot_ms[k] = 0;
+        ctx->n_launch[k] = 0;
+        ctx->work[k] = 0;
+    }
+    ctx->prof = on != 0;
+    return KOMA_OK;
+}
+
+koma_status koma_ctx_kernel_stats(koma_ctx *ctx, int kind, double *total_ms, int64_t *launches,
+                                  int64_t *work_units) {
+    if (!ctx || kind < 0 || kind >= K_KINDS) return KOMA_E_ARG;
+    if (ctx->poisoned) return KOMA_E_DEVICE;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    for (auto &r : ctx->recs) {
+        HIPCHK(ctx, hipEventSynchronize(r.b));
+        float ms = 0;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, r.a, r.b));
+        ctx->tot_ms[r.kind] += ms;
+        ctx->n_launch[r.kind] += 1;
+        ctx->work[r.kind] += r.work;
+        ctx->ev_free.push_back(r.a);
+        ctx->ev_free.push_back(r.b);
+    }
+    ctx->recs.clear();
+    if (total_ms) *total_ms = ctx->tot_ms[kind];
+    if (launches) *launches = ctx->n_launch[kind];
+    if (work_units) *work_units = ctx->work[kind];
+    return KOMA_OK;
+}
+
+koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phantom *ph,
+                          const koma_sequence *seq, koma_mem where, void *hip_stream, double *sig,
+                          double *m_final) {
+    if (!ctx) return KOMA_E_ARG;
+    if (ctx->poisoned) return fail(ctx, KOMA_E_DEVICE, "context poisoned by an earlier device error");
+    ctx->err.clear();
+    koma_status st;
+    if (where != KOMA_HOST && where != KOMA_DEVICE) return fail(ctx, KOMA_E_ARG, "bad koma_mem");
+    if ((st = check_scanner(ctx, sc)) != KOMA_OK) return st;
+    if ((st = check_phantom_shape(ctx, ph)) != KOMA_OK) return st;
+    if ((st = check_sequence(ctx, seq)) != KOMA_OK) return st;
+    if (seq->n_adc > 0 && !sig) return fail(ctx, KOMA_E_ARG, "sig is NULL");
+    if (where == KOMA_HOST && (st = check_phantom_values_host(ctx, ph)) != KOMA_OK) return st;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    const bool fp64 = ctx->cfg.precision == KOMA_FP64;
+    const size_t r = fp64 ? 8 : 4;
+
+    Plan P;
+    if ((st = build_plan(ctx, ctx->cfg, sc->gamma, ph, seq, P)) != KOMA_OK) return st;
+    if (ctx->cfg.hbm_budget && plan_footprint(P, fp64, m_final != nullptr, where == KOMA_HOST) > ctx->cfg.hbm_budget)
+        return fail(ctx, KOMA_E_BUDGET, "footprint exceeds hbm_budget");
+
+    Bufs B{};
+    // phantom
+    const float *src[7] = {ph->x, ph->y, ph->z, ph->pd, ph->t1, ph->t2, ph->dw};
+    const float *dptr[7];
+    if (where == KOMA_HOST) {
+        for (int i = 0; i < 7; ++i) {
+            if ((st = dev_reserve(ctx, ctx->s_ph[i], (size_t)ph->n * 4)) != KOMA_OK) return st;
+            HIPCHK(ctx, hipMemcpyAsync(ctx->s_ph[i].p, src[i], (size_t)ph->n * 4, hipMemcpyHostToDevice, s));
+            dptr[i] = (const float *)ctx->s_ph[i].p;
+        }
+    } else {
+        for (int i = 0; i < 7; ++i) dptr[i] = src[i];
+    }
+    B.ph = PhantomDev{dptr[0], dptr[1], dptr[2], dptr[3], dptr[4], dptr[5], dptr[6]};
+    if (where == KOMA_DEVICE && (st = validate_device_phantom(ctx, B.ph, ph->n, ctx->s_flags, s)) != KOMA_OK)
+        return st;
+
+    if ((st = upload(ctx, ctx->s_ev, P.ev, s)) != KOMA_OK) return st;
+    if ((st = upload(ctx, ctx->s_st, P.st, s)) != KOMA_OK) return st;
+    if ((st = upload(ctx, ctx->s_tiles, P.tiles, s)) != KOMA_OK) return st;
+    if ((st = upload(ctx, ctx->s_blocks, P.blocks, s)) != KOMA_OK) return st;
+    if ((st = upload(ctx, ctx->s_toff, P.tile_off, s)) != KOMA_OK) return st;
+    if ((st = upload(ctx, ctx->s_boff, P.blk_off, s)) != KOMA_OK) return st;
+    if ((st = upload(ctx, ctx->s_inl, P.inl_k, s)) != KOMA_OK) return st;
+    if ((st = upload(ctx, ctx->s_def, P.def_k, s)) != KOMA_OK) return st;
+    const size_t n_pad = (size_t)P.n_tiles * kWave;
+    if ((st = dev_reserve(ctx, ctx->s_snap, (size_t)P.n_slots * n_pad * 2 * r)) != KOMA_OK) return st;
+    if ((st = dev_reserve(ctx, ctx->s_pa, (size_t)P.n_tiles * P.inl_k.size() * 2 * r)) != KOMA_OK) return st;
+    if ((st = dev_reserve(ctx, ctx->s_pb, P.blocks.size() * (size_t)P.max_cols * 16)) != KOMA_OK) return st;
+    const bool store = m_final != nullptr;
+    if (store) {
+        if ((st = dev_reserve(ctx, ctx->s_mxy, n_pad * 2 * r)) != KOMA_OK) return st;
+        if ((st = dev_reserve(ctx, ctx->s_mz, n_pad * r)) != KOMA_OK) return st;
+    }
+    double *sig_dev = sig;
+    if (where == KOMA_HOST && P.n_adc > 0) {
+        if ((st = dev_reserve(ctx, ctx->s_sig, (size_t)P.n_groups * P.n_adc * 16)) != KOMA_OK) return st;
+        sig_dev = (double *)ctx->s_sig.p;
+    }
+    B.ev = (const Event *)ctx->s_ev.p;
+    B.st = (const Stretch *)ctx->s_st.p;
+    B.tiles = (const Tile *)ctx->s_tiles.p;
+    B.blocks = (const Block *)ctx->s_blocks.p;
+    B.toff = (const int32_t *)ctx->s_toff.p;
+    B.boff = (const int32_t *)ctx->s_boff.p;
+    B.inl = (const int32_t *)ctx->s_inl.p;
+    B.def = (const int32_t *)ctx->s_def.p;
+    B.snap = ctx->s_snap.p;
+    B.pa = ctx->s_pa.p;
+    B.pb = (double *)ctx->s_pb.p;
+    B.sig = sig_dev;
+    B.mxy = ctx->s_mxy.p;
+    B.mz = ctx->s_mz.p;
+
+    if ((st = run_seq(ctx, P, fp64, B, 0, (int64_t)P.ev.size(), true, store, s)) != KOMA_OK) return st;
+    if (P.n_adc > 0) {
+        for (const Chunk &c : P.chunks)
+            if ((st = run_chunk(ctx, P, fp64, B, c, s)) != KOMA_OK) return st;
+        if ((st = run_inline_reduce(ctx, P, fp64, B, s)) != KOMA_OK) return st;
+    }
+    if (store) {
+        double *mf = m_final;
+        if (where == KOMA_HOST) {
+            if ((st = dev_reserve(ctx, ctx->s_mf, (size_t)ph->n * 24)) != KOMA_OK) return st;
+            mf = (double *)ctx->s_mf.p;
+        }
+        LAUNCH(ctx, K_AUX, (int64_t)n_pad, s, launch_export(fp64, B.tiles, P.n_tiles, B.mxy, B.mz, mf, s));
+        if (where == KOMA_HOST)
+            HIPCHK(ctx, hipMemcpyAsync(m_final, mf, (size_t)ph->n * 24, hipMemcpyDeviceToHost, s));
+    }
+    if (where == KOMA_HOST && P.n_adc > 0)
+        HIPCHK(ctx, hipMemcpyAsync(sig, sig_dev, (size_t)P.n_groups * P.n_adc * 16, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return KOMA_OK;
+}
+
+// ---------------------------------------------------------------- requests
+
+static Bufs req_bufs(koma_req *q) {
+    Bufs B{};
+    B.ph = PhantomDev{(const float *)q->ph[0].p, (const float *)q->ph[1].p, (const float *)q->ph[2].p,
+                      (const float *)q->ph[3].p, (const float *)q->ph[4].p, (const float *)q->ph[5].p,
+                      (const float *)q->ph[6].p};
+    B.ev = (const Event *)q->ev.p;
+    B.st = (const Stretch *)q->st.p;
+    B.tiles = (const Tile *)q->tiles.p;
+    B.blocks = (const Block *)q->blocks.p;
+    B.toff = (const int32_t *)q->toff.p;
+    B.boff = (const int32_t *)q->boff.p;
+    B.inl = (const int32_t *)q->inl.p;
+    B.def = (const int32_t *)q->def.p;
+    B.snap = q->snap.p;
+    B.pa = q->pa.p;
+    B.pb = (double *)q->pb.p;
+    B.sig = (double *)q->sig.p;
+    B.mxy = q->mxy.p;
+    B.mz = q->mz.p;
+    return B;
+}
+
+static void req_free(koma_req *q) {
+    for (DevMem &m : q->ph) pool_put(q->ctx, m);
+    DevMem *all[] = {&q->ev, &q->st, &q->tiles, &q->blocks, &q->toff, &q->boff, &q->inl, &q->def,
+                     &q->snap, &q->pa, &q->pb, &q->sig, &q->mxy, &q->mz};
+    for (DevMem *m : all) pool_put(q->ctx, *m);
+}
+
+koma_status koma_req_open(koma_ctx *ctx, const koma_scanner *sc, const koma_phantom *ph,
+                          const koma_sequence *seq, koma_mem where, koma_req **out) {
+    if (!ctx || !out) return KOMA_E_ARG;
+    *out = nullptr;
+    if (ctx->poisoned) return fail(ctx, KOMA_E_DEVICE, "context poisoned by an earlier device error");
+    ctx->err.clear();
+    koma_status st;
+    if (where != KOMA_HOST && where != KOMA_DEVICE) return fail(ctx, KOMA_E_ARG, "bad koma_mem");
+    if ((st = check_scanner(ctx, sc)) != KOMA_OK) return st;
+    if ((st = check_phantom_shape(ctx, ph)) != KOMA_OK) return st;
+    if ((st = check_sequence(ctx, seq)) != KOMA_OK) return st;
+    if (where == KOMA_HOST && (st = check_phantom_values_host(ctx, ph)) != KOMA_OK) return st;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    koma_req *q = new (std::nothrow) koma_req();
+    if (!q) return fail(ctx, KOMA_E_NOMEM, "out of host memory");
+    q->ctx = ctx;
+    q->fp64 = ctx->cfg.precision == KOMA_FP64;
+    if ((st = build_plan(ctx, ctx->cfg, sc->gamma, ph, seq, q->plan)) != KOMA_OK) {
+        delete q;
+        return st;
+    }
+    const Plan &P = q->plan;
+    q->footprint = plan_footprint(P, q->fp64, true, true);
+    if (ctx->cfg.hbm_budget && q->footprint > ctx->cfg.hbm_budget) {
+        delete q;
+        return fail(ctx, KOMA_E_BUDGET, "request footprint %zu exceeds hbm_budget %zu", q->footprint,
+                    ctx->cfg.hbm_budget);
+    }
+    hipStream_t s = ctx->stream;
+    const size_t r = q->fp64 ? 8 : 4;
+    const size_t n_pad = (size_t)P.n_tiles * kWave;
+    auto bail = [&](koma_status e) {
+        (void)hipStreamSynchronize(s);
+        req_free(q);
+        delete q;
+        return e;
+    };
+    const float *src[7] = {ph->x, ph->y, ph->z, ph->pd, ph->t1, ph->t2, ph->dw};
+    for (int i = 0; i < 7; ++i) {
+        if ((st = pool_get(ctx, q->ph[i], (size_t)ph->n * 4)) != KOMA_OK) return bail(st);
+        hipError_t e = hipMemcpyAsync(q->ph[i].p, src[i], (size_t)ph->n * 4,
+                                      where == KOMA_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return bail(fail(ctx, KOMA_E_DEVICE, "phantom copy: %s", hipGetErrorString(e)));
+    }
+    if ((st = pool_upload(ctx, q->ev, P.ev, s)) != KOMA_OK) return bail(st);
+    if ((st = pool_upload(ctx, q->st, P.st, s)) != KOMA_OK) return bail(st);
+    if ((st = pool_upload(ctx, q->tiles, P.tiles, s)) != KOMA_OK) return bail(st);
+    if ((st = pool_upload(ctx, q->blocks, P.blocks, s)) != KOMA_OK) return bail(st);
+    if ((st = pool_upload(ctx, q->toff, P.tile_off, s)) != KOMA_OK) return bail(st);
+    if ((st = pool_upload(ctx, q->boff, P.blk_off, s)) != KOMA_OK) return bail(st);
+    if ((st = pool_upload(ctx, q->inl, P.inl_k, s)) != KOMA_OK) return bail(st);
+    if ((st = pool_upload(ctx, q->def, P.def_k, s)) != KOMA_OK) return bail(st);
+    if ((st = pool_get(ctx, q->snap, (size_t)P.n_slots * n_pad * 2 * r)) != KOMA_OK) return bail(st);
+    if ((st = pool_get(ctx, q->pa, (size_t)P.n_tiles * P.inl_k.size() * 2 * r)) != KOMA_OK) return bail(st);
+    if ((st = pool_get(ctx, q->pb, P.blocks.size() * (size_t)P.max_cols * 16)) != KOMA_OK) return bail(st);
+    if ((st = pool_get(ctx, q->sig, (size_t)P.n_groups * P.n_adc * 16)) != KOMA_OK) return bail(st);
+    if ((st = pool_get(ctx, q->mxy, n_pad * 2 * r)) != KOMA_OK) return bail(st);
+    if ((st = pool_get(ctx, q->mz, n_pad * r)) != KOMA_OK) return bail(st);
+    if (where == KOMA_DEVICE) {
+        Bufs B = req_bufs(q);
+        if ((st = validate_device_phantom(ctx, B.ph, ph->n, ctx->s_flags, s)) != KOMA_OK) return bail(st);
+    }
+    hipError_t e = hipStreamSynchronize(s);  // inputs are copied before the caller's buffers may change
+    if (e != hipSuccess) return bail(fail(ctx, KOMA_E_DEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e)));
+    *out = q;
+    return KOMA_OK;
+}
+
+koma_status koma_req_advance(koma_req *q, int64_t max_events, void *hip_stream) {
+    if (!q) return KOMA_E_ARG;
+    koma_ctx *ctx = q->ctx;
+    if (ctx->poisoned) return fail(ctx, KOMA_E_DEVICE, "context poisoned by an earlier device error");
+    if (q->cancelled) return fail(ctx, KOMA_E_CANCELLED, "request cancelled");
+    if (q->finished) return KOMA_OK;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    q->last_stream = s;
+    const Plan &P = q->plan;
+    const int64_t n_ev = (int64_t)P.ev.size();
+    const int64_t step = max_events > 0 ? max_events : ctx->cfg.chunk_events;
+    const int64_t e1 = std::min(n_ev, q->cursor + step);
+    Bufs B = req_bufs(q);
+    koma_status st;
+    if (e1 > q->cursor || q->cursor == 0) {
+        if ((st = run_seq(ctx, P, q->fp64, B, q->cursor, e1, q->cursor == 0, true, s)) != KOMA_OK) return st;
+        if (n_ev == 0 && q->cursor == 0) {
+            // no events: the state is thermal equilibrium; nothing else to do
+        }
+        q->cursor = e1;
+    }
+    while (q->next_chunk < P.chunks.size() && P.chunks[q->next_chunk].ready <= q->cursor) {
+        if ((st = run_chunk(ctx, P, q->fp64, B, P.chunks[q->next_chunk], s)) != KOMA_OK) return st;
+        ++q->next_chunk;
+    }
+    if (q->cursor >= n_ev && q->next_chunk >= P.chunks.size()) {
+        if ((st = run_inline_reduce(ctx, P, q->fp64, B, s)) != KOMA_OK) return st;
+        q->finished = true;
+    }
+    return KOMA_OK;
+}
+
+koma_status koma_req_done(const koma_req *q, int *done) {
+    if (!q || !done) return KOMA_E_ARG;
+    *done = q->finished ? 1 : 0;
+    return KOMA_OK;
+}
+
+koma_status koma_req_result(koma_req *q, double *sig, void *hip_stream) {
+    if (!q) return KOMA_E_ARG;
+    koma_ctx *ctx = q->ctx;
+    if (ctx->poisoned) return fail(ctx, KOMA_E_DEVICE, "context poisoned by an earlier device error");
+    if (q->cancelled) return fail(ctx, KOMA_E_CANCELLED, "request cancelled");
+    if (!q->finished) return fail(ctx, KOMA_E_STATE, "request not finished: advance until done");
+    const Plan &P = q->plan;
+    if (P.n_adc > 0 && !sig) return fail(ctx, KOMA_E_ARG, "sig is NULL");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    q->last_stream = s;
+    if (P.n_adc > 0)
+        HIPCHK(ctx, hipMemcpyAsync(sig, q->sig.p, (size_t)P.n_groups * P.n_adc * 16, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return KOMA_OK;
+}
+
+// Checkpoint layout: header, then the device buffers that carry progress.
+struct CkptHeader {
+    uint64_t magic;
+    int64_t cursor, next_chunk, finished;
+    uint64_t n_ev, n_tiles, n_inl, n_slots, n_adc, n_groups, fp64;
+    uint64_t bytes_mxy, bytes_mz, bytes_snap, bytes_pa, bytes_sig;
+};
+static constexpr uint64_t kCkptMagic = 0x314b504b414d4f4bull;
+
+static void ckpt_sizes(const koma_req *q, CkptHeader &h) {
+    const Plan &P = q->plan;
+    const size_t r = q->fp64 ? 8 : 4;
+    const size_t n_pad = (size_t)P.n_tiles * kWave;
+    h.magic = kCkptMagic;
+    h.cursor = q->cursor;
+    h.next_chunk = (int64_t)q->next_chunk;
+    h.finished = q->finished ? 1 : 0;
+    h.n_ev = P.ev.size();
+    h.n_tiles = (uint64_t)P.n_tiles;
+    h.n_inl = P.inl_k.size();
+    h.n_slots = (uint64_t)P.n_slots;
+    h.n_adc = (uint64_t)P.n_adc;
+    h.n_groups = (uint64_t)P.n_groups;
+    h.fp64 = q->fp64 ? 1 : 0;
+    h.bytes_mxy = n_pad * 2 * r;
+    h.bytes_mz = n_pad * r;
+    h.bytes_snap = (size_t)P.n_slots * n_pad * 2 * r;
+    h.bytes_pa = (size_t)P.n_tiles * P.inl_k.size() * 2 * r;
+    h.bytes_sig = (size_t)P.n_groups * P.n_adc * 16;
+}
+
+koma_status koma_req_save(const koma_req *q, void *host_buf, size_t *bytes) {
+    if (!q || !bytes) return KOMA_E_ARG;
+    koma_ctx *ctx = q->ctx;
+    CkptHeader h;
+    ckpt_sizes(q, h);
+    const size_t total = sizeof h + h.bytes_mxy + h.bytes_mz + h.bytes_snap + h.bytes_pa + h.bytes_sig;
+    if (!host_buf) {
+        *bytes = total;
+        return KOMA_OK;
+    }
+    if (*bytes < total) return fail(ctx, KOMA_E_ARG, "checkpoint buffer too small (%zu < %zu)", *bytes, total);
+    if (ctx->poisoned) return fail(ctx, KOMA_E_DEVICE, "context poisoned by an earlier device error");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, hipDeviceSynchronize());
+    char *p = (char *)host_buf;
+    memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    const std::pair<const DevMem *, uint64_t> parts[] = {
+        {&q->mxy, h.bytes_mxy}, {&q->mz, h.bytes_mz}, {&q->snap, h.bytes_snap}, {&q->pa, h.bytes_pa}, {&q->sig, h.bytes_sig}};
+    for (auto &pr : parts) {
+        if (pr.second) HIPCHK(ctx, hipMemcpy(p, pr.first->p, pr.second, hipMemcpyDeviceToHost));
+        p += pr.second;
+    }
+    *bytes = total;
+    return KOMA_OK;
+}
+
+koma_status koma_req_load(koma_req *q, const void *host_buf, size_t bytes) {
+    if (!q || !host_buf) return KOMA_E_ARG;
+    koma_ctx *ctx = q->ctx;
+    CkptHeader want, got;
+    ckpt_sizes(q, want);
+    if (bytes < sizeof got) return fail(ctx, KOMA_E_ARG, "checkpoint too short");
+    memcpy(&got, host_buf, sizeof got);
+    if (got.magic != kCkptMagic || got.n_ev != want.n_ev || got.n_tiles != want.n_tiles || got.n_inl != want.n_inl ||
+        got.n_slots != want.n_slots || got.n_adc != want.n_adc || got.n_groups != want.n_groups ||
+        got.fp64 != want.fp64 || got.bytes_mxy != want.bytes_mxy || got.bytes_snap != want.bytes_snap ||
+        got.bytes_pa != want.bytes_pa || got.bytes_sig != want.bytes_sig)
+        return fail(ctx, KOMA_E_STATE, "checkpoint does not match this request");
+    const size_t total = sizeof got + got.bytes_mxy + got.bytes_mz + got.bytes_snap + got.bytes_pa + got.bytes_sig;
+    if (bytes < total) return fail(ctx, KOMA_E_ARG, "checkpoint truncated");
+    if (got.cursor < 0 || (uint64_t)got.cursor > got.n_ev || got.next_chunk < 0 ||
+        (size_t)got.next_chunk > q->plan.chunks.size())
+        return fail(ctx, KOMA_E_STATE, "checkpoint cursor out of range");
+    if (ctx->poisoned) return fail(ctx, KOMA_E_DEVICE, "context poisoned by an earlier device error");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, hipDeviceSynchronize());
+    const char *p = (const char *)host_buf + sizeof got;
+    const std::pair<DevMem *, uint64_t> parts[] = {
+        {&q->mxy, got.bytes_mxy}, {&q->mz, got.bytes_mz}, {&q->snap, got.bytes_snap}, {&q->pa, got.bytes_pa}, {&q->sig, got.bytes_sig}};
+    for (auto &pr : parts) {
+        if (pr.second) HIPCHK(ctx, hipMemcpy(pr.first->p, p, pr.second, hipMemcpyHostToDevice));
+        p += pr.second;
+    }
+    q->cursor = got.cursor;
+    q->next_chunk = (size_t)got.next_chunk;
+    q->finished = got.finished != 0;
+    return KOMA_OK;
+}
+
+void koma_req_close(koma_req *q) {
+    if (!q) return;
+    (void)hipSetDevice(q->ctx->device);
+    // wait only for this request's own work; other requests keep running
+    (void)hipStreamSynchronize(q->ctx->stream);
+    if (q->last_stream) (void)hipStreamSynchronize(q->last_stream);
+    req_free(q);
+    delete q;
+}
+
+static void fill_info(const Plan &P, koma_req_info *info) {
+    info->n_spins = P.n_spins;
+    info->n_tiles = P.n_tiles;
+    info->n_groups = P.n_groups;
+    info->n_adc = P.n_adc;
+    info->n_events = (int64_t)P.ev.size();
+    info->n_rf = P.n_rf;
+    info->n_runs = P.n_runs;
+    info->n_inline_adc = (int64_t)P.inl_k.size();
+    info->n_deferred_adc = (int64_t)P.def_k.size();
+    info->n_stretches = (int64_t)P.st.size();
+    info->n_snapshots = P.n_slots;
+    info->n_blocks = (int64_t)P.blocks.size();
+    info->spins_per_lane = P.spl;
+    info->n_chunks = (int64_t)P.chunks.size();
+    info->events_done = 0;
+    info->footprint = 0;
+}
+
+koma_status koma_req_info_get(const koma_req *q, koma_req_info *info) {
+    if (!q || !info) return KOMA_E_ARG;
+    fill_info(q->plan, info);
+    info->events_done = q->cursor;
+    info->footprint = q->footprint;
+    return KOMA_OK;
+}
+
+koma_status koma_plan_info(const koma_scanner *sc, const koma_phantom *ph, const koma_sequence *seq,
+                           const koma_config *cfg, koma_req_info *info) {
+    koma_ctx tmp;
+    if (!info) return KOMA_E_ARG;
+    koma_config c;
+    if (cfg)
+        c = *cfg;
+    else
+        koma_config_default(&c);
+    koma_status st;
+    if ((st = check_config(&tmp, &c)) != KOMA_OK) return st;
+    if ((st = check_scanner(&tmp, sc)) != KOMA_OK) return st;
+    if ((st = check_phantom_shape(&tmp, ph)) != KOMA_OK) return st;
+    if ((st = check_sequence(&tmp, seq)) != KOMA_OK) return st;
+    Plan P;
+    if ((st = build_plan(&tmp, c, sc->gamma, ph, seq, P)) != KOMA_OK) return st;
+    fill_info(P, info);
+    info->footprint = plan_footprint(P, c.precision == KOMA_FP64, true, true);
+    return KOMA_OK;
+}
+
+}  // extern "C"

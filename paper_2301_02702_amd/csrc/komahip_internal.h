@@ -1,0 +1,131 @@
+// Internal layout shared by the host planner (komahip_host.cpp) and the
+// kernels (komahip_kernels.hip). Not part of the public ABI.
+//
+// The packed sequence is an "event program" that every spin runs in the
+// same order (so every branch on an event is uniform across a wavefront):
+//
+//   EV_RF    one excitation-regime interval: spinor rotation about
+//            B = (B1, x.G + dw/gamma) by -gamma|B|dt, then relaxation
+//            (Eq. Rot_exc and the relaxation update).
+//   EV_END   end of a precession block: rotate Mxy by the block's integral
+//            phase -2 pi (x.K + f tau) and relax over the elapsed time tau,
+//            where K = gamma_bar * sum(G_mean dt) (cycles/m) and f = dw/2pi
+//            are accumulated from the block start (section on precession
+//            blocks: exact for piecewise-linear G).
+//   EV_ADC   `count` evenly spaced ADC samples inside the current precession
+//            block, evaluated from the block-start state; the first at the
+//            anchor (K0, tau0), the next ones by the constant increment
+//            (dK, dtau). The per-wavefront sums go to inline partials.
+//   EV_SNAP  store the block-start Mxy in snapshot `a0`: the block's samples
+//            are then summed by the sample-parallel kernel from that snapshot
+//            (described by Stretch records).
+#pragma once
+#include <stdint.h>
+
+namespace koma {
+
+enum : int32_t { EV_RF = 0, EV_END = 1, EV_ADC = 2, EV_SNAP = 3 };
+
+struct alignas(16) Event {
+    int32_t kind;
+    int32_t a0;     // EV_ADC: first inline sample slot; EV_SNAP: snapshot slot
+    int32_t count;  // EV_ADC: number of samples
+    int32_t pad;
+    // EV_RF: gx, gy, gz (T/m, interval mean), b1_re, b1_im (T), |b1|^2,
+    //        hs = -gamma dt / (4 pi) (half rotation angle per tesla, in turns), dt (s)
+    float f[8];
+    // EV_RF: the same eight values in FP64.
+    // EV_END: kx, ky, kz (cycles/m), tau (s) of the block end.
+    // EV_ADC: kx, ky, kz, tau of the first sample, then dkx, dky, dkz, dtau.
+    double d[8];
+};
+static_assert(sizeof(Event) == 112, "Event layout");
+
+// Evenly spaced samples of one deferred precession block, summed by the
+// sample-parallel kernel from snapshot `slot`.
+struct alignas(16) Stretch {
+    int32_t slot;
+    int32_t d0;     // deferred sample index of the first sample
+    int32_t count;  // samples (<= 128)
+    int32_t pad;
+    double k0[4];   // kx, ky, kz, tau of the first sample
+    double dk[4];   // increments between consecutive samples
+};
+static_assert(sizeof(Stretch) == 80, "Stretch layout");
+
+// 64 consecutive spin slots of one signal group (one wavefront).
+struct alignas(16) Tile {
+    int64_t spin0;
+    int32_t count;  // valid lanes (1..64)
+    int32_t group;
+};
+
+// Consecutive tiles of one group summed into one cross-workgroup partial.
+struct alignas(16) Block {
+    int32_t tile0;
+    int32_t ntiles;
+    int32_t group;
+    int32_t pad;
+};
+
+struct PhantomDev {
+    const float *x, *y, *z, *pd, *t1, *t2, *dw;
+};
+
+constexpr int kWave = 64;
+constexpr int kWG = 256;            // 4 wavefronts
+constexpr int kWavesPerWG = kWG / kWave;
+constexpr int kBatch = 16;          // samples reduced together by the register transpose
+constexpr int kStretchMax = 128;
+
+struct SeqArgs {  // spin-sequential kernel
+    PhantomDev ph;
+    const Tile *tiles;
+    int64_t n_tiles;
+    const Event *ev;
+    int64_t e0, e1;
+    double inv_gamma;
+    int init;         // start from thermal equilibrium instead of the stored state
+    int store;        // store the state at the end
+    void *mxy;        // state: [n_tiles*64] complex (R2)
+    void *mz;         // [n_tiles*64] R
+    void *snap;       // [n_slots][n_tiles*64] complex (R2)
+    void *pa;         // inline partials [n_tiles][n_inline] complex (R2)
+    int64_t n_inline;
+};
+
+struct ParArgs {  // sample-parallel kernel
+    PhantomDev ph;
+    const Tile *tiles;
+    int64_t n_tiles;
+    const Block *blocks;
+    int64_t n_blocks;
+    const Stretch *st;
+    int64_t s0, s1;        // stretches of this launch
+    int64_t per_wg;        // stretches per workgroup (grid.y = ceil((s1-s0)/per_wg))
+    const void *snap;
+    double *pb;            // [n_blocks][cols] double2
+    int64_t col0, cols;    // deferred sample index of column 0, columns
+};
+
+struct ReduceArgs {  // cross-workgroup sums into the signal
+    const void *part;      // [n_rows][cols] complex
+    int64_t cols;
+    const int32_t *row_off;  // group g owns rows [row_off[g], row_off[g+1])
+    int64_t n_groups;
+    const int32_t *col_to_adc;  // column c -> ADC index
+    double *sig;           // [n_groups][n_adc] double2
+    int64_t n_adc;
+};
+
+}  // namespace koma
+
+// Launchers (komahip_kernels.hip). All asynchronous on `stream`.
+namespace koma {
+int launch_seq(bool fp64, const SeqArgs &a, void *stream);
+int launch_par(bool fp64, int spins_per_lane, const ParArgs &a, void *stream);
+int launch_reduce(bool part_fp64, const ReduceArgs &a, void *stream);
+int launch_validate(const PhantomDev &ph, int64_t n, int32_t *flags, void *stream);
+int launch_export(bool fp64, const Tile *tiles, int64_t n_tiles, const void *mxy, const void *mz,
+                  double *m_final, void *stream);
+}  // namespace koma

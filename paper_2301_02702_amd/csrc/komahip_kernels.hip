@@ -1,0 +1,612 @@
+// HIP kernels for gfx950 (CDNA4, wave64) of the Bloch-simulation hot path.
+//
+// Arithmetic of one spin follows the paper's first-order splitting
+// (section "Physical and Mathematical Background"):
+//   excitation interval: spinor rotation of Eq. Rot_exc with
+//     alpha = cos(phi/2) - i n_z sin(phi/2), beta = -i n_xy sin(phi/2),
+//     n = B/|B|, phi = -gamma |B| dt (Eq. angle_precession), B from Eq. B-def,
+//     then the relaxation update;
+//   precession block: Mxy * exp(i phi) with the integral phase of the block
+//     (section "Simulation blocks, Regime Switching, and Sequence-Aware Time
+//     Stepping"), then relaxation over the elapsed block time;
+//   ADC: sum of Mxy over the spins of a group (Figure 3).
+//
+// Kernels:
+//   k_seq   spin-sequential: one lane per spin, every wavefront walks the
+//           shared event program (uniform branches, events read through the
+//           scalar cache). Excitation intervals, block ends, short sample
+//           runs (summed per wavefront), snapshots of block-start states.
+//   k_par   sample-parallel: a workgroup owns up to 4*S tiles of one group
+//           and a few stretches of evenly spaced samples; each lane walks S
+//           spins, evaluates one exact anchor phasor in FP64 phase and then
+//           rotates by the per-sample increment (complex recurrence), and
+//           16 samples at a time are summed over the 64 lanes by a register
+//           transpose (permlane32/16 swaps, DPP row rotations and quad
+//           permutes). The four wavefronts are added in FP64 through LDS.
+//   k_reduce fixed-order FP64 sum of per-wavefront / per-workgroup partials.
+//   k_export state to the caller's (Mx, My, Mz) layout.
+//
+// No atomics anywhere: every sum has a fixed order, so results are bitwise
+// reproducible for a fixed launch configuration.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "komahip_internal.h"
+
+namespace koma {
+
+constexpr double kInv2Pi = 0.15915494309189533577;
+constexpr float kLog2e = 1.44269504088896340736f;
+
+// ---------------------------------------------------------------- precision
+
+// FP32 for rotations and relaxation; FP64 only where a phase accumulates.
+struct Mixed {
+    using R = float;
+    using R2 = float2;
+    static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+    // sin/cos of 2*pi*h for h in turns (hardware sine/cosine take turns)
+    static __device__ __forceinline__ void sincos_turns(float h, float &s, float &c) {
+        float r = __builtin_amdgcn_fractf(h);
+        s = __builtin_amdgcn_sinf(r);
+        c = __builtin_amdgcn_cosf(r);
+    }
+    // same for a phase held in FP64: the FP64 reduction to [0, 1) is exact
+    static __device__ __forceinline__ void sincos_turns(double h, float &s, float &c) {
+        float r = (float)__builtin_amdgcn_fract(h);
+        s = __builtin_amdgcn_sinf(r);
+        c = __builtin_amdgcn_cosf(r);
+    }
+    static __device__ __forceinline__ float exp_neg(float x) {  // exp(-x)
+        return __builtin_amdgcn_exp2f(-x * kLog2e);
+    }
+};
+
+struct FP64 {
+    using R = double;
+    using R2 = double2;
+    static __device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
+    static __device__ __forceinline__ void sincos_turns(double h, double &s, double &c) {
+        double r = h - rint(h);
+        sincospi(2.0 * r, &s, &c);
+    }
+    static __device__ __forceinline__ double exp_neg(double x) { return exp(-x); }
+};
+
+template <class R>
+struct C2 {
+    R re, im;
+};
+
+template <class R>
+__device__ __forceinline__ C2<R> cmul(C2<R> a, C2<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+// Unit phasor (c, s) renormalised by one Newton step towards |.| = 1, so
+// repeated products of hardware sines/cosines do not drift in magnitude. In
+// FP32 the defect c^2 + s^2 - 1 is formed exactly in FP64 (products of floats
+// are exact there) and applied with one FP32 fma: a correction factor rounded
+// to FP32 near 1.0 would be quantised unevenly and bias every step.
+__device__ __forceinline__ void renorm(float &c, float &s) {
+    const double d = fma((double)c, (double)c, fma((double)s, (double)s, -1.0));
+    const float h = (float)(-0.5 * d);
+    c = fmaf(c, h, c);
+    s = fmaf(s, h, s);
+}
+__device__ __forceinline__ void renorm(double &c, double &s) {
+    const double h = -0.5 * fma(c, c, fma(s, s, -1.0));
+    c = fma(c, h, c);
+    s = fma(s, h, s);
+}
+
+// ---------------------------------------------------------------- spin data
+
+template <class R>
+struct SpinP {
+    R x, y, z, pd, r1, r2, bz0;  // bz0 = dw / gamma (T)
+    double xd, yd, zd, f;        // FP64 copies for block phases, f = dw / 2 pi (Hz)
+};
+
+template <class R>
+__device__ __forceinline__ SpinP<R> load_spin(const PhantomDev &ph, const Tile &t, int lane,
+                                              double inv_gamma) {
+    SpinP<R> s;
+    float x = 0.f, y = 0.f, z = 0.f, pd = 0.f, t1 = __builtin_inff(), t2 = __builtin_inff(), dw = 0.f;
+    if (lane < t.count) {
+        const int64_t i = t.spin0 + lane;
+        x = ph.x[i];
+        y = ph.y[i];
+        z = ph.z[i];
+        pd = ph.pd[i];
+        t1 = ph.t1[i];
+        t2 = ph.t2[i];
+        dw = ph.dw[i];
+    }
+    s.x = x;
+    s.y = y;
+    s.z = z;
+    s.pd = pd;
+    s.r1 = R(1) / R(t1);  // T = +inf gives exactly 0: no relaxation
+    s.r2 = R(1) / R(t2);
+    s.bz0 = R((double)dw * inv_gamma);
+    s.xd = x;
+    s.yd = y;
+    s.zd = z;
+    s.f = (double)dw * kInv2Pi;
+    return s;
+}
+
+// ---------------------------------------------------------------- wave sums
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    uint64_t u = __builtin_bit_cast(uint64_t, v);
+    int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+    int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+constexpr int DPP_ROR8 = 0x128;
+constexpr int DPP_HALF_MIRROR = 0x141;
+constexpr int DPP_QUAD_1032 = 0xB1;  // quad_perm [1,0,3,2]: lane ^ 1
+constexpr int DPP_QUAD_2301 = 0x4E;  // quad_perm [2,3,0,1]: lane ^ 2
+
+// After the call: a = [a lanes 0-31, b lanes 0-31], b = [a lanes 32-63, b lanes 32-63].
+__device__ __forceinline__ void swap32(float &a, float &b) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+// Within each half wave: a = [a 0-15, b 0-15], b = [a 16-31, b 16-31] (and the same for 32-63).
+__device__ __forceinline__ void swap16(float &a, float &b) {
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void split(double v, uint32_t &lo, uint32_t &hi) {
+    uint64_t u = __builtin_bit_cast(uint64_t, v);
+    lo = (uint32_t)u;
+    hi = (uint32_t)(u >> 32);
+}
+__device__ __forceinline__ double join(uint32_t lo, uint32_t hi) {
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ void swap32(double &a, double &b) {
+    uint32_t al, ah, bl, bh;
+    split(a, al, ah);
+    split(b, bl, bh);
+    auto lo = __builtin_amdgcn_permlane32_swap(al, bl, false, false);
+    auto hi = __builtin_amdgcn_permlane32_swap(ah, bh, false, false);
+    a = join(lo[0], hi[0]);
+    b = join(lo[1], hi[1]);
+}
+__device__ __forceinline__ void swap16(double &a, double &b) {
+    uint32_t al, ah, bl, bh;
+    split(a, al, ah);
+    split(b, bl, bh);
+    auto lo = __builtin_amdgcn_permlane16_swap(al, bl, false, false);
+    auto hi = __builtin_amdgcn_permlane16_swap(ah, bh, false, false);
+    a = join(lo[0], hi[0]);
+    b = join(lo[1], hi[1]);
+}
+
+// Sum over the 64 lanes; every lane receives the total. Fixed pairing order.
+template <class R>
+__device__ __forceinline__ R wave_allsum(R v) {
+    R a = v, b = v;
+    swap32(a, b);  // a + b = v[l] + v[l ^ 32]
+    v = a + b;
+    a = v;
+    b = v;
+    swap16(a, b);  // + v[l ^ 16]
+    v = a + b;
+    v = v + dpp<DPP_ROR8>(v);         // + lane l ^ 8 within the row
+    v = v + dpp<DPP_HALF_MIRROR>(v);  // + lane 7 - l within the half row
+    v = v + dpp<DPP_QUAD_1032>(v);
+    v = v + dpp<DPP_QUAD_2301>(v);
+    return v;
+}
+
+// Register transpose-sum of 16 samples held by every lane: on return lane l
+// holds in v[0] the sum over all 64 lanes of sample (l >> 2) (the four lanes
+// of a quad hold the same value).
+template <class R>
+__device__ __forceinline__ void transpose_sum16(R (&v)[16]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {  // lanes 0-31 keep samples 0-7, lanes 32-63 samples 8-15
+        swap32(v[i], v[i + 8]);
+        v[i] = v[i] + v[i + 8];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {  // sample i + 4*bit4 + 8*bit5
+        swap16(v[i], v[i + 4]);
+        v[i] = v[i] + v[i + 4];
+    }
+    const bool b3 = lane & 8, b2 = lane & 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {  // sample i + 2*bit3 + 4*bit4 + 8*bit5
+        R keep = b3 ? v[i + 2] : v[i];
+        R send = b3 ? v[i] : v[i + 2];
+        v[i] = keep + dpp<DPP_ROR8>(send);
+    }
+    {  // sample bit2 + 2*bit3 + 4*bit4 + 8*bit5 = lane >> 2
+        R keep = b2 ? v[1] : v[0];
+        R send = b2 ? v[0] : v[1];
+        v[0] = keep + dpp<DPP_HALF_MIRROR>(send);
+    }
+    v[0] = v[0] + dpp<DPP_QUAD_1032>(v[0]);
+    v[0] = v[0] + dpp<DPP_QUAD_2301>(v[0]);
+}
+
+// ---------------------------------------------------------------- the steps
+
+// Block phase (turns) at moment K (cycles/m) and elapsed tau: -(x.K + f tau).
+template <class R>
+__device__ __forceinline__ double block_phase(const SpinP<R> &s, const double *k) {
+    return -fma(s.xd, k[0], fma(s.yd, k[1], fma(s.zd, k[2], s.f * k[3])));
+}
+
+// exp(i*2*pi*theta) * exp(-tau * r2) as a complex factor
+template <class P>
+__device__ __forceinline__ C2<typename P::R> block_factor(const SpinP<typename P::R> &s, double theta,
+                                                          double tau) {
+    using R = typename P::R;
+    R sn, cs;
+    P::sincos_turns(theta, sn, cs);
+    renorm(cs, sn);
+    R e2 = P::exp_neg(R(tau) * s.r2);
+    return {cs * e2, sn * e2};
+}
+
+// One excitation interval (Eq. Rot_exc) followed by relaxation with the
+// cached eps = 1 - exp(-dt/T) (applied as M - eps*M, exact in the factor).
+template <class P>
+__device__ __forceinline__ void excite_relax(const SpinP<typename P::R> &s, const typename P::R *q,
+                                             typename P::R eps1, typename P::R eps2,
+                                             typename P::R &mr, typename P::R &mi,
+                                             typename P::R &mz) {
+    using R = typename P::R;
+    const R gx = q[0], gy = q[1], gz = q[2], b1r = q[3], b1i = q[4], b1sq = q[5], hs = q[6];
+    const R bz = fma(s.x, gx, fma(s.y, gy, fma(s.z, gz, s.bz0)));
+    const R nb2 = fma(bz, bz, b1sq);
+    // |B| = 0 (possible only if |b1|^2 underflows) leaves the spin unrotated
+    const R inv = nb2 > R(0) ? P::rsq(nb2) : R(0);
+    const R nb = nb2 * inv;
+    R sn, cs;
+    P::sincos_turns(hs * nb, sn, cs);  // sin, cos of phi/2
+    R sk = sn * inv;                   // sin(phi/2) / |B|
+    // normalise the spinor, |alpha|^2 + |beta|^2 = cs^2 + sk^2 |B|^2 -> 1, with
+    // the defect formed exactly in FP64 (see renorm)
+    {
+        const double B2 = fma((double)bz, (double)bz, fma((double)b1r, (double)b1r, (double)b1i * (double)b1i));
+        const double sk2 = (double)sk * (double)sk;
+        const R h = R(-0.5 * fma(sk2, B2, fma((double)cs, (double)cs, -1.0)));
+        cs = fma(cs, h, cs);
+        sk = fma(sk, h, sk);
+    }
+    const R ar = cs, ai = -bz * sk;        // alpha = cos - i n_z sin
+    const R br = b1i * sk, bi = -b1r * sk;  // beta = -i (b1/|B|) sin
+    // conj(alpha)^2, beta^2, conj(alpha) beta, alpha beta
+    const R ur = ar * ar - ai * ai, ui = R(-2) * ar * ai;
+    const R vr = br * br - bi * bi, vi = R(2) * br * bi;
+    const R wr = ar * br + ai * bi, wi = ar * bi - ai * br;
+    const R pr = ar * br - ai * bi, pi = ar * bi + ai * br;
+    const R dz = (ar * ar + ai * ai) - (br * br + bi * bi);
+    // Mxy+ = 2 conj(a) b Mz + conj(a)^2 Mxy - b^2 conj(Mxy)
+    const R nr = R(2) * wr * mz + (ur - vr) * mr - (ui + vi) * mi;
+    const R ni = R(2) * wi * mz + (ur + vr) * mi + (ui - vi) * mr;
+    // Mz+ = (|a|^2 - |b|^2) Mz - 2 Re(a b conj(Mxy))
+    const R nz = dz * mz - R(2) * (pr * mr + pi * mi);
+    // relaxation: Mxy (1 - eps2), Mz - eps1 (Mz - M0)
+    mr = fma(-eps2, nr, nr);
+    mi = fma(-eps2, ni, ni);
+    mz = fma(-eps1, nz - s.pd, nz);
+}
+
+// ---------------------------------------------------------------- k_seq
+
+template <class P>
+__global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
+    using R = typename P::R;
+    using R2 = typename P::R2;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t tile = (int64_t)blockIdx.x * kWavesPerWG + wave;
+    if (tile >= a.n_tiles) return;  // whole wavefront; no barrier in this kernel
+    const Tile T = a.tiles[tile];
+    const SpinP<R> s = load_spin<R>(a.ph, T, lane, a.inv_gamma);
+    const int64_t n_pad = a.n_tiles * kWave;
+    const int64_t pidx = tile * kWave + lane;
+
+    R mr, mi, mz;
+    if (a.init) {
+        mr = R(0);
+        mi = R(0);
+        mz = s.pd;
+    } else {
+        R2 m = reinterpret_cast<const R2 *>(a.mxy)[pidx];
+        mr = m.x;
+        mi = m.y;
+        mz = reinterpret_cast<const R *>(a.mz)[pidx];
+    }
+    R eps1 = R(0), eps2 = R(0);
+    double dt_cached = -1.0;  // uniform
+
+    for (int64_t e = a.e0; e < a.e1; ++e) {
+        const Event &ev = a.ev[e];
+        const int kind = ev.kind;
+        if (kind == EV_RF) {
+            R q[7];
+            const double dt = ev.d[7];
+            if constexpr (sizeof(R) == 4) {
+#pragma unroll
+                for (int i = 0; i < 7; ++i) q[i] = ev.f[i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 7; ++i) q[i] = ev.d[i];
+            }
+            if (dt != dt_cached) {  // uniform: same interval length for every spin
+                dt_cached = dt;
+                eps1 = R(-expm1(-dt * (double)s.r1));
+                eps2 = R(-expm1(-dt * (double)s.r2));
+            }
+            excite_relax<P>(s, q, eps1, eps2, mr, mi, mz);
+        } else if (kind == EV_END) {
+            const double theta = block_phase(s, ev.d);
+            const double tau = ev.d[3];
+            C2<R> f = block_factor<P>(s, theta, tau);
+            C2<R> m = cmul(C2<R>{mr, mi}, f);
+            mr = m.re;
+            mi = m.im;
+            mz = s.pd + (mz - s.pd) * P::exp_neg(R(tau) * s.r1);
+        } else if (kind == EV_ADC) {
+            C2<R> c = cmul(C2<R>{mr, mi}, block_factor<P>(s, block_phase(s, ev.d), ev.d[3]));
+            const int cnt = ev.count;
+            C2<R> w{R(1), R(0)};
+            if (cnt > 1) w = block_factor<P>(s, block_phase(s, ev.d + 4), ev.d[7]);
+            R2 *pa = reinterpret_cast<R2 *>(a.pa) + tile * a.n_inline + ev.a0;
+            for (int i = 0; i < cnt; ++i) {
+                const R sr = wave_allsum(c.re);
+                const R si = wave_allsum(c.im);
+                if (lane == 0) pa[i] = R2{sr, si};
+                c = cmul(c, w);
+            }
+        } else {  // EV_SNAP
+            reinterpret_cast<R2 *>(a.snap)[(int64_t)ev.a0 * n_pad + pidx] = R2{mr, mi};
+        }
+    }
+    if (a.store) {
+        reinterpret_cast<R2 *>(a.mxy)[pidx] = R2{mr, mi};
+        reinterpret_cast<R *>(a.mz)[pidx] = mz;
+    }
+}
+
+// ---------------------------------------------------------------- k_par
+
+template <class P, int S>
+__global__ __launch_bounds__(kWG) void k_par(ParArgs a) {
+    using R = typename P::R;
+    using R2 = typename P::R2;
+    __shared__ double2 red[kWavesPerWG][kStretchMax];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const Block B = a.blocks[blockIdx.x];
+    const int64_t n_pad = a.n_tiles * kWave;
+
+    SpinP<R> sp[S];
+    int64_t pidx[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int tl = wave + kWavesPerWG * j;
+        Tile T;
+        if (tl < B.ntiles) {
+            T = a.tiles[B.tile0 + tl];
+        } else {  // no spin: zero contribution
+            T.spin0 = 0;
+            T.count = 0;
+            T.group = 0;
+        }
+        sp[j] = load_spin<R>(a.ph, T, lane, 0.0);
+        pidx[j] = (tl < B.ntiles) ? (int64_t)(B.tile0 + tl) * kWave + lane : -1;
+    }
+
+    const int64_t st0 = a.s0 + (int64_t)blockIdx.y * a.per_wg;
+    const int64_t st1 = min(st0 + a.per_wg, a.s1);
+    for (int64_t st = st0; st < st1; ++st) {
+        const Stretch &S_ = a.st[st];
+        const int cnt = S_.count;
+        C2<R> c[S], w[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            C2<R> m{R(0), R(0)};
+            if (pidx[j] >= 0) {
+                R2 v = reinterpret_cast<const R2 *>(a.snap)[(int64_t)S_.slot * n_pad + pidx[j]];
+                m = C2<R>{v.x, v.y};
+            }
+            c[j] = cmul(m, block_factor<P>(sp[j], block_phase(sp[j], S_.k0), S_.k0[3]));
+            w[j] = block_factor<P>(sp[j], block_phase(sp[j], S_.dk), S_.dk[3]);
+        }
+        for (int b0 = 0; b0 < cnt; b0 += kBatch) {
+            R are[kBatch], aim[kBatch];
+#pragma unroll
+            for (int i = 0; i < kBatch; ++i) {
+                are[i] = R(0);
+                aim[i] = R(0);
+            }
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+#pragma unroll
+                for (int i = 0; i < kBatch; ++i) {
+                    are[i] += c[j].re;
+                    aim[i] += c[j].im;
+                    c[j] = cmul(c[j], w[j]);
+                }
+            }
+            transpose_sum16(are);
+            transpose_sum16(aim);
+            const int smp = b0 + (lane >> 2);
+            if ((lane & 3) == 0 && smp < cnt) red[wave][smp] = make_double2((double)are[0], (double)aim[0]);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt; i += kWG) {
+            double2 t = red[0][i];
+#pragma unroll
+            for (int wv = 1; wv < kWavesPerWG; ++wv) {
+                t.x += red[wv][i].x;
+                t.y += red[wv][i].y;
+            }
+            reinterpret_cast<double2 *>(a.pb)[(int64_t)blockIdx.x * a.cols + (S_.d0 - a.col0) + i] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- k_reduce
+
+// sig[g][adc(c)] = sum over rows r of group g (in order) of part[r][c].
+// A workgroup covers 64 columns; its 4 wavefronts take rows r = r0 + w (mod 4)
+// and the four partial sums are added in wave order.
+template <class T2>
+__global__ __launch_bounds__(kWG) void k_reduce(ReduceArgs a) {
+    __shared__ double2 red[kWavesPerWG][kWave];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t col = (int64_t)blockIdx.x * kWave + lane;
+    for (int64_t g = blockIdx.y; g < a.n_groups; g += gridDim.y) {  // uniform per workgroup
+        const int32_t r0 = a.row_off[g], r1 = a.row_off[g + 1];
+        double sx = 0.0, sy = 0.0;
+        if (col < a.cols) {
+            const T2 *p = reinterpret_cast<const T2 *>(a.part);
+            for (int32_t r = r0 + wave; r < r1; r += kWavesPerWG) {
+                T2 v = p[(int64_t)r * a.cols + col];
+                sx += (double)v.x;
+                sy += (double)v.y;
+            }
+        }
+        red[wave][lane] = make_double2(sx, sy);
+        __syncthreads();
+        if (wave == 0 && col < a.cols) {
+            double2 t = red[0][lane];
+#pragma unroll
+            for (int wv = 1; wv < kWavesPerWG; ++wv) {
+                t.x += red[wv][lane].x;
+                t.y += red[wv][lane].y;
+            }
+            reinterpret_cast<double2 *>(a.sig)[g * a.n_adc + a.col_to_adc[col]] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- k_export
+
+template <class R, class R2>
+__global__ __launch_bounds__(kWG) void k_export(const Tile *tiles, int64_t n_tiles, const R2 *mxy,
+                                                const R *mz, double *out) {
+    const int64_t p = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    const int64_t tile = p / kWave;
+    const int lane = (int)(p % kWave);
+    if (tile >= n_tiles) return;
+    const Tile T = tiles[tile];
+    if (lane >= T.count) return;
+    const int64_t i = T.spin0 + lane;
+    out[3 * i + 0] = (double)mxy[p].x;
+    out[3 * i + 1] = (double)mxy[p].y;
+    out[3 * i + 2] = (double)mz[p];
+}
+
+// ---------------------------------------------------------------- k_validate
+
+// Per-workgroup flags of invalid phantom values (device-resident phantoms):
+// bit 0 non-finite x, y, z, dw or PD; bit 1 PD < 0; bit 2 T1 or T2 <= 0 or NaN.
+__global__ __launch_bounds__(kWG) void k_validate(PhantomDev ph, int64_t n, int32_t *flags) {
+    __shared__ int32_t f[kWG];
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    int32_t bad = 0;
+    if (i < n) {
+        const float x = ph.x[i], y = ph.y[i], z = ph.z[i], dw = ph.dw[i], pd = ph.pd[i];
+        const float t1 = ph.t1[i], t2 = ph.t2[i];
+        if (!isfinite(x) || !isfinite(y) || !isfinite(z) || !isfinite(dw) || !isfinite(pd)) bad |= 1;
+        if (pd < 0.f) bad |= 2;
+        if (!(t1 > 0.f) || !(t2 > 0.f)) bad |= 4;
+    }
+    f[threadIdx.x] = bad;
+    __syncthreads();
+    for (int s = kWG / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) f[threadIdx.x] |= f[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) flags[blockIdx.x] = f[0];
+}
+
+// ---------------------------------------------------------------- launchers
+
+static int check_launch() { return hipGetLastError() == hipSuccess ? 0 : -1; }
+
+int launch_seq(bool fp64, const SeqArgs &a, void *stream) {
+    if (a.n_tiles <= 0 || a.e1 <= a.e0) return 0;
+    dim3 grid((unsigned)((a.n_tiles + kWavesPerWG - 1) / kWavesPerWG));
+    if (fp64)
+        hipLaunchKernelGGL(k_seq<FP64>, grid, dim3(kWG), 0, (hipStream_t)stream, a);
+    else
+        hipLaunchKernelGGL(k_seq<Mixed>, grid, dim3(kWG), 0, (hipStream_t)stream, a);
+    return check_launch();
+}
+
+template <class P>
+static void par_dispatch(int spl, dim3 grid, const ParArgs &a, hipStream_t st) {
+    switch (spl) {
+        case 1: hipLaunchKernelGGL((k_par<P, 1>), grid, dim3(kWG), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_par<P, 2>), grid, dim3(kWG), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_par<P, 4>), grid, dim3(kWG), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_par<P, 8>), grid, dim3(kWG), 0, st, a); break;
+    }
+}
+
+int launch_par(bool fp64, int spl, const ParArgs &a, void *stream) {
+    if (a.n_blocks <= 0 || a.s1 <= a.s0) return 0;
+    dim3 grid((unsigned)a.n_blocks, (unsigned)((a.s1 - a.s0 + a.per_wg - 1) / a.per_wg));
+    if (fp64)
+        par_dispatch<FP64>(spl, grid, a, (hipStream_t)stream);
+    else
+        par_dispatch<Mixed>(spl, grid, a, (hipStream_t)stream);
+    return check_launch();
+}
+
+int launch_reduce(bool part_fp64, const ReduceArgs &a, void *stream) {
+    if (a.cols <= 0 || a.n_groups <= 0) return 0;
+    dim3 grid((unsigned)((a.cols + kWave - 1) / kWave), (unsigned)(a.n_groups < 65535 ? a.n_groups : 65535));
+    if (part_fp64)
+        hipLaunchKernelGGL(k_reduce<double2>, grid, dim3(kWG), 0, (hipStream_t)stream, a);
+    else
+        hipLaunchKernelGGL(k_reduce<float2>, grid, dim3(kWG), 0, (hipStream_t)stream, a);
+    return check_launch();
+}
+
+int launch_validate(const PhantomDev &ph, int64_t n, int32_t *flags, void *stream) {
+    if (n <= 0) return 0;
+    dim3 grid((unsigned)((n + kWG - 1) / kWG));
+    hipLaunchKernelGGL(k_validate, grid, dim3(kWG), 0, (hipStream_t)stream, ph, n, flags);
+    return check_launch();
+}
+
+int launch_export(bool fp64, const Tile *tiles, int64_t n_tiles, const void *mxy, const void *mz,
+                  double *m_final, void *stream) {
+    if (n_tiles <= 0) return 0;
+    const int64_t n = n_tiles * kWave;
+    dim3 grid((unsigned)((n + kWG - 1) / kWG));
+    if (fp64)
+        hipLaunchKernelGGL((k_export<double, double2>), grid, dim3(kWG), 0, (hipStream_t)stream, tiles,
+                           n_tiles, (const double2 *)mxy, (const double *)mz, m_final);
+    else
+        hipLaunchKernelGGL((k_export<float, float2>), grid, dim3(kWG), 0, (hipStream_t)stream, tiles,
+                           n_tiles, (const float2 *)mxy, (const float *)mz, m_final);
+    return check_launch();
+}
+
+}  // namespace koma

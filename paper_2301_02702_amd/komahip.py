@@ -1,0 +1,336 @@
+"""Thin ctypes binding of ``libkomahip.so`` (see ``include/komahip.h``).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+library. The ``koma_*`` functions mirror the C entry points one to one;
+``Context`` and ``Request`` wrap them for numpy / torch callers. Importing
+this module raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int, c_int64, c_size_t, c_void_p
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkomahip.so")
+
+KOMA_OK = 0
+STATUS = {0: "KOMA_OK", -1: "KOMA_E_ARG", -2: "KOMA_E_PHANTOM", -3: "KOMA_E_SEQUENCE",
+          -4: "KOMA_E_NOMEM", -5: "KOMA_E_BUDGET", -6: "KOMA_E_DEVICE", -7: "KOMA_E_CANCELLED",
+          -8: "KOMA_E_STATE"}
+KOMA_FP64, KOMA_MIXED = 0, 1
+KOMA_HOST, KOMA_DEVICE = 0, 1
+KERNEL_KINDS = {"seq": 0, "par": 1, "reduce": 2, "aux": 3}
+
+
+class KomaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class koma_scanner(ctypes.Structure):
+    _fields_ = [("b0", c_double), ("gamma", c_double)]
+
+
+class koma_phantom(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("x", c_void_p), ("y", c_void_p), ("z", c_void_p), ("pd", c_void_p),
+                ("t1", c_void_p), ("t2", c_void_p), ("dw", c_void_p), ("n_groups", c_int64),
+                ("group_off", c_void_p)]
+
+
+class koma_sequence(ctypes.Structure):
+    _fields_ = [("n_t", c_int64), ("t", c_void_p), ("gx", c_void_p), ("gy", c_void_p),
+                ("gz", c_void_p), ("b1_re", c_void_p), ("b1_im", c_void_p), ("n_adc", c_int64),
+                ("adc_idx", c_void_p)]
+
+
+class koma_config(ctypes.Structure):
+    _fields_ = [("precision", c_int), ("spins_per_lane", c_int), ("wg_size", c_int),
+                ("chunk_events", c_int64), ("hbm_budget", c_size_t), ("partial_budget", c_size_t),
+                ("defer_min_adc", c_int), ("stretch_max", c_int)]
+
+
+class koma_req_info(ctypes.Structure):
+    _fields_ = [(k, c_int64) for k in (
+        "n_spins", "n_tiles", "n_groups", "n_adc", "n_events", "n_rf", "n_runs", "n_inline_adc",
+        "n_deferred_adc", "n_stretches", "n_snapshots", "n_blocks", "spins_per_lane", "n_chunks",
+        "events_done")] + [("footprint", c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = {
+    "koma_config_default": (None, [POINTER(koma_config)]),
+    "koma_ctx_create": (c_int, [c_int, POINTER(koma_config), POINTER(c_void_p)]),
+    "koma_ctx_destroy": (None, [c_void_p]),
+    "koma_last_error": (c_char_p, [c_void_p]),
+    "koma_ctx_set_config": (c_int, [c_void_p, POINTER(koma_config)]),
+    "koma_footprint": (c_int, [POINTER(koma_phantom), POINTER(koma_sequence), POINTER(koma_config),
+                               POINTER(c_size_t)]),
+    "koma_simulate": (c_int, [c_void_p, POINTER(koma_scanner), POINTER(koma_phantom),
+                              POINTER(koma_sequence), c_int, c_void_p, c_void_p, c_void_p]),
+    "koma_req_open": (c_int, [c_void_p, POINTER(koma_scanner), POINTER(koma_phantom),
+                              POINTER(koma_sequence), c_int, POINTER(c_void_p)]),
+    "koma_req_advance": (c_int, [c_void_p, c_int64, c_void_p]),
+    "koma_req_done": (c_int, [c_void_p, POINTER(c_int)]),
+    "koma_req_result": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "koma_req_save": (c_int, [c_void_p, c_void_p, POINTER(c_size_t)]),
+    "koma_req_load": (c_int, [c_void_p, c_void_p, c_size_t]),
+    "koma_req_close": (None, [c_void_p]),
+    "koma_req_info_get": (c_int, [c_void_p, POINTER(koma_req_info)]),
+    "koma_plan_info": (c_int, [POINTER(koma_scanner), POINTER(koma_phantom), POINTER(koma_sequence),
+                               POINTER(koma_config), POINTER(koma_req_info)]),
+    "koma_ctx_profile": (c_int, [c_void_p, c_int]),
+    "koma_ctx_kernel_stats": (c_int, [c_void_p, c_int, POINTER(c_double), POINTER(c_int64),
+                                      POINTER(c_int64)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load the library; raise if it is missing (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        try:
+            # torch ships its own HIP runtime under the same soname; loading it
+            # first makes this library bind to it, so the process holds one
+            # runtime and torch's device memory and streams are valid here
+            import torch  # noqa: F401
+        except ImportError:  # pragma: no cover
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2301_02702_amd.build` (there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status, ctx=None):
+    if status != KOMA_OK:
+        msg = lib().koma_last_error(ctx)
+        raise KomaError(status, msg.decode() if msg else "")
+
+
+# ---------------------------------------------------------------- marshalling
+def _ptr(a):
+    """Pointer of a numpy array or torch tensor (None stays NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()  # torch tensor
+
+
+def make_config(precision="mixed", **kw) -> koma_config:
+    c = koma_config()
+    lib().koma_config_default(ctypes.byref(c))
+    c.precision = {"fp64": KOMA_FP64, "mixed": KOMA_MIXED}[precision] if isinstance(precision, str) else precision
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def make_scanner(scanner) -> koma_scanner:
+    return koma_scanner(float(scanner.b0), float(scanner.gamma))
+
+
+class _PhantomArgs:
+    """Holds the arrays (numpy host arrays or torch device tensors) alive."""
+
+    KEYS = ("x", "y", "z", "pd", "t1", "t2", "dw")
+
+    def __init__(self, phantom, device: bool):
+        self.keep = []
+        if device:
+            arrs = [phantom[k] if isinstance(phantom, dict) else getattr(phantom, k) for k in self.KEYS]
+            for a in arrs:
+                if not (hasattr(a, "is_cuda") and a.is_cuda and a.is_contiguous()
+                        and str(a.dtype) == "torch.float32"):
+                    raise TypeError("device phantom arrays must be contiguous float32 GPU tensors")
+            goff = phantom.get("group_off") if isinstance(phantom, dict) else phantom.group_off
+            n = int(arrs[0].numel())
+        else:
+            arrs = [np.ascontiguousarray(getattr(phantom, k), dtype=np.float32) for k in self.KEYS]
+            goff = phantom.group_off
+            n = int(arrs[0].shape[0])
+        self.keep += arrs
+        if goff is not None:
+            goff = np.ascontiguousarray(goff, dtype=np.int64)
+            self.keep.append(goff)
+        ng = 1 if goff is None else int(goff.shape[0] - 1)
+        self.n_groups = ng
+        self.n = n
+        self.c = koma_phantom(n, *[_ptr(a) for a in arrs], ng, _ptr(goff))
+
+
+class _SeqArgs:
+    def __init__(self, seq):
+        f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)  # noqa: E731
+        self.keep = [f64(seq.t), f64(seq.gx), f64(seq.gy), f64(seq.gz), f64(np.real(seq.b1)),
+                     f64(np.imag(seq.b1)), np.ascontiguousarray(seq.adc_idx, dtype=np.int64)]
+        k = self.keep
+        self.n_adc = int(k[6].shape[0])
+        self.c = koma_sequence(int(k[0].shape[0]), *[_ptr(a) for a in k[:6]], self.n_adc,
+                               _ptr(k[6]) if self.n_adc else None)
+
+
+# ---------------------------------------------------------------- 1:1 wrappers
+def koma_footprint(phantom, seq, cfg: koma_config) -> int:
+    p, s = _PhantomArgs(phantom, False), _SeqArgs(seq)
+    out = c_size_t(0)
+    _check(lib().koma_footprint(ctypes.byref(p.c), ctypes.byref(s.c), ctypes.byref(cfg), ctypes.byref(out)))
+    return out.value
+
+
+def koma_plan_info(scanner, phantom, seq, cfg: koma_config, device: bool = False) -> dict:
+    p, s = _PhantomArgs(phantom, device), _SeqArgs(seq)
+    info = koma_req_info()
+    sc = make_scanner(scanner)
+    _check(lib().koma_plan_info(ctypes.byref(sc), ctypes.byref(p.c), ctypes.byref(s.c), ctypes.byref(cfg),
+                                ctypes.byref(info)))
+    return info.as_dict()
+
+
+class Context:
+    """A koma_ctx on one HIP device."""
+
+    def __init__(self, device: int = 0, precision="mixed", **cfg):
+        self.cfg = make_config(precision, **cfg)
+        h = c_void_p()
+        st = lib().koma_ctx_create(int(device), ctypes.byref(self.cfg), ctypes.byref(h))
+        _check(st, None)
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().koma_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_config(self, precision=None, **kw):
+        c = koma_config.from_buffer_copy(self.cfg)
+        if precision is not None:
+            c.precision = {"fp64": KOMA_FP64, "mixed": KOMA_MIXED}[precision]
+        for k, v in kw.items():
+            setattr(c, k, v)
+        _check(lib().koma_ctx_set_config(self.h, ctypes.byref(c)), self.h)
+        self.cfg = c
+
+    def simulate(self, scanner, phantom, seq, where: str = "host", stream=None, sig=None,
+                 want_m: bool = False):
+        """koma_simulate. ``where='host'``: numpy phantom, returns complex128
+        ``[n_groups, n_adc]`` (and ``[n, 3]`` final M if ``want_m``).
+        ``where='device'``: torch GPU tensors (dict or object with x..dw,
+        group_off on the host); ``sig`` a float64 GPU tensor
+        ``[n_groups, n_adc, 2]`` that is written in place."""
+        dev = where == "device"
+        p, s = _PhantomArgs(phantom, dev), _SeqArgs(seq)
+        sc = make_scanner(scanner)
+        stream_h = None if stream is None else c_void_p(stream if isinstance(stream, int) else stream.cuda_stream)
+        if dev:
+            if sig is None:
+                raise ValueError("device simulate needs a preallocated sig tensor")
+            m = None
+            if want_m:
+                import torch
+                m = torch.empty((p.n, 3), dtype=torch.float64, device=sig.device)
+            _check(lib().koma_simulate(self.h, ctypes.byref(sc), ctypes.byref(p.c), ctypes.byref(s.c),
+                                       KOMA_DEVICE, stream_h, _ptr(sig), _ptr(m)), self.h)
+            return (sig, m) if want_m else sig
+        out = np.zeros((p.n_groups, s.n_adc, 2), dtype=np.float64)
+        m = np.zeros((p.n, 3), dtype=np.float64) if want_m else None
+        _check(lib().koma_simulate(self.h, ctypes.byref(sc), ctypes.byref(p.c), ctypes.byref(s.c),
+                                   KOMA_HOST, stream_h, _ptr(out), _ptr(m)), self.h)
+        z = out[..., 0] + 1j * out[..., 1]
+        return (z, m) if want_m else z
+
+    def open(self, scanner, phantom, seq, where: str = "host") -> "Request":
+        return Request(self, scanner, phantom, seq, where)
+
+    def profile(self, on: bool = True):
+        _check(lib().koma_ctx_profile(self.h, 1 if on else 0), self.h)
+
+    def kernel_stats(self, kind) -> dict:
+        k = KERNEL_KINDS[kind] if isinstance(kind, str) else int(kind)
+        ms, n, w = c_double(0), c_int64(0), c_int64(0)
+        _check(lib().koma_ctx_kernel_stats(self.h, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(w)), self.h)
+        return {"total_ms": ms.value, "launches": n.value, "work": w.value}
+
+
+class Request:
+    """A koma_req: phantom and spin state resident on the device."""
+
+    def __init__(self, ctx: Context, scanner, phantom, seq, where="host"):
+        self.ctx = ctx
+        p, s = _PhantomArgs(phantom, where == "device"), _SeqArgs(seq)
+        sc = make_scanner(scanner)
+        h = c_void_p()
+        _check(lib().koma_req_open(ctx.h, ctypes.byref(sc), ctypes.byref(p.c), ctypes.byref(s.c),
+                                   KOMA_DEVICE if where == "device" else KOMA_HOST, ctypes.byref(h)), ctx.h)
+        self.h = h
+        self.n_groups, self.n_adc = p.n_groups, s.n_adc
+
+    def advance(self, max_events: int = 0, stream=None):
+        sh = None if stream is None else c_void_p(stream if isinstance(stream, int) else stream.cuda_stream)
+        _check(lib().koma_req_advance(self.h, int(max_events), sh), self.ctx.h)
+
+    def done(self) -> bool:
+        d = c_int(0)
+        _check(lib().koma_req_done(self.h, ctypes.byref(d)), self.ctx.h)
+        return bool(d.value)
+
+    def result(self, stream=None) -> np.ndarray:
+        sh = None if stream is None else c_void_p(stream if isinstance(stream, int) else stream.cuda_stream)
+        out = np.zeros((self.n_groups, self.n_adc, 2), dtype=np.float64)
+        _check(lib().koma_req_result(self.h, _ptr(out), sh), self.ctx.h)
+        return out[..., 0] + 1j * out[..., 1]
+
+    def save(self) -> bytes:
+        n = c_size_t(0)
+        _check(lib().koma_req_save(self.h, None, ctypes.byref(n)), self.ctx.h)
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib().koma_req_save(self.h, buf, ctypes.byref(n)), self.ctx.h)
+        return buf.raw[:n.value]
+
+    def load(self, blob: bytes):
+        _check(lib().koma_req_load(self.h, blob, len(blob)), self.ctx.h)
+
+    def info(self) -> dict:
+        i = koma_req_info()
+        _check(lib().koma_req_info_get(self.h, ctypes.byref(i)), self.ctx.h)
+        return i.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().koma_req_close(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def device_phantom(phantom, device="cuda:0") -> dict:
+    """Copy a workloads.Phantom into float32 GPU tensors (group offsets stay on the host)."""
+    import torch
+    d = {k: torch.from_numpy(np.ascontiguousarray(getattr(phantom, k), dtype=np.float32)).to(device)
+         for k in _PhantomArgs.KEYS}
+    d["group_off"] = phantom.group_off
+    return d

@@ -1,0 +1,72 @@
+"""Helpers shared by the GPU tests (parity metrics, cached oracle runs)."""
+import functools
+import sys
+
+import numpy as np
+
+from paper_2301_02702_amd import workloads as W
+
+
+def nrmse(got, ref):
+    """sqrt(mean |got - ref|^2) / max |ref| (per row if 2-D)."""
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    if ref.ndim == 1:
+        return float(np.sqrt(np.mean(np.abs(got - ref) ** 2)) / max(np.max(np.abs(ref)), 1e-300))
+    return np.sqrt(np.mean(np.abs(got - ref) ** 2, axis=1)) / np.maximum(np.max(np.abs(ref), axis=1), 1e-300)
+
+
+def mae(got, ref):
+    return float(np.mean(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_cached(key):
+    """Oracle signal of a named case, computed once per test session."""
+    import oracle
+    sc, ph, seq = case(key)
+    return oracle.simulate(sc, ph, seq, mode=oracle.MODE_BLOCK)
+
+
+@functools.lru_cache(maxsize=None)
+def case(key):
+    sc = W.Scanner()
+    if key == "gre":
+        return (sc,) + W.config(1)[1:]
+    if key == "epi":
+        return (sc,) + W.config(2)[1:]
+    if key == "epi_small":  # ragged: 60 x 61 grid -> 3660 spins (57 tiles + 12 lanes)
+        ph = W.epi_phantom(n=61)
+        ph = ph.subset(np.arange(60 * 61))
+        return sc, ph, W.epi_sequence(n=64, ramp=8)
+    if key == "mrf40":  # 40 dictionary entries (T1/T2 spread over the grid)
+        full = W.mrf_phantom()
+        idx = np.linspace(0, 9999, 40).astype(int)
+        parts = [full.groups(int(e), int(e) + 1) for e in idx]
+        x = np.concatenate([p.x for p in parts])
+        off = np.arange(41) * W.MRF_ISO
+        ph = W.Phantom(x, np.concatenate([p.y for p in parts]), np.concatenate([p.z for p in parts]),
+                       np.concatenate([p.pd for p in parts]), np.concatenate([p.t1 for p in parts]),
+                       np.concatenate([p.t2 for p in parts]), np.concatenate([p.dw for p in parts]), off)
+        return sc, ph, W.mrf_sequence()
+    if key == "seepi_subset":  # 2000 seeded spins of the full 5e6 over all 20 planes, full sequence
+        ph = seepi_full()
+        rng = np.random.default_rng(4242)
+        idx = np.sort(rng.choice(ph.n, 2000, replace=False))
+        return sc, ph.subset(idx), seepi_seq()
+    raise KeyError(key)
+
+
+@functools.lru_cache(maxsize=None)
+def seepi_full():
+    return W.seepi_phantom()
+
+
+@functools.lru_cache(maxsize=None)
+def seepi_seq():
+    return W.seepi_sequence()

@@ -1,0 +1,125 @@
+"""C-ABI contract on the host: the library loads, exports every entry point
+the header declares, plans sequences on the host and rejects bad inputs with
+the documented status codes. No device work is done here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2301_02702_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_2301_02702_amd import build, komahip
+    if build.stale():
+        build.build()
+    komahip.lib()
+    return komahip
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "komahip.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(koma_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(K):
+    names = header_functions()
+    assert len(names) >= 18
+    L = ctypes.CDLL(K.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(names) == set(K.EXPORTS), set(names) ^ set(K.EXPORTS)
+
+
+def test_config_defaults(K):
+    c = K.make_config()
+    assert c.precision == K.KOMA_MIXED and c.wg_size == 256 and c.spins_per_lane == 0
+    assert c.defer_min_adc == 32 and c.stretch_max == 128 and c.partial_budget == 1 << 30
+
+
+@pytest.mark.parametrize("k,expect", [
+    (1, dict(n_rf=6400, n_runs=64, n_deferred_adc=4096, n_inline_adc=0, n_stretches=64, n_snapshots=64)),
+    (2, dict(n_rf=50, n_runs=1, n_deferred_adc=16384, n_inline_adc=0, n_stretches=128, n_snapshots=1)),
+    (4, dict(n_rf=10000, n_runs=1000, n_deferred_adc=0, n_inline_adc=1000, n_stretches=0, n_snapshots=0)),
+])
+def test_host_plans_of_the_workloads(K, k, expect):
+    sc, ph, seq = W.config(k)
+    info = K.koma_plan_info(sc, ph, seq, K.make_config())
+    for key, v in expect.items():
+        assert info[key] == v, (key, info[key], v)
+    assert info["n_tiles"] == sum(-(-int(b - a) // 64) for a, b in zip(
+        *(lambda o: (o[:-1], o[1:]))(ph.group_off if ph.group_off is not None else np.array([0, ph.n]))))
+    # one event per excitation interval, block end, snapshot and inline stretch
+    assert info["n_events"] >= expect["n_rf"] + expect["n_runs"] + expect["n_snapshots"]
+
+
+def test_stretches_split_at_the_length_cap(K):
+    sc, ph, seq = W.config(2)
+    for smax, want in ((128, 128), (100, 256), (1, 16384)):
+        info = K.koma_plan_info(sc, ph, seq, K.make_config(stretch_max=smax))
+        assert info["n_stretches"] == want
+
+
+def test_defer_threshold_moves_samples_inline(K):
+    sc, ph, seq = W.config(1)
+    info = K.koma_plan_info(sc, ph, seq, K.make_config(defer_min_adc=-1))
+    assert info["n_deferred_adc"] == 0 and info["n_inline_adc"] == 4096 and info["n_snapshots"] == 0
+    info = K.koma_plan_info(sc, ph, seq, K.make_config(defer_min_adc=65))
+    assert info["n_deferred_adc"] == 0
+
+
+def _seq(**kw):
+    t = np.array([0.0, 1e-3, 2e-3, 3e-3])
+    d = dict(t=t, g=np.zeros((4, 3)), b1=np.array([1e-6, 0, 0], dtype=complex), adc=[1, 3])
+    d.update(kw)
+    return W.make_sequence(d["t"], d["g"], d["b1"], d["adc"])
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(t=np.array([0.0, 1e-3, 1e-3, 3e-3])), -3),        # not strictly increasing
+    (dict(t=np.array([0.0, np.nan, 2e-3, 3e-3])), -3),      # NaN time
+    (dict(adc=[3, 1]), -3),                                 # ADC not increasing
+    (dict(adc=[0, 4]), -3),                                 # ADC out of range
+    (dict(b1=np.array([np.inf, 0, 0], dtype=complex)), -3),  # non-finite B1
+])
+def test_sequence_validation(K, bad, code):
+    seq = _seq(**bad)
+    with pytest.raises(K.KomaError) as e:
+        K.koma_plan_info(W.Scanner(), W.single_spin(), seq, K.make_config())
+    assert e.value.status == code
+
+
+def test_phantom_and_config_validation(K):
+    seq = _seq()
+    ph = W.random_spins(np.random.default_rng(0), 10)
+    ph.group_off = np.array([0, 5, 4, 10])
+    with pytest.raises(K.KomaError) as e:
+        K.koma_plan_info(W.Scanner(), ph, seq, K.make_config())
+    assert e.value.status == -2
+    ph.group_off = np.array([0, 5, 9])  # does not end at n
+    with pytest.raises(K.KomaError) as e:
+        K.koma_plan_info(W.Scanner(), ph, seq, K.make_config())
+    assert e.value.status == -2
+    ph.group_off = None
+    for bad in (dict(spins_per_lane=3), dict(wg_size=128), dict(stretch_max=0), dict(stretch_max=129),
+                dict(chunk_events=0), dict(partial_budget=1000)):
+        with pytest.raises(K.KomaError) as e:
+            K.koma_plan_info(W.Scanner(), ph, seq, K.make_config(**bad))
+        assert e.value.status == -1, bad
+    with pytest.raises(K.KomaError) as e:
+        K.koma_plan_info(W.Scanner(gamma=-1.0), ph, seq, K.make_config())
+    assert e.value.status == -1
+
+
+def test_footprint_counts_snapshots_and_partials(K):
+    sc, ph, seq = W.config(2)
+    f_mixed = K.koma_footprint(ph, seq, K.make_config("mixed"))
+    f_fp64 = K.koma_footprint(ph, seq, K.make_config("fp64"))
+    n_pad = 1024 * 64
+    assert f_fp64 > f_mixed > n_pad * (8 + 12)  # snapshot + state at least
