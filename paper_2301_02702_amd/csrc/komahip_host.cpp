@@ -92,6 +92,13 @@ struct koma_ctx {
     double tot_ms[K_KINDS] = {0, 0, 0, 0};
     int64_t n_launch[K_KINDS] = {0, 0, 0, 0};
     int64_t work[K_KINDS] = {0, 0, 0, 0};
+    Plan plan;  // reused by koma_simulate (capacity kept across calls)
+    // pinned host staging for the packed tables (one upload per call) and the
+    // validation flag read-back
+    void *h_stage = nullptr;
+    size_t h_stage_cap = 0;
+    int32_t *h_flag = nullptr;
+    DevMem s_tables;
     // device blocks released by closed requests, reused by later ones (by size)
     std::multimap<size_t, void *> pool;
     size_t pool_bytes = 0;
@@ -250,6 +257,7 @@ static koma_status check_scanner(koma_ctx *ctx, const koma_scanner *sc) {
     return KOMA_OK;
 }
 
+// Structure of the sequence: sizes, pointers, ADC indices.
 static koma_status check_sequence(koma_ctx *ctx, const koma_sequence *q) {
     if (!q) return fail(ctx, KOMA_E_ARG, "sequence is NULL");
     if (q->n_t < 2) return fail(ctx, KOMA_E_SEQUENCE, "n_t must be >= 2 (got %lld)", (long long)q->n_t);
@@ -258,6 +266,20 @@ static koma_status check_sequence(koma_ctx *ctx, const koma_sequence *q) {
         return fail(ctx, KOMA_E_ARG, "sequence array is NULL");
     if (q->n_adc < 0) return fail(ctx, KOMA_E_SEQUENCE, "n_adc must be >= 0");
     if (q->n_adc > 0 && !q->adc_idx) return fail(ctx, KOMA_E_ARG, "adc_idx is NULL");
+    for (int64_t k = 0; k < q->n_adc; ++k) {
+        if (q->adc_idx[k] < 0 || q->adc_idx[k] >= q->n_t)
+            return fail(ctx, KOMA_E_SEQUENCE, "adc_idx[%lld] = %lld out of [0, n_t)", (long long)k,
+                        (long long)q->adc_idx[k]);
+        if (k > 0 && q->adc_idx[k] <= q->adc_idx[k - 1])
+            return fail(ctx, KOMA_E_SEQUENCE, "adc_idx not strictly increasing at %lld", (long long)k);
+    }
+    return KOMA_OK;
+}
+
+// Values of the sequence: finite, t strictly increasing. The packer tests the
+// same conditions branch-free while it reads the arrays (one pass over them)
+// and calls this only to name the offending index.
+static koma_status check_sequence_values(koma_ctx *ctx, const koma_sequence *q) {
     for (int64_t i = 0; i < q->n_t; ++i) {
         if (!finite_d(q->t[i]) || !finite_d(q->gx[i]) || !finite_d(q->gy[i]) || !finite_d(q->gz[i]))
             return fail(ctx, KOMA_E_SEQUENCE, "non-finite time or gradient at point %lld", (long long)i);
@@ -267,14 +289,14 @@ static koma_status check_sequence(koma_ctx *ctx, const koma_sequence *q) {
     for (int64_t i = 0; i + 1 < q->n_t; ++i)
         if (!finite_d(q->b1_re[i]) || !finite_d(q->b1_im[i]))
             return fail(ctx, KOMA_E_SEQUENCE, "non-finite B1 on interval %lld", (long long)i);
-    for (int64_t k = 0; k < q->n_adc; ++k) {
-        if (q->adc_idx[k] < 0 || q->adc_idx[k] >= q->n_t)
-            return fail(ctx, KOMA_E_SEQUENCE, "adc_idx[%lld] = %lld out of [0, n_t)", (long long)k,
-                        (long long)q->adc_idx[k]);
-        if (k > 0 && q->adc_idx[k] <= q->adc_idx[k - 1])
-            return fail(ctx, KOMA_E_SEQUENCE, "adc_idx not strictly increasing at %lld", (long long)k);
-    }
-    return KOMA_OK;
+    return fail(ctx, KOMA_E_SEQUENCE, "invalid sequence value");
+}
+
+// Bit 63 of the result is set iff x is infinite or NaN (exponent all ones).
+static inline uint64_t nonfinite_bit(double x) {
+    uint64_t u;
+    memcpy(&u, &x, sizeof u);
+    return (u & 0x7ff0000000000000ull) + (1ull << 52);
 }
 
 static koma_status check_phantom_shape(koma_ctx *ctx, const koma_phantom *p) {
@@ -311,48 +333,63 @@ static koma_status check_phantom_values_host(koma_ctx *ctx, const koma_phantom *
 
 namespace {
 
-struct Sample {
-    int32_t k;
-    double v[4];  // kx, ky, kz, tau
+// ADC samples of one precession block (structure of arrays): ADC index,
+// moments kx, ky, kz (cycles/m) and elapsed time tau (s) from the block start.
+struct Samples {
+    const int32_t *k;
+    const double *v[4];
+    size_t n;
+    size_t size() const { return n; }
 };
 
-// Split the samples of one block into evenly spaced stretches.
+// True when samples i..i+len-1 all lie within the tolerances of the straight
+// line through the first and the last of them; the line's increments go to
+// inc. Branch-free compare-and-or loops, so the compiler vectorises them.
+inline bool on_line(const Samples &s, size_t i, size_t len, double *inc) {
+    for (int c = 0; c < 4; ++c) {
+        const double *__restrict v = s.v[c] + i;
+        const double v0 = v[0];
+        const double d = (v[len - 1] - v0) / (double)(len - 1);
+        const double tol = c < 3 ? kStretchTolK : kStretchTolT;
+        int bad = 0;
+        const int n = (int)len - 1;  // the last sample lies on the line by construction
+        for (int q = 1; q < n; ++q) bad |= std::fabs(v[q] - (v0 + (double)q * d)) > tol;
+        if (bad) return false;
+        inc[c] = d;
+    }
+    return true;
+}
+
+// Split the samples of one block into evenly spaced stretches of at most
+// max_len samples: every sample of a stretch lies within the tolerances of
+// the straight line through its first and last sample.
 template <class Emit>
-void make_stretches(const std::vector<Sample> &s, int max_len, Emit emit) {
+void make_stretches(const Samples &s, int max_len, Emit emit) {
     const size_t m = s.size();
     size_t i = 0;
     while (i < m) {
-        size_t len = 1;
         double inc[4] = {0, 0, 0, 0};
-        if (i + 1 < m && max_len > 1) {
-            // greedy: extend while the next sample stays on the line of the first step
+        size_t len = std::min<size_t>((size_t)max_len, m - i);
+        if (len > 1 && !on_line(s, i, len, inc)) {
+            // greedy: extend while the next sample stays near the line of the first step
             size_t j = i + 1;
-            double d0[4];
-            for (int c = 0; c < 4; ++c) d0[c] = s[i + 1].v[c] - s[i].v[c];
             while (j < m && (j - i + 1) <= (size_t)max_len) {
                 bool ok = true;
                 const double n = (double)(j - i);
                 for (int c = 0; c < 4 && ok; ++c) {
+                    const double d0 = s.v[c][i + 1] - s.v[c][i];
                     const double tol = (c < 3 ? kStretchTolK : kStretchTolT) * (1.0 + n);
-                    ok = std::fabs(s[j].v[c] - (s[i].v[c] + n * d0[c])) <= tol;
+                    ok = std::fabs(s.v[c][j] - (s.v[c][i] + n * d0)) <= tol;
                 }
                 if (!ok) break;
                 ++j;
             }
             len = j - i;
-            // verify against the line through the first and last sample; shrink if needed
-            while (len > 1) {
-                for (int c = 0; c < 4; ++c) inc[c] = (s[i + len - 1].v[c] - s[i].v[c]) / (double)(len - 1);
-                bool ok = true;
-                for (size_t q = 1; q < len && ok; ++q)
-                    for (int c = 0; c < 4 && ok; ++c) {
-                        const double tol = c < 3 ? kStretchTolK : kStretchTolT;
-                        ok = std::fabs(s[i + q].v[c] - (s[i].v[c] + (double)q * inc[c])) <= tol;
-                    }
-                if (ok) break;
-                len = len / 2;
-            }
-            if (len == 1) inc[0] = inc[1] = inc[2] = inc[3] = 0;
+            while (len > 1 && !on_line(s, i, len, inc)) len /= 2;
+        }
+        if (len <= 1) {
+            len = 1;
+            inc[0] = inc[1] = inc[2] = inc[3] = 0;
         }
         emit(i, len, inc);
         i += len;
@@ -363,7 +400,21 @@ void make_stretches(const std::vector<Sample> &s, int max_len, Emit emit) {
 
 static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamma, const koma_phantom *ph,
                               const koma_sequence *q, Plan &P) {
-    P = Plan();
+    // reset, keeping the vectors' capacity (plans are rebuilt every call)
+    P.ev.clear();
+    P.st.clear();
+    P.inl_k.clear();
+    P.def_k.clear();
+    P.snap_event.clear();
+    P.tiles.clear();
+    P.tile_off.clear();
+    P.blocks.clear();
+    P.blk_off.clear();
+    P.chunks.clear();
+    P.n_slots = P.n_rf = P.n_runs = 0;
+    P.spl = 1;
+    P.per_wg = 1;
+    P.max_cols = 0;
     P.gamma = gamma;
     P.n_spins = ph->n;
     P.n_groups = ph->n_groups;
@@ -373,6 +424,7 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
 
     // ---- spin tiles: 64-spin slots that never straddle a signal group
     P.tile_off.assign(P.n_groups + 1, 0);
+    P.tiles.reserve((size_t)(ph->n / kWave + P.n_groups + 1));
     for (int64_t g = 0; g < P.n_groups; ++g) {
         const int64_t a = ph->group_off ? ph->group_off[g] : 0;
         const int64_t b = ph->group_off ? ph->group_off[g + 1] : ph->n;
@@ -390,40 +442,61 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     P.n_tiles = (int64_t)P.tiles.size();
 
     // ---- event program
-    std::vector<uint8_t> is_adc(n_t, 0);
-    for (int64_t k = 0; k < q->n_adc; ++k) is_adc[q->adc_idx[k]] = 1;
-    std::vector<int32_t> adc_pos(n_t, -1);
+    // planner scratch lives per thread and only grows: large per-call
+    // allocations would be fresh pages (page faults) on every call
+    thread_local std::vector<int32_t> adc_pos, smp_k;
+    thread_local std::vector<double> smp_v[4];
+    if (adc_pos.size() < (size_t)n_t) adc_pos.resize((size_t)n_t);
+    std::fill(adc_pos.begin(), adc_pos.begin() + n_t, -1);
     for (int64_t k = 0; k < q->n_adc; ++k) adc_pos[q->adc_idx[k]] = (int32_t)k;
-    auto is_rf = [&](int64_t n) { return q->b1_re[n] != 0.0 || q->b1_im[n] != 0.0; };
+    if (smp_k.size() < (size_t)q->n_adc + 1) {
+        smp_k.resize((size_t)q->n_adc + 1);
+        for (auto &v : smp_v) v.resize((size_t)q->n_adc + 1);
+    }
+    uint64_t nonfinite = 0;  // bit 63: some value is infinite or NaN
+    int disorder = 0;        // some interval has t[n+1] <= t[n]
+    auto is_rf = [&](int64_t n) {
+        const double r = q->b1_re[n], i = q->b1_im[n];
+        nonfinite |= nonfinite_bit(r) | nonfinite_bit(i);
+        return r != 0.0 || i != 0.0;
+    };
     const int defer_min = cfg.defer_min_adc;
 
+    P.def_k.reserve((size_t)q->n_adc);
+    const double *__restrict T = q->t;
+    const double *__restrict GX = q->gx;
+    const double *__restrict GY = q->gy;
+    const double *__restrict GZ = q->gz;
     int64_t a = 0;
-    std::vector<Sample> samples;
+    Samples samples{smp_k.data(), {smp_v[0].data(), smp_v[1].data(), smp_v[2].data(), smp_v[3].data()}, 0};
     for (;;) {
         // precession block [a, b]
         int64_t b = a;
         while (b < n_int && !is_rf(b)) ++b;
-        samples.clear();
+        size_t ns = 0;
         double K[3] = {0, 0, 0};
+        const double ta = T[a];
         for (int64_t p = a; p <= b; ++p) {
-            if (is_adc[p]) {
-                Sample s;
-                s.k = adc_pos[p];
-                s.v[0] = K[0];
-                s.v[1] = K[1];
-                s.v[2] = K[2];
-                s.v[3] = q->t[p] - q->t[a];
-                samples.push_back(s);
+            nonfinite |= nonfinite_bit(T[p]) | nonfinite_bit(GX[p]) | nonfinite_bit(GY[p]) | nonfinite_bit(GZ[p]);
+            if (adc_pos[p] >= 0) {
+                smp_k[ns] = adc_pos[p];
+                smp_v[0][ns] = K[0];
+                smp_v[1][ns] = K[1];
+                smp_v[2][ns] = K[2];
+                smp_v[3][ns] = T[p] - ta;
+                ++ns;
             }
             if (p < b) {
-                const double dt = q->t[p + 1] - q->t[p];
-                K[0] += gbar * 0.5 * (q->gx[p] + q->gx[p + 1]) * dt;
-                K[1] += gbar * 0.5 * (q->gy[p] + q->gy[p + 1]) * dt;
-                K[2] += gbar * 0.5 * (q->gz[p] + q->gz[p + 1]) * dt;
+                disorder |= !(T[p + 1] > T[p]);
+                const double hdt = 0.5 * gbar * (T[p + 1] - T[p]);
+                K[0] += (GX[p] + GX[p + 1]) * hdt;
+                K[1] += (GY[p] + GY[p + 1]) * hdt;
+                K[2] += (GZ[p] + GZ[p + 1]) * hdt;
             }
         }
+        samples.n = ns;
         const bool defer = defer_min >= 0 && b > a && (int64_t)samples.size() >= std::max(1, defer_min);
-        if (!samples.empty()) {
+        if (samples.size() > 0) {
             if (defer) {
                 const int32_t slot = (int32_t)P.n_slots++;
                 Event e{};
@@ -437,10 +510,10 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
                     s.d0 = (int32_t)P.def_k.size();
                     s.count = (int32_t)len;
                     for (int c = 0; c < 4; ++c) {
-                        s.k0[c] = samples[i].v[c];
+                        s.k0[c] = samples.v[c][i];
                         s.dk[c] = inc[c];
                     }
-                    for (size_t j = 0; j < len; ++j) P.def_k.push_back(samples[i + j].k);
+                    P.def_k.insert(P.def_k.end(), samples.k + i, samples.k + i + len);
                     P.st.push_back(s);
                 });
             } else {
@@ -450,10 +523,10 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
                     e.a0 = (int32_t)P.inl_k.size();
                     e.count = (int32_t)len;
                     for (int c = 0; c < 4; ++c) {
-                        e.d[c] = samples[i].v[c];
+                        e.d[c] = samples.v[c][i];
                         e.d[4 + c] = inc[c];
                     }
-                    for (size_t j = 0; j < len; ++j) P.inl_k.push_back(samples[i + j].k);
+                    P.inl_k.insert(P.inl_k.end(), samples.k + i, samples.k + i + len);
                     P.ev.push_back(e);
                 });
             }
@@ -472,6 +545,7 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
         // excitation interval b
         {
             const double dt = q->t[b + 1] - q->t[b];
+            disorder |= !(dt > 0.0);
             const double v[8] = {0.5 * (q->gx[b] + q->gx[b + 1]),
                                  0.5 * (q->gy[b] + q->gy[b + 1]),
                                  0.5 * (q->gz[b] + q->gz[b + 1]),
@@ -492,6 +566,7 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
         a = b + 1;
         if ((int64_t)P.ev.size() >= ((int64_t)1 << 31) - 4) return fail(ctx, KOMA_E_SEQUENCE, "sequence too long");
     }
+    if ((nonfinite >> 63) || disorder) return check_sequence_values(ctx, q);
     if ((int64_t)P.inl_k.size() + (int64_t)P.def_k.size() != q->n_adc)
         return fail(ctx, KOMA_E_SEQUENCE, "internal: ADC samples lost in packing");
 
@@ -500,7 +575,7 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     int spl = cfg.spins_per_lane;
     if (spl == 0) {
         spl = 1;
-        for (int cand : {4, 2}) {  // largest S that still gives >= 8 workgroups per CU
+        for (int cand : {8, 4, 2}) {  // largest S that still gives >= 8 workgroups per CU
             int64_t nb = 0;
             for (int64_t g = 0; g < P.n_groups; ++g) {
                 const int64_t nt = P.tile_off[g + 1] - P.tile_off[g];
@@ -774,6 +849,9 @@ void koma_ctx_destroy(koma_ctx *ctx) {
                      &ctx->s_mxy, &ctx->s_mz, &ctx->s_flags, &ctx->s_mf};
     for (DevMem *m : all) dev_free(*m);
     for (DevMem &m : ctx->s_ph) dev_free(m);
+    dev_free(ctx->s_tables);
+    if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+    if (ctx->h_flag) (void)hipHostFree(ctx->h_flag);
     pool_trim(ctx);
     for (auto &r : ctx->recs) {
         (void)hipEventDestroy(r.a);
@@ -869,7 +947,7 @@ koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
     const bool fp64 = ctx->cfg.precision == KOMA_FP64;
     const size_t r = fp64 ? 8 : 4;
 
-    Plan P;
+    Plan &P = ctx->plan;
     if ((st = build_plan(ctx, ctx->cfg, sc->gamma, ph, seq, P)) != KOMA_OK) return st;
     if (ctx->cfg.hbm_budget && plan_footprint(P, fp64, m_final != nullptr, where == KOMA_HOST) > ctx->cfg.hbm_budget)
         return fail(ctx, KOMA_E_BUDGET, "footprint exceeds hbm_budget");
@@ -888,17 +966,60 @@ koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
         for (int i = 0; i < 7; ++i) dptr[i] = src[i];
     }
     B.ph = PhantomDev{dptr[0], dptr[1], dptr[2], dptr[3], dptr[4], dptr[5], dptr[6]};
-    if (where == KOMA_DEVICE && (st = validate_device_phantom(ctx, B.ph, ph->n, ctx->s_flags, s)) != KOMA_OK)
-        return st;
 
-    if ((st = upload(ctx, ctx->s_ev, P.ev, s)) != KOMA_OK) return st;
-    if ((st = upload(ctx, ctx->s_st, P.st, s)) != KOMA_OK) return st;
-    if ((st = upload(ctx, ctx->s_tiles, P.tiles, s)) != KOMA_OK) return st;
-    if ((st = upload(ctx, ctx->s_blocks, P.blocks, s)) != KOMA_OK) return st;
-    if ((st = upload(ctx, ctx->s_toff, P.tile_off, s)) != KOMA_OK) return st;
-    if ((st = upload(ctx, ctx->s_boff, P.blk_off, s)) != KOMA_OK) return st;
-    if ((st = upload(ctx, ctx->s_inl, P.inl_k, s)) != KOMA_OK) return st;
-    if ((st = upload(ctx, ctx->s_def, P.def_k, s)) != KOMA_OK) return st;
+    // packed tables: one pinned staging buffer, one upload
+    struct Part {
+        const void *src;
+        size_t bytes, off;
+    } parts[8] = {{P.ev.data(), P.ev.size() * sizeof(Event), 0},
+                  {P.st.data(), P.st.size() * sizeof(Stretch), 0},
+                  {P.tiles.data(), P.tiles.size() * sizeof(Tile), 0},
+                  {P.blocks.data(), P.blocks.size() * sizeof(Block), 0},
+                  {P.tile_off.data(), P.tile_off.size() * 4, 0},
+                  {P.blk_off.data(), P.blk_off.size() * 4, 0},
+                  {P.inl_k.data(), P.inl_k.size() * 4, 0},
+                  {P.def_k.data(), P.def_k.size() * 4, 0}};
+    size_t total = 0;
+    for (auto &pt : parts) {
+        pt.off = total;
+        total += (pt.bytes + 255) & ~(size_t)255;
+    }
+    if (ctx->h_stage_cap < total) {
+        if (ctx->h_stage) HIPCHK(ctx, hipHostFree(ctx->h_stage));
+        ctx->h_stage = nullptr;
+        ctx->h_stage_cap = 0;
+        HIPCHK(ctx, hipHostMalloc(&ctx->h_stage, total, hipHostMallocDefault));
+        ctx->h_stage_cap = total;
+    }
+    if (!ctx->h_flag) HIPCHK(ctx, hipHostMalloc((void **)&ctx->h_flag, 64, hipHostMallocDefault));
+    for (auto &pt : parts)
+        if (pt.bytes) memcpy((char *)ctx->h_stage + pt.off, pt.src, pt.bytes);
+    if ((st = dev_reserve(ctx, ctx->s_tables, total)) != KOMA_OK) return st;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->s_tables.p, ctx->h_stage, total, hipMemcpyHostToDevice, s));
+    char *tb = (char *)ctx->s_tables.p;
+    B.ev = (const Event *)(tb + parts[0].off);
+    B.st = (const Stretch *)(tb + parts[1].off);
+    B.tiles = (const Tile *)(tb + parts[2].off);
+    B.blocks = (const Block *)(tb + parts[3].off);
+    B.toff = (const int32_t *)(tb + parts[4].off);
+    B.boff = (const int32_t *)(tb + parts[5].off);
+    B.inl = (const int32_t *)(tb + parts[6].off);
+    B.def = (const int32_t *)(tb + parts[7].off);
+
+    // device-resident phantom: validation flags reduced on the device; the
+    // results are committed to the caller's buffers only if they are clean,
+    // and the host reads the flag after the one synchronisation at the end
+    const bool dev_check = where == KOMA_DEVICE;
+    int32_t *flag_total = nullptr;
+    if (dev_check) {
+        const int64_t nwg = (ph->n + kWG - 1) / kWG;
+        if ((st = dev_reserve(ctx, ctx->s_flags, (size_t)(nwg + 1) * 4)) != KOMA_OK) return st;
+        int32_t *flags = (int32_t *)ctx->s_flags.p;
+        flag_total = flags + nwg;
+        LAUNCH(ctx, K_AUX, ph->n, s, launch_validate(B.ph, ph->n, flags, s));
+        LAUNCH(ctx, K_AUX, nwg, s, launch_flags_or(flags, nwg, flag_total, s));
+    }
+
     const size_t n_pad = (size_t)P.n_tiles * kWave;
     if ((st = dev_reserve(ctx, ctx->s_snap, (size_t)P.n_slots * n_pad * 2 * r)) != KOMA_OK) return st;
     if ((st = dev_reserve(ctx, ctx->s_pa, (size_t)P.n_tiles * P.inl_k.size() * 2 * r)) != KOMA_OK) return st;
@@ -907,24 +1028,14 @@ koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
     if (store) {
         if ((st = dev_reserve(ctx, ctx->s_mxy, n_pad * 2 * r)) != KOMA_OK) return st;
         if ((st = dev_reserve(ctx, ctx->s_mz, n_pad * r)) != KOMA_OK) return st;
+        if ((st = dev_reserve(ctx, ctx->s_mf, (size_t)ph->n * 24)) != KOMA_OK) return st;
     }
-    double *sig_dev = sig;
-    if (where == KOMA_HOST && P.n_adc > 0) {
-        if ((st = dev_reserve(ctx, ctx->s_sig, (size_t)P.n_groups * P.n_adc * 16)) != KOMA_OK) return st;
-        sig_dev = (double *)ctx->s_sig.p;
-    }
-    B.ev = (const Event *)ctx->s_ev.p;
-    B.st = (const Stretch *)ctx->s_st.p;
-    B.tiles = (const Tile *)ctx->s_tiles.p;
-    B.blocks = (const Block *)ctx->s_blocks.p;
-    B.toff = (const int32_t *)ctx->s_toff.p;
-    B.boff = (const int32_t *)ctx->s_boff.p;
-    B.inl = (const int32_t *)ctx->s_inl.p;
-    B.def = (const int32_t *)ctx->s_def.p;
+    const size_t sig_n = (size_t)P.n_groups * P.n_adc * 2;  // doubles
+    if ((st = dev_reserve(ctx, ctx->s_sig, sig_n * 8)) != KOMA_OK) return st;
     B.snap = ctx->s_snap.p;
     B.pa = ctx->s_pa.p;
     B.pb = (double *)ctx->s_pb.p;
-    B.sig = sig_dev;
+    B.sig = (double *)ctx->s_sig.p;
     B.mxy = ctx->s_mxy.p;
     B.mz = ctx->s_mz.p;
 
@@ -934,19 +1045,23 @@ koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
             if ((st = run_chunk(ctx, P, fp64, B, c, s)) != KOMA_OK) return st;
         if ((st = run_inline_reduce(ctx, P, fp64, B, s)) != KOMA_OK) return st;
     }
-    if (store) {
-        double *mf = m_final;
-        if (where == KOMA_HOST) {
-            if ((st = dev_reserve(ctx, ctx->s_mf, (size_t)ph->n * 24)) != KOMA_OK) return st;
-            mf = (double *)ctx->s_mf.p;
-        }
-        LAUNCH(ctx, K_AUX, (int64_t)n_pad, s, launch_export(fp64, B.tiles, P.n_tiles, B.mxy, B.mz, mf, s));
-        if (where == KOMA_HOST)
-            HIPCHK(ctx, hipMemcpyAsync(m_final, mf, (size_t)ph->n * 24, hipMemcpyDeviceToHost, s));
+    double *mf = store ? (double *)ctx->s_mf.p : nullptr;
+    if (store) LAUNCH(ctx, K_AUX, (int64_t)n_pad, s, launch_export(fp64, B.tiles, P.n_tiles, B.mxy, B.mz, mf, s));
+    if (dev_check) {
+        if (sig_n) LAUNCH(ctx, K_AUX, (int64_t)sig_n, s, launch_commit(flag_total, B.sig, sig, (int64_t)sig_n, s));
+        if (store) LAUNCH(ctx, K_AUX, ph->n * 3, s, launch_commit(flag_total, mf, m_final, ph->n * 3, s));
+        HIPCHK(ctx, hipMemcpyAsync(ctx->h_flag, flag_total, 4, hipMemcpyDeviceToHost, s));
+    } else {
+        if (sig_n) HIPCHK(ctx, hipMemcpyAsync(sig, B.sig, sig_n * 8, hipMemcpyDeviceToHost, s));
+        if (store) HIPCHK(ctx, hipMemcpyAsync(m_final, mf, (size_t)ph->n * 24, hipMemcpyDeviceToHost, s));
     }
-    if (where == KOMA_HOST && P.n_adc > 0)
-        HIPCHK(ctx, hipMemcpyAsync(sig, sig_dev, (size_t)P.n_groups * P.n_adc * 16, hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
+    if (dev_check && *ctx->h_flag) {
+        const int32_t bad = *ctx->h_flag;
+        if (bad & 1) return fail(ctx, KOMA_E_PHANTOM, "non-finite position, dw or PD in the phantom");
+        if (bad & 2) return fail(ctx, KOMA_E_PHANTOM, "PD < 0 in the phantom");
+        return fail(ctx, KOMA_E_PHANTOM, "T1/T2 must be > 0 (or +inf)");
+    }
     return KOMA_OK;
 }
 

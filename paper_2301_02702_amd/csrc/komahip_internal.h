@@ -126,6 +126,8 @@ int launch_seq(bool fp64, const SeqArgs &a, void *stream);
 int launch_par(bool fp64, int spins_per_lane, const ParArgs &a, void *stream);
 int launch_reduce(bool part_fp64, const ReduceArgs &a, void *stream);
 int launch_validate(const PhantomDev &ph, int64_t n, int32_t *flags, void *stream);
+int launch_flags_or(const int32_t *flags, int64_t n, int32_t *out, void *stream);
+int launch_commit(const int32_t *flag, const double *src, double *dst, int64_t n, void *stream);
 int launch_export(bool fp64, const Tile *tiles, int64_t n_tiles, const void *mxy, const void *mz,
                   double *m_final, void *stream);
 }  // namespace koma

@@ -311,6 +311,17 @@ __device__ __forceinline__ void excite_relax(const SpinP<typename P::R> &s, cons
 
 // ---------------------------------------------------------------- k_seq
 
+// The event program and stretch tables are read-only for a whole launch and
+// read at the same address by every lane: reading them through the constant
+// address space lets the compiler use scalar loads (scalar cache, SGPRs)
+// instead of one vector load per lane.
+template <class T>
+using ConstPtr = const __attribute__((address_space(4))) T *;
+template <class T>
+__device__ __forceinline__ ConstPtr<T> as_const(const T *p) {
+    return (ConstPtr<T>)p;
+}
+
 template <class P>
 __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
     using R = typename P::R;
@@ -338,8 +349,9 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
     R eps1 = R(0), eps2 = R(0);
     double dt_cached = -1.0;  // uniform
 
+    const ConstPtr<Event> evs = as_const(a.ev);
     for (int64_t e = a.e0; e < a.e1; ++e) {
-        const Event &ev = a.ev[e];
+        const auto &ev = evs[e];
         const int kind = ev.kind;
         if (kind == EV_RF) {
             R q[7];
@@ -358,18 +370,21 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
             }
             excite_relax<P>(s, q, eps1, eps2, mr, mi, mz);
         } else if (kind == EV_END) {
-            const double theta = block_phase(s, ev.d);
-            const double tau = ev.d[3];
+            const double k[4] = {ev.d[0], ev.d[1], ev.d[2], ev.d[3]};
+            const double theta = block_phase(s, k);
+            const double tau = k[3];
             C2<R> f = block_factor<P>(s, theta, tau);
             C2<R> m = cmul(C2<R>{mr, mi}, f);
             mr = m.re;
             mi = m.im;
             mz = s.pd + (mz - s.pd) * P::exp_neg(R(tau) * s.r1);
         } else if (kind == EV_ADC) {
-            C2<R> c = cmul(C2<R>{mr, mi}, block_factor<P>(s, block_phase(s, ev.d), ev.d[3]));
+            const double k0[4] = {ev.d[0], ev.d[1], ev.d[2], ev.d[3]};
+            const double dk[4] = {ev.d[4], ev.d[5], ev.d[6], ev.d[7]};
+            C2<R> c = cmul(C2<R>{mr, mi}, block_factor<P>(s, block_phase(s, k0), k0[3]));
             const int cnt = ev.count;
             C2<R> w{R(1), R(0)};
-            if (cnt > 1) w = block_factor<P>(s, block_phase(s, ev.d + 4), ev.d[7]);
+            if (cnt > 1) w = block_factor<P>(s, block_phase(s, dk), dk[3]);
             R2 *pa = reinterpret_cast<R2 *>(a.pa) + tile * a.n_inline + ev.a0;
             for (int i = 0; i < cnt; ++i) {
                 const R sr = wave_allsum(c.re);
@@ -389,6 +404,27 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
 
 // ---------------------------------------------------------------- k_par
 
+// Spin parameters the sample-parallel kernel needs, kept in FP32 registers
+// (the inputs are FP32); the FP64 block phase is formed at each anchor.
+struct ParSpin {
+    float x, y, z, dw, t2;  // t2 = +inf: no decay (also for empty lanes)
+};
+
+template <class R>
+__device__ __forceinline__ double par_phase(const ParSpin &s, const double *k) {
+    return -fma((double)s.x, k[0], fma((double)s.y, k[1], fma((double)s.z, k[2], (double)s.dw * kInv2Pi * k[3])));
+}
+
+template <class P>
+__device__ __forceinline__ C2<typename P::R> par_factor(const ParSpin &s, const double *k) {
+    using R = typename P::R;
+    R sn, cs;
+    P::sincos_turns(par_phase<R>(s, k), sn, cs);
+    renorm(cs, sn);
+    const R e2 = P::exp_neg(R(k[3]) / R(s.t2));
+    return {cs * e2, sn * e2};
+}
+
 template <class P, int S>
 __global__ __launch_bounds__(kWG) void k_par(ParArgs a) {
     using R = typename P::R;
@@ -399,38 +435,37 @@ __global__ __launch_bounds__(kWG) void k_par(ParArgs a) {
     const Block B = a.blocks[blockIdx.x];
     const int64_t n_pad = a.n_tiles * kWave;
 
-    SpinP<R> sp[S];
-    int64_t pidx[S];
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-        const int tl = wave + kWavesPerWG * j;
-        Tile T;
-        if (tl < B.ntiles) {
-            T = a.tiles[B.tile0 + tl];
-        } else {  // no spin: zero contribution
-            T.spin0 = 0;
-            T.count = 0;
-            T.group = 0;
-        }
-        sp[j] = load_spin<R>(a.ph, T, lane, 0.0);
-        pidx[j] = (tl < B.ntiles) ? (int64_t)(B.tile0 + tl) * kWave + lane : -1;
-    }
-
     const int64_t st0 = a.s0 + (int64_t)blockIdx.y * a.per_wg;
     const int64_t st1 = min(st0 + a.per_wg, a.s1);
     for (int64_t st = st0; st < st1; ++st) {
-        const Stretch &S_ = a.st[st];
+        const auto &S_ = as_const(a.st)[st];
         const int cnt = S_.count;
+        const int slot = S_.slot;
+        const int d0 = S_.d0;
+        const double k0[4] = {S_.k0[0], S_.k0[1], S_.k0[2], S_.k0[3]};
+        const double dk[4] = {S_.dk[0], S_.dk[1], S_.dk[2], S_.dk[3]};
+        // exact anchor and per-sample factor of each of this lane's S spins
+        // (tiles wave, wave + 4, ... of the block; FP64 phase). Spin data are
+        // re-read per stretch (L2-resident) so that only the S recurrences and
+        // the 16 sample sums stay in registers across the sample loop.
         C2<R> c[S], w[S];
 #pragma unroll
         for (int j = 0; j < S; ++j) {
+            const int tl = wave + kWavesPerWG * j;
+            ParSpin sp{0.f, 0.f, 0.f, 0.f, __builtin_inff()};
             C2<R> m{R(0), R(0)};
-            if (pidx[j] >= 0) {
-                R2 v = reinterpret_cast<const R2 *>(a.snap)[(int64_t)S_.slot * n_pad + pidx[j]];
-                m = C2<R>{v.x, v.y};
+            if (tl < B.ntiles) {
+                const Tile T = a.tiles[B.tile0 + tl];
+                if (lane < T.count) {
+                    const int64_t i = T.spin0 + lane;
+                    sp = ParSpin{a.ph.x[i], a.ph.y[i], a.ph.z[i], a.ph.dw[i], a.ph.t2[i]};
+                    const R2 v = reinterpret_cast<const R2 *>(a.snap)[(int64_t)slot * n_pad +
+                                                                      (int64_t)(B.tile0 + tl) * kWave + lane];
+                    m = C2<R>{v.x, v.y};
+                }
             }
-            c[j] = cmul(m, block_factor<P>(sp[j], block_phase(sp[j], S_.k0), S_.k0[3]));
-            w[j] = block_factor<P>(sp[j], block_phase(sp[j], S_.dk), S_.dk[3]);
+            c[j] = cmul(m, par_factor<P>(sp, k0));
+            w[j] = par_factor<P>(sp, dk);
         }
         for (int b0 = 0; b0 < cnt; b0 += kBatch) {
             R are[kBatch], aim[kBatch];
@@ -461,7 +496,7 @@ __global__ __launch_bounds__(kWG) void k_par(ParArgs a) {
                 t.x += red[wv][i].x;
                 t.y += red[wv][i].y;
             }
-            reinterpret_cast<double2 *>(a.pb)[(int64_t)blockIdx.x * a.cols + (S_.d0 - a.col0) + i] = t;
+            reinterpret_cast<double2 *>(a.pb)[(int64_t)blockIdx.x * a.cols + (d0 - a.col0) + i] = t;
         }
         __syncthreads();
     }
@@ -544,6 +579,27 @@ __global__ __launch_bounds__(kWG) void k_validate(PhantomDev ph, int64_t n, int3
     if (threadIdx.x == 0) flags[blockIdx.x] = f[0];
 }
 
+// OR of n per-workgroup validation flags into out[0] (one workgroup).
+__global__ __launch_bounds__(kWG) void k_flags_or(const int32_t *flags, int64_t n, int32_t *out) {
+    __shared__ int32_t f[kWG];
+    int32_t v = 0;
+    for (int64_t i = threadIdx.x; i < n; i += kWG) v |= flags[i];
+    f[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kWG / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) f[threadIdx.x] |= f[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = f[0];
+}
+
+// Copy n doubles from src to dst only if *flag == 0 (the inputs were valid),
+// so a rejected call leaves the caller's output untouched.
+__global__ __launch_bounds__(kWG) void k_commit(const int32_t *flag, const double *src, double *dst, int64_t n) {
+    if (*flag != 0) return;
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG) dst[i] = src[i];
+}
+
 // ---------------------------------------------------------------- launchers
 
 static int check_launch() { return hipGetLastError() == hipSuccess ? 0 : -1; }
@@ -592,6 +648,19 @@ int launch_validate(const PhantomDev &ph, int64_t n, int32_t *flags, void *strea
     if (n <= 0) return 0;
     dim3 grid((unsigned)((n + kWG - 1) / kWG));
     hipLaunchKernelGGL(k_validate, grid, dim3(kWG), 0, (hipStream_t)stream, ph, n, flags);
+    return check_launch();
+}
+
+int launch_flags_or(const int32_t *flags, int64_t n, int32_t *out, void *stream) {
+    hipLaunchKernelGGL(k_flags_or, dim3(1), dim3(kWG), 0, (hipStream_t)stream, flags, n, out);
+    return check_launch();
+}
+
+int launch_commit(const int32_t *flag, const double *src, double *dst, int64_t n, void *stream) {
+    if (n <= 0) return 0;
+    int64_t g = (n + kWG - 1) / kWG;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_commit, dim3((unsigned)g), dim3(kWG), 0, (hipStream_t)stream, flag, src, dst, n);
     return check_launch();
 }
 

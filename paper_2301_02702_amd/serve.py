@@ -49,19 +49,29 @@ class Server:
     """One context, a pool of streams, at most ``max_slots`` requests in flight."""
 
     def __init__(self, device: int = 0, precision: str = "mixed", max_slots: int = 8,
-                 hbm_budget: Optional[int] = None, chunk_events: int = 1024, keep_signal: bool = False):
-        import torch
-        self.torch = torch
-        self.ctx = K.Context(device, precision, chunk_events=int(chunk_events))
+                 hbm_budget: Optional[int] = None, chunk_events: int = 1024, keep_signal: bool = False,
+                 backend=None):
+        """``backend`` = (context, stream factory, event factory) replaces the
+        HIP context and torch streams/events (used to test the scheduler on the CPU)."""
         self.max_slots = int(max_slots)
-        if hbm_budget is None:
-            free, _ = torch.cuda.mem_get_info(device)
-            hbm_budget = int(0.8 * free)
-        self.hbm_budget = int(hbm_budget)
         self.chunk_events = int(chunk_events)
-        # streams at the default priority
-        self.streams = [torch.cuda.Stream(device=device) for _ in range(self.max_slots)]
+        if backend is None:
+            import torch
+            self.ctx = K.Context(device, precision, chunk_events=int(chunk_events))
+            if hbm_budget is None:
+                free, _ = torch.cuda.mem_get_info(device)
+                hbm_budget = int(0.8 * free)
+            # streams at the default priority
+            self.streams = [torch.cuda.Stream(device=device) for _ in range(self.max_slots)]
+            self.new_event = torch.cuda.Event
+        else:
+            self.ctx, make_stream, self.new_event = backend
+            self.streams = [make_stream() for _ in range(self.max_slots)]
+        self.hbm_budget = int(hbm_budget)
         self.keep_signal = keep_signal
+        self.peak_used = 0  # largest sum of admitted footprints seen
+        self.peak_active = 0
+        self.admit_order = []
 
     def close(self):
         self.ctx.close()
@@ -76,7 +86,6 @@ class Server:
     def run(self, jobs, log: Optional[Callable] = None, realtime: bool = True):
         """Serve ``jobs`` (sorted by arrival). With ``realtime`` the arrival times
         are honoured on the wall clock; otherwise everything arrives at once."""
-        torch = self.torch
         pending = deque(sorted(jobs, key=lambda j: j.arrival))
         queue: deque = deque()
         active = []  # (job, request, stream, event)
@@ -110,6 +119,9 @@ class Server:
                     continue
                 used += job.footprint
                 active.append([job, req, free_streams.pop(), None])
+                self.peak_used = max(self.peak_used, used)
+                self.peak_active = max(self.peak_active, len(active))
+                self.admit_order.append(job.rid)
             progressed = False
             for slot in list(active):
                 job, req, stream, ev = slot
@@ -130,7 +142,7 @@ class Server:
                         done.append(job)
                         continue
                     req.advance(self.chunk_events, stream)
-                    ev = torch.cuda.Event()
+                    ev = self.new_event()
                     ev.record(stream)
                     slot[3] = ev
                 except K.KomaError as e:
@@ -180,19 +192,21 @@ def benchmark(ctx_device: int = 0, n_requests: int = 200, rho: float = 0.8, seed
     continuous batching."""
     import torch
     srv1 = Server(ctx_device, "mixed", max_slots=1)
-    warm, jobs = make_jobs(n_requests, seed, 0.0, warm=10)
+    warm, jobs = make_jobs(n_requests, seed, 1.0, warm=10)  # unit-mean gaps, scaled below
     for j in warm + jobs:
         srv1.prepare(j)
     srv1.run(warm, realtime=False)
     # saturated FIFO capacity: everything queued at t = 0
+    arrivals = [j.arrival for j in jobs]
     t = time.perf_counter()
     srv1.run(jobs, realtime=False)
     torch.cuda.synchronize()
     t_fifo_sat = time.perf_counter() - t
     mu = len(jobs) / t_fifo_sat  # requests/s one at a time
     gap = 1.0 / (rho * mu)
-    for j in jobs:
-        j.arrival = j.arrival * gap
+    t_first = arrivals[0]
+    for j, a in zip(jobs, arrivals):
+        j.arrival = (a - t_first) * gap
         j.admit = j.finish = float("nan")
         j.status = "queued"
     out = {"requests": len(jobs), "rho_of_fifo_capacity": rho, "fifo_capacity_req_s": mu,
@@ -209,8 +223,9 @@ def benchmark(ctx_device: int = 0, n_requests: int = 200, rho: float = 0.8, seed
     t = time.perf_counter()
     res = srv.run(jobs, realtime=True)
     out["batched"] = summarize(res, time.perf_counter() - t)
-    # saturated throughput of the batched server
+    # saturated throughput of the batched server (everything queued at t = 0)
     for j in jobs:
+        j.arrival = 0.0
         j.admit = j.finish = float("nan")
         j.status = "queued"
     t = time.perf_counter()
