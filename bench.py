@@ -190,13 +190,15 @@ def main():
             sck, phk, seqk = W.config(k)
             ss = phk.n * seqk.n_int
             rep = 3 if k != 5 else 2
-            tm, sm, _ = run_workload(K, ctx, torch, sck, phk, seqk, "mixed", rep, 1)
-            t6, s6, _ = run_workload(K, ctx, torch, sck, phk, seqk, "fp64", rep, 1)
+            tm, sm, km = run_workload(K, ctx, torch, sck, phk, seqk, "mixed", rep, 1, True)
+            t6, s6, k6 = run_workload(K, ctx, torch, sck, phk, seqk, "fp64", rep, 1, True)
             e = np.sqrt(np.mean(np.abs(sm - s6) ** 2, axis=1)) / np.max(np.abs(s6), axis=1)
             extra[W.WORKLOAD_NAMES[k].split(" ")[0]] = {
                 "spins": phk.n, "intervals": seqk.n_int, "spin_steps": ss,
                 "mixed_gsps": round(ss / tm / 1e9, 3), "fp64_gsps": round(ss / t6 / 1e9, 3),
                 "mixed_ms": round(tm * 1e3, 3), "fp64_ms": round(t6 * 1e3, 3),
+                "kernel_ms": {p: {kk: round(v["total_ms"] / rep, 3) for kk, v in st.items()}
+                              for p, st in (("mixed", km), ("fp64", k6))},
                 "nrmse_mixed_vs_fp64_max": float(np.max(e))}
             log(f"[bench] {W.WORKLOAD_NAMES[k]}: mixed {ss / tm / 1e9:.2f}, fp64 {ss / t6 / 1e9:.2f} G spin-steps/s")
             del phk

@@ -560,6 +560,28 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
                 e.d[c] = v[c];
                 e.f[c] = (float)v[c];
             }
+            e.b1sq_f32 = (double)e.f[3] * (double)e.f[3] + (double)e.f[4] * (double)e.f[4];
+            e.rot = -1;
+            if (v[0] == 0.0 && v[1] == 0.0 && v[2] == 0.0) {
+                // zero gradient: for Bz = 0 the field is (b1, 0) for every spin;
+                // alpha = cos(phi/2), beta = -i (b1/|b1|) sin(phi/2), phi = -gamma |b1| dt
+                const double nb = std::sqrt(v[5]);
+                const double h = -0.5 * gamma * nb * dt;
+                const double ar = std::cos(h), ai = 0.0;
+                const double sn = std::sin(h) / nb;
+                const double br = q->b1_im[b] * sn, bi = -q->b1_re[b] * sn;
+                const double ur = ar * ar - ai * ai, ui = -2.0 * ar * ai;
+                const double vr = br * br - bi * bi, vi = 2.0 * br * bi;
+                const double wr = ar * br + ai * bi, wi = ar * bi - ai * br;
+                const double pr = ar * br - ai * bi, pi = ar * bi + ai * br;
+                const double c[9] = {2.0 * wr, ur - vr, -(ui + vi), 2.0 * wi, ur + vr, ui - vi,
+                                     (ar * ar + ai * ai) - (br * br + bi * bi), -2.0 * pr, -2.0 * pi};
+                for (int k = 0; k < 9; ++k) {
+                    e.c64[k] = c[k];
+                    e.c32[k] = (float)c[k];
+                }
+                e.rot = 1;
+            }
             P.ev.push_back(e);
             ++P.n_rf;
         }

@@ -30,7 +30,7 @@ struct alignas(16) Event {
     int32_t kind;
     int32_t a0;     // EV_ADC: first inline sample slot; EV_SNAP: snapshot slot
     int32_t count;  // EV_ADC: number of samples
-    int32_t pad;
+    int32_t rot;    // EV_RF: 1 if the rotation for Bz = 0 is precomputed (zero gradient), else -1
     // EV_RF: gx, gy, gz (T/m, interval mean), b1_re, b1_im (T), |b1|^2,
     //        hs = -gamma dt / (4 pi) (half rotation angle per tesla, in turns), dt (s)
     float f[8];
@@ -38,8 +38,19 @@ struct alignas(16) Event {
     // EV_END: kx, ky, kz (cycles/m), tau (s) of the block end.
     // EV_ADC: kx, ky, kz, tau of the first sample, then dkx, dky, dkz, dtau.
     double d[8];
+    // EV_RF: exact |b1|^2 of the FP32-rounded b1 (f[3], f[4]) for the FP32 kernel.
+    double b1sq_f32;
+    double pad2;
+    // EV_RF with zero gradient (rot >= 0): the interval's rotation for spins
+    // without off-resonance (Bz = 0, the same field for all of them), the
+    // spinor update of Eq. Rot_exc computed once on the host in FP64:
+    //   Mxy_re' = c[0] Mz + c[1] Mxy_re + c[2] Mxy_im
+    //   Mxy_im' = c[3] Mz + c[4] Mxy_im + c[5] Mxy_re
+    //   Mz'     = c[6] Mz + c[7] Mxy_re + c[8] Mxy_im
+    float c32[12];   // 9 used (rounded for the FP32 kernel)
+    double c64[10];  // 9 used
 };
-static_assert(sizeof(Event) == 112, "Event layout");
+static_assert(sizeof(Event) == 256, "Event layout");
 
 // Evenly spaced samples of one deferred precession block, summed by the
 // sample-parallel kernel from snapshot `slot`.

@@ -268,7 +268,7 @@ __device__ __forceinline__ C2<typename P::R> block_factor(const SpinP<typename P
 // cached eps = 1 - exp(-dt/T) (applied as M - eps*M, exact in the factor).
 template <class P>
 __device__ __forceinline__ void excite_relax(const SpinP<typename P::R> &s, const typename P::R *q,
-                                             typename P::R eps1, typename P::R eps2,
+                                             double b1sq_exact, typename P::R eps1, typename P::R eps2,
                                              typename P::R &mr, typename P::R &mi,
                                              typename P::R &mz) {
     using R = typename P::R;
@@ -284,7 +284,8 @@ __device__ __forceinline__ void excite_relax(const SpinP<typename P::R> &s, cons
     // normalise the spinor, |alpha|^2 + |beta|^2 = cs^2 + sk^2 |B|^2 -> 1, with
     // the defect formed exactly in FP64 (see renorm)
     {
-        const double B2 = fma((double)bz, (double)bz, fma((double)b1r, (double)b1r, (double)b1i * (double)b1i));
+        // b1sq_exact = b1r^2 + b1i^2 of the very values used below, exact in FP64
+        const double B2 = fma((double)bz, (double)bz, b1sq_exact);
         const double sk2 = (double)sk * (double)sk;
         const R h = R(-0.5 * fma(sk2, B2, fma((double)cs, (double)cs, -1.0)));
         cs = fma(cs, h, cs);
@@ -322,25 +323,57 @@ __device__ __forceinline__ ConstPtr<T> as_const(const T *p) {
     return (ConstPtr<T>)p;
 }
 
+// Events are staged through LDS in chunks: the workgroup copies kChunk
+// events with coalesced 16-byte loads, and every lane then reads the fields
+// of the current event at one LDS address (a broadcast).
+constexpr int kChunk = 32;
+constexpr int kEvWords = (int)(sizeof(Event) / 4);  // 64 dwords
+static_assert(sizeof(Event) % 16 == 0, "Event is copied as 16-byte words");
+
+struct EvL {  // view of one staged event
+    const uint32_t *u;
+    __device__ __forceinline__ uint32_t word(int i) const { return u[i]; }
+    __device__ __forceinline__ int kind() const { return (int)u[0]; }
+    __device__ __forceinline__ int a0() const { return (int)u[1]; }
+    __device__ __forceinline__ int count() const { return (int)u[2]; }
+    __device__ __forceinline__ int rot() const { return (int)u[3]; }
+    __device__ __forceinline__ float f(int i) const { return __uint_as_float(u[4 + i]); }
+    __device__ __forceinline__ double d(int i) const {
+        return __builtin_bit_cast(double, ((uint64_t)u[12 + 2 * i + 1] << 32) | u[12 + 2 * i]);
+    }
+    __device__ __forceinline__ double b1sq() const {
+        return __builtin_bit_cast(double, ((uint64_t)u[29] << 32) | u[28]);
+    }
+    __device__ __forceinline__ float c32(int i) const { return __uint_as_float(u[32 + i]); }
+    __device__ __forceinline__ double c64(int i) const {
+        return __builtin_bit_cast(double, ((uint64_t)u[44 + 2 * i + 1] << 32) | u[44 + 2 * i]);
+    }
+};
+
 template <class P>
 __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
     using R = typename P::R;
     using R2 = typename P::R2;
+    __shared__ uint4 lds_ev[kChunk * kEvWords / 4];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int64_t tile = (int64_t)blockIdx.x * kWavesPerWG + wave;
-    if (tile >= a.n_tiles) return;  // whole wavefront; no barrier in this kernel
-    const Tile T = a.tiles[tile];
+    // wavefronts past the last tile still help staging and reach every barrier
+    const bool active = tile < a.n_tiles;
+    Tile T;
+    if (active) {
+        T = a.tiles[tile];
+    } else {
+        T.spin0 = 0;
+        T.count = 0;
+        T.group = 0;
+    }
     const SpinP<R> s = load_spin<R>(a.ph, T, lane, a.inv_gamma);
     const int64_t n_pad = a.n_tiles * kWave;
     const int64_t pidx = tile * kWave + lane;
 
-    R mr, mi, mz;
-    if (a.init) {
-        mr = R(0);
-        mi = R(0);
-        mz = s.pd;
-    } else {
+    R mr = R(0), mi = R(0), mz = s.pd;
+    if (active && !a.init) {
         R2 m = reinterpret_cast<const R2 *>(a.mxy)[pidx];
         mr = m.x;
         mi = m.y;
@@ -348,55 +381,73 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
     }
     R eps1 = R(0), eps2 = R(0);
     double dt_cached = -1.0;  // uniform
+    // no spin of this wavefront has off-resonance: zero-gradient excitation
+    // intervals are then the same rotation for all of them (precomputed)
+    const bool no_offres = __ballot(s.bz0 != R(0)) == 0;
+    const uint4 *gev = reinterpret_cast<const uint4 *>(a.ev);
 
-    const ConstPtr<Event> evs = as_const(a.ev);
-    for (int64_t e = a.e0; e < a.e1; ++e) {
-        const auto &ev = evs[e];
-        const int kind = ev.kind;
-        if (kind == EV_RF) {
-            R q[7];
-            const double dt = ev.d[7];
-            if constexpr (sizeof(R) == 4) {
+    for (int64_t c0 = a.e0; c0 < a.e1; c0 += kChunk) {
+        const int n = (int)min<int64_t>(kChunk, a.e1 - c0);
+        __syncthreads();  // the previous chunk is no longer read
+        for (int i = threadIdx.x; i < n * (kEvWords / 4); i += kWG) lds_ev[i] = gev[c0 * (kEvWords / 4) + i];
+        __syncthreads();
+        if (!active) continue;
+        for (int k = 0; k < n; ++k) {
+            const EvL ev{reinterpret_cast<const uint32_t *>(lds_ev) + k * kEvWords};
+            const int kind = ev.kind();
+            if (kind == EV_RF) {
+                const double dt = ev.d(7);
+                if (dt != dt_cached) {  // uniform: same interval length for every spin
+                    dt_cached = dt;
+                    eps1 = R(-expm1(-dt * (double)s.r1));
+                    eps2 = R(-expm1(-dt * (double)s.r2));
+                }
+                if (ev.rot() >= 0 && no_offres) {
+                    R c[9];
 #pragma unroll
-                for (int i = 0; i < 7; ++i) q[i] = ev.f[i];
-            } else {
+                    for (int i = 0; i < 9; ++i) c[i] = sizeof(R) == 4 ? R(ev.c32(i)) : R(ev.c64(i));
+                    const R nr = fma(c[0], mz, fma(c[1], mr, c[2] * mi));
+                    const R ni = fma(c[3], mz, fma(c[4], mi, c[5] * mr));
+                    const R nz = fma(c[6], mz, fma(c[7], mr, c[8] * mi));
+                    mr = fma(-eps2, nr, nr);
+                    mi = fma(-eps2, ni, ni);
+                    mz = fma(-eps1, nz - s.pd, nz);
+                } else {
+                    R q[7];
 #pragma unroll
-                for (int i = 0; i < 7; ++i) q[i] = ev.d[i];
+                    for (int i = 0; i < 7; ++i) q[i] = sizeof(R) == 4 ? R(ev.f(i)) : R(ev.d(i));
+                    // |b1|^2 of exactly the b1 values the precision uses
+                    const double b1sq = sizeof(R) == 4 ? ev.b1sq() : ev.d(5);
+                    excite_relax<P>(s, q, b1sq, eps1, eps2, mr, mi, mz);
+                }
+            } else if (kind == EV_END) {
+                const double k4[4] = {ev.d(0), ev.d(1), ev.d(2), ev.d(3)};
+                const double tau = k4[3];
+                C2<R> f = block_factor<P>(s, block_phase(s, k4), tau);
+                C2<R> m = cmul(C2<R>{mr, mi}, f);
+                mr = m.re;
+                mi = m.im;
+                mz = s.pd + (mz - s.pd) * P::exp_neg(R(tau) * s.r1);
+            } else if (kind == EV_ADC) {
+                const double k0[4] = {ev.d(0), ev.d(1), ev.d(2), ev.d(3)};
+                const double dk[4] = {ev.d(4), ev.d(5), ev.d(6), ev.d(7)};
+                C2<R> c = cmul(C2<R>{mr, mi}, block_factor<P>(s, block_phase(s, k0), k0[3]));
+                const int cnt = ev.count();
+                C2<R> w{R(1), R(0)};
+                if (cnt > 1) w = block_factor<P>(s, block_phase(s, dk), dk[3]);
+                R2 *pa = reinterpret_cast<R2 *>(a.pa) + tile * a.n_inline + ev.a0();
+                for (int i = 0; i < cnt; ++i) {
+                    const R sr = wave_allsum(c.re);
+                    const R si = wave_allsum(c.im);
+                    if (lane == 0) pa[i] = R2{sr, si};
+                    c = cmul(c, w);
+                }
+            } else {  // EV_SNAP
+                reinterpret_cast<R2 *>(a.snap)[(int64_t)ev.a0() * n_pad + pidx] = R2{mr, mi};
             }
-            if (dt != dt_cached) {  // uniform: same interval length for every spin
-                dt_cached = dt;
-                eps1 = R(-expm1(-dt * (double)s.r1));
-                eps2 = R(-expm1(-dt * (double)s.r2));
-            }
-            excite_relax<P>(s, q, eps1, eps2, mr, mi, mz);
-        } else if (kind == EV_END) {
-            const double k[4] = {ev.d[0], ev.d[1], ev.d[2], ev.d[3]};
-            const double theta = block_phase(s, k);
-            const double tau = k[3];
-            C2<R> f = block_factor<P>(s, theta, tau);
-            C2<R> m = cmul(C2<R>{mr, mi}, f);
-            mr = m.re;
-            mi = m.im;
-            mz = s.pd + (mz - s.pd) * P::exp_neg(R(tau) * s.r1);
-        } else if (kind == EV_ADC) {
-            const double k0[4] = {ev.d[0], ev.d[1], ev.d[2], ev.d[3]};
-            const double dk[4] = {ev.d[4], ev.d[5], ev.d[6], ev.d[7]};
-            C2<R> c = cmul(C2<R>{mr, mi}, block_factor<P>(s, block_phase(s, k0), k0[3]));
-            const int cnt = ev.count;
-            C2<R> w{R(1), R(0)};
-            if (cnt > 1) w = block_factor<P>(s, block_phase(s, dk), dk[3]);
-            R2 *pa = reinterpret_cast<R2 *>(a.pa) + tile * a.n_inline + ev.a0;
-            for (int i = 0; i < cnt; ++i) {
-                const R sr = wave_allsum(c.re);
-                const R si = wave_allsum(c.im);
-                if (lane == 0) pa[i] = R2{sr, si};
-                c = cmul(c, w);
-            }
-        } else {  // EV_SNAP
-            reinterpret_cast<R2 *>(a.snap)[(int64_t)ev.a0 * n_pad + pidx] = R2{mr, mi};
         }
     }
-    if (a.store) {
+    if (active && a.store) {
         reinterpret_cast<R2 *>(a.mxy)[pidx] = R2{mr, mi};
         reinterpret_cast<R *>(a.mz)[pidx] = mz;
     }

@@ -207,3 +207,41 @@ def test_invalid_device_phantom_is_rejected(ctx, K):
     assert e.value.status == -2
     # the context still works afterwards
     assert np.isfinite(ctx.simulate(sc, ph, seq)).all()
+
+
+def test_precomputed_zero_gradient_rotation_matches_general_path(ctx):
+    """Zero-gradient excitation intervals of wavefronts without off-resonance
+    use a rotation precomputed on the host; spins with a negligible (but not
+    zero) off-resonance take the per-spin spinor path. Both must agree, and
+    both must match the oracle."""
+    import oracle
+    sc, ph, seq = case("mrf40")
+    ph2 = W.Phantom(ph.x, ph.y, ph.z, ph.pd, ph.t1, ph.t2, np.full(ph.n, 1e-30), ph.group_off)
+    ref = oracle_cached("mrf40")
+    for prec, tol in (("fp64", 1e-12), ("mixed", 1e-5)):
+        ctx.set_config(prec)
+        fast = ctx.simulate(sc, ph, seq)
+        slow = ctx.simulate(sc, ph2, seq)
+        e = float(np.max(nrmse(fast, slow)))
+        say(f"[rot] {prec}: fast vs per-spin path NRMSE {e:.3e}; vs oracle "
+            f"{float(np.max(nrmse(fast, ref))):.3e} / {float(np.max(nrmse(slow, ref))):.3e}")
+        assert e <= tol
+
+
+def test_magnitude_preserved_by_repeated_hard_pulses(ctx):
+    """T = inf, no gradient, no off-resonance: 10^4 excitation intervals of
+    varying flip (the precomputed-rotation path) keep |M| = PD."""
+    rng = np.random.default_rng(17)
+    n = 10_000
+    dt = rng.uniform(1e-6, 1e-5, n)
+    t = np.concatenate([[0.0], np.cumsum(dt)])
+    b1 = rng.uniform(-2e-5, 2e-5, n) + 1j * rng.uniform(-2e-5, 2e-5, n)
+    seq = W.make_sequence(t, np.zeros((n + 1, 3)), b1, [])
+    ph = W.random_spins(rng, 200, finite_t=False)
+    ph.dw[:] = 0
+    for prec, tol in (("fp64", 1e-11), ("mixed", 5e-5)):
+        ctx.set_config(prec)
+        _, m = ctx.simulate(W.Scanner(), ph, seq, want_m=True)
+        err = np.max(np.abs(np.linalg.norm(m, axis=1) / ph.pd - 1))
+        say(f"[|M| hard] {prec}: max relative drift {err:.3e} over {n} intervals")
+        assert err < tol
