@@ -204,6 +204,31 @@ def main():
             del phk
         out["workloads"] = extra
 
+    if not args.no_extra:
+        # sequence-aware time stepping: the same sequences from their block
+        # form, discretised by the library to the minimal grid
+        seqaware = {}
+        for k, blocks_fn in ((1, W.gre_blocks), (2, W.epi_blocks)):
+            sck, phk, seqk = W.config(k) if k != 2 else (sc, ph, seq)
+            blocks = blocks_fn()
+            t0 = time.perf_counter()
+            m = K.koma_discretize(blocks)
+            t_disc = time.perf_counter() - t0
+            rep = 5 if k == 1 else args.steps
+            tr, sr, _ = run_workload(K, ctx, torch, sck, phk, seqk, "mixed", rep, 1)
+            tm, sm, km = run_workload(K, ctx, torch, sck, phk, m, "mixed", rep, 1, True)
+            name = W.WORKLOAD_NAMES[k].split(" ")[0]
+            seqaware[name] = {
+                "blocks": len(blocks), "raster_intervals": seqk.n_int, "minimal_intervals": m.n_int,
+                "discretise_ms": round(t_disc * 1e3, 3),
+                "raster_ms": round(tr * 1e3, 3), "minimal_ms": round(tm * 1e3, 3),
+                "speedup": round(tr / tm, 3),
+                "nrmse_minimal_vs_raster": float(np.max(np.sqrt(np.mean(np.abs(sm - sr) ** 2, axis=1))
+                                                        / np.max(np.abs(sr), axis=1)))}
+            log(f"[bench] minimal grid {name}: {m.n_int} vs {seqk.n_int} intervals, "
+                f"{tm * 1e3:.3f} vs {tr * 1e3:.3f} ms")
+        out["sequence_aware"] = seqaware
+
     if not args.no_serving:
         from paper_2301_02702_amd import serve
         log(f"[bench] serving: {args.serving_requests} requests ...")

@@ -49,7 +49,7 @@ typedef enum {
     KOMA_E_PHANTOM = -2,   /* non-finite value, PD < 0, T1/T2 <= 0 or NaN, bad group offsets */
     KOMA_E_SEQUENCE = -3,  /* n_t < 2, non-finite value, t not strictly increasing,
                               ADC indices out of [0, n_t) or not strictly increasing */
-    KOMA_E_NOMEM = -4,     /* device allocation failed */
+    KOMA_E_NOMEM = -4,     /* device (or, in koma_discretize, host) allocation failed */
     KOMA_E_BUDGET = -5,    /* the request's device footprint exceeds hbm_budget */
     KOMA_E_DEVICE = -6,    /* a HIP call failed; the context is poisoned */
     KOMA_E_CANCELLED = -7, /* the request was cancelled */
@@ -122,7 +122,8 @@ void koma_ctx_destroy(koma_ctx *ctx);
 
 /* Message of the last error on this context (empty string if none). The
  * pointer stays valid until the next call on the context. ctx may be NULL
- * (message of the last failed koma_ctx_create on this thread). */
+ * (message of the last failed koma_ctx_create or koma_discretize on this
+ * thread). */
 const char *koma_last_error(const koma_ctx *ctx);
 
 /* Replace the context configuration (validated as in koma_ctx_create). */
@@ -196,6 +197,85 @@ koma_status koma_plan_info(const koma_scanner *sc, const koma_phantom *ph, const
 koma_status koma_ctx_profile(koma_ctx *ctx, int on);
 koma_status koma_ctx_kernel_stats(koma_ctx *ctx, int kind, double *total_ms, int64_t *launches,
                                   int64_t *work_units);
+
+/* ---- sequence-aware time stepping ----------------------------------------
+ * Section "Simulation blocks, Regime Switching, and Sequence-Aware Time
+ * Stepping": with G piecewise linear the trapezoidal phase of a precession
+ * interval is exact when only the vertices of G are sampled, and with B1
+ * piecewise constant the spinor rotation of Eq. Rot_exc is exact per RF
+ * sample; extra points are needed only for the ADC (and for motion). The
+ * paper's user knobs are the longest step between intermediate gradient
+ * samples (Delta t, here dt_max) and between RF samples (Delta t_rf, here
+ * dt_rf_max).
+ *
+ * A sequence is a list of blocks played back to back from t = 0. Times
+ * inside a block are relative to its start; every event must end within the
+ * block's duration. */
+typedef enum { KOMA_GRAD_NONE = 0, KOMA_GRAD_TRAP = 1, KOMA_GRAD_PWL = 2 } koma_grad_kind;
+
+/* Trapezoid: zero until delay, linear ramp to amp over rise, flat for flat,
+ * linear ramp back to zero over fall (rise, fall > 0; delay, flat >= 0). */
+typedef struct {
+    double amp; /* T/m, finite */
+    double delay, rise, flat, fall; /* s */
+} koma_trap;
+
+/* One gradient axis of a block. KOMA_GRAD_PWL: a piecewise-linear waveform
+ * through pwl_n >= 2 vertices (pwl_t[i] s, block-local, strictly increasing,
+ * in [0, duration]; pwl_amp[i] T/m), zero outside them (an arbitrary
+ * gradient sampled on a raster is the case pwl_t[i] = delay + i dt). G must
+ * stay continuous: the first amplitude is 0 unless the waveform starts at the
+ * block start, the last is 0 unless it ends at the block end, and where a
+ * waveform meets a block boundary its value equals the neighbouring block's
+ * value there (relative tolerance 1e-9). The caller's arrays are read during
+ * the call only. */
+typedef struct {
+    int kind; /* koma_grad_kind */
+    koma_trap trap;
+    int64_t pwl_n;
+    const double *pwl_t, *pwl_amp;
+} koma_grad;
+
+/* RF: n piecewise-constant samples (re[i], im[i]) in T, sample i held on
+ * [delay + i dt, delay + (i + 1) dt). n = 0: no RF. */
+typedef struct {
+    double delay, dt;
+    int64_t n;
+    const double *re, *im;
+} koma_rf;
+
+/* ADC: n samples at delay + i * dwell (dwell > 0 when n > 1). */
+typedef struct {
+    double delay, dwell;
+    int64_t n;
+} koma_adc;
+
+typedef struct {
+    double duration; /* s, > 0 */
+    koma_grad g[3];  /* x, y, z */
+    koma_rf rf;
+    koma_adc adc;
+} koma_block;
+
+/* Discretise `n_blocks` blocks into a koma_sequence grid (host memory only).
+ * Time points: every block boundary, every gradient vertex, every RF sample
+ * boundary (a sample longer than dt_rf_max split into equal parts), every ADC
+ * sample, and, on intervals outside RF samples, equally spaced points so that
+ * no interval exceeds dt_max; points within 1 ps of each other are one point.
+ * dt_max, dt_rf_max > 0; +INFINITY means no such subdivision (the minimal
+ * grid). Outputs: t[n_t], gx/gy/gz[n_t] (G at each point), b1_re/b1_im
+ * [n_t - 1] (the RF sample in force on each interval, else 0), adc_idx[n_adc]
+ * (the point of each ADC sample, in time order).
+ * Two calls: with t == NULL, *n_t and *n_adc receive the sizes; then call
+ * again with arrays of at least those sizes (*n_t, *n_adc give their
+ * capacities and receive the sizes written). Errors: KOMA_E_ARG (NULL or
+ * small outputs, dt <= 0, unknown gradient kind), KOMA_E_SEQUENCE (a block
+ * or event out of its bounds, a non-finite value, vertex times not
+ * increasing, G not continuous, two ADC samples at one instant),
+ * KOMA_E_NOMEM; the message is in koma_last_error(NULL). */
+koma_status koma_discretize(const koma_block *blocks, int64_t n_blocks, double dt_max, double dt_rf_max,
+                            int64_t *n_t, int64_t *n_adc, double *t, double *gx, double *gy, double *gz,
+                            double *b1_re, double *b1_im, int64_t *adc_idx);
 
 #ifdef __cplusplus
 }

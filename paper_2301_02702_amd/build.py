@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", "komahip_host.cpp"), os.path.join(HERE, "csrc", "komahip_kernels.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("komahip_host.cpp", "komahip_discretize.cpp", "komahip_kernels.hip")]
 DEPS = SRC + [os.path.join(HERE, "csrc", "komahip_internal.h"), os.path.join(ROOT, "include", "komahip.h")]
 LIB = os.path.join(HERE, "libkomahip.so")
 

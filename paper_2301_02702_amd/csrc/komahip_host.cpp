@@ -821,6 +821,11 @@ static koma_status validate_device_phantom(koma_ctx *ctx, const PhantomDev &ph, 
 
 // ---------------------------------------------------------------- C ABI
 
+namespace koma {
+// Errors of calls that have no context (koma_ctx_create, koma_discretize).
+void set_thread_error(const std::string &msg) { g_create_error = msg; }
+}  // namespace koma
+
 extern "C" {
 
 void koma_config_default(koma_config *cfg) {

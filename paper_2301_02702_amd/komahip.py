@@ -63,6 +63,30 @@ class koma_req_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class koma_trap(ctypes.Structure):
+    _fields_ = [("amp", c_double), ("delay", c_double), ("rise", c_double), ("flat", c_double),
+                ("fall", c_double)]
+
+
+class koma_grad(ctypes.Structure):
+    _fields_ = [("kind", c_int), ("trap", koma_trap), ("pwl_n", c_int64), ("pwl_t", c_void_p),
+                ("pwl_amp", c_void_p)]
+
+
+class koma_rf(ctypes.Structure):
+    _fields_ = [("delay", c_double), ("dt", c_double), ("n", c_int64), ("re", c_void_p), ("im", c_void_p)]
+
+
+class koma_adc(ctypes.Structure):
+    _fields_ = [("delay", c_double), ("dwell", c_double), ("n", c_int64)]
+
+
+class koma_block(ctypes.Structure):
+    _fields_ = [("duration", c_double), ("g", koma_grad * 3), ("rf", koma_rf), ("adc", koma_adc)]
+
+
+KOMA_GRAD_NONE, KOMA_GRAD_TRAP, KOMA_GRAD_PWL = 0, 1, 2
+
 EXPORTS = {
     "koma_config_default": (None, [POINTER(koma_config)]),
     "koma_ctx_create": (c_int, [c_int, POINTER(koma_config), POINTER(c_void_p)]),
@@ -87,6 +111,8 @@ EXPORTS = {
     "koma_ctx_profile": (c_int, [c_void_p, c_int]),
     "koma_ctx_kernel_stats": (c_int, [c_void_p, c_int, POINTER(c_double), POINTER(c_int64),
                                       POINTER(c_int64)]),
+    "koma_discretize": (c_int, [POINTER(koma_block), c_int64, c_double, c_double, POINTER(c_int64),
+                                POINTER(c_int64)] + [c_void_p] * 7),
 }
 
 _lib = None
@@ -182,6 +208,66 @@ class _SeqArgs:
         self.n_adc = int(k[6].shape[0])
         self.c = koma_sequence(int(k[0].shape[0]), *[_ptr(a) for a in k[:6]], self.n_adc,
                                _ptr(k[6]) if self.n_adc else None)
+
+
+class _BlockArgs:
+    """koma_block array for a list of block descriptions (objects with
+    ``duration``, ``gx``/``gy``/``gz`` (None, a trapezoid with amp / delay /
+    rise / flat / fall, or a waveform with vertex arrays ``t`` and ``amp``),
+    ``rf`` (None or delay / dt / complex ``samples``) and ``adc`` (None or
+    delay / dwell / n))."""
+
+    def __init__(self, blocks):
+        self.keep = []
+        n = len(blocks)
+        self.n = n
+        self.c = (koma_block * max(n, 1))()
+        for i, b in enumerate(blocks):
+            cb = self.c[i]
+            cb.duration = float(b.duration)
+            for a, g in enumerate((b.gx, b.gy, b.gz)):
+                cg = cb.g[a]
+                if g is None:
+                    cg.kind = KOMA_GRAD_NONE
+                elif hasattr(g, "rise"):
+                    cg.kind = KOMA_GRAD_TRAP
+                    cg.trap = koma_trap(float(g.amp), float(g.delay), float(g.rise), float(g.flat),
+                                        float(g.fall))
+                else:
+                    tv = np.ascontiguousarray(g.t, dtype=np.float64)
+                    av = np.ascontiguousarray(g.amp, dtype=np.float64)
+                    self.keep += [tv, av]
+                    cg.kind = KOMA_GRAD_PWL
+                    cg.pwl_n = int(tv.shape[0]) if tv.shape == av.shape else -1
+                    cg.pwl_t, cg.pwl_amp = _ptr(tv), _ptr(av)
+            if b.rf is not None:
+                smp = np.asarray(b.rf.samples, dtype=np.complex128)
+                re = np.ascontiguousarray(smp.real)
+                im = np.ascontiguousarray(smp.imag)
+                self.keep += [re, im]
+                cb.rf = koma_rf(float(b.rf.delay), float(b.rf.dt), int(smp.shape[0]), _ptr(re), _ptr(im))
+            if b.adc is not None:
+                cb.adc = koma_adc(float(b.adc.delay), float(b.adc.dwell), int(b.adc.n))
+
+
+def koma_discretize(blocks, dt_max: float = np.inf, dt_rf_max: float = np.inf, name: str = "discretised"):
+    """Sequence-aware discretisation of a block list (two calls: sizes, then
+    values). Returns a sequence object with ``t``, ``gx``, ``gy``, ``gz``,
+    complex ``b1`` per interval and ``adc_idx``."""
+    from .workloads import Sequence
+    b = _BlockArgs(blocks)
+    L = lib()
+    n_t, n_adc = c_int64(0), c_int64(0)
+    _check(L.koma_discretize(b.c, b.n, float(dt_max), float(dt_rf_max), ctypes.byref(n_t),
+                             ctypes.byref(n_adc), *([None] * 7)))
+    t, gx, gy, gz = (np.empty(n_t.value) for _ in range(4))
+    re, im = np.empty(max(n_t.value - 1, 0)), np.empty(max(n_t.value - 1, 0))
+    adc = np.empty(n_adc.value, dtype=np.int64)
+    _check(L.koma_discretize(b.c, b.n, float(dt_max), float(dt_rf_max), ctypes.byref(n_t),
+                             ctypes.byref(n_adc), *[_ptr(a) for a in (t, gx, gy, gz, re, im)],
+                             _ptr(adc) if n_adc.value else None))
+    return Sequence(t, gx, gy, gz, re + 1j * im, adc, name=name,
+                    meta={"dt_max": dt_max, "dt_rf_max": dt_rf_max, "n_blocks": b.n})
 
 
 # ---------------------------------------------------------------- 1:1 wrappers

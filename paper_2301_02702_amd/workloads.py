@@ -666,3 +666,166 @@ def epi_te_sequence(n: int = 100, fov: float = 0.23, te: float = 0.1, dt: float 
     k0_point = p_ro + k0_rel
     return s.build(f"epi{n}_te{te * 1e3:g}ms", fov=fov, n=n, te=te,
                    k0_adc=int(np.searchsorted(np.array(s.adc), k0_point)), k0_point=k0_point)
+
+
+# --------------------------------------------------------------------------
+# Block-structured sequences (input of the sequence-aware discretiser)
+# --------------------------------------------------------------------------
+# A sequence is a list of blocks played back to back; times inside a block
+# are relative to its start. Gradients are trapezoids or piecewise-linear
+# waveforms through given vertices, RF is a train of piecewise-constant
+# samples, the ADC samples at delay + i * dwell.
+@dataclass
+class Trap:
+    amp: float  # T/m
+    delay: float
+    rise: float
+    flat: float
+    fall: float
+
+
+@dataclass
+class PWL:
+    t: np.ndarray    # block-local vertex times, s
+    amp: np.ndarray  # T/m
+
+
+@dataclass
+class RFTrain:
+    delay: float
+    dt: float
+    samples: np.ndarray  # complex, T
+
+
+@dataclass
+class ADCWindow:
+    delay: float
+    dwell: float
+    n: int
+
+
+@dataclass
+class Block:
+    duration: float
+    gx: Optional[object] = None
+    gy: Optional[object] = None
+    gz: Optional[object] = None
+    rf: Optional[RFTrain] = None
+    adc: Optional[ADCWindow] = None
+
+    @property
+    def grads(self):
+        return (self.gx, self.gy, self.gz)
+
+
+def trap_of_area(area: float, ramp: float, flat: float, delay: float = 0.0) -> Trap:
+    """Trapezoid of ``area`` T s/m (area = amp * (ramp + flat))."""
+    return Trap(area / (ramp + flat), delay, ramp, flat, ramp)
+
+
+def gre_blocks(n: int = 64, fov: float = 0.2, dt: float = 10e-6, tr_int: int = 1000,
+               gamma: float = GAMMA):
+    """The gradient echo of :func:`gre_sequence` as blocks: per TR an RF
+    block, a prephaser / phase-encode block, a readout block, a rewinder /
+    spoiler block and an idle block, with the same timings on the same raster."""
+    gbar = gamma / (2 * np.pi)
+    dk = 1.0 / fov
+    g_ro = dk / (gbar * dt)
+    ramp = 10
+    blocks = []
+    for line in range(n):
+        ky = (line - n // 2) * dk
+        kx_pre = -(n // 2) * dk - g_ro * gbar * ramp * dt / 2.0
+        blocks.append(Block(100 * dt, rf=RFTrain(0.0, dt, sinc_pulse(100, dt, np.pi / 2, 2.0, gamma))))
+        blocks.append(Block(100 * dt, gx=trap_of_area(kx_pre / gbar, ramp * dt, 80 * dt),
+                            gy=trap_of_area(ky / gbar, ramp * dt, 80 * dt)))
+        blocks.append(Block((2 * ramp + n) * dt, gx=Trap(g_ro, 0.0, ramp * dt, n * dt, ramp * dt),
+                            adc=ADCWindow(ramp * dt, dt, n)))
+        blocks.append(Block(100 * dt, gx=Trap(0.020, 0.0, ramp * dt, 80 * dt, ramp * dt),
+                            gy=trap_of_area(-ky / gbar, ramp * dt, 80 * dt)))
+        blocks.append(Block((tr_int - 300 - (2 * ramp + n)) * dt))
+    return blocks
+
+
+def epi_blocks(n: int = 128, fov: float = 0.23, dt: float = 4e-6, rf_int: int = 50,
+               ramp: int = 15, gamma: float = GAMMA):
+    """The single-shot EPI of :func:`epi_sequence` as blocks: an RF block, a
+    prephaser block and one block per line. Each Gy blip straddles two line
+    blocks, so the line blocks carry its halves as piecewise-linear
+    waveforms that meet at the boundary with the blip's peak."""
+    gbar = gamma / (2 * np.pi)
+    dk = 1.0 / fov
+    g_ro = dk / (gbar * dt)
+    ramp_area = g_ro * ramp * dt / 2.0
+    kx_pre = -(n // 2) * dk / gbar - ramp_area
+    blip_r = 10
+    blip_amp = (dk / gbar) / (blip_r * dt)
+    dur = (2 * ramp + n) * dt
+    blocks = [Block(rf_int * dt, rf=RFTrain(0.0, dt, hard_pulse(rf_int, dt, np.pi / 2, gamma))),
+              Block(100 * dt, gx=trap_of_area(kx_pre, 10 * dt, 80 * dt),
+                    gy=trap_of_area(-(n // 2) * dk / gbar, 10 * dt, 80 * dt))]
+    for line in range(n):
+        sign = 1.0 if line % 2 == 0 else -1.0
+        tv, av = [], []
+        if line > 0:  # falling half of the previous blip
+            tv += [0.0, blip_r * dt]
+            av += [blip_amp, 0.0]
+        if line < n - 1:  # rising half of the next blip
+            tv += [dur - blip_r * dt, dur]
+            av += [0.0, blip_amp]
+        gy = PWL(np.array(tv), np.array(av)) if tv else None
+        blocks.append(Block(dur, gx=Trap(sign * g_ro, 0.0, ramp * dt, n * dt, ramp * dt), gy=gy,
+                            adc=ADCWindow(ramp * dt, dt, n)))
+    return blocks
+
+
+def random_blocks(rng, n_blocks: int, p_rf: float = 0.4, p_adc: float = 0.5, g_max: float = 0.03,
+                  b1_max: float = 2e-5):
+    """Random block sequence off any raster: trapezoids, piecewise-linear
+    waveforms (some meeting the next block with a non-zero value), RF trains
+    and ADC windows at random offsets."""
+    blocks = []
+    carry = [0.0, 0.0, 0.0]  # G each axis must start from (continuity)
+    for b in range(n_blocks):
+        dur = rng.uniform(0.2e-3, 2e-3)
+        grads = []
+        nxt = [0.0, 0.0, 0.0]
+        for a in range(3):
+            kind = rng.integers(0, 3) if carry[a] == 0.0 else 2
+            if kind == 0:
+                grads.append(None)
+            elif kind == 1:
+                rise, fall = rng.uniform(0.02, 0.2, 2) * dur
+                flat = rng.uniform(0.0, 0.3) * dur
+                delay = rng.uniform(0.0, dur - rise - flat - fall)
+                grads.append(Trap(rng.uniform(-g_max, g_max), delay, rise, flat, fall))
+            else:
+                m = int(rng.integers(2, 7))
+                ends_at_end = b + 1 < n_blocks and rng.uniform() < 0.5
+                starts_at_0 = carry[a] != 0.0
+                t0 = 0.0 if starts_at_0 else rng.uniform(0.0, 0.3) * dur
+                t1 = dur if ends_at_end else rng.uniform(0.7, 1.0) * dur
+                tv = np.sort(np.concatenate([[t0, t1], rng.uniform(t0, t1, m - 2)]))
+                av = rng.uniform(-g_max, g_max, m)
+                av[0] = carry[a] if starts_at_0 else 0.0
+                av[-1] = av[-1] if ends_at_end else 0.0
+                if ends_at_end:
+                    nxt[a] = av[-1]
+                grads.append(PWL(tv, av))
+        carry = nxt
+        rf = None
+        if rng.uniform() < p_rf:
+            k = int(rng.integers(1, 20))
+            dt = rng.uniform(2e-6, 40e-6)
+            delay = rng.uniform(0.0, max(dur - k * dt, 0.0))
+            if delay + k * dt <= dur:
+                rf = RFTrain(delay, dt, rng.uniform(-b1_max, b1_max, k) + 1j * rng.uniform(-b1_max, b1_max, k))
+        adc = None
+        if rng.uniform() < p_adc:
+            k = int(rng.integers(1, 40))
+            dwell = rng.uniform(3e-6, 30e-6)
+            delay = rng.uniform(0.0, max(dur - (k - 1) * dwell, 0.0))
+            if delay + (k - 1) * dwell <= dur:
+                adc = ADCWindow(delay, dwell, k)
+        blocks.append(Block(dur, *grads, rf=rf, adc=adc))
+    return blocks
