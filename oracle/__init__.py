@@ -41,8 +41,8 @@ def _load():
         P = ctypes.c_void_p
         i64 = ctypes.c_int64
         lib.oracle_simulate.restype = ctypes.c_int
-        lib.oracle_simulate.argtypes = [ctypes.c_double, i64] + [P] * 7 + [i64, P, i64] + [P] * 6 + \
-            [i64, P, ctypes.c_int, ctypes.c_int, P, P]
+        lib.oracle_simulate.argtypes = [ctypes.c_double, i64] + [P] * 10 + [i64, P, P] + [i64, P, i64] + \
+            [P] * 6 + [i64, P, ctypes.c_int, ctypes.c_int, P, P]
         lib.oracle_excite_step.restype = None
         lib.oracle_excite_step.argtypes = [ctypes.c_double, P, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_double, P]
@@ -66,24 +66,37 @@ def _p(a):
 
 def simulate(scanner, phantom, seq, mode: int = MODE_STEP, threads: int | None = None,
              want_m: bool = False):
-    """Signal ``[n_groups, n_adc]`` complex128 (and ``[n, 3]`` final M if asked)."""
+    """Signal ``[n_groups, n_adc]`` complex128, or ``[n_coils, n_groups, n_adc]``
+    when the phantom carries coil sensitivities (and ``[n, 3]`` final M if
+    asked). A phantom with velocities ``vx, vy, vz`` moves as x + v t."""
     lib = _load()
     n = phantom.n
     ng = phantom.n_groups
-    sig = np.zeros((ng, seq.n_adc, 2), dtype=np.float64)
+    sens = getattr(phantom, "sens", None)
+    nc = 0 if sens is None else int(sens.shape[0])
+    sig = np.zeros((max(nc, 1), ng, seq.n_adc, 2), dtype=np.float64)
     m = np.zeros((n, 3), dtype=np.float64) if want_m else None
     f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)  # noqa: E731
     f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)  # noqa: E731
     arrs = [f32(getattr(phantom, k)) for k in ("x", "y", "z", "pd", "t1", "t2", "dw")]
+    vel = [None] * 3
+    if getattr(phantom, "vx", None) is not None:
+        vel = [f32(getattr(phantom, k)) for k in ("vx", "vy", "vz")]
+    sr = si = None
+    if nc:
+        sr, si = f32(np.real(sens)), f32(np.imag(sens))
     goff = None if phantom.group_off is None else np.ascontiguousarray(phantom.group_off, np.int64)
     sq = [f64(seq.t), f64(seq.gx), f64(seq.gy), f64(seq.gz), f64(seq.b1.real), f64(seq.b1.imag)]
     adc = np.ascontiguousarray(seq.adc_idx, dtype=np.int64)
-    rc = lib.oracle_simulate(float(scanner.gamma), n, *[_p(a) for a in arrs], ng, _p(goff),
+    rc = lib.oracle_simulate(float(scanner.gamma), n, *[_p(a) for a in arrs], *[_p(a) for a in vel],
+                             nc, _p(sr), _p(si), ng, _p(goff),
                              seq.n_t, *[_p(a) for a in sq], seq.n_adc, _p(adc), int(mode),
                              int(threads or default_threads()), _p(sig), _p(m))
     if rc != 0:
         raise RuntimeError(f"oracle_simulate failed: {rc}")
     s = sig[..., 0] + 1j * sig[..., 1]
+    if not nc:
+        s = s[0]
     return (s, m) if want_m else s
 
 

@@ -55,12 +55,34 @@ class Phantom:
     dw: np.ndarray
     group_off: Optional[np.ndarray] = None
     name: str = "phantom"
+    # motion: velocities (m/s), position x + v t; None for static spins
+    vx: Optional[np.ndarray] = None
+    vy: Optional[np.ndarray] = None
+    vz: Optional[np.ndarray] = None
+    # receive coils: complex sensitivities [n_coils, n] (complex64); None: plain sum
+    sens: Optional[np.ndarray] = None
 
     def __post_init__(self):
         for k in ("x", "y", "z", "pd", "t1", "t2", "dw"):
             setattr(self, k, np.ascontiguousarray(getattr(self, k), dtype=np.float32))
         if self.group_off is not None:
             self.group_off = np.ascontiguousarray(self.group_off, dtype=np.int64)
+        if (self.vx is None) != (self.vy is None) or (self.vx is None) != (self.vz is None):
+            raise ValueError("give all three velocity components or none")
+        if self.vx is not None:
+            for k in ("vx", "vy", "vz"):
+                setattr(self, k, np.ascontiguousarray(getattr(self, k), dtype=np.float32))
+        if self.sens is not None:
+            self.sens = np.ascontiguousarray(np.atleast_2d(self.sens), dtype=np.complex64)
+
+    def _extra(self, idx):
+        """Motion and coil fields of the spins ``idx``."""
+        kw = {}
+        if self.vx is not None:
+            kw.update(vx=self.vx[idx], vy=self.vy[idx], vz=self.vz[idx])
+        if self.sens is not None:
+            kw["sens"] = self.sens[:, idx]
+        return kw
 
     @property
     def n(self) -> int:
@@ -75,7 +97,7 @@ class Phantom:
         idx = np.asarray(idx)
         return Phantom(self.x[idx], self.y[idx], self.z[idx], self.pd[idx],
                        self.t1[idx], self.t2[idx], self.dw[idx], None,
-                       name=f"{self.name}[subset {idx.shape[0]}]")
+                       name=f"{self.name}[subset {idx.shape[0]}]", **self._extra(idx))
 
     def groups(self, g0: int, g1: int) -> "Phantom":
         """Groups ``g0..g1-1`` with their own offsets."""
@@ -84,12 +106,28 @@ class Phantom:
         sl = slice(s0, s1)
         return Phantom(self.x[sl], self.y[sl], self.z[sl], self.pd[sl], self.t1[sl],
                        self.t2[sl], self.dw[sl], off[g0:g1 + 1] - s0,
-                       name=f"{self.name}[groups {g0}:{g1}]")
+                       name=f"{self.name}[groups {g0}:{g1}]", **self._extra(sl))
 
     def concat(self, other: "Phantom") -> "Phantom":
+        kw = {}
+        if self.vx is not None or other.vx is not None:
+            v = lambda p, k: getattr(p, k) if p.vx is not None else np.zeros(p.n, np.float32)  # noqa: E731
+            kw = {k: np.concatenate([v(self, k), v(other, k)]) for k in ("vx", "vy", "vz")}
+        if self.sens is not None or other.sens is not None:
+            if self.sens is None or other.sens is None or self.sens.shape[0] != other.sens.shape[0]:
+                raise ValueError("both phantoms need sensitivities for the same coils")
+            kw["sens"] = np.concatenate([self.sens, other.sens], axis=1)
         return Phantom(*(np.concatenate([getattr(self, k), getattr(other, k)])
                          for k in ("x", "y", "z", "pd", "t1", "t2", "dw")),
-                       name=f"{self.name}+{other.name}")
+                       name=f"{self.name}+{other.name}", **kw)
+
+    @property
+    def n_coils(self) -> int:
+        return 0 if self.sens is None else int(self.sens.shape[0])
+
+    @property
+    def moving(self) -> bool:
+        return self.vx is not None
 
 
 @dataclass
@@ -829,3 +867,39 @@ def random_blocks(rng, n_blocks: int, p_rf: float = 0.4, p_adc: float = 0.5, g_m
                 adc = ADCWindow(delay, dwell, k)
         blocks.append(Block(dur, *grads, rf=rf, adc=adc))
     return blocks
+
+
+# --------------------------------------------------------------------------
+# Motion and receive coils
+# --------------------------------------------------------------------------
+def with_velocity(ph: Phantom, v=(0.0, 0.1, 0.0), spread: float = 0.0, seed: int = 0) -> Phantom:
+    """The phantom moving with velocity ``v`` (m/s), position x + v t; the
+    paper's motion example is u_y = v_y t with v_y = 0.1 m/s. ``spread``
+    adds a seeded per-spin Gaussian velocity of that standard deviation."""
+    rng = np.random.default_rng(seed)
+    vel = [np.full(ph.n, float(c)) + (spread * rng.normal(size=ph.n) if spread else 0.0) for c in v]
+    out = Phantom(ph.x, ph.y, ph.z, ph.pd, ph.t1, ph.t2, ph.dw, ph.group_off, name=f"{ph.name}+motion",
+                  vx=vel[0], vy=vel[1], vz=vel[2], sens=ph.sens)
+    return out
+
+
+def coil_sensitivities(ph: Phantom, n_coils: int = 8, radius: float = 0.16, width: float = 0.12) -> np.ndarray:
+    """Synthetic smooth receive sensitivities [n_coils, n] (complex64): coils
+    evenly spaced on a circle of ``radius`` in the xy plane around the FOV,
+    magnitude falling off with distance as 1 / (1 + (d / width)^2), phase
+    turning with the angle seen from the coil (a loop-coil-like field)."""
+    ang = 2 * np.pi * np.arange(n_coils) / n_coils
+    cx, cy = radius * np.cos(ang), radius * np.sin(ang)
+    dx = ph.x.astype(np.float64)[None, :] - cx[:, None]
+    dy = ph.y.astype(np.float64)[None, :] - cy[:, None]
+    dz = ph.z.astype(np.float64)[None, :]
+    d2 = dx * dx + dy * dy + dz * dz
+    mag = 1.0 / (1.0 + d2 / width ** 2)
+    phase = np.arctan2(dy, dx) - ang[:, None]
+    return (mag * np.exp(1j * phase)).astype(np.complex64)
+
+
+def with_coils(ph: Phantom, n_coils: int = 8, **kw) -> Phantom:
+    out = Phantom(ph.x, ph.y, ph.z, ph.pd, ph.t1, ph.t2, ph.dw, ph.group_off, name=f"{ph.name}+{n_coils}coils",
+                  vx=ph.vx, vy=ph.vy, vz=ph.vz, sens=coil_sensitivities(ph, n_coils, **kw))
+    return out
