@@ -83,6 +83,13 @@ typedef struct {
     int64_t n_groups;         /* >= 1 */
     const int64_t *group_off; /* host memory always: n_groups + 1 non-decreasing offsets
                                  from 0 to n; NULL means one group */
+    /* Motion (section "Overview": the phantom's displacement field): NULL
+     * for static spins, or all three velocities (m/s, finite), with the
+     * spin at (x, y, z) + v t at sequence time t. The field of an interval is
+     * the mean of its end-point fields with the position updated to each end
+     * point (the trapezoidal rule of the precession phase); ADC samples are
+     * then evaluated one by one, never by a linear recurrence. */
+    const float *vx, *vy, *vz;
 } koma_phantom;
 
 /* Discretised sequence (host memory). */

@@ -63,7 +63,23 @@ struct Plan {
     std::vector<Chunk> chunks;
     int64_t max_cols = 0;
     double gamma = 0;
+    bool moving = false;  // spins carry velocities
 };
+
+// Phantom arrays: x, y, z, pd, t1, t2, dw, then vx, vy, vz for moving spins.
+constexpr int kPhStatic = 7, kPhArrays = 10;
+
+static inline int ph_arrays(const koma_phantom *p) { return p->vx ? kPhArrays : kPhStatic; }
+
+static inline void ph_sources(const koma_phantom *p, const float *src[kPhArrays]) {
+    const float *all[kPhArrays] = {p->x, p->y, p->z, p->pd, p->t1, p->t2, p->dw, p->vx, p->vy, p->vz};
+    for (int i = 0; i < kPhArrays; ++i) src[i] = all[i];
+}
+
+static inline PhantomDev ph_dev(const float *const d[kPhArrays], bool moving) {
+    return PhantomDev{d[0], d[1], d[2], d[3], d[4], d[5], d[6], moving ? d[7] : nullptr,
+                      moving ? d[8] : nullptr, moving ? d[9] : nullptr};
+}
 
 struct DevMem {  // request-owned or context-scratch device allocation
     void *p = nullptr;
@@ -104,7 +120,7 @@ struct koma_ctx {
     size_t pool_bytes = 0;
     // scratch reused by koma_simulate (grow-only)
     DevMem s_ev, s_st, s_tiles, s_blocks, s_toff, s_boff, s_inl, s_def, s_snap, s_pa, s_pb, s_sig,
-        s_mxy, s_mz, s_flags, s_mf, s_ph[7];
+        s_mxy, s_mz, s_flags, s_mf, s_ph[kPhArrays];
 };
 
 struct koma_req {
@@ -112,7 +128,7 @@ struct koma_req {
     Plan plan;
     bool fp64 = false;
     // request-owned device memory
-    DevMem ph[7], ev, st, tiles, blocks, toff, boff, inl, def, snap, pa, pb, sig, mxy, mz;
+    DevMem ph[kPhArrays], ev, st, tiles, blocks, toff, boff, inl, def, snap, pa, pb, sig, mxy, mz;
     hipStream_t last_stream = nullptr;  // stream of the last enqueued work
     int64_t cursor = 0;
     size_t next_chunk = 0;
@@ -304,6 +320,8 @@ static koma_status check_phantom_shape(koma_ctx *ctx, const koma_phantom *p) {
     if (p->n < 1) return fail(ctx, KOMA_E_PHANTOM, "phantom needs n >= 1 spins");
     if (!p->x || !p->y || !p->z || !p->pd || !p->t1 || !p->t2 || !p->dw)
         return fail(ctx, KOMA_E_ARG, "phantom array is NULL");
+    if ((p->vx || p->vy || p->vz) && !(p->vx && p->vy && p->vz))
+        return fail(ctx, KOMA_E_ARG, "give all three velocity arrays or none");
     if (p->n_groups < 1) return fail(ctx, KOMA_E_PHANTOM, "n_groups must be >= 1");
     if (!p->group_off) {
         if (p->n_groups != 1) return fail(ctx, KOMA_E_PHANTOM, "group_off is NULL but n_groups != 1");
@@ -326,6 +344,10 @@ static koma_status check_phantom_values_host(koma_ctx *ctx, const koma_phantom *
         if (!(p->t1[i] > 0) || !(p->t2[i] > 0))
             return fail(ctx, KOMA_E_PHANTOM, "T1/T2 must be > 0 (or +inf) at spin %lld", (long long)i);
     }
+    if (p->vx)
+        for (int64_t i = 0; i < p->n; ++i)
+            if (!std::isfinite(p->vx[i]) || !std::isfinite(p->vy[i]) || !std::isfinite(p->vz[i]))
+                return fail(ctx, KOMA_E_PHANTOM, "non-finite velocity at spin %lld", (long long)i);
     return KOMA_OK;
 }
 
@@ -416,6 +438,7 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     P.per_wg = 1;
     P.max_cols = 0;
     P.gamma = gamma;
+    P.moving = ph->vx != nullptr;
     P.n_spins = ph->n;
     P.n_groups = ph->n_groups;
     P.n_adc = q->n_adc;
@@ -460,7 +483,10 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
         nonfinite |= nonfinite_bit(r) | nonfinite_bit(i);
         return r != 0.0 || i != 0.0;
     };
-    const int defer_min = cfg.defer_min_adc;
+    // moving spins: no sample-parallel deferral and no sample recurrences
+    // (their phase is not linear in the sample index)
+    const int defer_min = P.moving ? -1 : cfg.defer_min_adc;
+    const bool moving = P.moving;
 
     P.def_k.reserve((size_t)q->n_adc);
     const double *__restrict T = q->t;
@@ -475,16 +501,33 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
         while (b < n_int && !is_rf(b)) ++b;
         size_t ns = 0;
         double K[3] = {0, 0, 0};
+        double K1[3] = {0, 0, 0};  // first moments gamma_bar sum(mean(G t) dt), moving spins only
         const double ta = T[a];
         for (int64_t p = a; p <= b; ++p) {
             nonfinite |= nonfinite_bit(T[p]) | nonfinite_bit(GX[p]) | nonfinite_bit(GY[p]) | nonfinite_bit(GZ[p]);
             if (adc_pos[p] >= 0) {
-                smp_k[ns] = adc_pos[p];
-                smp_v[0][ns] = K[0];
-                smp_v[1][ns] = K[1];
-                smp_v[2][ns] = K[2];
-                smp_v[3][ns] = T[p] - ta;
-                ++ns;
+                if (moving) {
+                    Event e{};
+                    e.kind = EV_ADC;
+                    e.a0 = (int32_t)P.inl_k.size();
+                    e.count = 1;
+                    e.d[0] = K[0];
+                    e.d[1] = K[1];
+                    e.d[2] = K[2];
+                    e.d[3] = T[p] - ta;
+                    e.c64[0] = K1[0];
+                    e.c64[1] = K1[1];
+                    e.c64[2] = K1[2];
+                    P.inl_k.push_back(adc_pos[p]);
+                    P.ev.push_back(e);
+                } else {
+                    smp_k[ns] = adc_pos[p];
+                    smp_v[0][ns] = K[0];
+                    smp_v[1][ns] = K[1];
+                    smp_v[2][ns] = K[2];
+                    smp_v[3][ns] = T[p] - ta;
+                    ++ns;
+                }
             }
             if (p < b) {
                 disorder |= !(T[p + 1] > T[p]);
@@ -492,6 +535,12 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
                 K[0] += (GX[p] + GX[p + 1]) * hdt;
                 K[1] += (GY[p] + GY[p + 1]) * hdt;
                 K[2] += (GZ[p] + GZ[p + 1]) * hdt;
+                if (moving) {
+                    const double t0 = T[p], t1 = T[p + 1];
+                    K1[0] += (GX[p] * t0 + GX[p + 1] * t1) * hdt;
+                    K1[1] += (GY[p] * t0 + GY[p + 1] * t1) * hdt;
+                    K1[2] += (GZ[p] * t0 + GZ[p + 1] * t1) * hdt;
+                }
             }
         }
         samples.n = ns;
@@ -538,6 +587,9 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
             e.d[1] = K[1];
             e.d[2] = K[2];
             e.d[3] = q->t[b] - q->t[a];
+            e.d[4] = K1[0];
+            e.d[5] = K1[1];
+            e.d[6] = K1[2];
             P.ev.push_back(e);
             ++P.n_runs;
         }
@@ -562,7 +614,19 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
             }
             e.b1sq_f32 = (double)e.f[3] * (double)e.f[3] + (double)e.f[4] * (double)e.f[4];
             e.rot = -1;
-            if (v[0] == 0.0 && v[1] == 0.0 && v[2] == 0.0) {
+            // moving spins: the interval mean of G(t) t, the velocity's share of Bz
+            double gt[3] = {0, 0, 0};
+            if (moving) {
+                const double t0 = q->t[b], t1 = q->t[b + 1];
+                gt[0] = 0.5 * (q->gx[b] * t0 + q->gx[b + 1] * t1);
+                gt[1] = 0.5 * (q->gy[b] * t0 + q->gy[b + 1] * t1);
+                gt[2] = 0.5 * (q->gz[b] * t0 + q->gz[b + 1] * t1);
+                for (int c = 0; c < 3; ++c) {
+                    e.c64[c] = gt[c];
+                    e.c32[c] = (float)gt[c];
+                }
+            }
+            if (v[0] == 0.0 && v[1] == 0.0 && v[2] == 0.0 && gt[0] == 0.0 && gt[1] == 0.0 && gt[2] == 0.0) {
                 // zero gradient: for Bz = 0 the field is (b1, 0) for every spin;
                 // alpha = cos(phi/2), beta = -i (b1/|b1|) sin(phi/2), phi = -gamma |b1| dt
                 const double nb = std::sqrt(v[5]);
@@ -667,7 +731,7 @@ static size_t plan_footprint(const Plan &P, bool fp64, bool with_state, bool wit
     b += (size_t)P.blocks.size() * (size_t)P.max_cols * 16;       // cross-workgroup partials
     b += (size_t)P.n_groups * (size_t)P.n_adc * 16;               // signal
     if (with_state) b += n_pad * 3 * r;
-    if (with_phantom) b += (size_t)P.n_spins * 7 * 4;
+    if (with_phantom) b += (size_t)P.n_spins * (P.moving ? kPhArrays : kPhStatic) * 4;
     return b;
 }
 
@@ -750,7 +814,7 @@ static koma_status run_seq(koma_ctx *ctx, const Plan &P, bool fp64, const Bufs &
     a.snap = B.snap;
     a.pa = B.pa;
     a.n_inline = (int64_t)P.inl_k.size();
-    LAUNCH(ctx, K_SEQ, P.n_tiles * kWave * (e1 - e0), s, launch_seq(fp64, a, s));
+    LAUNCH(ctx, K_SEQ, P.n_tiles * kWave * (e1 - e0), s, launch_seq(fp64, P.moving, a, s));
     return KOMA_OK;
 }
 
@@ -813,7 +877,7 @@ static koma_status validate_device_phantom(koma_ctx *ctx, const PhantomDev &ph, 
     HIPCHK(ctx, hipStreamSynchronize(s));
     int32_t bad = 0;
     for (int32_t v : h) bad |= v;
-    if (bad & 1) return fail(ctx, KOMA_E_PHANTOM, "non-finite position, dw or PD in the phantom");
+    if (bad & 1) return fail(ctx, KOMA_E_PHANTOM, "non-finite position, velocity, dw or PD in the phantom");
     if (bad & 2) return fail(ctx, KOMA_E_PHANTOM, "PD < 0 in the phantom");
     if (bad & 4) return fail(ctx, KOMA_E_PHANTOM, "T1/T2 must be > 0 (or +inf)");
     return KOMA_OK;
@@ -981,18 +1045,20 @@ koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
 
     Bufs B{};
     // phantom
-    const float *src[7] = {ph->x, ph->y, ph->z, ph->pd, ph->t1, ph->t2, ph->dw};
-    const float *dptr[7];
+    const float *src[kPhArrays];
+    ph_sources(ph, src);
+    const float *dptr[kPhArrays] = {};
+    const int n_arr = ph_arrays(ph);
     if (where == KOMA_HOST) {
-        for (int i = 0; i < 7; ++i) {
+        for (int i = 0; i < n_arr; ++i) {
             if ((st = dev_reserve(ctx, ctx->s_ph[i], (size_t)ph->n * 4)) != KOMA_OK) return st;
             HIPCHK(ctx, hipMemcpyAsync(ctx->s_ph[i].p, src[i], (size_t)ph->n * 4, hipMemcpyHostToDevice, s));
             dptr[i] = (const float *)ctx->s_ph[i].p;
         }
     } else {
-        for (int i = 0; i < 7; ++i) dptr[i] = src[i];
+        for (int i = 0; i < n_arr; ++i) dptr[i] = src[i];
     }
-    B.ph = PhantomDev{dptr[0], dptr[1], dptr[2], dptr[3], dptr[4], dptr[5], dptr[6]};
+    B.ph = ph_dev(dptr, P.moving);
 
     // packed tables: one pinned staging buffer, one upload
     struct Part {
@@ -1085,7 +1151,7 @@ koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
     HIPCHK(ctx, hipStreamSynchronize(s));
     if (dev_check && *ctx->h_flag) {
         const int32_t bad = *ctx->h_flag;
-        if (bad & 1) return fail(ctx, KOMA_E_PHANTOM, "non-finite position, dw or PD in the phantom");
+        if (bad & 1) return fail(ctx, KOMA_E_PHANTOM, "non-finite position, velocity, dw or PD in the phantom");
         if (bad & 2) return fail(ctx, KOMA_E_PHANTOM, "PD < 0 in the phantom");
         return fail(ctx, KOMA_E_PHANTOM, "T1/T2 must be > 0 (or +inf)");
     }
@@ -1096,9 +1162,9 @@ koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
 
 static Bufs req_bufs(koma_req *q) {
     Bufs B{};
-    B.ph = PhantomDev{(const float *)q->ph[0].p, (const float *)q->ph[1].p, (const float *)q->ph[2].p,
-                      (const float *)q->ph[3].p, (const float *)q->ph[4].p, (const float *)q->ph[5].p,
-                      (const float *)q->ph[6].p};
+    const float *d[kPhArrays];
+    for (int i = 0; i < kPhArrays; ++i) d[i] = (const float *)q->ph[i].p;
+    B.ph = ph_dev(d, q->plan.moving);
     B.ev = (const Event *)q->ev.p;
     B.st = (const Stretch *)q->st.p;
     B.tiles = (const Tile *)q->tiles.p;
@@ -1160,8 +1226,9 @@ koma_status koma_req_open(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
         delete q;
         return e;
     };
-    const float *src[7] = {ph->x, ph->y, ph->z, ph->pd, ph->t1, ph->t2, ph->dw};
-    for (int i = 0; i < 7; ++i) {
+    const float *src[kPhArrays];
+    ph_sources(ph, src);
+    for (int i = 0; i < ph_arrays(ph); ++i) {
         if ((st = pool_get(ctx, q->ph[i], (size_t)ph->n * 4)) != KOMA_OK) return bail(st);
         hipError_t e = hipMemcpyAsync(q->ph[i].p, src[i], (size_t)ph->n * 4,
                                       where == KOMA_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s);

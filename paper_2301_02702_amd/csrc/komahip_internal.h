@@ -35,8 +35,10 @@ struct alignas(16) Event {
     //        hs = -gamma dt / (4 pi) (half rotation angle per tesla, in turns), dt (s)
     float f[8];
     // EV_RF: the same eight values in FP64.
-    // EV_END: kx, ky, kz (cycles/m), tau (s) of the block end.
-    // EV_ADC: kx, ky, kz, tau of the first sample, then dkx, dky, dkz, dtau.
+    // EV_END: kx, ky, kz (cycles/m), tau (s) of the block end; for moving
+    //         spins then the first moments k1x, k1y, k1z (cycles s/m).
+    // EV_ADC: kx, ky, kz, tau of the first sample, then dkx, dky, dkz, dtau
+    //         (for moving spins count = 1 and the first moments are in c64).
     double d[8];
     // EV_RF: exact |b1|^2 of the FP32-rounded b1 (f[3], f[4]) for the FP32 kernel.
     double b1sq_f32;
@@ -47,6 +49,8 @@ struct alignas(16) Event {
     //   Mxy_re' = c[0] Mz + c[1] Mxy_re + c[2] Mxy_im
     //   Mxy_im' = c[3] Mz + c[4] Mxy_im + c[5] Mxy_re
     //   Mz'     = c[6] Mz + c[7] Mxy_re + c[8] Mxy_im
+    // Moving spins, EV_RF with rot < 0: c32/c64[0..2] = interval mean of
+    // G(t) t (T s/m); EV_ADC: c64[0..2] = first moments k1 of the sample.
     float c32[12];   // 9 used (rounded for the FP32 kernel)
     double c64[10];  // 9 used
 };
@@ -81,6 +85,7 @@ struct alignas(16) Block {
 
 struct PhantomDev {
     const float *x, *y, *z, *pd, *t1, *t2, *dw;
+    const float *vx, *vy, *vz;  // nullptr: static spins
 };
 
 constexpr int kWave = 64;
@@ -133,7 +138,7 @@ struct ReduceArgs {  // cross-workgroup sums into the signal
 
 // Launchers (komahip_kernels.hip). All asynchronous on `stream`.
 namespace koma {
-int launch_seq(bool fp64, const SeqArgs &a, void *stream);
+int launch_seq(bool fp64, bool moving, const SeqArgs &a, void *stream);
 int launch_par(bool fp64, int spins_per_lane, const ParArgs &a, void *stream);
 int launch_reduce(bool part_fp64, const ReduceArgs &a, void *stream);
 int launch_validate(const PhantomDev &ph, int64_t n, int32_t *flags, void *stream);

@@ -106,13 +106,16 @@ template <class R>
 struct SpinP {
     R x, y, z, pd, r1, r2, bz0;  // bz0 = dw / gamma (T)
     double xd, yd, zd, f;        // FP64 copies for block phases, f = dw / 2 pi (Hz)
+    R vx, vy, vz;                // velocity (moving spins; 0 otherwise)
+    double vxd, vyd, vzd;
 };
 
-template <class R>
+template <class R, bool MOV>
 __device__ __forceinline__ SpinP<R> load_spin(const PhantomDev &ph, const Tile &t, int lane,
                                               double inv_gamma) {
     SpinP<R> s;
     float x = 0.f, y = 0.f, z = 0.f, pd = 0.f, t1 = __builtin_inff(), t2 = __builtin_inff(), dw = 0.f;
+    float vx = 0.f, vy = 0.f, vz = 0.f;
     if (lane < t.count) {
         const int64_t i = t.spin0 + lane;
         x = ph.x[i];
@@ -122,7 +125,18 @@ __device__ __forceinline__ SpinP<R> load_spin(const PhantomDev &ph, const Tile &
         t1 = ph.t1[i];
         t2 = ph.t2[i];
         dw = ph.dw[i];
+        if (MOV) {
+            vx = ph.vx[i];
+            vy = ph.vy[i];
+            vz = ph.vz[i];
+        }
     }
+    s.vx = vx;
+    s.vy = vy;
+    s.vz = vz;
+    s.vxd = vx;
+    s.vyd = vy;
+    s.vzd = vz;
     s.x = x;
     s.y = y;
     s.z = z;
@@ -251,6 +265,13 @@ template <class R>
 __device__ __forceinline__ double block_phase(const SpinP<R> &s, const double *k) {
     return -fma(s.xd, k[0], fma(s.yd, k[1], fma(s.zd, k[2], s.f * k[3])));
 }
+// The same for a moving spin, x(t) = x + v t: -(x.K + v.K1 + f tau), with K1
+// the first moment (cycles s/m) accumulated by the same trapezoidal rule.
+template <class R>
+__device__ __forceinline__ double block_phase(const SpinP<R> &s, const double *k, const double *k1) {
+    return -fma(s.xd, k[0], fma(s.yd, k[1], fma(s.zd, k[2],
+                fma(s.vxd, k1[0], fma(s.vyd, k1[1], fma(s.vzd, k1[2], s.f * k[3]))))));
+}
 
 // exp(i*2*pi*theta) * exp(-tau * r2) as a complex factor
 template <class P>
@@ -266,14 +287,18 @@ __device__ __forceinline__ C2<typename P::R> block_factor(const SpinP<typename P
 
 // One excitation interval (Eq. Rot_exc) followed by relaxation with the
 // cached eps = 1 - exp(-dt/T) (applied as M - eps*M, exact in the factor).
-template <class P>
+// For moving spins gt holds the interval mean of G(t) t: Bz gains v . gt.
+template <class P, bool MOV>
 __device__ __forceinline__ void excite_relax(const SpinP<typename P::R> &s, const typename P::R *q,
-                                             double b1sq_exact, typename P::R eps1, typename P::R eps2,
+                                             const typename P::R *gt, double b1sq_exact,
+                                             typename P::R eps1, typename P::R eps2,
                                              typename P::R &mr, typename P::R &mi,
                                              typename P::R &mz) {
     using R = typename P::R;
     const R gx = q[0], gy = q[1], gz = q[2], b1r = q[3], b1i = q[4], b1sq = q[5], hs = q[6];
-    const R bz = fma(s.x, gx, fma(s.y, gy, fma(s.z, gz, s.bz0)));
+    R bz0 = s.bz0;
+    if (MOV) bz0 = fma(s.vx, gt[0], fma(s.vy, gt[1], fma(s.vz, gt[2], bz0)));
+    const R bz = fma(s.x, gx, fma(s.y, gy, fma(s.z, gz, bz0)));
     const R nb2 = fma(bz, bz, b1sq);
     // |B| = 0 (possible only if |b1|^2 underflows) leaves the spin unrotated
     const R inv = nb2 > R(0) ? P::rsq(nb2) : R(0);
@@ -350,7 +375,7 @@ struct EvL {  // view of one staged event
     }
 };
 
-template <class P>
+template <class P, bool MOV>
 __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
     using R = typename P::R;
     using R2 = typename P::R2;
@@ -368,7 +393,7 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
         T.count = 0;
         T.group = 0;
     }
-    const SpinP<R> s = load_spin<R>(a.ph, T, lane, a.inv_gamma);
+    const SpinP<R> s = load_spin<R, MOV>(a.ph, T, lane, a.inv_gamma);
     const int64_t n_pad = a.n_tiles * kWave;
     const int64_t pidx = tile * kWave + lane;
 
@@ -416,18 +441,37 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
                     R q[7];
 #pragma unroll
                     for (int i = 0; i < 7; ++i) q[i] = sizeof(R) == 4 ? R(ev.f(i)) : R(ev.d(i));
+                    R gt[3] = {R(0), R(0), R(0)};
+                    if (MOV && ev.rot() < 0) {  // (rot >= 0: G and G t are zero on the interval)
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) gt[i] = sizeof(R) == 4 ? R(ev.c32(i)) : R(ev.c64(i));
+                    }
                     // |b1|^2 of exactly the b1 values the precision uses
                     const double b1sq = sizeof(R) == 4 ? ev.b1sq() : ev.d(5);
-                    excite_relax<P>(s, q, b1sq, eps1, eps2, mr, mi, mz);
+                    excite_relax<P, MOV>(s, q, gt, b1sq, eps1, eps2, mr, mi, mz);
                 }
             } else if (kind == EV_END) {
                 const double k4[4] = {ev.d(0), ev.d(1), ev.d(2), ev.d(3)};
                 const double tau = k4[3];
-                C2<R> f = block_factor<P>(s, block_phase(s, k4), tau);
+                double th;
+                if (MOV) {
+                    const double k1[3] = {ev.d(4), ev.d(5), ev.d(6)};
+                    th = block_phase(s, k4, k1);
+                } else {
+                    th = block_phase(s, k4);
+                }
+                C2<R> f = block_factor<P>(s, th, tau);
                 C2<R> m = cmul(C2<R>{mr, mi}, f);
                 mr = m.re;
                 mi = m.im;
                 mz = s.pd + (mz - s.pd) * P::exp_neg(R(tau) * s.r1);
+            } else if (MOV && kind == EV_ADC) {  // one sample, first moments in c64
+                const double k0[4] = {ev.d(0), ev.d(1), ev.d(2), ev.d(3)};
+                const double k1[3] = {ev.c64(0), ev.c64(1), ev.c64(2)};
+                const C2<R> c = cmul(C2<R>{mr, mi}, block_factor<P>(s, block_phase(s, k0, k1), k0[3]));
+                const R sr = wave_allsum(c.re);
+                const R si = wave_allsum(c.im);
+                if (lane == 0) reinterpret_cast<R2 *>(a.pa)[tile * a.n_inline + ev.a0()] = R2{sr, si};
             } else if (kind == EV_ADC) {
                 const double k0[4] = {ev.d(0), ev.d(1), ev.d(2), ev.d(3)};
                 const double dk[4] = {ev.d(4), ev.d(5), ev.d(6), ev.d(7)};
@@ -609,7 +653,8 @@ __global__ __launch_bounds__(kWG) void k_export(const Tile *tiles, int64_t n_til
 // ---------------------------------------------------------------- k_validate
 
 // Per-workgroup flags of invalid phantom values (device-resident phantoms):
-// bit 0 non-finite x, y, z, dw or PD; bit 1 PD < 0; bit 2 T1 or T2 <= 0 or NaN.
+// bit 0 non-finite x, y, z, dw, PD or velocity; bit 1 PD < 0; bit 2 T1 or T2
+// <= 0 or NaN.
 __global__ __launch_bounds__(kWG) void k_validate(PhantomDev ph, int64_t n, int32_t *flags) {
     __shared__ int32_t f[kWG];
     const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
@@ -620,6 +665,7 @@ __global__ __launch_bounds__(kWG) void k_validate(PhantomDev ph, int64_t n, int3
         if (!isfinite(x) || !isfinite(y) || !isfinite(z) || !isfinite(dw) || !isfinite(pd)) bad |= 1;
         if (pd < 0.f) bad |= 2;
         if (!(t1 > 0.f) || !(t2 > 0.f)) bad |= 4;
+        if (ph.vx && (!isfinite(ph.vx[i]) || !isfinite(ph.vy[i]) || !isfinite(ph.vz[i]))) bad |= 1;
     }
     f[threadIdx.x] = bad;
     __syncthreads();
@@ -655,13 +701,23 @@ __global__ __launch_bounds__(kWG) void k_commit(const int32_t *flag, const doubl
 
 static int check_launch() { return hipGetLastError() == hipSuccess ? 0 : -1; }
 
-int launch_seq(bool fp64, const SeqArgs &a, void *stream) {
+int launch_seq(bool fp64, bool moving, const SeqArgs &a, void *stream) {
     if (a.n_tiles <= 0 || a.e1 <= a.e0) return 0;
+    // moving spins need all three velocity arrays (checked on the host)
+    if (moving && (!a.ph.vx || !a.ph.vy || !a.ph.vz)) return -1;
     dim3 grid((unsigned)((a.n_tiles + kWavesPerWG - 1) / kWavesPerWG));
-    if (fp64)
-        hipLaunchKernelGGL(k_seq<FP64>, grid, dim3(kWG), 0, (hipStream_t)stream, a);
-    else
-        hipLaunchKernelGGL(k_seq<Mixed>, grid, dim3(kWG), 0, (hipStream_t)stream, a);
+    hipStream_t st = (hipStream_t)stream;
+    if (fp64) {
+        if (moving)
+            hipLaunchKernelGGL((k_seq<FP64, true>), grid, dim3(kWG), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_seq<FP64, false>), grid, dim3(kWG), 0, st, a);
+    } else {
+        if (moving)
+            hipLaunchKernelGGL((k_seq<Mixed, true>), grid, dim3(kWG), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_seq<Mixed, false>), grid, dim3(kWG), 0, st, a);
+    }
     return check_launch();
 }
 

@@ -38,7 +38,7 @@ class koma_scanner(ctypes.Structure):
 class koma_phantom(ctypes.Structure):
     _fields_ = [("n", c_int64), ("x", c_void_p), ("y", c_void_p), ("z", c_void_p), ("pd", c_void_p),
                 ("t1", c_void_p), ("t2", c_void_p), ("dw", c_void_p), ("n_groups", c_int64),
-                ("group_off", c_void_p)]
+                ("group_off", c_void_p), ("vx", c_void_p), ("vy", c_void_p), ("vz", c_void_p)]
 
 
 class koma_sequence(ctypes.Structure):
@@ -174,21 +174,28 @@ class _PhantomArgs:
     """Holds the arrays (numpy host arrays or torch device tensors) alive."""
 
     KEYS = ("x", "y", "z", "pd", "t1", "t2", "dw")
+    VEL = ("vx", "vy", "vz")
 
     def __init__(self, phantom, device: bool):
         self.keep = []
+        get = (lambda k: phantom.get(k)) if isinstance(phantom, dict) else (lambda k: getattr(phantom, k, None))
+        moving = get("vx") is not None
+        keys = self.KEYS + (self.VEL if moving else ())
         if device:
-            arrs = [phantom[k] if isinstance(phantom, dict) else getattr(phantom, k) for k in self.KEYS]
+            arrs = [get(k) for k in keys]
             for a in arrs:
                 if not (hasattr(a, "is_cuda") and a.is_cuda and a.is_contiguous()
                         and str(a.dtype) == "torch.float32"):
                     raise TypeError("device phantom arrays must be contiguous float32 GPU tensors")
-            goff = phantom.get("group_off") if isinstance(phantom, dict) else phantom.group_off
+            goff = get("group_off")
             n = int(arrs[0].numel())
         else:
-            arrs = [np.ascontiguousarray(getattr(phantom, k), dtype=np.float32) for k in self.KEYS]
+            arrs = [np.ascontiguousarray(get(k), dtype=np.float32) for k in keys]
             goff = phantom.group_off
             n = int(arrs[0].shape[0])
+        for a in arrs[1:]:
+            if (a.numel() if device else a.shape[0]) != n:
+                raise ValueError("phantom arrays differ in length")
         self.keep += arrs
         if goff is not None:
             goff = np.ascontiguousarray(goff, dtype=np.int64)
@@ -196,7 +203,8 @@ class _PhantomArgs:
         ng = 1 if goff is None else int(goff.shape[0] - 1)
         self.n_groups = ng
         self.n = n
-        self.c = koma_phantom(n, *[_ptr(a) for a in arrs], ng, _ptr(goff))
+        self.c = koma_phantom(n, *[_ptr(a) for a in arrs[:7]], ng, _ptr(goff),
+                              *([_ptr(a) for a in arrs[7:]] if moving else [None] * 3))
 
 
 class _SeqArgs:
@@ -416,7 +424,8 @@ class Request:
 def device_phantom(phantom, device="cuda:0") -> dict:
     """Copy a workloads.Phantom into float32 GPU tensors (group offsets stay on the host)."""
     import torch
+    keys = _PhantomArgs.KEYS + (_PhantomArgs.VEL if getattr(phantom, "vx", None) is not None else ())
     d = {k: torch.from_numpy(np.ascontiguousarray(getattr(phantom, k), dtype=np.float32)).to(device)
-         for k in _PhantomArgs.KEYS}
+         for k in keys}
     d["group_off"] = phantom.group_off
     return d

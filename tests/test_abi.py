@@ -123,3 +123,32 @@ def test_footprint_counts_snapshots_and_partials(K):
     f_fp64 = K.koma_footprint(ph, seq, K.make_config("fp64"))
     n_pad = 1024 * 64
     assert f_fp64 > f_mixed > n_pad * (8 + 12)  # snapshot + state at least
+
+
+def test_moving_phantom_plans_every_sample_inline(K):
+    sc, ph, seq = W.config(2)
+    ph = ph.subset(np.arange(0, ph.n, 64))
+    info = K.koma_plan_info(sc, W.with_velocity(ph), seq, K.make_config())
+    assert info["n_deferred_adc"] == 0 and info["n_stretches"] == 0 and info["n_snapshots"] == 0
+    assert info["n_inline_adc"] == seq.n_adc
+    # one event per sample, per excitation interval and per block end
+    assert info["n_events"] == seq.n_adc + info["n_rf"] + info["n_runs"]
+    f_static = K.koma_footprint(ph, seq, K.make_config())
+    f_moving = K.koma_footprint(W.with_velocity(ph), seq, K.make_config())
+    assert f_moving > f_static
+
+
+def test_velocity_validation(K):
+    seq = _seq()
+    ph = W.random_spins(np.random.default_rng(0), 10)
+    assert K.koma_plan_info(W.Scanner(), W.with_velocity(ph), seq, K.make_config())["n_spins"] == 10
+    # a partial velocity set is an argument error
+    p = K._PhantomArgs(W.with_velocity(ph), False)
+    p.c.vy = None
+    info = K.koma_req_info()
+    sc = K.make_scanner(W.Scanner())
+    s = K._SeqArgs(seq)
+    cfg = K.make_config()
+    st = K.lib().koma_plan_info(ctypes.byref(sc), ctypes.byref(p.c), ctypes.byref(s.c), ctypes.byref(cfg),
+                                ctypes.byref(info))
+    assert st == -1
