@@ -90,6 +90,14 @@ typedef struct {
      * point (the trapezoidal rule of the precession phase); ADC samples are
      * then evaluated one by one, never by a linear recurrence. */
     const float *vx, *vy, *vz;
+    /* Receive coils (section "Overview": coil sensitivities; section
+     * "Limitations": multiple coils): n_coils = 0 for the plain sum, or
+     * n_coils >= 1 complex sensitivities per spin, sens_re/sens_im laid out
+     * [n_coils][n] (finite; where `where` says). Coil c's signal is the sum
+     * over a group's spins of sens_c * Mxy (unconjugated); a spin's
+     * sensitivity is fixed (it does not follow the motion). At most 1024. */
+    int64_t n_coils;
+    const float *sens_re, *sens_im;
 } koma_phantom;
 
 /* Discretised sequence (host memory). */
@@ -145,7 +153,8 @@ koma_status koma_footprint(const koma_phantom *ph, const koma_sequence *seq,
 /* One whole simulation, synchronous on `hip_stream` (NULL: the context's
  * stream). Phantom arrays, sig and m_final live where `where` says (device
  * pointers must be on the context's device and stay valid until return).
- *   sig:     [n_groups][n_adc][2] doubles (re, im), caller-owned, overwritten.
+ *   sig:     [n_sig][n_groups][n_adc][2] doubles (re, im), n_sig = max(n_coils, 1),
+ *            caller-owned, overwritten.
  *   m_final: NULL or [n][3] doubles (Mx, My, Mz) after the last interval.
  * Nothing is kept after return. */
 koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phantom *ph,
@@ -160,8 +169,8 @@ koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
  * chunk_events) on `hip_stream` without waiting; the signal of every
  * precession block finished so far is summed at the same time. koma_req_done
  * reports whether all events have been enqueued. koma_req_result enqueues
- * the final cross-workgroup sums and copies the signal ([n_groups][n_adc][2]
- * doubles, host memory) back, synchronising `hip_stream`. Requests are
+ * the final cross-workgroup sums and copies the signal ([n_sig][n_groups]
+ * [n_adc][2] doubles, host memory) back, synchronising `hip_stream`. Requests are
  * independent: one request's result does not depend on which other requests
  * run at the same time. All calls on one request use one stream (or the caller
  * orders them); koma_req_close waits for that stream only, and the request's

@@ -64,21 +64,43 @@ struct Plan {
     int64_t max_cols = 0;
     double gamma = 0;
     bool moving = false;  // spins carry velocities
+    int64_t n_coils = 0;  // receive coils (0: plain sums)
+    int64_t n_sig = 1;    // signal planes: max(n_coils, 1)
 };
 
-// Phantom arrays: x, y, z, pd, t1, t2, dw, then vx, vy, vz for moving spins.
-constexpr int kPhStatic = 7, kPhArrays = 10;
+// Phantom arrays: x, y, z, pd, t1, t2, dw ([n] each), then vx, vy, vz ([n],
+// moving spins only), then sens_re, sens_im ([n_coils][n], coils only).
+constexpr int kPhArrays = 12;
+constexpr int64_t kMaxCoils = 1024;
 
-static inline int ph_arrays(const koma_phantom *p) { return p->vx ? kPhArrays : kPhStatic; }
+static inline bool ph_used(const koma_phantom *p, int i) {
+    return i < 7 || (i < 10 ? p->vx != nullptr : p->n_coils > 0);
+}
+static inline size_t ph_bytes(const koma_phantom *p, int i) {
+    return (size_t)p->n * (i < 10 ? 1 : (size_t)p->n_coils) * sizeof(float);
+}
 
 static inline void ph_sources(const koma_phantom *p, const float *src[kPhArrays]) {
-    const float *all[kPhArrays] = {p->x, p->y, p->z, p->pd, p->t1, p->t2, p->dw, p->vx, p->vy, p->vz};
+    const float *all[kPhArrays] = {p->x,  p->y,  p->z,  p->pd, p->t1,      p->t2,
+                                   p->dw, p->vx, p->vy, p->vz, p->sens_re, p->sens_im};
     for (int i = 0; i < kPhArrays; ++i) src[i] = all[i];
 }
 
-static inline PhantomDev ph_dev(const float *const d[kPhArrays], bool moving) {
-    return PhantomDev{d[0], d[1], d[2], d[3], d[4], d[5], d[6], moving ? d[7] : nullptr,
-                      moving ? d[8] : nullptr, moving ? d[9] : nullptr};
+static inline PhantomDev ph_dev(const float *const d[kPhArrays], bool moving, int64_t n, int64_t n_coils) {
+    return PhantomDev{d[0],
+                      d[1],
+                      d[2],
+                      d[3],
+                      d[4],
+                      d[5],
+                      d[6],
+                      moving ? d[7] : nullptr,
+                      moving ? d[8] : nullptr,
+                      moving ? d[9] : nullptr,
+                      n,
+                      n_coils,
+                      n_coils > 0 ? d[10] : nullptr,
+                      n_coils > 0 ? d[11] : nullptr};
 }
 
 struct DevMem {  // request-owned or context-scratch device allocation
@@ -322,6 +344,10 @@ static koma_status check_phantom_shape(koma_ctx *ctx, const koma_phantom *p) {
         return fail(ctx, KOMA_E_ARG, "phantom array is NULL");
     if ((p->vx || p->vy || p->vz) && !(p->vx && p->vy && p->vz))
         return fail(ctx, KOMA_E_ARG, "give all three velocity arrays or none");
+    if (p->n_coils < 0 || p->n_coils > kMaxCoils)
+        return fail(ctx, KOMA_E_ARG, "n_coils must be in [0, %lld]", (long long)kMaxCoils);
+    if (p->n_coils > 0 && (!p->sens_re || !p->sens_im))
+        return fail(ctx, KOMA_E_ARG, "coil sensitivity array is NULL");
     if (p->n_groups < 1) return fail(ctx, KOMA_E_PHANTOM, "n_groups must be >= 1");
     if (!p->group_off) {
         if (p->n_groups != 1) return fail(ctx, KOMA_E_PHANTOM, "group_off is NULL but n_groups != 1");
@@ -348,6 +374,9 @@ static koma_status check_phantom_values_host(koma_ctx *ctx, const koma_phantom *
         for (int64_t i = 0; i < p->n; ++i)
             if (!std::isfinite(p->vx[i]) || !std::isfinite(p->vy[i]) || !std::isfinite(p->vz[i]))
                 return fail(ctx, KOMA_E_PHANTOM, "non-finite velocity at spin %lld", (long long)i);
+    for (int64_t i = 0; i < p->n * p->n_coils; ++i)
+        if (!std::isfinite(p->sens_re[i]) || !std::isfinite(p->sens_im[i]))
+            return fail(ctx, KOMA_E_PHANTOM, "non-finite coil sensitivity at element %lld", (long long)i);
     return KOMA_OK;
 }
 
@@ -439,6 +468,8 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     P.max_cols = 0;
     P.gamma = gamma;
     P.moving = ph->vx != nullptr;
+    P.n_coils = ph->n_coils;
+    P.n_sig = std::max<int64_t>(1, ph->n_coils);
     P.n_spins = ph->n;
     P.n_groups = ph->n_groups;
     P.n_adc = q->n_adc;
@@ -698,7 +729,8 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     // ---- deferred sample chunks, sized by the partial budget
     if (n_st > 0) {
         const int64_t cap_cols = std::max<int64_t>(
-            kStretchMax, (int64_t)(cfg.partial_budget / (size_t)(std::max<int64_t>(n_blocks, 1) * 16)));
+            kStretchMax,
+            (int64_t)(cfg.partial_budget / (size_t)(std::max<int64_t>(n_blocks, 1) * 16 * P.n_sig)));
         int64_t s = 0;
         while (s < n_st) {
             Chunk c;
@@ -727,11 +759,12 @@ static size_t plan_footprint(const Plan &P, bool fp64, bool with_state, bool wit
     b += P.tiles.size() * sizeof(Tile) + P.blocks.size() * sizeof(Block);
     b += (P.tile_off.size() + P.blk_off.size() + P.inl_k.size() + P.def_k.size()) * 4;
     b += (size_t)P.n_slots * n_pad * 2 * r;                       // snapshots
-    b += (size_t)P.n_tiles * P.inl_k.size() * 2 * r;              // inline partials
-    b += (size_t)P.blocks.size() * (size_t)P.max_cols * 16;       // cross-workgroup partials
-    b += (size_t)P.n_groups * (size_t)P.n_adc * 16;               // signal
+    const size_t ns = (size_t)P.n_sig;
+    b += ns * (size_t)P.n_tiles * P.inl_k.size() * 2 * r;              // inline partials
+    b += ns * (size_t)P.blocks.size() * (size_t)P.max_cols * 16;       // cross-workgroup partials
+    b += ns * (size_t)P.n_groups * (size_t)P.n_adc * 16;               // signal
     if (with_state) b += n_pad * 3 * r;
-    if (with_phantom) b += (size_t)P.n_spins * (P.moving ? kPhArrays : kPhStatic) * 4;
+    if (with_phantom) b += (size_t)P.n_spins * (7 + (P.moving ? 3 : 0) + 2 * (size_t)P.n_coils) * 4;
     return b;
 }
 
@@ -841,6 +874,8 @@ static koma_status run_chunk(koma_ctx *ctx, const Plan &P, bool fp64, const Bufs
         LAUNCH(ctx, K_PAR, P.n_tiles * kWave * cols, s, launch_par(fp64, P.spl, a, s));
     }
     ReduceArgs r{};
+    r.n_sig = P.n_sig;
+    r.part_stride = (int64_t)P.blocks.size() * (c.c1 - c.c0);
     r.part = B.pb;
     r.cols = c.c1 - c.c0;
     r.row_off = B.boff;
@@ -848,13 +883,15 @@ static koma_status run_chunk(koma_ctx *ctx, const Plan &P, bool fp64, const Bufs
     r.col_to_adc = B.def + c.c0;
     r.sig = B.sig;
     r.n_adc = P.n_adc;
-    LAUNCH(ctx, K_RED, (int64_t)P.blocks.size() * (c.c1 - c.c0) * 16, s, launch_reduce(true, r, s));
+    LAUNCH(ctx, K_RED, P.n_sig * (int64_t)P.blocks.size() * (c.c1 - c.c0) * 16, s, launch_reduce(true, r, s));
     return KOMA_OK;
 }
 
 static koma_status run_inline_reduce(koma_ctx *ctx, const Plan &P, bool fp64, const Bufs &B, hipStream_t s) {
     if (P.inl_k.empty()) return KOMA_OK;
     ReduceArgs r{};
+    r.n_sig = P.n_sig;
+    r.part_stride = P.n_tiles * (int64_t)P.inl_k.size();
     r.part = B.pa;
     r.cols = (int64_t)P.inl_k.size();
     r.row_off = B.toff;
@@ -862,7 +899,7 @@ static koma_status run_inline_reduce(koma_ctx *ctx, const Plan &P, bool fp64, co
     r.col_to_adc = B.inl;
     r.sig = B.sig;
     r.n_adc = P.n_adc;
-    LAUNCH(ctx, K_RED, P.n_tiles * r.cols * (fp64 ? 16 : 8), s, launch_reduce(fp64, r, s));
+    LAUNCH(ctx, K_RED, P.n_sig * P.n_tiles * r.cols * (fp64 ? 16 : 8), s, launch_reduce(fp64, r, s));
     return KOMA_OK;
 }
 
@@ -880,6 +917,7 @@ static koma_status validate_device_phantom(koma_ctx *ctx, const PhantomDev &ph, 
     if (bad & 1) return fail(ctx, KOMA_E_PHANTOM, "non-finite position, velocity, dw or PD in the phantom");
     if (bad & 2) return fail(ctx, KOMA_E_PHANTOM, "PD < 0 in the phantom");
     if (bad & 4) return fail(ctx, KOMA_E_PHANTOM, "T1/T2 must be > 0 (or +inf)");
+    if (bad & 8) return fail(ctx, KOMA_E_PHANTOM, "non-finite coil sensitivity in the phantom");
     return KOMA_OK;
 }
 
@@ -1048,17 +1086,17 @@ koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
     const float *src[kPhArrays];
     ph_sources(ph, src);
     const float *dptr[kPhArrays] = {};
-    const int n_arr = ph_arrays(ph);
-    if (where == KOMA_HOST) {
-        for (int i = 0; i < n_arr; ++i) {
-            if ((st = dev_reserve(ctx, ctx->s_ph[i], (size_t)ph->n * 4)) != KOMA_OK) return st;
-            HIPCHK(ctx, hipMemcpyAsync(ctx->s_ph[i].p, src[i], (size_t)ph->n * 4, hipMemcpyHostToDevice, s));
+    for (int i = 0; i < kPhArrays; ++i) {
+        if (!ph_used(ph, i)) continue;
+        if (where == KOMA_HOST) {
+            if ((st = dev_reserve(ctx, ctx->s_ph[i], ph_bytes(ph, i))) != KOMA_OK) return st;
+            HIPCHK(ctx, hipMemcpyAsync(ctx->s_ph[i].p, src[i], ph_bytes(ph, i), hipMemcpyHostToDevice, s));
             dptr[i] = (const float *)ctx->s_ph[i].p;
+        } else {
+            dptr[i] = src[i];
         }
-    } else {
-        for (int i = 0; i < n_arr; ++i) dptr[i] = src[i];
     }
-    B.ph = ph_dev(dptr, P.moving);
+    B.ph = ph_dev(dptr, P.moving, ph->n, P.n_coils);
 
     // packed tables: one pinned staging buffer, one upload
     struct Part {
@@ -1115,15 +1153,16 @@ koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
 
     const size_t n_pad = (size_t)P.n_tiles * kWave;
     if ((st = dev_reserve(ctx, ctx->s_snap, (size_t)P.n_slots * n_pad * 2 * r)) != KOMA_OK) return st;
-    if ((st = dev_reserve(ctx, ctx->s_pa, (size_t)P.n_tiles * P.inl_k.size() * 2 * r)) != KOMA_OK) return st;
-    if ((st = dev_reserve(ctx, ctx->s_pb, P.blocks.size() * (size_t)P.max_cols * 16)) != KOMA_OK) return st;
+    const size_t nsig = (size_t)P.n_sig;
+    if ((st = dev_reserve(ctx, ctx->s_pa, nsig * (size_t)P.n_tiles * P.inl_k.size() * 2 * r)) != KOMA_OK) return st;
+    if ((st = dev_reserve(ctx, ctx->s_pb, nsig * P.blocks.size() * (size_t)P.max_cols * 16)) != KOMA_OK) return st;
     const bool store = m_final != nullptr;
     if (store) {
         if ((st = dev_reserve(ctx, ctx->s_mxy, n_pad * 2 * r)) != KOMA_OK) return st;
         if ((st = dev_reserve(ctx, ctx->s_mz, n_pad * r)) != KOMA_OK) return st;
         if ((st = dev_reserve(ctx, ctx->s_mf, (size_t)ph->n * 24)) != KOMA_OK) return st;
     }
-    const size_t sig_n = (size_t)P.n_groups * P.n_adc * 2;  // doubles
+    const size_t sig_n = nsig * (size_t)P.n_groups * P.n_adc * 2;  // doubles
     if ((st = dev_reserve(ctx, ctx->s_sig, sig_n * 8)) != KOMA_OK) return st;
     B.snap = ctx->s_snap.p;
     B.pa = ctx->s_pa.p;
@@ -1153,7 +1192,8 @@ koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
         const int32_t bad = *ctx->h_flag;
         if (bad & 1) return fail(ctx, KOMA_E_PHANTOM, "non-finite position, velocity, dw or PD in the phantom");
         if (bad & 2) return fail(ctx, KOMA_E_PHANTOM, "PD < 0 in the phantom");
-        return fail(ctx, KOMA_E_PHANTOM, "T1/T2 must be > 0 (or +inf)");
+        if (bad & 4) return fail(ctx, KOMA_E_PHANTOM, "T1/T2 must be > 0 (or +inf)");
+        return fail(ctx, KOMA_E_PHANTOM, "non-finite coil sensitivity in the phantom");
     }
     return KOMA_OK;
 }
@@ -1164,7 +1204,7 @@ static Bufs req_bufs(koma_req *q) {
     Bufs B{};
     const float *d[kPhArrays];
     for (int i = 0; i < kPhArrays; ++i) d[i] = (const float *)q->ph[i].p;
-    B.ph = ph_dev(d, q->plan.moving);
+    B.ph = ph_dev(d, q->plan.moving, q->plan.n_spins, q->plan.n_coils);
     B.ev = (const Event *)q->ev.p;
     B.st = (const Stretch *)q->st.p;
     B.tiles = (const Tile *)q->tiles.p;
@@ -1228,9 +1268,10 @@ koma_status koma_req_open(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
     };
     const float *src[kPhArrays];
     ph_sources(ph, src);
-    for (int i = 0; i < ph_arrays(ph); ++i) {
-        if ((st = pool_get(ctx, q->ph[i], (size_t)ph->n * 4)) != KOMA_OK) return bail(st);
-        hipError_t e = hipMemcpyAsync(q->ph[i].p, src[i], (size_t)ph->n * 4,
+    for (int i = 0; i < kPhArrays; ++i) {
+        if (!ph_used(ph, i)) continue;
+        if ((st = pool_get(ctx, q->ph[i], ph_bytes(ph, i))) != KOMA_OK) return bail(st);
+        hipError_t e = hipMemcpyAsync(q->ph[i].p, src[i], ph_bytes(ph, i),
                                       where == KOMA_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return bail(fail(ctx, KOMA_E_DEVICE, "phantom copy: %s", hipGetErrorString(e)));
     }
@@ -1243,9 +1284,10 @@ koma_status koma_req_open(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
     if ((st = pool_upload(ctx, q->inl, P.inl_k, s)) != KOMA_OK) return bail(st);
     if ((st = pool_upload(ctx, q->def, P.def_k, s)) != KOMA_OK) return bail(st);
     if ((st = pool_get(ctx, q->snap, (size_t)P.n_slots * n_pad * 2 * r)) != KOMA_OK) return bail(st);
-    if ((st = pool_get(ctx, q->pa, (size_t)P.n_tiles * P.inl_k.size() * 2 * r)) != KOMA_OK) return bail(st);
-    if ((st = pool_get(ctx, q->pb, P.blocks.size() * (size_t)P.max_cols * 16)) != KOMA_OK) return bail(st);
-    if ((st = pool_get(ctx, q->sig, (size_t)P.n_groups * P.n_adc * 16)) != KOMA_OK) return bail(st);
+    const size_t nsig = (size_t)P.n_sig;
+    if ((st = pool_get(ctx, q->pa, nsig * (size_t)P.n_tiles * P.inl_k.size() * 2 * r)) != KOMA_OK) return bail(st);
+    if ((st = pool_get(ctx, q->pb, nsig * P.blocks.size() * (size_t)P.max_cols * 16)) != KOMA_OK) return bail(st);
+    if ((st = pool_get(ctx, q->sig, nsig * (size_t)P.n_groups * P.n_adc * 16)) != KOMA_OK) return bail(st);
     if ((st = pool_get(ctx, q->mxy, n_pad * 2 * r)) != KOMA_OK) return bail(st);
     if ((st = pool_get(ctx, q->mz, n_pad * r)) != KOMA_OK) return bail(st);
     if (where == KOMA_DEVICE) {
@@ -1309,7 +1351,8 @@ koma_status koma_req_result(koma_req *q, double *sig, void *hip_stream) {
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     q->last_stream = s;
     if (P.n_adc > 0)
-        HIPCHK(ctx, hipMemcpyAsync(sig, q->sig.p, (size_t)P.n_groups * P.n_adc * 16, hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipMemcpyAsync(sig, q->sig.p, (size_t)P.n_sig * P.n_groups * P.n_adc * 16,
+                                   hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     return KOMA_OK;
 }
@@ -1318,7 +1361,7 @@ koma_status koma_req_result(koma_req *q, double *sig, void *hip_stream) {
 struct CkptHeader {
     uint64_t magic;
     int64_t cursor, next_chunk, finished;
-    uint64_t n_ev, n_tiles, n_inl, n_slots, n_adc, n_groups, fp64;
+    uint64_t n_ev, n_tiles, n_inl, n_slots, n_adc, n_groups, fp64, n_sig;
     uint64_t bytes_mxy, bytes_mz, bytes_snap, bytes_pa, bytes_sig;
 };
 static constexpr uint64_t kCkptMagic = 0x314b504b414d4f4bull;
@@ -1338,11 +1381,12 @@ static void ckpt_sizes(const koma_req *q, CkptHeader &h) {
     h.n_adc = (uint64_t)P.n_adc;
     h.n_groups = (uint64_t)P.n_groups;
     h.fp64 = q->fp64 ? 1 : 0;
+    h.n_sig = (uint64_t)P.n_sig;
     h.bytes_mxy = n_pad * 2 * r;
     h.bytes_mz = n_pad * r;
     h.bytes_snap = (size_t)P.n_slots * n_pad * 2 * r;
-    h.bytes_pa = (size_t)P.n_tiles * P.inl_k.size() * 2 * r;
-    h.bytes_sig = (size_t)P.n_groups * P.n_adc * 16;
+    h.bytes_pa = (size_t)P.n_sig * P.n_tiles * P.inl_k.size() * 2 * r;
+    h.bytes_sig = (size_t)P.n_sig * P.n_groups * P.n_adc * 16;
 }
 
 koma_status koma_req_save(const koma_req *q, void *host_buf, size_t *bytes) {
@@ -1358,7 +1402,9 @@ koma_status koma_req_save(const koma_req *q, void *host_buf, size_t *bytes) {
     if (*bytes < total) return fail(ctx, KOMA_E_ARG, "checkpoint buffer too small (%zu < %zu)", *bytes, total);
     if (ctx->poisoned) return fail(ctx, KOMA_E_DEVICE, "context poisoned by an earlier device error");
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    HIPCHK(ctx, hipDeviceSynchronize());
+    // wait for this request's own work only (other requests keep running)
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (q->last_stream) HIPCHK(ctx, hipStreamSynchronize(q->last_stream));
     char *p = (char *)host_buf;
     memcpy(p, &h, sizeof h);
     p += sizeof h;
@@ -1381,7 +1427,7 @@ koma_status koma_req_load(koma_req *q, const void *host_buf, size_t bytes) {
     memcpy(&got, host_buf, sizeof got);
     if (got.magic != kCkptMagic || got.n_ev != want.n_ev || got.n_tiles != want.n_tiles || got.n_inl != want.n_inl ||
         got.n_slots != want.n_slots || got.n_adc != want.n_adc || got.n_groups != want.n_groups ||
-        got.fp64 != want.fp64 || got.bytes_mxy != want.bytes_mxy || got.bytes_snap != want.bytes_snap ||
+        got.fp64 != want.fp64 || got.n_sig != want.n_sig || got.bytes_mxy != want.bytes_mxy || got.bytes_snap != want.bytes_snap ||
         got.bytes_pa != want.bytes_pa || got.bytes_sig != want.bytes_sig)
         return fail(ctx, KOMA_E_STATE, "checkpoint does not match this request");
     const size_t total = sizeof got + got.bytes_mxy + got.bytes_mz + got.bytes_snap + got.bytes_pa + got.bytes_sig;
@@ -1391,7 +1437,8 @@ koma_status koma_req_load(koma_req *q, const void *host_buf, size_t bytes) {
         return fail(ctx, KOMA_E_STATE, "checkpoint cursor out of range");
     if (ctx->poisoned) return fail(ctx, KOMA_E_DEVICE, "context poisoned by an earlier device error");
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    HIPCHK(ctx, hipDeviceSynchronize());
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (q->last_stream) HIPCHK(ctx, hipStreamSynchronize(q->last_stream));
     const char *p = (const char *)host_buf + sizeof got;
     const std::pair<DevMem *, uint64_t> parts[] = {
         {&q->mxy, got.bytes_mxy}, {&q->mz, got.bytes_mz}, {&q->snap, got.bytes_snap}, {&q->pa, got.bytes_pa}, {&q->sig, got.bytes_sig}};

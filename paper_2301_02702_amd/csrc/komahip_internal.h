@@ -86,6 +86,9 @@ struct alignas(16) Block {
 struct PhantomDev {
     const float *x, *y, *z, *pd, *t1, *t2, *dw;
     const float *vx, *vy, *vz;  // nullptr: static spins
+    int64_t n;                  // spins (stride of the sensitivity planes)
+    int64_t n_coils;            // 0: plain sums
+    const float *sre, *sim;     // [n_coils][n] receive sensitivities
 };
 
 constexpr int kWave = 64;
@@ -106,7 +109,7 @@ struct SeqArgs {  // spin-sequential kernel
     void *mxy;        // state: [n_tiles*64] complex (R2)
     void *mz;         // [n_tiles*64] R
     void *snap;       // [n_slots][n_tiles*64] complex (R2)
-    void *pa;         // inline partials [n_tiles][n_inline] complex (R2)
+    void *pa;         // inline partials [n_sig][n_tiles][n_inline] complex (R2)
     int64_t n_inline;
 };
 
@@ -120,17 +123,19 @@ struct ParArgs {  // sample-parallel kernel
     int64_t s0, s1;        // stretches of this launch
     int64_t per_wg;        // stretches per workgroup (grid.y = ceil((s1-s0)/per_wg))
     const void *snap;
-    double *pb;            // [n_blocks][cols] double2
+    double *pb;            // [n_sig][n_blocks][cols] double2 (grid.z = coil)
     int64_t col0, cols;    // deferred sample index of column 0, columns
 };
 
-struct ReduceArgs {  // cross-workgroup sums into the signal
-    const void *part;      // [n_rows][cols] complex
+struct ReduceArgs {  // cross-workgroup sums into the signal (grid.z = coil)
+    int64_t n_sig;         // signal planes (coils, or 1)
+    int64_t part_stride;   // complex elements between the partial planes of two coils
+    const void *part;      // [n_sig][n_rows][cols] complex
     int64_t cols;
     const int32_t *row_off;  // group g owns rows [row_off[g], row_off[g+1])
     int64_t n_groups;
     const int32_t *col_to_adc;  // column c -> ADC index
-    double *sig;           // [n_groups][n_adc] double2
+    double *sig;           // [n_sig][n_groups][n_adc] double2
     int64_t n_adc;
 };
 

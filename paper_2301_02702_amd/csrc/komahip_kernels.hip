@@ -375,6 +375,30 @@ struct EvL {  // view of one staged event
     }
 };
 
+// One inline ADC sample: the wavefront's sum of Mxy (c), or of sens_k * Mxy
+// for every receive coil k, into the per-wavefront partials.
+template <class R, class R2>
+__device__ __forceinline__ void inline_sample(const SeqArgs &a, const Tile &T, int64_t tile, int lane,
+                                              int col, C2<R> c) {
+    const int64_t n_coils = a.ph.n_coils;  // uniform
+    if (n_coils == 0) {
+        const R sr = wave_allsum(c.re);
+        const R si = wave_allsum(c.im);
+        if (lane == 0) reinterpret_cast<R2 *>(a.pa)[tile * a.n_inline + col] = R2{sr, si};
+        return;
+    }
+    const bool valid = lane < T.count;
+    const int64_t i = T.spin0 + lane;
+    for (int64_t k = 0; k < n_coils; ++k) {
+        C2<R> sk{R(0), R(0)};
+        if (valid) sk = C2<R>{R(a.ph.sre[k * a.ph.n + i]), R(a.ph.sim[k * a.ph.n + i])};
+        const C2<R> v = cmul(sk, c);
+        const R sr = wave_allsum(v.re);
+        const R si = wave_allsum(v.im);
+        if (lane == 0) reinterpret_cast<R2 *>(a.pa)[(k * a.n_tiles + tile) * a.n_inline + col] = R2{sr, si};
+    }
+}
+
 template <class P, bool MOV>
 __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
     using R = typename P::R;
@@ -469,9 +493,7 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
                 const double k0[4] = {ev.d(0), ev.d(1), ev.d(2), ev.d(3)};
                 const double k1[3] = {ev.c64(0), ev.c64(1), ev.c64(2)};
                 const C2<R> c = cmul(C2<R>{mr, mi}, block_factor<P>(s, block_phase(s, k0, k1), k0[3]));
-                const R sr = wave_allsum(c.re);
-                const R si = wave_allsum(c.im);
-                if (lane == 0) reinterpret_cast<R2 *>(a.pa)[tile * a.n_inline + ev.a0()] = R2{sr, si};
+                inline_sample<R, R2>(a, T, tile, lane, ev.a0(), c);
             } else if (kind == EV_ADC) {
                 const double k0[4] = {ev.d(0), ev.d(1), ev.d(2), ev.d(3)};
                 const double dk[4] = {ev.d(4), ev.d(5), ev.d(6), ev.d(7)};
@@ -479,11 +501,8 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
                 const int cnt = ev.count();
                 C2<R> w{R(1), R(0)};
                 if (cnt > 1) w = block_factor<P>(s, block_phase(s, dk), dk[3]);
-                R2 *pa = reinterpret_cast<R2 *>(a.pa) + tile * a.n_inline + ev.a0();
                 for (int i = 0; i < cnt; ++i) {
-                    const R sr = wave_allsum(c.re);
-                    const R si = wave_allsum(c.im);
-                    if (lane == 0) pa[i] = R2{sr, si};
+                    inline_sample<R, R2>(a, T, tile, lane, ev.a0() + i, c);
                     c = cmul(c, w);
                 }
             } else {  // EV_SNAP
@@ -529,6 +548,8 @@ __global__ __launch_bounds__(kWG) void k_par(ParArgs a) {
     const int lane = threadIdx.x & 63;
     const Block B = a.blocks[blockIdx.x];
     const int64_t n_pad = a.n_tiles * kWave;
+    const int64_t coil = blockIdx.z;  // 0 without receive coils
+    const bool coils = a.ph.n_coils > 0;
 
     const int64_t st0 = a.s0 + (int64_t)blockIdx.y * a.per_wg;
     const int64_t st1 = min(st0 + a.per_wg, a.s1);
@@ -557,6 +578,8 @@ __global__ __launch_bounds__(kWG) void k_par(ParArgs a) {
                     const R2 v = reinterpret_cast<const R2 *>(a.snap)[(int64_t)slot * n_pad +
                                                                       (int64_t)(B.tile0 + tl) * kWave + lane];
                     m = C2<R>{v.x, v.y};
+                    if (coils)  // coil `coil` sees sens * Mxy: fold it into the anchor
+                        m = cmul(m, C2<R>{R(a.ph.sre[coil * a.ph.n + i]), R(a.ph.sim[coil * a.ph.n + i])});
                 }
             }
             c[j] = cmul(m, par_factor<P>(sp, k0));
@@ -591,7 +614,7 @@ __global__ __launch_bounds__(kWG) void k_par(ParArgs a) {
                 t.x += red[wv][i].x;
                 t.y += red[wv][i].y;
             }
-            reinterpret_cast<double2 *>(a.pb)[(int64_t)blockIdx.x * a.cols + (d0 - a.col0) + i] = t;
+            reinterpret_cast<double2 *>(a.pb)[(coil * a.n_blocks + (int64_t)blockIdx.x) * a.cols + (d0 - a.col0) + i] = t;
         }
         __syncthreads();
     }
@@ -599,21 +622,24 @@ __global__ __launch_bounds__(kWG) void k_par(ParArgs a) {
 
 // ---------------------------------------------------------------- k_reduce
 
-// sig[g][adc(c)] = sum over rows r of group g (in order) of part[r][c].
-// A workgroup covers 64 columns; its 4 wavefronts take rows r = r0 + w (mod 4)
-// and the four partial sums are added in wave order.
+// sig[k][g][adc(c)] = sum over rows r of group g (in order) of part[k][r][c],
+// k = blockIdx.z the coil. A workgroup covers 64 columns; its 4 wavefronts
+// take rows r = r0 + w (mod 4) and the four partial sums are added in wave
+// order.
 template <class T2>
 __global__ __launch_bounds__(kWG) void k_reduce(ReduceArgs a) {
     __shared__ double2 red[kWavesPerWG][kWave];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t col = (int64_t)blockIdx.x * kWave + lane;
+    const int64_t k = blockIdx.z;
+    const T2 *part = reinterpret_cast<const T2 *>(a.part) + k * a.part_stride;
+    double2 *sig = reinterpret_cast<double2 *>(a.sig) + k * a.n_groups * a.n_adc;
     for (int64_t g = blockIdx.y; g < a.n_groups; g += gridDim.y) {  // uniform per workgroup
         const int32_t r0 = a.row_off[g], r1 = a.row_off[g + 1];
         double sx = 0.0, sy = 0.0;
         if (col < a.cols) {
-            const T2 *p = reinterpret_cast<const T2 *>(a.part);
             for (int32_t r = r0 + wave; r < r1; r += kWavesPerWG) {
-                T2 v = p[(int64_t)r * a.cols + col];
+                T2 v = part[(int64_t)r * a.cols + col];
                 sx += (double)v.x;
                 sy += (double)v.y;
             }
@@ -627,7 +653,7 @@ __global__ __launch_bounds__(kWG) void k_reduce(ReduceArgs a) {
                 t.x += red[wv][lane].x;
                 t.y += red[wv][lane].y;
             }
-            reinterpret_cast<double2 *>(a.sig)[g * a.n_adc + a.col_to_adc[col]] = t;
+            sig[g * a.n_adc + a.col_to_adc[col]] = t;
         }
         __syncthreads();
     }
@@ -654,7 +680,7 @@ __global__ __launch_bounds__(kWG) void k_export(const Tile *tiles, int64_t n_til
 
 // Per-workgroup flags of invalid phantom values (device-resident phantoms):
 // bit 0 non-finite x, y, z, dw, PD or velocity; bit 1 PD < 0; bit 2 T1 or T2
-// <= 0 or NaN.
+// <= 0 or NaN; bit 3 non-finite coil sensitivity.
 __global__ __launch_bounds__(kWG) void k_validate(PhantomDev ph, int64_t n, int32_t *flags) {
     __shared__ int32_t f[kWG];
     const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
@@ -666,6 +692,8 @@ __global__ __launch_bounds__(kWG) void k_validate(PhantomDev ph, int64_t n, int3
         if (pd < 0.f) bad |= 2;
         if (!(t1 > 0.f) || !(t2 > 0.f)) bad |= 4;
         if (ph.vx && (!isfinite(ph.vx[i]) || !isfinite(ph.vy[i]) || !isfinite(ph.vz[i]))) bad |= 1;
+        for (int64_t k = 0; k < ph.n_coils; ++k)
+            if (!isfinite(ph.sre[k * ph.n + i]) || !isfinite(ph.sim[k * ph.n + i])) bad |= 8;
     }
     f[threadIdx.x] = bad;
     __syncthreads();
@@ -705,6 +733,7 @@ int launch_seq(bool fp64, bool moving, const SeqArgs &a, void *stream) {
     if (a.n_tiles <= 0 || a.e1 <= a.e0) return 0;
     // moving spins need all three velocity arrays (checked on the host)
     if (moving && (!a.ph.vx || !a.ph.vy || !a.ph.vz)) return -1;
+    if (a.ph.n_coils < 0 || (a.ph.n_coils > 0 && (!a.ph.sre || !a.ph.sim))) return -1;
     dim3 grid((unsigned)((a.n_tiles + kWavesPerWG - 1) / kWavesPerWG));
     hipStream_t st = (hipStream_t)stream;
     if (fp64) {
@@ -733,7 +762,9 @@ static void par_dispatch(int spl, dim3 grid, const ParArgs &a, hipStream_t st) {
 
 int launch_par(bool fp64, int spl, const ParArgs &a, void *stream) {
     if (a.n_blocks <= 0 || a.s1 <= a.s0) return 0;
-    dim3 grid((unsigned)a.n_blocks, (unsigned)((a.s1 - a.s0 + a.per_wg - 1) / a.per_wg));
+    if (a.ph.n_coils < 0 || a.ph.n_coils > 65535 || (a.ph.n_coils > 0 && (!a.ph.sre || !a.ph.sim))) return -1;
+    dim3 grid((unsigned)a.n_blocks, (unsigned)((a.s1 - a.s0 + a.per_wg - 1) / a.per_wg),
+              (unsigned)(a.ph.n_coils > 0 ? a.ph.n_coils : 1));
     if (fp64)
         par_dispatch<FP64>(spl, grid, a, (hipStream_t)stream);
     else
@@ -743,7 +774,9 @@ int launch_par(bool fp64, int spl, const ParArgs &a, void *stream) {
 
 int launch_reduce(bool part_fp64, const ReduceArgs &a, void *stream) {
     if (a.cols <= 0 || a.n_groups <= 0) return 0;
-    dim3 grid((unsigned)((a.cols + kWave - 1) / kWave), (unsigned)(a.n_groups < 65535 ? a.n_groups : 65535));
+    if (a.n_sig < 1 || a.n_sig > 65535) return -1;
+    dim3 grid((unsigned)((a.cols + kWave - 1) / kWave), (unsigned)(a.n_groups < 65535 ? a.n_groups : 65535),
+              (unsigned)a.n_sig);
     if (part_fp64)
         hipLaunchKernelGGL(k_reduce<double2>, grid, dim3(kWG), 0, (hipStream_t)stream, a);
     else

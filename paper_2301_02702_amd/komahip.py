@@ -38,7 +38,8 @@ class koma_scanner(ctypes.Structure):
 class koma_phantom(ctypes.Structure):
     _fields_ = [("n", c_int64), ("x", c_void_p), ("y", c_void_p), ("z", c_void_p), ("pd", c_void_p),
                 ("t1", c_void_p), ("t2", c_void_p), ("dw", c_void_p), ("n_groups", c_int64),
-                ("group_off", c_void_p), ("vx", c_void_p), ("vy", c_void_p), ("vz", c_void_p)]
+                ("group_off", c_void_p), ("vx", c_void_p), ("vy", c_void_p), ("vz", c_void_p),
+                ("n_coils", c_int64), ("sens_re", c_void_p), ("sens_im", c_void_p)]
 
 
 class koma_sequence(ctypes.Structure):
@@ -197,6 +198,26 @@ class _PhantomArgs:
             if (a.numel() if device else a.shape[0]) != n:
                 raise ValueError("phantom arrays differ in length")
         self.keep += arrs
+        # receive coils: [n_coils, n] sensitivities
+        n_coils, sre, sim = 0, None, None
+        if device and get("sens_re") is not None:
+            sre, sim = get("sens_re"), get("sens_im")
+            for a in (sre, sim):
+                if not (a.is_cuda and a.is_contiguous() and str(a.dtype) == "torch.float32" and a.dim() == 2
+                        and a.shape[1] == n):
+                    raise TypeError("device sensitivities must be contiguous float32 GPU tensors [n_coils, n]")
+            n_coils = int(sre.shape[0])
+        elif not device and get("sens") is not None:
+            sens = np.asarray(get("sens"))
+            if sens.ndim != 2 or sens.shape[1] != n:
+                raise ValueError("sensitivities must be [n_coils, n]")
+            sre = np.ascontiguousarray(sens.real, dtype=np.float32)
+            sim = np.ascontiguousarray(sens.imag, dtype=np.float32)
+            n_coils = int(sens.shape[0])
+        if n_coils:
+            self.keep += [sre, sim]
+        self.n_coils = n_coils
+        self.n_sig = max(n_coils, 1)
         if goff is not None:
             goff = np.ascontiguousarray(goff, dtype=np.int64)
             self.keep.append(goff)
@@ -204,7 +225,8 @@ class _PhantomArgs:
         self.n_groups = ng
         self.n = n
         self.c = koma_phantom(n, *[_ptr(a) for a in arrs[:7]], ng, _ptr(goff),
-                              *([_ptr(a) for a in arrs[7:]] if moving else [None] * 3))
+                              *([_ptr(a) for a in arrs[7:]] if moving else [None] * 3),
+                              n_coils, _ptr(sre), _ptr(sim))
 
 
 class _SeqArgs:
@@ -328,10 +350,12 @@ class Context:
     def simulate(self, scanner, phantom, seq, where: str = "host", stream=None, sig=None,
                  want_m: bool = False):
         """koma_simulate. ``where='host'``: numpy phantom, returns complex128
-        ``[n_groups, n_adc]`` (and ``[n, 3]`` final M if ``want_m``).
+        ``[n_groups, n_adc]``, or ``[n_coils, n_groups, n_adc]`` for a phantom
+        with coil sensitivities (and ``[n, 3]`` final M if ``want_m``).
         ``where='device'``: torch GPU tensors (dict or object with x..dw,
-        group_off on the host); ``sig`` a float64 GPU tensor
-        ``[n_groups, n_adc, 2]`` that is written in place."""
+        optional vx, vy, vz and sens_re, sens_im; group_off on the host);
+        ``sig`` a float64 GPU tensor ``[(n_coils,) n_groups, n_adc, 2]``
+        that is written in place."""
         dev = where == "device"
         p, s = _PhantomArgs(phantom, dev), _SeqArgs(seq)
         sc = make_scanner(scanner)
@@ -339,6 +363,8 @@ class Context:
         if dev:
             if sig is None:
                 raise ValueError("device simulate needs a preallocated sig tensor")
+            if sig.numel() != 2 * p.n_sig * p.n_groups * s.n_adc or not sig.is_contiguous():
+                raise ValueError("sig must be a contiguous [(n_coils,) n_groups, n_adc, 2] tensor")
             m = None
             if want_m:
                 import torch
@@ -346,11 +372,13 @@ class Context:
             _check(lib().koma_simulate(self.h, ctypes.byref(sc), ctypes.byref(p.c), ctypes.byref(s.c),
                                        KOMA_DEVICE, stream_h, _ptr(sig), _ptr(m)), self.h)
             return (sig, m) if want_m else sig
-        out = np.zeros((p.n_groups, s.n_adc, 2), dtype=np.float64)
+        out = np.zeros((p.n_sig, p.n_groups, s.n_adc, 2), dtype=np.float64)
         m = np.zeros((p.n, 3), dtype=np.float64) if want_m else None
         _check(lib().koma_simulate(self.h, ctypes.byref(sc), ctypes.byref(p.c), ctypes.byref(s.c),
                                    KOMA_HOST, stream_h, _ptr(out), _ptr(m)), self.h)
         z = out[..., 0] + 1j * out[..., 1]
+        if not p.n_coils:
+            z = z[0]
         return (z, m) if want_m else z
 
     def open(self, scanner, phantom, seq, where: str = "host") -> "Request":
@@ -377,7 +405,7 @@ class Request:
         _check(lib().koma_req_open(ctx.h, ctypes.byref(sc), ctypes.byref(p.c), ctypes.byref(s.c),
                                    KOMA_DEVICE if where == "device" else KOMA_HOST, ctypes.byref(h)), ctx.h)
         self.h = h
-        self.n_groups, self.n_adc = p.n_groups, s.n_adc
+        self.n_groups, self.n_adc, self.n_coils = p.n_groups, s.n_adc, p.n_coils
 
     def advance(self, max_events: int = 0, stream=None):
         sh = None if stream is None else c_void_p(stream if isinstance(stream, int) else stream.cuda_stream)
@@ -390,9 +418,10 @@ class Request:
 
     def result(self, stream=None) -> np.ndarray:
         sh = None if stream is None else c_void_p(stream if isinstance(stream, int) else stream.cuda_stream)
-        out = np.zeros((self.n_groups, self.n_adc, 2), dtype=np.float64)
+        out = np.zeros((max(self.n_coils, 1), self.n_groups, self.n_adc, 2), dtype=np.float64)
         _check(lib().koma_req_result(self.h, _ptr(out), sh), self.ctx.h)
-        return out[..., 0] + 1j * out[..., 1]
+        z = out[..., 0] + 1j * out[..., 1]
+        return z if self.n_coils else z[0]
 
     def save(self) -> bytes:
         n = c_size_t(0)
@@ -428,4 +457,7 @@ def device_phantom(phantom, device="cuda:0") -> dict:
     d = {k: torch.from_numpy(np.ascontiguousarray(getattr(phantom, k), dtype=np.float32)).to(device)
          for k in keys}
     d["group_off"] = phantom.group_off
+    if getattr(phantom, "sens", None) is not None:
+        d["sens_re"] = torch.from_numpy(np.ascontiguousarray(phantom.sens.real, dtype=np.float32)).to(device)
+        d["sens_im"] = torch.from_numpy(np.ascontiguousarray(phantom.sens.imag, dtype=np.float32)).to(device)
     return d

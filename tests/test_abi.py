@@ -152,3 +152,28 @@ def test_velocity_validation(K):
     st = K.lib().koma_plan_info(ctypes.byref(sc), ctypes.byref(p.c), ctypes.byref(s.c), ctypes.byref(cfg),
                                 ctypes.byref(info))
     assert st == -1
+
+
+def test_coil_plans_and_validation(K):
+    sc, ph, seq = W.config(2)
+    ph = ph.subset(np.arange(0, ph.n, 16))
+    f1 = K.koma_footprint(ph, seq, K.make_config())
+    pc = W.with_coils(ph, 8)
+    f8 = K.koma_footprint(pc, seq, K.make_config())
+    assert f8 > f1 + 8 * ph.n * 8  # sensitivities at least
+    i1 = K.koma_plan_info(sc, ph, seq, K.make_config(partial_budget=1 << 20))
+    i8 = K.koma_plan_info(sc, pc, seq, K.make_config(partial_budget=1 << 20))
+    assert i8["n_chunks"] >= 4 * i1["n_chunks"]  # the partial budget is shared by the coils
+    p = K._PhantomArgs(pc, False)
+    info = K.koma_req_info()
+    s = K._SeqArgs(seq)
+    cfg = K.make_config()
+    scc = K.make_scanner(sc)
+    for mutate in (lambda c: setattr(c, "n_coils", 1025), lambda c: setattr(c, "sens_im", None),
+                   lambda c: setattr(c, "n_coils", -1)):
+        q = K._PhantomArgs(pc, False)
+        mutate(q.c)
+        st = K.lib().koma_plan_info(ctypes.byref(scc), ctypes.byref(q.c), ctypes.byref(s.c), ctypes.byref(cfg),
+                                    ctypes.byref(info))
+        assert st == -1
+    assert p.n_coils == 8
