@@ -208,11 +208,30 @@ koma_status koma_plan_info(const koma_scanner *sc, const koma_phantom *ph, const
  *   kind 0: spin-sequential kernel (excitation, block ends, inline samples)
  *   kind 1: sample-parallel kernel (samples of long precession blocks)
  *   kind 2: cross-workgroup reduction into the signal
- *   kind 3: state initialisation / export
+ *   kind 3: state initialisation / export, MRF operand packing and final argmax
+ *   kind 4: MRF matching contraction (koma_mrf_match)
  * Totals are reset by koma_ctx_profile(ctx, 1). */
 koma_status koma_ctx_profile(koma_ctx *ctx, int on);
 koma_status koma_ctx_kernel_stats(koma_ctx *ctx, int kind, double *total_ms, int64_t *launches,
                                   int64_t *work_units);
+
+/* ---- MRF dictionary matching ----------------------------------------------
+ * The paper's MR-fingerprinting experiment (Full-Dict reconstruction): each
+ * pixel's fingerprint x (n_t complex values, one per TR) is assigned the
+ * dictionary entry with the maximum dot product against the normalised
+ * entries, best = argmax_e |<d_e, x>|^2 / ||d_e||^2, <d, x> = sum_t conj(d_t) x_t.
+ * Precision: the decision is taken on binary16 operands. Every row (entry or
+ * fingerprint) is first scaled by an exact power of two so that its largest
+ * |Re| or |Im| lies in [0.5, 1), then each part is rounded to binary16 (ties
+ * to even); ||d_e||^2 is that of the rounded entry; the dot products
+ * accumulate in FP32 on the matrix cores. Ties go to the lower index.
+ *   dict:  [n_entries][n_t][2] floats (re, im); fp: [n_pix][n_t][2] floats.
+ *   best:  [n_pix] entry index (-1 if every entry is zero).
+ *   proj:  [n_pix][2] doubles, <d_best, x> / ||d_best|| in the caller's units
+ *          (the pixel's complex scale relative to the unit-norm entry).
+ * All four arrays live where `where` says; synchronous on `hip_stream`. */
+koma_status koma_mrf_match(koma_ctx *ctx, const float *dict, int64_t n_entries, const float *fp, int64_t n_pix,
+                           int64_t n_t, koma_mem where, void *hip_stream, int32_t *best, double *proj);
 
 /* ---- sequence-aware time stepping ----------------------------------------
  * Section "Simulation blocks, Regime Switching, and Sequence-Aware Time

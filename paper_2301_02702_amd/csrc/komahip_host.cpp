@@ -24,6 +24,7 @@
 
 #include "komahip.h"
 #include "komahip_internal.h"
+#include "komahip_mrf.h"
 
 using namespace koma;
 
@@ -108,7 +109,7 @@ struct DevMem {  // request-owned or context-scratch device allocation
     size_t cap = 0;
 };
 
-enum { K_SEQ = 0, K_PAR = 1, K_RED = 2, K_AUX = 3, K_KINDS = 4 };
+enum { K_SEQ = 0, K_PAR = 1, K_RED = 2, K_AUX = 3, K_MRF = 4, K_KINDS = 5 };
 
 struct ProfRec {
     hipEvent_t a, b;
@@ -127,9 +128,9 @@ struct koma_ctx {
     bool prof = false;
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> ev_free;
-    double tot_ms[K_KINDS] = {0, 0, 0, 0};
-    int64_t n_launch[K_KINDS] = {0, 0, 0, 0};
-    int64_t work[K_KINDS] = {0, 0, 0, 0};
+    double tot_ms[K_KINDS] = {};
+    int64_t n_launch[K_KINDS] = {};
+    int64_t work[K_KINDS] = {};
     Plan plan;  // reused by koma_simulate (capacity kept across calls)
     // pinned host staging for the packed tables (one upload per call) and the
     // validation flag read-back
@@ -143,6 +144,8 @@ struct koma_ctx {
     // scratch reused by koma_simulate (grow-only)
     DevMem s_ev, s_st, s_tiles, s_blocks, s_toff, s_boff, s_inl, s_def, s_snap, s_pa, s_pb, s_sig,
         s_mxy, s_mz, s_flags, s_mf, s_ph[kPhArrays];
+    // MRF matching scratch (grow-only)
+    DevMem m_src_d, m_src_x, m_dh, m_xh, m_dexp, m_xexp, m_inv, m_ps, m_pi, m_pip, m_best, m_proj;
 };
 
 struct koma_req {
@@ -978,6 +981,9 @@ void koma_ctx_destroy(koma_ctx *ctx) {
                      &ctx->s_mxy, &ctx->s_mz, &ctx->s_flags, &ctx->s_mf};
     for (DevMem *m : all) dev_free(*m);
     for (DevMem &m : ctx->s_ph) dev_free(m);
+    DevMem *mrf[] = {&ctx->m_src_d, &ctx->m_src_x, &ctx->m_dh, &ctx->m_xh, &ctx->m_dexp, &ctx->m_xexp,
+                     &ctx->m_inv, &ctx->m_ps, &ctx->m_pi, &ctx->m_pip, &ctx->m_best, &ctx->m_proj};
+    for (DevMem *m : mrf) dev_free(*m);
     dev_free(ctx->s_tables);
     if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
     if (ctx->h_flag) (void)hipHostFree(ctx->h_flag);
@@ -1507,6 +1513,85 @@ koma_status koma_plan_info(const koma_scanner *sc, const koma_phantom *ph, const
     if ((st = build_plan(&tmp, c, sc->gamma, ph, seq, P)) != KOMA_OK) return st;
     fill_info(P, info);
     info->footprint = plan_footprint(P, c.precision == KOMA_FP64, true, true);
+    return KOMA_OK;
+}
+
+// ---------------------------------------------------------------- MRF matching
+
+koma_status koma_mrf_match(koma_ctx *ctx, const float *dict, int64_t n_entries, const float *fp, int64_t n_pix,
+                           int64_t n_t, koma_mem where, void *hip_stream, int32_t *best, double *proj) {
+    if (!ctx) return KOMA_E_ARG;
+    if (ctx->poisoned) return fail(ctx, KOMA_E_DEVICE, "context poisoned by an earlier device error");
+    ctx->err.clear();
+    if (where != KOMA_HOST && where != KOMA_DEVICE) return fail(ctx, KOMA_E_ARG, "bad koma_mem");
+    if (n_entries < 1 || n_pix < 1 || n_t < 1) return fail(ctx, KOMA_E_ARG, "n_entries, n_pix and n_t must be >= 1");
+    if (!dict || !fp || !best || !proj) return fail(ctx, KOMA_E_ARG, "NULL array");
+    if (n_entries > ((int64_t)1 << 30) || n_pix > ((int64_t)1 << 30) || n_t > ((int64_t)1 << 24))
+        return fail(ctx, KOMA_E_ARG, "sizes too large");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    koma_status st;
+    const int64_t kp = (2 * n_t + 15) / 16 * 16;
+    const int64_t n_ent_tiles = (n_entries + 63) / 64;
+    const int64_t n_ent_pad = n_ent_tiles * 64;
+    const int64_t n_pix_pad = (n_pix + 127) / 128 * 128;
+    const int64_t pix_tiles = n_pix_pad / 128;
+    // entry splits: enough workgroups to fill the chip several times over
+    const int64_t n_split = std::max<int64_t>(1, std::min<int64_t>(n_ent_tiles, (4096 + pix_tiles - 1) / pix_tiles));
+    const int64_t tiles_per_split = (n_ent_tiles + n_split - 1) / n_split;
+    const float2 *src_d = (const float2 *)dict, *src_x = (const float2 *)fp;
+    if (where == KOMA_HOST) {
+        const size_t bd = (size_t)n_entries * n_t * 8, bx = (size_t)n_pix * n_t * 8;
+        if ((st = dev_reserve(ctx, ctx->m_src_d, bd)) != KOMA_OK) return st;
+        if ((st = dev_reserve(ctx, ctx->m_src_x, bx)) != KOMA_OK) return st;
+        HIPCHK(ctx, hipMemcpyAsync(ctx->m_src_d.p, dict, bd, hipMemcpyHostToDevice, s));
+        HIPCHK(ctx, hipMemcpyAsync(ctx->m_src_x.p, fp, bx, hipMemcpyHostToDevice, s));
+        src_d = (const float2 *)ctx->m_src_d.p;
+        src_x = (const float2 *)ctx->m_src_x.p;
+    }
+    if ((st = dev_reserve(ctx, ctx->m_dh, (size_t)n_ent_pad * kp * 2)) != KOMA_OK) return st;
+    if ((st = dev_reserve(ctx, ctx->m_xh, (size_t)n_pix_pad * kp * 2)) != KOMA_OK) return st;
+    if ((st = dev_reserve(ctx, ctx->m_dexp, (size_t)n_ent_pad * 4)) != KOMA_OK) return st;
+    if ((st = dev_reserve(ctx, ctx->m_xexp, (size_t)n_pix_pad * 4)) != KOMA_OK) return st;
+    if ((st = dev_reserve(ctx, ctx->m_inv, (size_t)n_ent_pad * 4)) != KOMA_OK) return st;
+    if ((st = dev_reserve(ctx, ctx->m_ps, (size_t)n_split * n_pix_pad * 4)) != KOMA_OK) return st;
+    if ((st = dev_reserve(ctx, ctx->m_pi, (size_t)n_split * n_pix_pad * 4)) != KOMA_OK) return st;
+    if ((st = dev_reserve(ctx, ctx->m_pip, (size_t)n_split * n_pix_pad * 8)) != KOMA_OK) return st;
+    int32_t *d_best = best;
+    double *d_proj = proj;
+    if (where == KOMA_HOST) {
+        if ((st = dev_reserve(ctx, ctx->m_best, (size_t)n_pix * 4)) != KOMA_OK) return st;
+        if ((st = dev_reserve(ctx, ctx->m_proj, (size_t)n_pix * 16)) != KOMA_OK) return st;
+        d_best = (int32_t *)ctx->m_best.p;
+        d_proj = (double *)ctx->m_proj.p;
+    }
+    _Float16 *dh = (_Float16 *)ctx->m_dh.p, *xh = (_Float16 *)ctx->m_xh.p;
+    LAUNCH(ctx, K_AUX, n_ent_pad * n_t, s,
+           launch_mrf_pack(src_d, n_entries, n_ent_pad, n_t, kp, dh, (int32_t *)ctx->m_dexp.p, (float *)ctx->m_inv.p, s));
+    LAUNCH(ctx, K_AUX, n_pix_pad * n_t, s,
+           launch_mrf_pack(src_x, n_pix, n_pix_pad, n_t, kp, xh, (int32_t *)ctx->m_xexp.p, nullptr, s));
+    MrfArgs a{};
+    a.xh = xh;
+    a.dh = dh;
+    a.inv_norm2 = (const float *)ctx->m_inv.p;
+    a.x_exp = (const int32_t *)ctx->m_xexp.p;
+    a.kp = kp;
+    a.n_pix = n_pix;
+    a.n_pix_pad = n_pix_pad;
+    a.n_ent_tiles = n_ent_tiles;
+    a.n_split = n_split;
+    a.tiles_per_split = tiles_per_split;
+    a.part_score = (float *)ctx->m_ps.p;
+    a.part_idx = (int32_t *)ctx->m_pi.p;
+    a.part_ip = (float2 *)ctx->m_pip.p;
+    // work units: complex multiply-adds of the contraction (8 real FLOP each)
+    LAUNCH(ctx, K_MRF, n_pix_pad * n_ent_pad * (kp / 2), s, launch_mrf_match(a, s));
+    LAUNCH(ctx, K_AUX, n_pix, s, launch_mrf_final(a, d_best, d_proj, s));
+    if (where == KOMA_HOST) {
+        HIPCHK(ctx, hipMemcpyAsync(best, d_best, (size_t)n_pix * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipMemcpyAsync(proj, d_proj, (size_t)n_pix * 16, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(ctx, hipStreamSynchronize(s));
     return KOMA_OK;
 }
 

@@ -22,7 +22,7 @@ STATUS = {0: "KOMA_OK", -1: "KOMA_E_ARG", -2: "KOMA_E_PHANTOM", -3: "KOMA_E_SEQU
           -8: "KOMA_E_STATE"}
 KOMA_FP64, KOMA_MIXED = 0, 1
 KOMA_HOST, KOMA_DEVICE = 0, 1
-KERNEL_KINDS = {"seq": 0, "par": 1, "reduce": 2, "aux": 3}
+KERNEL_KINDS = {"seq": 0, "par": 1, "reduce": 2, "aux": 3, "mrf": 4}
 
 
 class KomaError(RuntimeError):
@@ -114,6 +114,8 @@ EXPORTS = {
                                       POINTER(c_int64)]),
     "koma_discretize": (c_int, [POINTER(koma_block), c_int64, c_double, c_double, POINTER(c_int64),
                                 POINTER(c_int64)] + [c_void_p] * 7),
+    "koma_mrf_match": (c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, c_int, c_void_p,
+                               c_void_p, c_void_p]),
 }
 
 _lib = None
@@ -380,6 +382,36 @@ class Context:
         if not p.n_coils:
             z = z[0]
         return (z, m) if want_m else z
+
+    def mrf_match(self, dictionary, fingerprints, where: str = "host", stream=None, best=None, proj=None):
+        """koma_mrf_match. Host: complex ``[n_entries, n_t]`` and ``[n_pix, n_t]``
+        arrays (rounded to complex64), returns (best int32 [n_pix], proj complex128
+        [n_pix]). Device: float32 GPU tensors ``[n, n_t, 2]`` and preallocated
+        ``best`` (int32 [n_pix]) and ``proj`` (float64 [n_pix, 2]) tensors."""
+        sh = None if stream is None else c_void_p(stream if isinstance(stream, int) else stream.cuda_stream)
+        if where == "device":
+            for t in (dictionary, fingerprints):
+                if not (t.is_cuda and t.is_contiguous() and str(t.dtype) == "torch.float32" and t.dim() == 3
+                        and t.shape[2] == 2):
+                    raise TypeError("device operands must be contiguous float32 GPU tensors [n, n_t, 2]")
+            n_e, n_t = int(dictionary.shape[0]), int(dictionary.shape[1])
+            n_p = int(fingerprints.shape[0])
+            if int(fingerprints.shape[1]) != n_t or best is None or proj is None:
+                raise ValueError("mismatched n_t or missing output tensors")
+            if best.numel() != n_p or proj.numel() != 2 * n_p:
+                raise ValueError("output tensors have the wrong size")
+            _check(lib().koma_mrf_match(self.h, _ptr(dictionary), n_e, _ptr(fingerprints), n_p, n_t, KOMA_DEVICE,
+                                        sh, _ptr(best), _ptr(proj)), self.h)
+            return best, proj
+        d = np.ascontiguousarray(np.asarray(dictionary, dtype=np.complex64))
+        x = np.ascontiguousarray(np.asarray(fingerprints, dtype=np.complex64))
+        if d.ndim != 2 or x.ndim != 2 or d.shape[1] != x.shape[1]:
+            raise ValueError("dictionary [n_entries, n_t] and fingerprints [n_pix, n_t] expected")
+        b = np.zeros(x.shape[0], dtype=np.int32)
+        pr = np.zeros((x.shape[0], 2), dtype=np.float64)
+        _check(lib().koma_mrf_match(self.h, _ptr(d), d.shape[0], _ptr(x), x.shape[0], d.shape[1], KOMA_HOST, sh,
+                                    _ptr(b), _ptr(pr)), self.h)
+        return b, pr[:, 0] + 1j * pr[:, 1]
 
     def open(self, scanner, phantom, seq, where: str = "host") -> "Request":
         return Request(self, scanner, phantom, seq, where)

@@ -1,0 +1,123 @@
+"""GPU parity of MRF dictionary matching (MFMA contraction + fused argmax)
+against the reference matching on the same binary16 operands.
+
+The decision is an argmax taken in floating point, so both sides take it on
+the same rounded operands (the library's binary16 rows); they then differ
+only in the accumulation (FP32 on the matrix cores, FP64 in the reference).
+Where the reference's best and second-best scores are further apart than a
+bound on that accumulation error the indices must be identical; inside the
+bound the library's pick must score within it of the best. The projection
+<d, x>/||d|| is compared to 1e-5 relative.
+"""
+import numpy as np
+import pytest
+
+from paper_2301_02702_amd import workloads as W
+from tests._gpu import say
+
+pytestmark = pytest.mark.gpu
+
+GAP = 1e-4  # relative score bound of the FP32 accumulation (kp <= 2048 terms of binary16 products)
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_2301_02702_amd import komahip
+    komahip.lib()
+    return komahip
+
+
+@pytest.fixture(scope="module")
+def ctx(K):
+    c = K.Context(0, "mixed")
+    yield c
+    c.close()
+
+
+def check(best, proj, d, x, tag):
+    from oracle import mrf_match as M
+    rb, rp, rs, scores = M.match_rounded(d, x)
+    srt = np.sort(scores, axis=1)
+    second = srt[:, -2] if scores.shape[1] > 1 else np.zeros(len(rb))
+    clear = (rs - second) > GAP * rs
+    assert np.array_equal(best[clear], rb[clear]), (tag, np.nonzero(best[clear] != rb[clear])[0][:5])
+    rows = np.arange(len(rb))
+    near = ~clear
+    if np.any(near):
+        assert np.all(scores[rows[near], best[near]] >= rs[near] * (1 - GAP)), tag
+    same = best == rb
+    assert np.allclose(proj[same], rp[same], rtol=1e-5, atol=1e-6 * np.max(np.abs(rp))), tag
+    say(f"[mrf match] {tag}: {int(np.sum(same))}/{len(rb)} identical picks, {int(np.sum(near))} within the bound")
+
+
+def rnd(rng, shape):
+    return (rng.normal(size=shape) + 1j * rng.normal(size=shape)).astype(np.complex64)
+
+
+@pytest.mark.parametrize("n_e,n_p,n_t", [(300, 500, 100), (64, 128, 8), (1, 7, 3), (257, 129, 1), (130, 300, 333)])
+def test_random_operands_match_reference(ctx, n_e, n_p, n_t):
+    """Ragged sizes over several tiles: entry tiles of 64, pixel tiles of 128,
+    contraction steps of 8 TR values."""
+    rng = np.random.default_rng(n_e * 7 + n_p + n_t)
+    d = rnd(rng, (n_e, n_t)) * rng.uniform(0.01, 100.0, (n_e, 1)).astype(np.float32)
+    e = rng.integers(0, n_e, n_p)
+    x = (d[e] * (0.5 - 0.8j) + 0.3 * np.abs(d[e]).mean(1, keepdims=True) * rnd(rng, (n_p, n_t))).astype(np.complex64)
+    best, proj = ctx.mrf_match(d, x)
+    check(best, proj, d, x, f"random {n_e}x{n_p}x{n_t}")
+
+
+def test_noise_free_fingerprints_pick_their_entry(ctx):
+    """Fingerprints that are scaled copies of distinct random entries: the
+    MFMA operand layout must put every product where it belongs."""
+    rng = np.random.default_rng(7)
+    d = rnd(rng, (1000, 200))
+    e = rng.permutation(1000)[:640]
+    c = (rng.uniform(0.1, 10, 640) * np.exp(1j * rng.uniform(0, 6.28, 640))).astype(np.complex64)
+    x = (c[:, None] * d[e]).astype(np.complex64)
+    best, proj = ctx.mrf_match(d, x)
+    assert np.array_equal(best, e)
+    nrm = np.linalg.norm(d[e].astype(np.complex128), axis=1)
+    assert np.allclose(proj, c * nrm, rtol=2e-3)
+
+
+def test_zero_rows(ctx):
+    rng = np.random.default_rng(8)
+    d = rnd(rng, (70, 16))
+    d[3] = 0
+    x = rnd(rng, (5, 16))
+    x[2] = 0
+    x[4] = d[3]  # zero
+    best, proj = ctx.mrf_match(d, x)
+    assert 3 not in set(best[[0, 1, 3]].tolist())
+    assert best[2] == 0 and best[4] == 0 and proj[2] == 0 and proj[4] == 0  # all scores 0: lowest index
+
+
+def test_device_path_is_the_host_path(ctx):
+    import torch
+    rng = np.random.default_rng(9)
+    d = rnd(rng, (200, 50))
+    x = rnd(rng, (333, 50))
+    b1, p1 = ctx.mrf_match(d, x)
+    td = torch.from_numpy(np.stack([d.real, d.imag], -1).astype(np.float32)).cuda()
+    tx = torch.from_numpy(np.stack([x.real, x.imag], -1).astype(np.float32)).cuda()
+    bb = torch.empty(333, dtype=torch.int32, device="cuda")
+    pp = torch.empty((333, 2), dtype=torch.float64, device="cuda")
+    ctx.mrf_match(td, tx, where="device", best=bb, proj=pp)
+    p2 = pp.cpu().numpy()
+    assert np.array_equal(b1, bb.cpu().numpy()) and np.array_equal(p1, p2[:, 0] + 1j * p2[:, 1])
+
+
+def test_simulated_dictionary_recovers_t1_t2(ctx):
+    """A FISP dictionary simulated on the GPU (40 T1/T2 entries, 1000 TRs):
+    noisy scaled copies are matched back to their entries."""
+    from tests._gpu import case
+    sc, ph, seq = case("mrf40")
+    ctx.set_config("mixed")
+    dic = ctx.simulate(sc, ph, seq).astype(np.complex64)
+    rng = np.random.default_rng(10)
+    e = rng.integers(0, 40, 500)
+    amp = np.abs(dic[e]).max(1, keepdims=True)
+    x = (dic[e] * 0.7 + 0.01 * amp * rnd(rng, (500, seq.n_adc))).astype(np.complex64)
+    best, proj = ctx.mrf_match(dic, x)
+    check(best, proj, dic, x, "simulated mrf40")
+    assert np.mean(best == e) > 0.99
