@@ -145,7 +145,7 @@ struct koma_ctx {
     DevMem s_ev, s_st, s_tiles, s_blocks, s_toff, s_boff, s_inl, s_def, s_snap, s_pa, s_pb, s_sig,
         s_mxy, s_mz, s_flags, s_mf, s_ph[kPhArrays];
     // MRF matching scratch (grow-only)
-    DevMem m_src_d, m_src_x, m_dh, m_xh, m_dexp, m_xexp, m_inv, m_ps, m_pi, m_pip, m_best, m_proj;
+    DevMem m_src_d, m_src_x, m_dh, m_xh, m_dexp, m_xexp, m_inv, m_ps, m_pi, m_best, m_proj;
 };
 
 struct koma_req {
@@ -982,7 +982,7 @@ void koma_ctx_destroy(koma_ctx *ctx) {
     for (DevMem *m : all) dev_free(*m);
     for (DevMem &m : ctx->s_ph) dev_free(m);
     DevMem *mrf[] = {&ctx->m_src_d, &ctx->m_src_x, &ctx->m_dh, &ctx->m_xh, &ctx->m_dexp, &ctx->m_xexp,
-                     &ctx->m_inv, &ctx->m_ps, &ctx->m_pi, &ctx->m_pip, &ctx->m_best, &ctx->m_proj};
+                     &ctx->m_inv, &ctx->m_ps, &ctx->m_pi, &ctx->m_best, &ctx->m_proj};
     for (DevMem *m : mrf) dev_free(*m);
     dev_free(ctx->s_tables);
     if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
@@ -1531,13 +1531,13 @@ koma_status koma_mrf_match(koma_ctx *ctx, const float *dict, int64_t n_entries, 
     HIPCHK(ctx, hipSetDevice(ctx->device));
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     koma_status st;
-    const int64_t kp = (2 * n_t + 15) / 16 * 16;
-    const int64_t n_ent_tiles = (n_entries + 63) / 64;
-    const int64_t n_ent_pad = n_ent_tiles * 64;
+    const int64_t kp = (2 * n_t + 31) / 32 * 32;
+    const int64_t n_ent_tiles = (n_entries + 127) / 128;
+    const int64_t n_ent_pad = n_ent_tiles * 128;
     const int64_t n_pix_pad = (n_pix + 127) / 128 * 128;
     const int64_t pix_tiles = n_pix_pad / 128;
     // entry splits: enough workgroups to fill the chip several times over
-    const int64_t n_split = std::max<int64_t>(1, std::min<int64_t>(n_ent_tiles, (4096 + pix_tiles - 1) / pix_tiles));
+    const int64_t n_split = std::max<int64_t>(1, std::min<int64_t>(n_ent_tiles, (2048 + pix_tiles - 1) / pix_tiles));
     const int64_t tiles_per_split = (n_ent_tiles + n_split - 1) / n_split;
     const float2 *src_d = (const float2 *)dict, *src_x = (const float2 *)fp;
     if (where == KOMA_HOST) {
@@ -1554,9 +1554,8 @@ koma_status koma_mrf_match(koma_ctx *ctx, const float *dict, int64_t n_entries, 
     if ((st = dev_reserve(ctx, ctx->m_dexp, (size_t)n_ent_pad * 4)) != KOMA_OK) return st;
     if ((st = dev_reserve(ctx, ctx->m_xexp, (size_t)n_pix_pad * 4)) != KOMA_OK) return st;
     if ((st = dev_reserve(ctx, ctx->m_inv, (size_t)n_ent_pad * 4)) != KOMA_OK) return st;
-    if ((st = dev_reserve(ctx, ctx->m_ps, (size_t)n_split * n_pix_pad * 4)) != KOMA_OK) return st;
-    if ((st = dev_reserve(ctx, ctx->m_pi, (size_t)n_split * n_pix_pad * 4)) != KOMA_OK) return st;
-    if ((st = dev_reserve(ctx, ctx->m_pip, (size_t)n_split * n_pix_pad * 8)) != KOMA_OK) return st;
+    if ((st = dev_reserve(ctx, ctx->m_ps, (size_t)2 * n_split * n_pix_pad * 4)) != KOMA_OK) return st;
+    if ((st = dev_reserve(ctx, ctx->m_pi, (size_t)2 * n_split * n_pix_pad * 4)) != KOMA_OK) return st;
     int32_t *d_best = best;
     double *d_proj = proj;
     if (where == KOMA_HOST) {
@@ -1581,9 +1580,9 @@ koma_status koma_mrf_match(koma_ctx *ctx, const float *dict, int64_t n_entries, 
     a.n_ent_tiles = n_ent_tiles;
     a.n_split = n_split;
     a.tiles_per_split = tiles_per_split;
+    a.n_planes = 2 * n_split;
     a.part_score = (float *)ctx->m_ps.p;
     a.part_idx = (int32_t *)ctx->m_pi.p;
-    a.part_ip = (float2 *)ctx->m_pip.p;
     // work units: complex multiply-adds of the contraction (8 real FLOP each)
     LAUNCH(ctx, K_MRF, n_pix_pad * n_ent_pad * (kp / 2), s, launch_mrf_match(a, s));
     LAUNCH(ctx, K_AUX, n_pix, s, launch_mrf_final(a, d_best, d_proj, s));

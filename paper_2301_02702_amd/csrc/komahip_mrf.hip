@@ -12,18 +12,18 @@
 //                and rounded to binary16, interleaved (re, im) along the
 //                contraction axis and zero-padded; entries also get
 //                1 / ||rounded entry||^2.
-//   k_mrf_match  a workgroup owns 128 pixels (one 32-pixel slab per
-//                wavefront) and a range of entries; per 64-entry tile each
-//                wavefront accumulates Re and Im of <d, x> for 32 x 64
-//                (pixel, entry) pairs with v_mfma_f32_32x32x16_f16
-//                (FP32 accumulation), then scores the tile and keeps the
-//                running best entry of each of its pixels (ties: lower
-//                index). Re <d, x> = [xr, xi] . [dr, di] and
+//   k_mrf_match  a workgroup owns 128 pixels and a range of 128-entry
+//                tiles; operand slices are staged through LDS (double
+//                buffered) and each wavefront accumulates Re and Im of
+//                <d, x> for 64 x 64 (pixel, entry) pairs with
+//                v_mfma_f32_32x32x16_f16 (FP32 accumulation), then scores
+//                the tile and keeps, per lane and row, the best entry seen
+//                (ties: lower index). Re <d, x> = [xr, xi] . [dr, di] and
 //                Im <d, x> = [xr, xi] . [-di, dr]: the second operand is
 //                formed from the first in registers.
-//   k_mrf_final  the best of the workgroups' partial results per pixel, in
-//                entry order, and the projection <d, x> / ||d|| in the
-//                caller's units.
+//   k_mrf_final  the best of the partial results per pixel, and the
+//                projection <d, x> / ||d|| recomputed in FP64 from the
+//                binary16 operands, in the caller's units.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -36,8 +36,8 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kMrfWG = 256;
 constexpr int kMrfWaves = 4;
-constexpr int kPixTile = 32 * kMrfWaves;  // pixels per workgroup
-constexpr int kEntTile = 64;              // entries per tile (two 32-wide MFMA columns)
+constexpr int kPixTile = 128;  // pixels per workgroup
+constexpr int kEntTile = 128;  // entries per workgroup tile
 
 // ---------------------------------------------------------------- packing
 
@@ -101,12 +101,6 @@ __global__ __launch_bounds__(kMrfWG) void k_mrf_pack(const float2 *src, int64_t 
 
 // ---------------------------------------------------------------- matching
 
-struct Best {
-    float score;
-    int32_t idx;
-    float re, im;
-};
-
 __device__ __forceinline__ bool better(float s, int32_t i, float bs, int32_t bi) {
     return s > bs || (s == bs && i < bi);
 }
@@ -123,104 +117,199 @@ __device__ __forceinline__ half8 times_i_conj(half8 v) {
     return r;
 }
 
-// Grid: x = pixel tiles of 128, y = entry splits. Each workgroup scans entry
-// tiles [y * tiles_per_split, ...) and writes one partial best per pixel.
+// Workgroup tile: 128 pixels x 128 entries, staged through LDS in slices of
+// 32 binary16 values of the contraction axis (16 TR values), double
+// buffered. Wavefront w owns pixels 64 (w & 1) .. +63 and entries
+// 64 (w >> 1) .. +63 of the tile: 2 x 2 blocks of 32 x 32, each with a Re
+// and an Im accumulator (8 MFMA accumulators of 16 floats per lane).
+constexpr int kSlice = 32;          // halfs of the contraction axis per stage
+constexpr int kLdsRow = kSlice + 8; // padded row (80 bytes) against bank conflicts
+constexpr int kTileRows = 128;
+
 __global__ __launch_bounds__(kMrfWG) void k_mrf_match(MrfArgs a) {
-    const int wave = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    const int64_t p0 = (int64_t)blockIdx.x * kPixTile + 32 * wave;  // this wave's 32 pixels
+    __shared__ __attribute__((aligned(16))) _Float16 lds[2][2][kTileRows * kLdsRow];  // [stage][A|B]
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int half = lane >> 5;  // k offset 8 * half within a 16-wide MFMA step
+    const int col = lane & 31;   // MFMA row (A) / column (B) index of this lane
+    const int wp = (wave & 1) * 64, we = (wave >> 1) * 64;
+    const int64_t P0 = (int64_t)blockIdx.x * kPixTile;
     const int64_t kp = a.kp;
-    const int half = lane >> 5;   // which 8-wide k slice of a 16-wide step this lane feeds
-    const int col = lane & 31;    // MFMA row (A) / column (B) index of this lane
-    const half8 *xa = reinterpret_cast<const half8 *>(a.xh + (p0 + col) * kp + 8 * half);
+    const int n_stage = (int)(kp / kSlice);
 
-    // running best of the 16 rows this lane holds (rows 8(r/4) + 4 half + r % 4)
-    Best best[16];
+    // running best per lane: 2 pixel blocks x 16 rows, over the columns this lane has seen
+    float bs[2][16];
+    int32_t bi[2][16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) best[r] = Best{-1.0f, 0x7fffffff, 0.0f, 0.0f};
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            bs[i][r] = -1.0f;
+            bi[i][r] = 0x7fffffff;
+        }
 
+    // global -> LDS copy: 4 chunks of 16 bytes per thread and stage (A: 512, B: 512)
+    const int crow0 = tid >> 2, cpart = tid & 3;  // chunk tid and tid + 256: rows crow0, crow0 + 64
     const int64_t t0 = (int64_t)blockIdx.y * a.tiles_per_split;
     const int64_t t1 = min(t0 + a.tiles_per_split, a.n_ent_tiles);
     for (int64_t et = t0; et < t1; ++et) {
-        const int64_t e0 = et * kEntTile;
-        const half8 *db0 = reinterpret_cast<const half8 *>(a.dh + (e0 + col) * kp + 8 * half);
-        const half8 *db1 = reinterpret_cast<const half8 *>(a.dh + (e0 + 32 + col) * kp + 8 * half);
-        f32x16 re0 = {}, im0 = {}, re1 = {}, im1 = {};
-        // k advances 16 halfs (8 complex TR values) per MFMA step; a half8 is 16 of them
-        for (int64_t k = 0; k < kp; k += 16) {
-            const int64_t q = k >> 3;  // half8 index
-            const half8 av = xa[q];
-            const half8 b0 = db0[q];
-            const half8 b1 = db1[q];
-            re0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, b0, re0, 0, 0, 0);
-            im0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, times_i_conj(b0), im0, 0, 0, 0);
-            re1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, b1, re1, 0, 0, 0);
-            im1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, times_i_conj(b1), im1, 0, 0, 0);
-        }
-        // score the tile: lane holds column e0 + col (and + 32) for its 16 rows
-        const float w0 = a.inv_norm2[e0 + col], w1 = a.inv_norm2[e0 + 32 + col];
-        const int32_t i0 = (int32_t)(e0 + col), i1 = (int32_t)(e0 + 32 + col);
+        const int64_t E0 = et * kTileRows;
+        const uint4 *ga0 = reinterpret_cast<const uint4 *>(a.xh + (P0 + crow0) * kp + 8 * cpart);
+        const uint4 *ga1 = reinterpret_cast<const uint4 *>(a.xh + (P0 + crow0 + 64) * kp + 8 * cpart);
+        const uint4 *gb0 = reinterpret_cast<const uint4 *>(a.dh + (E0 + crow0) * kp + 8 * cpart);
+        const uint4 *gb1 = reinterpret_cast<const uint4 *>(a.dh + (E0 + crow0 + 64) * kp + 8 * cpart);
+        uint4 ra0 = ga0[0], ra1 = ga1[0], rb0 = gb0[0], rb1 = gb1[0];
+        f32x16 acc[2][2][2];  // [pixel block][entry block][re, im]
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            float s0 = (re0[r] * re0[r] + im0[r] * im0[r]) * w0;
-            float s1 = (re1[r] * re1[r] + im1[r] * im1[r]) * w1;
-            if (w0 < 0.0f) s0 = -1.0f;
-            if (w1 < 0.0f) s1 = -1.0f;
-            Best c = better(s1, i1, s0, i0) ? Best{s1, i1, re1[r], im1[r]} : Best{s0, i0, re0[r], im0[r]};
-            // best over the 32 columns of this half wave (fixed butterfly; ties -> lower index)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int m = 1; m < 32; m <<= 1) {
-                const float os = __shfl_xor(c.score, m, 32);
-                const int32_t oi = __shfl_xor(c.idx, m, 32);
-                const float ore = __shfl_xor(c.re, m, 32);
-                const float oim = __shfl_xor(c.im, m, 32);
-                if (better(os, oi, c.score, c.idx)) c = Best{os, oi, ore, oim};
+            for (int j = 0; j < 2; ++j) {
+                acc[i][j][0] = f32x16{};
+                acc[i][j][1] = f32x16{};
             }
-            if (better(c.score, c.idx, best[r].score, best[r].idx)) best[r] = c;
+        for (int st = 0; st < n_stage; ++st) {
+            const int buf = st & 1;
+            _Float16 *la = lds[buf][0];
+            _Float16 *lb = lds[buf][1];
+            *reinterpret_cast<uint4 *>(la + crow0 * kLdsRow + 8 * cpart) = ra0;
+            *reinterpret_cast<uint4 *>(la + (crow0 + 64) * kLdsRow + 8 * cpart) = ra1;
+            *reinterpret_cast<uint4 *>(lb + crow0 * kLdsRow + 8 * cpart) = rb0;
+            *reinterpret_cast<uint4 *>(lb + (crow0 + 64) * kLdsRow + 8 * cpart) = rb1;
+            __syncthreads();
+            if (st + 1 < n_stage) {  // next slice in flight while this one is multiplied
+                const int q = (st + 1) * (kSlice / 8);
+                ra0 = ga0[q];
+                ra1 = ga1[q];
+                rb0 = gb0[q];
+                rb1 = gb1[q];
+            }
+#pragma unroll
+            for (int kk = 0; kk < kSlice; kk += 16) {
+                half8 av[2], bv[2], bw[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    av[i] = *reinterpret_cast<const half8 *>(la + (wp + 32 * i + col) * kLdsRow + kk + 8 * half);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    bv[j] = *reinterpret_cast<const half8 *>(lb + (we + 32 * j + col) * kLdsRow + kk + 8 * half);
+                    bw[j] = times_i_conj(bv[j]);
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        acc[i][j][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av[i], bv[j], acc[i][j][0], 0, 0, 0);
+                        acc[i][j][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av[i], bw[j], acc[i][j][1], 0, 0, 0);
+                    }
+            }
+            // the other buffer is written next; one barrier per stage suffices
+            // because stage st + 1 writes buffer buf ^ 1, last read in stage st - 1
+        }
+        __syncthreads();  // all reads of this tile done before the next tile's first write
+        // score: this lane holds columns E0 + we + 32 j + col
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int64_t e = E0 + we + 32 * j + col;
+            const float w = a.inv_norm2[e];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float re = acc[i][j][0][r], im = acc[i][j][1][r];
+                    const float s = w < 0.0f ? -1.0f : (re * re + im * im) * w;
+                    if (better(s, (int32_t)e, bs[i][r], bi[i][r])) {
+                        bs[i][r] = s;
+                        bi[i][r] = (int32_t)e;
+                    }
+                }
         }
     }
-    // one lane per half wave writes its 16 rows
-    if (col == 0) {
+    // best over the 32 columns of each half wave; then one lane per half wave writes
+    // its rows to the partial plane of (split, entry half of the tile)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int64_t p = p0 + 8 * (r >> 2) + 4 * half + (r & 3);
-            const int64_t o = (int64_t)blockIdx.y * a.n_pix_pad + p;
-            a.part_score[o] = best[r].score;
-            a.part_idx[o] = best[r].idx;
-            a.part_ip[o] = make_float2(best[r].re, best[r].im);
+            float s = bs[i][r];
+            int32_t id = bi[i][r];
+#pragma unroll
+            for (int m = 1; m < 32; m <<= 1) {
+                const float os = __shfl_xor(s, m, 32);
+                const int32_t oi = __shfl_xor(id, m, 32);
+                if (better(os, oi, s, id)) {
+                    s = os;
+                    id = oi;
+                }
+            }
+            bs[i][r] = s;
+            bi[i][r] = id;
         }
+    if (col == 0) {
+        const int64_t plane = (int64_t)blockIdx.y * 2 + (wave >> 1);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t p = P0 + wp + 32 * i + 8 * (r >> 2) + 4 * half + (r & 3);
+                const int64_t o = plane * a.n_pix_pad + p;
+                a.part_score[o] = bs[i][r];
+                a.part_idx[o] = bi[i][r];
+            }
     }
 }
 
-// Best over the splits (in split order, i.e. entry order) and the output in
-// the caller's units.
+// One wavefront per pixel: the best of the partial planes (any order: the
+// order (score desc, index asc) is total), then <d, x> of the chosen entry
+// recomputed in FP64 from the binary16 operands, in the caller's units.
 __global__ __launch_bounds__(kMrfWG) void k_mrf_final(MrfArgs a, int32_t *best, double *proj) {
-    const int64_t p = (int64_t)blockIdx.x * kMrfWG + threadIdx.x;
-    if (p >= a.n_pix) return;
-    float bs = -1.0f;
-    int32_t bi = 0x7fffffff;
-    float2 ip = make_float2(0.0f, 0.0f);
-    for (int64_t s = 0; s < a.n_split; ++s) {
+    const int lane = threadIdx.x & 63;
+    const int64_t p = (int64_t)blockIdx.x * kMrfWaves + (threadIdx.x >> 6);
+    if (p >= a.n_pix) return;  // uniform per wavefront
+    float bsc = -1.0f;
+    int32_t bid = 0x7fffffff;
+    for (int64_t s = lane; s < a.n_planes; s += 64) {
         const int64_t o = s * a.n_pix_pad + p;
-        const float sc = a.part_score[o];
-        const int32_t id = a.part_idx[o];
-        if (better(sc, id, bs, bi)) {
-            bs = sc;
-            bi = id;
-            ip = a.part_ip[o];
+        if (better(a.part_score[o], a.part_idx[o], bsc, bid)) {
+            bsc = a.part_score[o];
+            bid = a.part_idx[o];
         }
     }
-    if (bi == 0x7fffffff || bs < 0.0f) {  // no valid entry
-        best[p] = -1;
-        proj[2 * p] = 0.0;
-        proj[2 * p + 1] = 0.0;
+    for (int m = 1; m < 64; m <<= 1) {
+        const float os = __shfl_xor(bsc, m);
+        const int32_t oi = __shfl_xor(bid, m);
+        if (better(os, oi, bsc, bid)) {
+            bsc = os;
+            bid = oi;
+        }
+    }
+    if (bid == 0x7fffffff || bsc < 0.0f) {  // no valid entry
+        if (lane == 0) {
+            best[p] = -1;
+            proj[2 * p] = 0.0;
+            proj[2 * p + 1] = 0.0;
+        }
         return;
     }
-    best[p] = bi;
-    // <d, x>/||d|| on the scaled operands is 2^kx times the caller's value
-    const double f = sqrt((double)a.inv_norm2[bi]) * ldexp(1.0, -a.x_exp[p]);
-    proj[2 * p] = (double)ip.x * f;
-    proj[2 * p + 1] = (double)ip.y * f;
+    const _Float16 *xr = a.xh + p * a.kp;
+    const _Float16 *dr = a.dh + (int64_t)bid * a.kp;
+    double sr = 0.0, si = 0.0;
+    for (int64_t k = 2 * lane; k < a.kp; k += 128) {
+        const double x0 = (double)xr[k], x1 = (double)xr[k + 1];
+        const double d0 = (double)dr[k], d1 = (double)dr[k + 1];
+        sr += d0 * x0 + d1 * x1;  // Re conj(d) x
+        si += d0 * x1 - d1 * x0;  // Im conj(d) x
+    }
+    for (int m = 1; m < 64; m <<= 1) {
+        sr += __shfl_xor(sr, m);
+        si += __shfl_xor(si, m);
+    }
+    if (lane == 0) {
+        best[p] = bid;
+        const double f = sqrt((double)a.inv_norm2[bid]) * ldexp(1.0, -a.x_exp[p]);
+        proj[2 * p] = sr * f;
+        proj[2 * p + 1] = si * f;
+    }
 }
 
 static int check_launch() { return hipGetLastError() == hipSuccess ? 0 : -1; }
@@ -228,14 +317,16 @@ static int check_launch() { return hipGetLastError() == hipSuccess ? 0 : -1; }
 int launch_mrf_pack(const float2 *src, int64_t n_rows, int64_t n_rows_pad, int64_t n_t, int64_t kp,
                     _Float16 *dst, int32_t *exps, float *inv_norm2, void *stream) {
     if (n_rows_pad <= 0) return 0;
-    if (n_rows_pad > 0x7fffffff || kp < 2 * n_t || kp % 16) return -1;
+    if (n_rows_pad > 0x7fffffff || kp < 2 * n_t || kp % 32) return -1;
     hipLaunchKernelGGL(k_mrf_pack, dim3((unsigned)n_rows_pad), dim3(kMrfWG), 0, (hipStream_t)stream, src, n_rows,
                        n_t, kp, dst, exps, inv_norm2);
     return check_launch();
 }
 
 int launch_mrf_match(const MrfArgs &a, void *stream) {
-    if (a.n_pix_pad % kPixTile || a.n_ent_tiles <= 0 || a.kp % 16 || a.n_split <= 0 || a.n_split > 65535) return -1;
+    if (a.n_pix_pad % kPixTile || a.n_ent_tiles <= 0 || a.kp % kSlice || a.n_split <= 0 || a.n_split > 65535 ||
+        a.n_planes != 2 * a.n_split)
+        return -1;
     dim3 grid((unsigned)(a.n_pix_pad / kPixTile), (unsigned)a.n_split);
     hipLaunchKernelGGL(k_mrf_match, grid, dim3(kMrfWG), 0, (hipStream_t)stream, a);
     return check_launch();
@@ -243,7 +334,7 @@ int launch_mrf_match(const MrfArgs &a, void *stream) {
 
 int launch_mrf_final(const MrfArgs &a, int32_t *best, double *proj, void *stream) {
     if (a.n_pix <= 0) return 0;
-    dim3 grid((unsigned)((a.n_pix + kMrfWG - 1) / kMrfWG));
+    dim3 grid((unsigned)((a.n_pix + kMrfWaves - 1) / kMrfWaves));
     hipLaunchKernelGGL(k_mrf_final, grid, dim3(kMrfWG), 0, (hipStream_t)stream, a, best, proj);
     return check_launch();
 }
