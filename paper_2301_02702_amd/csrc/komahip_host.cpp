@@ -452,6 +452,46 @@ void make_stretches(const Samples &s, int max_len, Emit emit) {
 
 }  // namespace
 
+// Moments of one precession block (points [a, b]): K = gamma_bar sum of
+// (G_n + G_{n+1}) dt_n / 2 from the block start, accumulated in order, and at
+// every ADC point of the block (cursor into the increasing ADC indices) the
+// sample's ADC index, K and elapsed time into the sample arrays. Returns the
+// number of samples written; k receives K at point b. A function of its own so
+// that the running sums stay in registers.
+static size_t block_moments(const double *__restrict T, const double *__restrict GX, const double *__restrict GY,
+                            const double *__restrict GZ, int64_t a, int64_t b, double gbar,
+                            const int64_t *__restrict AI, int64_t n_adc, int64_t &cursor, int32_t *__restrict sk,
+                            double *__restrict s0, double *__restrict s1, double *__restrict s2,
+                            double *__restrict s3, double k[3]) {
+    const double ta = T[a];
+    int64_t cur = cursor;
+    int64_t next = cur < n_adc ? AI[cur] : -1;
+    double kx = 0, ky = 0, kz = 0;
+    size_t ns = 0;
+    for (int64_t p = a;; ++p) {
+        if (next == p) {
+            sk[ns] = (int32_t)cur;
+            s0[ns] = kx;
+            s1[ns] = ky;
+            s2[ns] = kz;
+            s3[ns] = T[p] - ta;
+            ++ns;
+            ++cur;
+            next = cur < n_adc ? AI[cur] : -1;
+        }
+        if (p == b) break;
+        const double hdt = 0.5 * gbar * (T[p + 1] - T[p]);
+        kx += (GX[p] + GX[p + 1]) * hdt;
+        ky += (GY[p] + GY[p + 1]) * hdt;
+        kz += (GZ[p] + GZ[p + 1]) * hdt;
+    }
+    cursor = cur;
+    k[0] = kx;
+    k[1] = ky;
+    k[2] = kz;
+    return ns;
+}
+
 static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamma, const koma_phantom *ph,
                               const koma_sequence *q, Plan &P) {
     // reset, keeping the vectors' capacity (plans are rebuilt every call)
@@ -499,24 +539,29 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     P.n_tiles = (int64_t)P.tiles.size();
 
     // ---- event program
+    // values first: one branch-free pass (vectorised) over every array; the
+    // slow path only names the offending index
+    {
+        const double *__restrict T = q->t;
+        uint64_t nonfinite = 0;  // bit 63: some value is infinite or NaN
+        int disorder = 0;        // some interval has t[n+1] <= t[n]
+        for (int64_t i = 0; i < n_t; ++i)
+            nonfinite |= nonfinite_bit(T[i]) | nonfinite_bit(q->gx[i]) | nonfinite_bit(q->gy[i]) |
+                         nonfinite_bit(q->gz[i]);
+        for (int64_t i = 0; i < n_int; ++i) {
+            nonfinite |= nonfinite_bit(q->b1_re[i]) | nonfinite_bit(q->b1_im[i]);
+            disorder |= !(T[i + 1] > T[i]);
+        }
+        if ((nonfinite >> 63) || disorder) return check_sequence_values(ctx, q);
+    }
     // planner scratch lives per thread and only grows: large per-call
     // allocations would be fresh pages (page faults) on every call
-    thread_local std::vector<int32_t> adc_pos, smp_k;
+    thread_local std::vector<int32_t> smp_k;
     thread_local std::vector<double> smp_v[4];
-    if (adc_pos.size() < (size_t)n_t) adc_pos.resize((size_t)n_t);
-    std::fill(adc_pos.begin(), adc_pos.begin() + n_t, -1);
-    for (int64_t k = 0; k < q->n_adc; ++k) adc_pos[q->adc_idx[k]] = (int32_t)k;
     if (smp_k.size() < (size_t)q->n_adc + 1) {
         smp_k.resize((size_t)q->n_adc + 1);
         for (auto &v : smp_v) v.resize((size_t)q->n_adc + 1);
     }
-    uint64_t nonfinite = 0;  // bit 63: some value is infinite or NaN
-    int disorder = 0;        // some interval has t[n+1] <= t[n]
-    auto is_rf = [&](int64_t n) {
-        const double r = q->b1_re[n], i = q->b1_im[n];
-        nonfinite |= nonfinite_bit(r) | nonfinite_bit(i);
-        return r != 0.0 || i != 0.0;
-    };
     // moving spins: no sample-parallel deferral and no sample recurrences
     // (their phase is not linear in the sample index)
     const int defer_min = P.moving ? -1 : cfg.defer_min_adc;
@@ -527,56 +572,67 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     const double *__restrict GX = q->gx;
     const double *__restrict GY = q->gy;
     const double *__restrict GZ = q->gz;
+    const double *__restrict BR = q->b1_re;
+    const double *__restrict BI = q->b1_im;
+    const int64_t *__restrict AI = q->adc_idx;
+    const int64_t n_adc = q->n_adc;
+    int64_t cursor = 0;  // next ADC sample (indices are strictly increasing)
     int64_t a = 0;
     Samples samples{smp_k.data(), {smp_v[0].data(), smp_v[1].data(), smp_v[2].data(), smp_v[3].data()}, 0};
     for (;;) {
-        // precession block [a, b]
+        // precession block: points [a, b], intervals [a, b)
         int64_t b = a;
-        while (b < n_int && !is_rf(b)) ++b;
+        while (b < n_int && BR[b] == 0.0 && BI[b] == 0.0) ++b;
         size_t ns = 0;
-        double K[3] = {0, 0, 0};
-        double K1[3] = {0, 0, 0};  // first moments gamma_bar sum(mean(G t) dt), moving spins only
         const double ta = T[a];
-        for (int64_t p = a; p <= b; ++p) {
-            nonfinite |= nonfinite_bit(T[p]) | nonfinite_bit(GX[p]) | nonfinite_bit(GY[p]) | nonfinite_bit(GZ[p]);
-            if (adc_pos[p] >= 0) {
-                if (moving) {
+        int64_t next = cursor < n_adc ? AI[cursor] : -1;
+        // running moments in locals (registers); a sample at point p sees the
+        // moments accumulated up to p
+        double kx = 0, ky = 0, kz = 0;
+        double k1x = 0, k1y = 0, k1z = 0;  // first moments gamma_bar sum(mean(G t) dt), moving spins only
+        int32_t *__restrict sk = smp_k.data();
+        double *__restrict s0 = smp_v[0].data(), *__restrict s1 = smp_v[1].data();
+        double *__restrict s2 = smp_v[2].data(), *__restrict s3 = smp_v[3].data();
+        if (!moving) {
+            double k[3];
+            ns = block_moments(T, GX, GY, GZ, a, b, gbar, AI, n_adc, cursor, sk, s0, s1, s2, s3, k);
+            kx = k[0];
+            ky = k[1];
+            kz = k[2];
+        } else {
+            int64_t p = a;
+            for (;;) {
+                if (next == p) {
                     Event e{};
                     e.kind = EV_ADC;
                     e.a0 = (int32_t)P.inl_k.size();
                     e.count = 1;
-                    e.d[0] = K[0];
-                    e.d[1] = K[1];
-                    e.d[2] = K[2];
+                    e.d[0] = kx;
+                    e.d[1] = ky;
+                    e.d[2] = kz;
                     e.d[3] = T[p] - ta;
-                    e.c64[0] = K1[0];
-                    e.c64[1] = K1[1];
-                    e.c64[2] = K1[2];
-                    P.inl_k.push_back(adc_pos[p]);
+                    e.c64[0] = k1x;
+                    e.c64[1] = k1y;
+                    e.c64[2] = k1z;
+                    P.inl_k.push_back((int32_t)cursor);
                     P.ev.push_back(e);
-                } else {
-                    smp_k[ns] = adc_pos[p];
-                    smp_v[0][ns] = K[0];
-                    smp_v[1][ns] = K[1];
-                    smp_v[2][ns] = K[2];
-                    smp_v[3][ns] = T[p] - ta;
-                    ++ns;
+                    ++cursor;
+                    next = cursor < n_adc ? AI[cursor] : -1;
                 }
-            }
-            if (p < b) {
-                disorder |= !(T[p + 1] > T[p]);
-                const double hdt = 0.5 * gbar * (T[p + 1] - T[p]);
-                K[0] += (GX[p] + GX[p + 1]) * hdt;
-                K[1] += (GY[p] + GY[p + 1]) * hdt;
-                K[2] += (GZ[p] + GZ[p + 1]) * hdt;
-                if (moving) {
-                    const double t0 = T[p], t1 = T[p + 1];
-                    K1[0] += (GX[p] * t0 + GX[p + 1] * t1) * hdt;
-                    K1[1] += (GY[p] * t0 + GY[p + 1] * t1) * hdt;
-                    K1[2] += (GZ[p] * t0 + GZ[p + 1] * t1) * hdt;
-                }
+                if (p == b) break;
+                const double t0 = T[p], t1 = T[p + 1];
+                const double hdt = 0.5 * gbar * (t1 - t0);
+                kx += (GX[p] + GX[p + 1]) * hdt;
+                ky += (GY[p] + GY[p + 1]) * hdt;
+                kz += (GZ[p] + GZ[p + 1]) * hdt;
+                k1x += (GX[p] * t0 + GX[p + 1] * t1) * hdt;
+                k1y += (GY[p] * t0 + GY[p + 1] * t1) * hdt;
+                k1z += (GZ[p] * t0 + GZ[p + 1] * t1) * hdt;
+                ++p;
             }
         }
+        const double K[3] = {kx, ky, kz};
+        const double K1[3] = {k1x, k1y, k1z};
         samples.n = ns;
         const bool defer = defer_min >= 0 && b > a && (int64_t)samples.size() >= std::max(1, defer_min);
         if (samples.size() > 0) {
@@ -631,7 +687,6 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
         // excitation interval b
         {
             const double dt = q->t[b + 1] - q->t[b];
-            disorder |= !(dt > 0.0);
             const double v[8] = {0.5 * (q->gx[b] + q->gx[b + 1]),
                                  0.5 * (q->gy[b] + q->gy[b + 1]),
                                  0.5 * (q->gz[b] + q->gz[b + 1]),
@@ -686,7 +741,6 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
         a = b + 1;
         if ((int64_t)P.ev.size() >= ((int64_t)1 << 31) - 4) return fail(ctx, KOMA_E_SEQUENCE, "sequence too long");
     }
-    if ((nonfinite >> 63) || disorder) return check_sequence_values(ctx, q);
     if ((int64_t)P.inl_k.size() + (int64_t)P.def_k.size() != q->n_adc)
         return fail(ctx, KOMA_E_SEQUENCE, "internal: ADC samples lost in packing");
 
@@ -1531,7 +1585,7 @@ koma_status koma_mrf_match(koma_ctx *ctx, const float *dict, int64_t n_entries, 
     HIPCHK(ctx, hipSetDevice(ctx->device));
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     koma_status st;
-    const int64_t kp = (2 * n_t + 31) / 32 * 32;
+    const int64_t kp = (2 * n_t + 63) / 64 * 64;  // a multiple of every slice width the kernel may use
     const int64_t n_ent_tiles = (n_entries + 127) / 128;
     const int64_t n_ent_pad = n_ent_tiles * 128;
     const int64_t n_pix_pad = (n_pix + 127) / 128 * 128;
@@ -1564,7 +1618,7 @@ koma_status koma_mrf_match(koma_ctx *ctx, const float *dict, int64_t n_entries, 
         d_best = (int32_t *)ctx->m_best.p;
         d_proj = (double *)ctx->m_proj.p;
     }
-    _Float16 *dh = (_Float16 *)ctx->m_dh.p, *xh = (_Float16 *)ctx->m_xh.p;
+    uint16_t *dh = (uint16_t *)ctx->m_dh.p, *xh = (uint16_t *)ctx->m_xh.p;
     LAUNCH(ctx, K_AUX, n_ent_pad * n_t, s,
            launch_mrf_pack(src_d, n_entries, n_ent_pad, n_t, kp, dh, (int32_t *)ctx->m_dexp.p, (float *)ctx->m_inv.p, s));
     LAUNCH(ctx, K_AUX, n_pix_pad * n_t, s,

@@ -7,8 +7,8 @@
 namespace koma {
 
 struct MrfArgs {
-    const _Float16 *xh;    // [n_pix_pad][kp] fingerprints, binary16 (re, im) interleaved
-    const _Float16 *dh;    // [n_ent_tiles * 128][kp] entries, same layout
+    const uint16_t *xh;    // [n_pix_pad][kp] fingerprints, binary16 bits (re, im) interleaved
+    const uint16_t *dh;    // [n_ent_tiles * 128][kp] entries, same layout
     const float *inv_norm2;  // [n_ent_tiles * 128] 1 / ||entry||^2 (-1: padding or zero entry)
     const int32_t *x_exp;  // [n_pix_pad] power-of-two exponent applied to each fingerprint
     int64_t kp;            // padded contraction length (halfs), multiple of 32
@@ -21,7 +21,7 @@ struct MrfArgs {
 };
 
 int launch_mrf_pack(const float2 *src, int64_t n_rows, int64_t n_rows_pad, int64_t n_t, int64_t kp,
-                    _Float16 *dst, int32_t *exps, float *inv_norm2, void *stream);
+                    uint16_t *dst, int32_t *exps, float *inv_norm2, void *stream);
 int launch_mrf_match(const MrfArgs &a, void *stream);
 int launch_mrf_final(const MrfArgs &a, int32_t *best, double *proj, void *stream);
 

@@ -122,11 +122,17 @@ __device__ __forceinline__ half8 times_i_conj(half8 v) {
 // buffered. Wavefront w owns pixels 64 (w & 1) .. +63 and entries
 // 64 (w >> 1) .. +63 of the tile: 2 x 2 blocks of 32 x 32, each with a Re
 // and an Im accumulator (8 MFMA accumulators of 16 floats per lane).
-constexpr int kSlice = 32;          // halfs of the contraction axis per stage
+#ifndef KOMA_MRF_SLICE
+#define KOMA_MRF_SLICE 32
+#endif
+#ifndef KOMA_MRF_MINW
+#define KOMA_MRF_MINW 1
+#endif
+constexpr int kSlice = KOMA_MRF_SLICE;  // halfs of the contraction axis per stage
 constexpr int kLdsRow = kSlice + 8; // padded row (80 bytes) against bank conflicts
 constexpr int kTileRows = 128;
 
-__global__ __launch_bounds__(kMrfWG) void k_mrf_match(MrfArgs a) {
+__global__ __launch_bounds__(kMrfWG, KOMA_MRF_MINW) void k_mrf_match(MrfArgs a) {
     __shared__ __attribute__((aligned(16))) _Float16 lds[2][2][kTileRows * kLdsRow];  // [stage][A|B]
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
@@ -149,17 +155,25 @@ __global__ __launch_bounds__(kMrfWG) void k_mrf_match(MrfArgs a) {
             bi[i][r] = 0x7fffffff;
         }
 
-    // global -> LDS copy: 4 chunks of 16 bytes per thread and stage (A: 512, B: 512)
-    const int crow0 = tid >> 2, cpart = tid & 3;  // chunk tid and tid + 256: rows crow0, crow0 + 64
+    // global -> LDS copy of a slice: kNC chunks of 16 bytes per row, kPer chunks
+    // per thread and operand (chunk c = tid + 256 u: row c / kNC, part c % kNC)
+    constexpr int kNC = kSlice / 8;
+    constexpr int kPer = kTileRows * kNC / kMrfWG;
+    const int cpart = tid % kNC;
     const int64_t t0 = (int64_t)blockIdx.y * a.tiles_per_split;
     const int64_t t1 = min(t0 + a.tiles_per_split, a.n_ent_tiles);
     for (int64_t et = t0; et < t1; ++et) {
         const int64_t E0 = et * kTileRows;
-        const uint4 *ga0 = reinterpret_cast<const uint4 *>(a.xh + (P0 + crow0) * kp + 8 * cpart);
-        const uint4 *ga1 = reinterpret_cast<const uint4 *>(a.xh + (P0 + crow0 + 64) * kp + 8 * cpart);
-        const uint4 *gb0 = reinterpret_cast<const uint4 *>(a.dh + (E0 + crow0) * kp + 8 * cpart);
-        const uint4 *gb1 = reinterpret_cast<const uint4 *>(a.dh + (E0 + crow0 + 64) * kp + 8 * cpart);
-        uint4 ra0 = ga0[0], ra1 = ga1[0], rb0 = gb0[0], rb1 = gb1[0];
+        const uint4 *ga[kPer], *gb[kPer];
+        uint4 ra[kPer], rb[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int row = (tid + kMrfWG * u) / kNC;
+            ga[u] = reinterpret_cast<const uint4 *>(a.xh + (P0 + row) * kp + 8 * cpart);
+            gb[u] = reinterpret_cast<const uint4 *>(a.dh + (E0 + row) * kp + 8 * cpart);  // binary16 bits
+            ra[u] = ga[u][0];
+            rb[u] = gb[u][0];
+        }
         f32x16 acc[2][2][2];  // [pixel block][entry block][re, im]
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -172,17 +186,20 @@ __global__ __launch_bounds__(kMrfWG) void k_mrf_match(MrfArgs a) {
             const int buf = st & 1;
             _Float16 *la = lds[buf][0];
             _Float16 *lb = lds[buf][1];
-            *reinterpret_cast<uint4 *>(la + crow0 * kLdsRow + 8 * cpart) = ra0;
-            *reinterpret_cast<uint4 *>(la + (crow0 + 64) * kLdsRow + 8 * cpart) = ra1;
-            *reinterpret_cast<uint4 *>(lb + crow0 * kLdsRow + 8 * cpart) = rb0;
-            *reinterpret_cast<uint4 *>(lb + (crow0 + 64) * kLdsRow + 8 * cpart) = rb1;
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int row = (tid + kMrfWG * u) / kNC;
+                *reinterpret_cast<uint4 *>(la + row * kLdsRow + 8 * cpart) = ra[u];
+                *reinterpret_cast<uint4 *>(lb + row * kLdsRow + 8 * cpart) = rb[u];
+            }
             __syncthreads();
             if (st + 1 < n_stage) {  // next slice in flight while this one is multiplied
-                const int q = (st + 1) * (kSlice / 8);
-                ra0 = ga0[q];
-                ra1 = ga1[q];
-                rb0 = gb0[q];
-                rb1 = gb1[q];
+                const int q = (st + 1) * kNC;
+#pragma unroll
+                for (int u = 0; u < kPer; ++u) {
+                    ra[u] = ga[u][q];
+                    rb[u] = gb[u][q];
+                }
             }
 #pragma unroll
             for (int kk = 0; kk < kSlice; kk += 16) {
@@ -291,8 +308,8 @@ __global__ __launch_bounds__(kMrfWG) void k_mrf_final(MrfArgs a, int32_t *best, 
         }
         return;
     }
-    const _Float16 *xr = a.xh + p * a.kp;
-    const _Float16 *dr = a.dh + (int64_t)bid * a.kp;
+    const _Float16 *xr = reinterpret_cast<const _Float16 *>(a.xh) + p * a.kp;
+    const _Float16 *dr = reinterpret_cast<const _Float16 *>(a.dh) + (int64_t)bid * a.kp;
     double sr = 0.0, si = 0.0;
     for (int64_t k = 2 * lane; k < a.kp; k += 128) {
         const double x0 = (double)xr[k], x1 = (double)xr[k + 1];
@@ -315,11 +332,11 @@ __global__ __launch_bounds__(kMrfWG) void k_mrf_final(MrfArgs a, int32_t *best, 
 static int check_launch() { return hipGetLastError() == hipSuccess ? 0 : -1; }
 
 int launch_mrf_pack(const float2 *src, int64_t n_rows, int64_t n_rows_pad, int64_t n_t, int64_t kp,
-                    _Float16 *dst, int32_t *exps, float *inv_norm2, void *stream) {
+                    uint16_t *dst, int32_t *exps, float *inv_norm2, void *stream) {
     if (n_rows_pad <= 0) return 0;
     if (n_rows_pad > 0x7fffffff || kp < 2 * n_t || kp % 32) return -1;
     hipLaunchKernelGGL(k_mrf_pack, dim3((unsigned)n_rows_pad), dim3(kMrfWG), 0, (hipStream_t)stream, src, n_rows,
-                       n_t, kp, dst, exps, inv_norm2);
+                       n_t, kp, reinterpret_cast<_Float16 *>(dst), exps, inv_norm2);
     return check_launch();
 }
 
