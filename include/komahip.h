@@ -121,13 +121,18 @@ typedef struct {
                               summed by the sample-parallel kernel; < 0 disables it */
     int stretch_max;       /* longest run of evenly spaced samples evaluated by recurrence
                               after one exact FP64 anchor; 1..128 */
+    int sample_engine;     /* KOMA_MIXED sums of deferred samples: 0 = matrix cores (FP32
+                              MFMA: the sum over spins of c w^j as a product of an
+                              [8 x spins] and a [spins x 16] matrix per 128 samples),
+                              1 = vector ALU (complex recurrence and a register
+                              transpose). KOMA_FP64 always uses the vector ALU. */
 } koma_config;
 
 typedef struct koma_ctx koma_ctx;
 typedef struct koma_req koma_req;
 
 /* Defaults: KOMA_MIXED, auto spins per lane, 256, 4096 events, no budget,
- * 1 GiB partials, defer_min_adc 32, stretch_max 128. */
+ * 1 GiB partials, defer_min_adc 32, stretch_max 128, sample_engine 0. */
 void koma_config_default(koma_config *cfg);
 
 /* Create a context on HIP device `device` (sets it current). The context
@@ -232,6 +237,26 @@ koma_status koma_ctx_kernel_stats(koma_ctx *ctx, int kind, double *total_ms, int
  * All four arrays live where `where` says; synchronous on `hip_stream`. */
 koma_status koma_mrf_match(koma_ctx *ctx, const float *dict, int64_t n_entries, const float *fp, int64_t n_pix,
                            int64_t n_t, koma_mem where, void *hip_stream, int32_t *best, double *proj);
+
+/* Low-rank dictionary compression (the paper's LRTV reconstruction matches
+ * against a dictionary of reduced rank 5): the `rank` leading right singular
+ * vectors of the dictionary D ([n_entries][n_t][2] floats) and its singular
+ * values, by subspace iteration on D^H D with rank + oversample vectors
+ * (<= 32, <= n_t) from a fixed pseudo-random start, `iters` iterations, then a
+ * Rayleigh-Ritz step (complex Jacobi); FP64 throughout, deterministic.
+ *   basis: [n_t][rank][2] doubles, orthonormal columns, descending singular
+ *          values (each column's complex phase is arbitrary);
+ *   sv:    [rank] doubles.
+ * Arrays live where `where` says; synchronous on `hip_stream`. */
+koma_status koma_mrf_svd(koma_ctx *ctx, const float *dict, int64_t n_entries, int64_t n_t, int rank, int oversample,
+                         int iters, koma_mem where, void *hip_stream, double *basis, double *sv);
+/* Coefficients of rows ([n_rows][n_t][2] floats) in a basis ([n_t][rank][2]
+ * doubles): out[r][j] = sum_t x_r[t] basis[t][j] ([n_rows][rank][2] floats,
+ * accumulated in FP64). With an orthonormal basis, inner products of rows in
+ * its span are preserved, so koma_mrf_match on the coefficients matches in
+ * the compressed domain. */
+koma_status koma_mrf_project(koma_ctx *ctx, const float *rows, int64_t n_rows, int64_t n_t, const double *basis,
+                             int rank, koma_mem where, void *hip_stream, float *out);
 
 /* ---- sequence-aware time stepping ----------------------------------------
  * Section "Simulation blocks, Regime Switching, and Sequence-Aware Time

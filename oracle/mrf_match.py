@@ -68,3 +68,17 @@ def match_rounded(dictionary, x):
     # scales as 2^-kx with x's
     proj = ip[rows, best] / np.sqrt(norm2[best]) * np.ldexp(1.0, -kx)
     return best.astype(np.int64), proj, score[rows, best], score
+
+
+def svd_basis(dictionary, rank):
+    """The `rank` leading right singular vectors (columns of V, [n_t, rank])
+    and singular values of the dictionary, D = U S V^H, in FP64 (the low-rank
+    compression of the paper's LRTV matching, rank 5)."""
+    d = np.asarray(dictionary, dtype=np.complex128)
+    _, s, vh = np.linalg.svd(d, full_matrices=False)
+    return vh[:rank].conj().T, s[:rank]
+
+
+def project(rows, basis):
+    """Coefficients of rows in a basis: c_j = sum_t x_t basis[t, j]."""
+    return np.asarray(rows, dtype=np.complex128) @ np.asarray(basis, dtype=np.complex128)

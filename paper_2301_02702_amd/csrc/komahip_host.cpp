@@ -24,6 +24,7 @@
 
 #include "komahip.h"
 #include "komahip_internal.h"
+#include "komahip_lowrank.h"
 #include "komahip_mrf.h"
 
 using namespace koma;
@@ -146,6 +147,7 @@ struct koma_ctx {
         s_mxy, s_mz, s_flags, s_mf, s_ph[kPhArrays];
     // MRF matching scratch (grow-only)
     DevMem m_src_d, m_src_x, m_dh, m_xh, m_dexp, m_xexp, m_inv, m_ps, m_pi, m_best, m_proj;
+    DevMem l_v, l_y, l_zp, l_z, l_basis, l_sv, l_out;  // dictionary compression scratch
 };
 
 struct koma_req {
@@ -288,6 +290,8 @@ static koma_status check_config(koma_ctx *ctx, const koma_config *c) {
     if (c->partial_budget < ((size_t)1 << 20)) return fail(ctx, KOMA_E_ARG, "partial_budget must be >= 1 MiB");
     if (c->stretch_max < 1 || c->stretch_max > kStretchMax)
         return fail(ctx, KOMA_E_ARG, "stretch_max must be in [1, %d]", kStretchMax);
+    if (c->sample_engine != 0 && c->sample_engine != 1)
+        return fail(ctx, KOMA_E_ARG, "sample_engine must be 0 (matrix cores) or 1 (vector ALU)");
     return KOMA_OK;
 }
 
@@ -922,6 +926,7 @@ static koma_status run_chunk(koma_ctx *ctx, const Plan &P, bool fp64, const Bufs
     a.pb = B.pb;
     a.col0 = c.c0;
     a.cols = c.c1 - c.c0;
+    a.engine = ctx->cfg.sample_engine;
     const int64_t max_st = 65535 * P.per_wg;  // grid.y limit
     for (int64_t s0 = c.s0; s0 < c.s1; s0 += max_st) {
         a.s0 = s0;
@@ -997,6 +1002,7 @@ void koma_config_default(koma_config *cfg) {
     cfg->partial_budget = (size_t)1 << 30;
     cfg->defer_min_adc = 32;
     cfg->stretch_max = 128;
+    cfg->sample_engine = 0;
 }
 
 koma_status koma_ctx_create(int device, const koma_config *cfg, koma_ctx **out) {
@@ -1036,7 +1042,8 @@ void koma_ctx_destroy(koma_ctx *ctx) {
     for (DevMem *m : all) dev_free(*m);
     for (DevMem &m : ctx->s_ph) dev_free(m);
     DevMem *mrf[] = {&ctx->m_src_d, &ctx->m_src_x, &ctx->m_dh, &ctx->m_xh, &ctx->m_dexp, &ctx->m_xexp,
-                     &ctx->m_inv, &ctx->m_ps, &ctx->m_pi, &ctx->m_best, &ctx->m_proj};
+                     &ctx->m_inv, &ctx->m_ps, &ctx->m_pi, &ctx->m_best, &ctx->m_proj,
+                     &ctx->l_v, &ctx->l_y, &ctx->l_zp, &ctx->l_z, &ctx->l_basis, &ctx->l_sv, &ctx->l_out};
     for (DevMem *m : mrf) dev_free(*m);
     dev_free(ctx->s_tables);
     if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
@@ -1644,6 +1651,88 @@ koma_status koma_mrf_match(koma_ctx *ctx, const float *dict, int64_t n_entries, 
         HIPCHK(ctx, hipMemcpyAsync(best, d_best, (size_t)n_pix * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(ctx, hipMemcpyAsync(proj, d_proj, (size_t)n_pix * 16, hipMemcpyDeviceToHost, s));
     }
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return KOMA_OK;
+}
+
+// ---------------------------------------------------------------- dictionary compression
+
+koma_status koma_mrf_svd(koma_ctx *ctx, const float *dict, int64_t n_entries, int64_t n_t, int rank, int oversample,
+                         int iters, koma_mem where, void *hip_stream, double *basis, double *sv) {
+    if (!ctx) return KOMA_E_ARG;
+    if (ctx->poisoned) return fail(ctx, KOMA_E_DEVICE, "context poisoned by an earlier device error");
+    ctx->err.clear();
+    if (where != KOMA_HOST && where != KOMA_DEVICE) return fail(ctx, KOMA_E_ARG, "bad koma_mem");
+    if (!dict || !basis || !sv) return fail(ctx, KOMA_E_ARG, "NULL array");
+    if (n_entries < 1 || n_t < 1 || n_entries > ((int64_t)1 << 30) || n_t > ((int64_t)1 << 24))
+        return fail(ctx, KOMA_E_ARG, "bad dictionary size");
+    const int p = rank + oversample;
+    if (rank < 1 || oversample < 0 || p > 32 || p > n_t || iters < 1 || iters > 10000)
+        return fail(ctx, KOMA_E_ARG, "need 1 <= rank, 0 <= oversample, rank + oversample <= min(32, n_t), iters >= 1");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    koma_status st;
+    const float2 *d = (const float2 *)dict;
+    if (where == KOMA_HOST) {
+        const size_t bd = (size_t)n_entries * n_t * 8;
+        if ((st = dev_reserve(ctx, ctx->m_src_d, bd)) != KOMA_OK) return st;
+        HIPCHK(ctx, hipMemcpyAsync(ctx->m_src_d.p, dict, bd, hipMemcpyHostToDevice, s));
+        d = (const float2 *)ctx->m_src_d.p;
+    }
+    const int64_t n_chunks = std::max<int64_t>(1, std::min<int64_t>(64, n_entries / 64));
+    if ((st = dev_reserve(ctx, ctx->l_v, (size_t)n_t * p * 16)) != KOMA_OK) return st;
+    if ((st = dev_reserve(ctx, ctx->l_z, (size_t)n_t * p * 16)) != KOMA_OK) return st;
+    if ((st = dev_reserve(ctx, ctx->l_zp, (size_t)n_chunks * n_t * p * 16)) != KOMA_OK) return st;
+    if ((st = dev_reserve(ctx, ctx->l_y, (size_t)n_entries * p * 16)) != KOMA_OK) return st;
+    double2 *dbasis = (double2 *)basis;
+    double *dsv = sv;
+    if (where == KOMA_HOST) {
+        if ((st = dev_reserve(ctx, ctx->l_basis, (size_t)n_t * rank * 16)) != KOMA_OK) return st;
+        if ((st = dev_reserve(ctx, ctx->l_sv, (size_t)rank * 8)) != KOMA_OK) return st;
+        dbasis = (double2 *)ctx->l_basis.p;
+        dsv = (double *)ctx->l_sv.p;
+    }
+    double2 *v = (double2 *)ctx->l_v.p, *y = (double2 *)ctx->l_y.p;
+    LAUNCH(ctx, K_AUX, (int64_t)iters * n_entries * n_t * p * 2, s,
+           launch_lr_iter(d, n_entries, n_t, p, iters, v, y, (double2 *)ctx->l_zp.p, n_chunks, (double2 *)ctx->l_z.p, s));
+    LAUNCH(ctx, K_AUX, n_entries * p * p, s, launch_lr_ritz(y, n_entries, v, n_t, p, rank, dbasis, dsv, s));
+    if (where == KOMA_HOST) {
+        HIPCHK(ctx, hipMemcpyAsync(basis, dbasis, (size_t)n_t * rank * 16, hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipMemcpyAsync(sv, dsv, (size_t)rank * 8, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return KOMA_OK;
+}
+
+koma_status koma_mrf_project(koma_ctx *ctx, const float *rows, int64_t n_rows, int64_t n_t, const double *basis,
+                             int rank, koma_mem where, void *hip_stream, float *out) {
+    if (!ctx) return KOMA_E_ARG;
+    if (ctx->poisoned) return fail(ctx, KOMA_E_DEVICE, "context poisoned by an earlier device error");
+    ctx->err.clear();
+    if (where != KOMA_HOST && where != KOMA_DEVICE) return fail(ctx, KOMA_E_ARG, "bad koma_mem");
+    if (!rows || !basis || !out) return fail(ctx, KOMA_E_ARG, "NULL array");
+    if (n_rows < 1 || n_t < 1 || rank < 1 || rank > 32 || n_rows > ((int64_t)1 << 30) || n_t > ((int64_t)1 << 24))
+        return fail(ctx, KOMA_E_ARG, "bad sizes (1 <= rank <= 32)");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    koma_status st;
+    const float2 *x = (const float2 *)rows;
+    const double2 *b = (const double2 *)basis;
+    float2 *o = (float2 *)out;
+    if (where == KOMA_HOST) {
+        const size_t bx = (size_t)n_rows * n_t * 8, bb = (size_t)n_t * rank * 16, bo = (size_t)n_rows * rank * 8;
+        if ((st = dev_reserve(ctx, ctx->m_src_x, bx)) != KOMA_OK) return st;
+        if ((st = dev_reserve(ctx, ctx->l_basis, bb)) != KOMA_OK) return st;
+        if ((st = dev_reserve(ctx, ctx->l_out, bo)) != KOMA_OK) return st;
+        HIPCHK(ctx, hipMemcpyAsync(ctx->m_src_x.p, rows, bx, hipMemcpyHostToDevice, s));
+        HIPCHK(ctx, hipMemcpyAsync(ctx->l_basis.p, basis, bb, hipMemcpyHostToDevice, s));
+        x = (const float2 *)ctx->m_src_x.p;
+        b = (const double2 *)ctx->l_basis.p;
+        o = (float2 *)ctx->l_out.p;
+    }
+    LAUNCH(ctx, K_AUX, n_rows * n_t * rank, s, launch_lr_xv(x, n_rows, n_t, b, rank, nullptr, o, s));
+    if (where == KOMA_HOST)
+        HIPCHK(ctx, hipMemcpyAsync(out, o, (size_t)n_rows * rank * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     return KOMA_OK;
 }

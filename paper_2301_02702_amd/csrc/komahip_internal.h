@@ -125,6 +125,7 @@ struct ParArgs {  // sample-parallel kernel
     const void *snap;
     double *pb;            // [n_sig][n_blocks][cols] double2 (grid.z = coil)
     int64_t col0, cols;    // deferred sample index of column 0, columns
+    int engine;            // mixed precision: 0 matrix cores (k_par_mm), 1 vector ALU (k_par)
 };
 
 struct ReduceArgs {  // cross-workgroup sums into the signal (grid.z = coil)

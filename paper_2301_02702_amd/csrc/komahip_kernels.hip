@@ -13,16 +13,22 @@
 //
 // Kernels:
 //   k_seq   spin-sequential: one lane per spin, every wavefront walks the
-//           shared event program (uniform branches, events read through the
-//           scalar cache). Excitation intervals, block ends, short sample
-//           runs (summed per wavefront), snapshots of block-start states.
-//   k_par   sample-parallel: a workgroup owns up to 4*S tiles of one group
-//           and a few stretches of evenly spaced samples; each lane walks S
-//           spins, evaluates one exact anchor phasor in FP64 phase and then
-//           rotates by the per-sample increment (complex recurrence), and
-//           16 samples at a time are summed over the 64 lanes by a register
-//           transpose (permlane32/16 swaps, DPP row rotations and quad
-//           permutes). The four wavefronts are added in FP64 through LDS.
+//           shared event program (uniform branches; the program is staged
+//           through LDS in chunks). Excitation intervals, block ends, short
+//           sample runs (summed per wavefront), snapshots of block-start
+//           states.
+//   k_par_mm sample-parallel, mixed precision, on the matrix cores: a
+//           workgroup owns up to 4*S tiles of one group and a few stretches
+//           of evenly spaced samples; per spin one exact anchor phasor (FP64
+//           phase) and the per-sample factor give the two factors of
+//           S[16 q + r] = sum_s (c w^(16 q)) (w^r), which FP32 MFMA
+//           instructions contract over the spins. The four wavefronts are
+//           added in FP64 through LDS.
+//   k_par   the same sums on the vector ALU (the FP64 form, and the mixed
+//           form on request): each lane walks S spins, rotates by the
+//           per-sample increment (complex recurrence), and 16 samples at a
+//           time are summed over the 64 lanes by a register transpose
+//           (permlane32/16 swaps, DPP row rotations and quad permutes).
 //   k_reduce fixed-order FP64 sum of per-wavefront / per-workgroup partials.
 //   k_export state to the caller's (Mx, My, Mz) layout.
 //
@@ -620,6 +626,141 @@ __global__ __launch_bounds__(kWG) void k_par(ParArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- k_par_mm
+//
+// The mixed-precision sample-parallel kernel on the matrix cores. For one
+// stretch, spin s contributes c_s w_s^j to sample j (c_s its anchor, w_s its
+// per-sample factor). Writing j = 16 q + r (q < 8, r < 16),
+//   S[16 q + r] = sum_s (c_s w_s^(16 q)) (w_s^r) = sum_s A[q][s] B[s][r],
+// a complex product of an 8 x n_spins and an n_spins x 16 matrix: the sum
+// over spins is the contraction. As a real product with rows (Re, Im) x q
+// and the spin's (Re, Im) pair on the contraction axis,
+//   [Re S; Im S] = [Re A, -Im A; Im A, Re A] [Re B; Im B],
+// it runs as v_mfma_f32_16x16x4f32 (FP32 products and sums), two spins per
+// instruction. Each lane forms its spin's 8 values A[q] = c w^(16 q) and 16
+// values B[r] = w^r (23 complex products, fewer roundings than a 127-step
+// recurrence), stages them through LDS, and the wavefront multiplies the 64
+// spins of the tile in 32 instructions. Lane l of the instruction holds
+// A[l % 16][l / 16], B[l / 16][l % 16] and the accumulator rows
+// 4 (l / 16) + i, column l % 16.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kSpinStride = 52;  // floats per staged spin: 16 (A) + 32 (B), padded
+
+template <int S>
+__global__ __launch_bounds__(kWG) void k_par_mm(ParArgs a) {
+    using P = Mixed;
+    using R = float;
+    __shared__ __attribute__((aligned(16))) float stage[kWavesPerWG][kWave * kSpinStride];
+    __shared__ double2 red[kWavesPerWG][kStretchMax];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const Block B = a.blocks[blockIdx.x];
+    const int64_t n_pad = a.n_tiles * kWave;
+    const int64_t coil = blockIdx.z;  // 0 without receive coils
+    const bool coils = a.ph.n_coils > 0;
+    float *my = stage[wave];
+    // this lane's operand positions: row m, contraction index k (spin pair half, re/im)
+    const int m = lane & 15, kq = lane >> 4;
+    const int q = m & 7, hi = m >> 3, comp = kq & 1, sp = kq >> 1;
+    const int a_idx = 2 * q + (hi ^ comp);             // A[m][k] = +-(Re or Im of A[q])
+    const float a_sign = (hi == 0 && comp == 1) ? -1.0f : 1.0f;
+    const int b_idx = 16 + 2 * m + comp;               // B[k][n = m] = Re or Im of w^n
+
+    const int64_t st0 = a.s0 + (int64_t)blockIdx.y * a.per_wg;
+    const int64_t st1 = min(st0 + a.per_wg, a.s1);
+    for (int64_t st = st0; st < st1; ++st) {
+        const auto &S_ = as_const(a.st)[st];
+        const int cnt = S_.count;
+        const int slot = S_.slot;
+        const int d0 = S_.d0;
+        const double k0[4] = {S_.k0[0], S_.k0[1], S_.k0[2], S_.k0[3]};
+        const double dk[4] = {S_.dk[0], S_.dk[1], S_.dk[2], S_.dk[3]};
+        // four independent accumulator chains keep the matrix pipeline busy
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
+        for (int j = 0; j < S; ++j) {
+            const int tl = wave + kWavesPerWG * j;
+            ParSpin spn{0.f, 0.f, 0.f, 0.f, __builtin_inff()};
+            C2<R> mm{R(0), R(0)};
+            if (tl < B.ntiles) {
+                const Tile T = a.tiles[B.tile0 + tl];
+                if (lane < T.count) {
+                    const int64_t i = T.spin0 + lane;
+                    spn = ParSpin{a.ph.x[i], a.ph.y[i], a.ph.z[i], a.ph.dw[i], a.ph.t2[i]};
+                    const float2 v = reinterpret_cast<const float2 *>(a.snap)[(int64_t)slot * n_pad +
+                                                                              (int64_t)(B.tile0 + tl) * kWave + lane];
+                    mm = C2<R>{v.x, v.y};
+                    if (coils)
+                        mm = cmul(mm, C2<R>{a.ph.sre[coil * a.ph.n + i], a.ph.sim[coil * a.ph.n + i]});
+                }
+            }
+            const C2<R> c = cmul(mm, par_factor<P>(spn, k0));
+            const C2<R> w = par_factor<P>(spn, dk);
+            // B[r] = w^r, A[q] = c w^(16 q), staged as this spin's row of 52 floats
+            float vals[48];
+            C2<R> p{R(1), R(0)};
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                vals[16 + 2 * r] = p.re;
+                vals[16 + 2 * r + 1] = p.im;
+                p = cmul(p, w);
+            }
+            C2<R> aq = c;  // p = w^16 now
+#pragma unroll
+            for (int qq = 0; qq < 8; ++qq) {
+                vals[2 * qq] = aq.re;
+                vals[2 * qq + 1] = aq.im;
+                aq = cmul(aq, p);
+            }
+            float4 *dst = reinterpret_cast<float4 *>(my + lane * kSpinStride);
+#pragma unroll
+            for (int v4 = 0; v4 < 12; ++v4)
+                dst[v4] = make_float4(vals[4 * v4], vals[4 * v4 + 1], vals[4 * v4 + 2], vals[4 * v4 + 3]);
+            // the stage is private to this wavefront, and its LDS operations
+            // complete in program order: the writes above are seen by the
+            // reads below, and these reads by the next tile's writes; only
+            // the compiler must not move LDS accesses across these points
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const float *src = my + sp * kSpinStride;
+#pragma unroll 2
+            for (int u = 0; u < kWave / 2; u += 4) {  // spins 2u .. 2u + 7
+                float av[4], bv[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    av[k] = a_sign * src[(2 * (u + k)) * kSpinStride + a_idx];
+                    bv[k] = src[(2 * (u + k)) * kSpinStride + b_idx];
+                }
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0], bv[0], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1], bv[1], acc1, 0, 0, 0);
+                acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2], bv[2], acc2, 0, 0, 0);
+                acc3 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[3], bv[3], acc3, 0, 0, 0);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        const f32x4 acc = (acc0 + acc1) + (acc2 + acc3);
+        // acc[i] = row 4 kq + i (q' = row & 7, Re if row < 8 else Im), column m: sample 16 q' + m
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = 4 * kq + i;
+            const int smp = 16 * (row & 7) + m;
+            double *slot_p = reinterpret_cast<double *>(&red[wave][smp]);
+            slot_p[row >> 3] = (double)acc[i];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt; i += kWG) {
+            double2 t = red[0][i];
+#pragma unroll
+            for (int wv = 1; wv < kWavesPerWG; ++wv) {
+                t.x += red[wv][i].x;
+                t.y += red[wv][i].y;
+            }
+            reinterpret_cast<double2 *>(a.pb)[(coil * a.n_blocks + (int64_t)blockIdx.x) * a.cols + (d0 - a.col0) + i] = t;
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- k_reduce
 
 // sig[k][g][adc(c)] = sum over rows r of group g (in order) of part[k][r][c],
@@ -750,6 +891,15 @@ int launch_seq(bool fp64, bool moving, const SeqArgs &a, void *stream) {
     return check_launch();
 }
 
+static void par_dispatch_mm(int spl, dim3 grid, const ParArgs &a, hipStream_t st) {
+    switch (spl) {
+        case 1: hipLaunchKernelGGL((k_par_mm<1>), grid, dim3(kWG), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_par_mm<2>), grid, dim3(kWG), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_par_mm<4>), grid, dim3(kWG), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_par_mm<8>), grid, dim3(kWG), 0, st, a); break;
+    }
+}
+
 template <class P>
 static void par_dispatch(int spl, dim3 grid, const ParArgs &a, hipStream_t st) {
     switch (spl) {
@@ -767,6 +917,8 @@ int launch_par(bool fp64, int spl, const ParArgs &a, void *stream) {
               (unsigned)(a.ph.n_coils > 0 ? a.ph.n_coils : 1));
     if (fp64)
         par_dispatch<FP64>(spl, grid, a, (hipStream_t)stream);
+    else if (a.engine == 0)
+        par_dispatch_mm(spl, grid, a, (hipStream_t)stream);
     else
         par_dispatch<Mixed>(spl, grid, a, (hipStream_t)stream);
     return check_launch();

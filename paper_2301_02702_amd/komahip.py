@@ -51,7 +51,7 @@ class koma_sequence(ctypes.Structure):
 class koma_config(ctypes.Structure):
     _fields_ = [("precision", c_int), ("spins_per_lane", c_int), ("wg_size", c_int),
                 ("chunk_events", c_int64), ("hbm_budget", c_size_t), ("partial_budget", c_size_t),
-                ("defer_min_adc", c_int), ("stretch_max", c_int)]
+                ("defer_min_adc", c_int), ("stretch_max", c_int), ("sample_engine", c_int)]
 
 
 class koma_req_info(ctypes.Structure):
@@ -116,6 +116,10 @@ EXPORTS = {
                                 POINTER(c_int64)] + [c_void_p] * 7),
     "koma_mrf_match": (c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, c_int, c_void_p,
                                c_void_p, c_void_p]),
+    "koma_mrf_svd": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_int, c_int, c_int, c_int, c_void_p,
+                             c_void_p, c_void_p]),
+    "koma_mrf_project": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_int, c_int, c_void_p,
+                                 c_void_p]),
 }
 
 _lib = None
@@ -412,6 +416,31 @@ class Context:
         _check(lib().koma_mrf_match(self.h, _ptr(d), d.shape[0], _ptr(x), x.shape[0], d.shape[1], KOMA_HOST, sh,
                                     _ptr(b), _ptr(pr)), self.h)
         return b, pr[:, 0] + 1j * pr[:, 1]
+
+    def mrf_svd(self, dictionary, rank: int = 5, oversample: int = 11, iters: int = 30):
+        """koma_mrf_svd on a host dictionary ``[n_entries, n_t]``: returns
+        (basis complex128 [n_t, rank], singular values [rank])."""
+        d = np.ascontiguousarray(np.asarray(dictionary, dtype=np.complex64))
+        n_e, n_t = d.shape
+        basis = np.zeros((n_t, rank, 2), dtype=np.float64)
+        sv = np.zeros(rank, dtype=np.float64)
+        _check(lib().koma_mrf_svd(self.h, _ptr(d), n_e, n_t, int(rank), int(oversample), int(iters), KOMA_HOST, None,
+                                  _ptr(basis), _ptr(sv)), self.h)
+        return basis[..., 0] + 1j * basis[..., 1], sv
+
+    def mrf_project(self, rows, basis):
+        """koma_mrf_project on host arrays: coefficients complex64 [n_rows, rank]."""
+        x = np.ascontiguousarray(np.asarray(rows, dtype=np.complex64))
+        b = np.asarray(basis, dtype=np.complex128)
+        bb = np.ascontiguousarray(np.stack([b.real, b.imag], -1))
+        n_rows, n_t = x.shape
+        rank = b.shape[1]
+        if b.shape[0] != n_t:
+            raise ValueError("basis must be [n_t, rank]")
+        out = np.zeros((n_rows, rank), dtype=np.complex64)
+        _check(lib().koma_mrf_project(self.h, _ptr(x), n_rows, n_t, _ptr(bb), rank, KOMA_HOST, None, _ptr(out)),
+               self.h)
+        return out
 
     def open(self, scanner, phantom, seq, where: str = "host") -> "Request":
         return Request(self, scanner, phantom, seq, where)

@@ -56,8 +56,8 @@ def rnd(rng, shape):
 
 @pytest.mark.parametrize("n_e,n_p,n_t", [(300, 500, 100), (64, 128, 8), (1, 7, 3), (257, 129, 1), (130, 300, 333)])
 def test_random_operands_match_reference(ctx, n_e, n_p, n_t):
-    """Ragged sizes over several tiles: entry tiles of 64, pixel tiles of 128,
-    contraction steps of 8 TR values."""
+    """Ragged sizes over several tiles: entry and pixel tiles of 128,
+    contraction slices of 16 TR values."""
     rng = np.random.default_rng(n_e * 7 + n_p + n_t)
     d = rnd(rng, (n_e, n_t)) * rng.uniform(0.01, 100.0, (n_e, 1)).astype(np.float32)
     e = rng.integers(0, n_e, n_p)
@@ -121,3 +121,47 @@ def test_simulated_dictionary_recovers_t1_t2(ctx):
     best, proj = ctx.mrf_match(dic, x)
     check(best, proj, dic, x, "simulated mrf40")
     assert np.mean(best == e) > 0.99
+
+
+def test_svd_recovers_a_planted_subspace(ctx):
+    rng = np.random.default_rng(11)
+    n_e, n_t, r = 3000, 200, 5
+    q, _ = np.linalg.qr(rng.normal(size=(n_t, r)) + 1j * rng.normal(size=(n_t, r)))
+    qa, _ = np.linalg.qr(rng.normal(size=(n_e, r)) + 1j * rng.normal(size=(n_e, r)))
+    norms = np.array([50.0, 20.0, 7.0, 3.0, 1.0])
+    d = ((qa * norms) @ q.conj().T).astype(np.complex64)
+    v, s = ctx.mrf_svd(d, rank=r, oversample=3, iters=20)
+    from oracle import mrf_match as M
+    vr, sr = M.svd_basis(d, r)  # of the float32-rounded dictionary
+    ep = np.max(np.abs(v @ v.conj().T - vr @ vr.conj().T))
+    es = np.max(np.abs(s - sr) / sr)
+    say(f"[mrf svd] planted rank {r}: projector diff {ep:.2e}, singular values rel {es:.2e}")
+    assert ep < 1e-9 and es < 1e-9
+    assert np.allclose(v.conj().T @ v, np.eye(r), atol=1e-10)
+
+
+def test_svd_and_compressed_matching_of_a_simulated_dictionary(ctx):
+    """The rank-5 basis of a GPU-simulated FISP dictionary against the FP64
+    SVD, projection against the reference, and matching in the compressed
+    domain against full matching."""
+    from oracle import mrf_match as M
+    from tests._gpu import case
+    sc, ph, seq = case("mrf40")
+    ctx.set_config("mixed")
+    dic = ctx.simulate(sc, ph, seq).astype(np.complex64)
+    v, s = ctx.mrf_svd(dic, rank=5)
+    vr, sr = M.svd_basis(dic, 5)
+    ep = np.max(np.abs(v @ v.conj().T - vr @ vr.conj().T))
+    es = np.max(np.abs(s - sr) / sr)
+    assert ep < 1e-6 and es < 1e-8, (ep, es)
+    rng = np.random.default_rng(13)
+    e = rng.integers(0, 40, 300)
+    x = (dic[e] * 0.9 + 0.005 * np.abs(dic).max() * rnd(rng, (300, seq.n_adc))).astype(np.complex64)
+    cd = ctx.mrf_project(dic, v)
+    cx = ctx.mrf_project(x, v)
+    assert np.allclose(cd, M.project(dic, v), rtol=1e-5, atol=1e-6 * np.abs(cd).max())
+    bf, _ = ctx.mrf_match(dic, x)
+    bc, _ = ctx.mrf_match(cd, cx)
+    agree = float(np.mean(bf == bc))
+    say(f"[mrf svd] mrf40 rank 5: projector diff {ep:.2e}, sv rel {es:.2e}, compressed vs full picks {agree:.3f}")
+    assert agree > 0.95

@@ -100,3 +100,32 @@ def test_simulated_mrf_dictionary_identifies_t1_t2(M, oracle_mod):
     best, proj, _ = M.match(dic, x)
     assert np.array_equal(best, e)
     assert np.allclose(np.abs(proj), 0.8 * np.linalg.norm(dic[e], axis=1), rtol=0.02)
+
+
+def test_svd_basis_recovers_a_planted_subspace(M):
+    """A dictionary built as A B with B (rank x n_t) of orthonormal rows and
+    A with orthogonal columns of known norms: the leading right singular
+    vectors span B's rows and the singular values are those norms."""
+    rng = np.random.default_rng(11)
+    n_e, n_t, r = 300, 80, 5
+    q, _ = np.linalg.qr(rng.normal(size=(n_t, r)) + 1j * rng.normal(size=(n_t, r)))
+    b = q.conj().T                                   # r x n_t, orthonormal rows
+    qa, _ = np.linalg.qr(rng.normal(size=(n_e, r)) + 1j * rng.normal(size=(n_e, r)))
+    norms = np.array([50.0, 20.0, 7.0, 3.0, 1.0])
+    d = (qa * norms) @ b
+    v, s = M.svd_basis(d, r)
+    assert np.allclose(s, norms, rtol=1e-12)
+    pv = v @ v.conj().T
+    pb = b.conj().T @ b
+    assert np.max(np.abs(pv - pb)) < 1e-12
+    assert np.allclose(v.conj().T @ v, np.eye(r), atol=1e-12)
+
+
+def test_projection_preserves_inner_products_in_the_span(M):
+    rng = np.random.default_rng(12)
+    q, _ = np.linalg.qr(rng.normal(size=(60, 4)) + 1j * rng.normal(size=(60, 4)))
+    coef = rng.normal(size=(10, 4)) + 1j * rng.normal(size=(10, 4))
+    rows = coef @ q.conj().T                          # in span(q)
+    c = M.project(rows, q)
+    assert np.allclose(c, coef, atol=1e-12)
+    assert np.allclose(rows @ rows.conj().T, c @ c.conj().T, atol=1e-12)
