@@ -644,14 +644,78 @@ __global__ __launch_bounds__(kWG) void k_par(ParArgs a) {
 // A[l % 16][l / 16], B[l / 16][l % 16] and the accumulator rows
 // 4 (l / 16) + i, column l % 16.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int kSpinStride = 52;  // floats per staged spin: 16 (A) + 32 (B), padded
+constexpr int kSpinStride = 48;  // floats per staged spin: 16 (A) + 32 (B)
+
+// This lane's spin of tile slot j of the block: its anchor c (snapshot times
+// the exact FP64-phase factor, times the coil sensitivity) and per-sample
+// factor w, and the 48 floats it stages: A[q] = c w^(16 q) (q < 8) and
+// B[r] = w^r (r < 16), (Re, Im) interleaved. Powers by a shallow product
+// tree (depth 5 instead of a 23-step chain). Lanes without a spin stage zeros
+// in A.
+__device__ __forceinline__ void mm_operands(const ParArgs &a, const Block &B, int wave, int lane, int j, int slot,
+                                            int64_t n_pad, int64_t coil, bool coils, const double *k0,
+                                            const double *dk, float *vals) {
+    using R = float;
+    const int tl = wave + kWavesPerWG * j;
+    ParSpin spn{0.f, 0.f, 0.f, 0.f, __builtin_inff()};
+    C2<R> mm{R(0), R(0)};
+    if (tl < B.ntiles) {
+        const Tile T = a.tiles[B.tile0 + tl];
+        if (lane < T.count) {
+            const int64_t i = T.spin0 + lane;
+            spn = ParSpin{a.ph.x[i], a.ph.y[i], a.ph.z[i], a.ph.dw[i], a.ph.t2[i]};
+            const float2 v = reinterpret_cast<const float2 *>(a.snap)[(int64_t)slot * n_pad +
+                                                                      (int64_t)(B.tile0 + tl) * kWave + lane];
+            mm = C2<R>{v.x, v.y};
+            if (coils) mm = cmul(mm, C2<R>{a.ph.sre[coil * a.ph.n + i], a.ph.sim[coil * a.ph.n + i]});
+        }
+    }
+    const C2<R> c = cmul(mm, par_factor<Mixed>(spn, k0));
+    const C2<R> w = par_factor<Mixed>(spn, dk);
+    C2<R> pw[16];
+    pw[0] = C2<R>{R(1), R(0)};
+    pw[1] = w;
+    pw[2] = cmul(w, w);
+    pw[3] = cmul(pw[2], w);
+    pw[4] = cmul(pw[2], pw[2]);
+#pragma unroll
+    for (int r = 5; r < 8; ++r) pw[r] = cmul(pw[4], pw[r - 4]);
+    const C2<R> w8 = cmul(pw[4], pw[4]);
+    pw[8] = w8;
+#pragma unroll
+    for (int r = 9; r < 16; ++r) pw[r] = cmul(w8, pw[r - 8]);
+    const C2<R> w16 = cmul(w8, w8);
+    const C2<R> w32 = cmul(w16, w16);
+    const C2<R> w64 = cmul(w32, w32);
+    C2<R> aq[8];
+    aq[0] = c;
+    aq[1] = cmul(c, w16);
+    aq[2] = cmul(c, w32);
+    aq[3] = cmul(aq[1], w32);
+#pragma unroll
+    for (int qq = 4; qq < 8; ++qq) aq[qq] = cmul(aq[qq - 4], w64);
+#pragma unroll
+    for (int qq = 0; qq < 8; ++qq) {
+        vals[2 * qq] = aq[qq].re;
+        vals[2 * qq + 1] = aq[qq].im;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        vals[16 + 2 * r] = pw[r].re;
+        vals[16 + 2 * r + 1] = pw[r].im;
+    }
+}
 
 template <int S>
 __global__ __launch_bounds__(kWG) void k_par_mm(ParArgs a) {
     using P = Mixed;
     using R = float;
+    // per-wavefront operand stages; after a stretch's products the same
+    // memory holds the four wavefronts' sample sums (48 KB: 3 workgroups per CU)
     __shared__ __attribute__((aligned(16))) float stage[kWavesPerWG][kWave * kSpinStride];
-    __shared__ double2 red[kWavesPerWG][kStretchMax];
+    static_assert(sizeof(double2) * kWavesPerWG * kStretchMax <= sizeof(float) * kWavesPerWG * kWave * kSpinStride,
+                  "sample sums fit in the stage");
+    double2(*red)[kStretchMax] = reinterpret_cast<double2(*)[kStretchMax]>(&stage[0][0]);
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const Block B = a.blocks[blockIdx.x];
@@ -677,40 +741,11 @@ __global__ __launch_bounds__(kWG) void k_par_mm(ParArgs a) {
         const double dk[4] = {S_.dk[0], S_.dk[1], S_.dk[2], S_.dk[3]};
         // four independent accumulator chains keep the matrix pipeline busy
         f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
+        // operands of the next tile are formed while the current tile's
+        // products run (software pipelining over the S tiles)
+        float vals[48];
+        mm_operands(a, B, wave, lane, 0, slot, n_pad, coil, coils, k0, dk, vals);
         for (int j = 0; j < S; ++j) {
-            const int tl = wave + kWavesPerWG * j;
-            ParSpin spn{0.f, 0.f, 0.f, 0.f, __builtin_inff()};
-            C2<R> mm{R(0), R(0)};
-            if (tl < B.ntiles) {
-                const Tile T = a.tiles[B.tile0 + tl];
-                if (lane < T.count) {
-                    const int64_t i = T.spin0 + lane;
-                    spn = ParSpin{a.ph.x[i], a.ph.y[i], a.ph.z[i], a.ph.dw[i], a.ph.t2[i]};
-                    const float2 v = reinterpret_cast<const float2 *>(a.snap)[(int64_t)slot * n_pad +
-                                                                              (int64_t)(B.tile0 + tl) * kWave + lane];
-                    mm = C2<R>{v.x, v.y};
-                    if (coils)
-                        mm = cmul(mm, C2<R>{a.ph.sre[coil * a.ph.n + i], a.ph.sim[coil * a.ph.n + i]});
-                }
-            }
-            const C2<R> c = cmul(mm, par_factor<P>(spn, k0));
-            const C2<R> w = par_factor<P>(spn, dk);
-            // B[r] = w^r, A[q] = c w^(16 q), staged as this spin's row of 52 floats
-            float vals[48];
-            C2<R> p{R(1), R(0)};
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                vals[16 + 2 * r] = p.re;
-                vals[16 + 2 * r + 1] = p.im;
-                p = cmul(p, w);
-            }
-            C2<R> aq = c;  // p = w^16 now
-#pragma unroll
-            for (int qq = 0; qq < 8; ++qq) {
-                vals[2 * qq] = aq.re;
-                vals[2 * qq + 1] = aq.im;
-                aq = cmul(aq, p);
-            }
             float4 *dst = reinterpret_cast<float4 *>(my + lane * kSpinStride);
 #pragma unroll
             for (int v4 = 0; v4 < 12; ++v4)
@@ -721,6 +756,7 @@ __global__ __launch_bounds__(kWG) void k_par_mm(ParArgs a) {
             // the compiler must not move LDS accesses across these points
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
+            if (j + 1 < S) mm_operands(a, B, wave, lane, j + 1, slot, n_pad, coil, coils, k0, dk, vals);
             const float *src = my + sp * kSpinStride;
 #pragma unroll 2
             for (int u = 0; u < kWave / 2; u += 4) {  // spins 2u .. 2u + 7
@@ -739,6 +775,7 @@ __global__ __launch_bounds__(kWG) void k_par_mm(ParArgs a) {
             __builtin_amdgcn_wave_barrier();
         }
         const f32x4 acc = (acc0 + acc1) + (acc2 + acc3);
+        __syncthreads();  // every wavefront is done with its stage
         // acc[i] = row 4 kq + i (q' = row & 7, Re if row < 8 else Im), column m: sample 16 q' + m
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
