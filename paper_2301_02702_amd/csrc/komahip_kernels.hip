@@ -644,7 +644,17 @@ __global__ __launch_bounds__(kWG) void k_par(ParArgs a) {
 // A[l % 16][l / 16], B[l / 16][l % 16] and the accumulator rows
 // 4 (l / 16) + i, column l % 16.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int kSpinStride = 48;  // floats per staged spin: 16 (A) + 32 (B)
+constexpr int kSpinStride = 52;  // floats per staged spin: 16 (A) + 32 (B), padded so that the
+                                 // 16-byte writes of consecutive lanes start 20 banks apart
+
+// par_factor with the decay rate 1/T2 given.
+__device__ __forceinline__ C2<float> mm_factor(const ParSpin &s, float r2, const double *k) {
+    float sn, cs;
+    Mixed::sincos_turns(par_phase<float>(s, k), sn, cs);
+    renorm(cs, sn);
+    const float e2 = Mixed::exp_neg(float(k[3]) * r2);
+    return {cs * e2, sn * e2};
+}
 
 // This lane's spin of tile slot j of the block: its anchor c (snapshot times
 // the exact FP64-phase factor, times the coil sensitivity) and per-sample
@@ -670,8 +680,10 @@ __device__ __forceinline__ void mm_operands(const ParArgs &a, const Block &B, in
             if (coils) mm = cmul(mm, C2<R>{a.ph.sre[coil * a.ph.n + i], a.ph.sim[coil * a.ph.n + i]});
         }
     }
-    const C2<R> c = cmul(mm, par_factor<Mixed>(spn, k0));
-    const C2<R> w = par_factor<Mixed>(spn, dk);
+    // one reciprocal of T2 for both factors (instead of two divisions)
+    const R r2 = R(1) / spn.t2;  // +inf -> 0: no decay
+    const C2<R> c = cmul(mm, mm_factor(spn, r2, k0));
+    const C2<R> w = mm_factor(spn, r2, dk);
     C2<R> pw[16];
     pw[0] = C2<R>{R(1), R(0)};
     pw[1] = w;
@@ -711,7 +723,7 @@ __global__ __launch_bounds__(kWG) void k_par_mm(ParArgs a) {
     using P = Mixed;
     using R = float;
     // per-wavefront operand stages; after a stretch's products the same
-    // memory holds the four wavefronts' sample sums (48 KB: 3 workgroups per CU)
+    // memory holds the four wavefronts' sample sums (52 KB: 3 workgroups per CU)
     __shared__ __attribute__((aligned(16))) float stage[kWavesPerWG][kWave * kSpinStride];
     static_assert(sizeof(double2) * kWavesPerWG * kStretchMax <= sizeof(float) * kWavesPerWG * kWave * kSpinStride,
                   "sample sums fit in the stage");
