@@ -184,6 +184,20 @@ def bench_mrf_match(K, ctx, torch, dictionary, no_cpu, n_pix=65536, reps=5):
     return out
 
 
+def gpu_clocks():
+    """Shader clock levels of the GPU as the driver reports them (sysfs,
+    read-only), to put box-to-box differences in context; None if absent."""
+    import glob
+    for f in sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk")):
+        try:
+            lines = open(f).read().strip().splitlines()
+        except OSError:
+            continue
+        if lines:
+            return {"levels": [ln.strip() for ln in lines][:8], "source": f}
+    return None
+
+
 def load_traffic(khash):
     p = os.path.join(ROOT, "profiles", "traffic_k_par_epi256.json")
     if not os.path.exists(p):
@@ -351,6 +365,8 @@ def main():
         log(f"[bench] serving: {args.serving_requests} requests ...")
         out["serving"] = serve.benchmark(ctx_device=0, n_requests=args.serving_requests, rho=0.8,
                                          log=log)
+
+    out["gpu_sclk"] = gpu_clocks()
 
     if args.calib_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0")

@@ -128,13 +128,13 @@ def test_random_sequences_edge_cases(ctx, prec):
         cuts = np.sort(rng.integers(0, n + 1, 3))
         ph.group_off = np.concatenate([[0], cuts, [cuts[-1]], [n]])  # one empty group
         ref = oracle.simulate(sc, ph, seq)
-        for dm in (-1, 0, 3):
-            ctx.set_config(prec, defer_min_adc=dm)
+        for dm, eng in ((-1, 0), (0, 0), (3, 0), (0, 1)):  # short stretches on both sample engines
+            ctx.set_config(prec, defer_min_adc=dm, sample_engine=eng)
             got = ctx.simulate(sc, ph, seq)
             e = np.max(nrmse(got[np.abs(ref).max(axis=1) > 0], ref[np.abs(ref).max(axis=1) > 0]))
-            assert e <= TOL[prec], (trial, dm, e)
+            assert e <= TOL[prec], (trial, dm, eng, e)
             assert np.all(got[np.abs(ref).max(axis=1) == 0] == 0)
-    ctx.set_config(prec, defer_min_adc=32)
+    ctx.set_config(prec, defer_min_adc=32, sample_engine=0)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
