@@ -166,6 +166,24 @@ koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
                           const koma_sequence *seq, koma_mem where, void *hip_stream,
                           double *sig, double *m_final);
 
+/* The same simulation (section "Overview": scanner, phantom and sequence in,
+ * raw signal out) enqueued on `hip_stream` (NULL: the context's stream)
+ * without waiting for it. The phantom arrays, sig and m_final are device
+ * pointers on the context's device and must stay valid until the stream has
+ * run the work; the host arrays of the sequence are read before return.
+ * Every host-side check and the packing of the sequence happen before return,
+ * with the errors of koma_simulate. The phantom's values are checked on the
+ * device: status (a device int32, or NULL) receives 0 if they are valid, else
+ * the validation bits (1 non-finite position, velocity, dw or PD; 2 PD < 0;
+ * 4 T1 or T2 <= 0 or NaN; 8 non-finite coil sensitivity), and then sig and
+ * m_final are left untouched. Later calls on the context that use its
+ * scratch (koma_simulate, koma_simulate_async) are ordered after the queued
+ * work on any stream, so consecutive calls pipeline: the host packs the next
+ * simulation while the device runs the previous one. */
+koma_status koma_simulate_async(koma_ctx *ctx, const koma_scanner *sc, const koma_phantom *ph,
+                                const koma_sequence *seq, void *hip_stream, double *sig,
+                                double *m_final, int32_t *status);
+
 /* ---- chunked execution with device-resident state (serving) ------------
  * koma_req_open copies the phantom (host or device memory per `where`) and
  * the packed sequence into request-owned device buffers and initialises the
@@ -195,7 +213,7 @@ void koma_req_close(koma_req *req);
 
 typedef struct {
     int64_t n_spins, n_tiles, n_groups, n_adc;
-    int64_t n_events, n_rf, n_runs, n_inline_adc, n_deferred_adc, n_stretches, n_snapshots;
+    int64_t n_events, n_rf, n_runs, n_inline_adc, n_deferred_adc, n_stretches, n_families, n_snapshots;
     int64_t n_blocks, spins_per_lane, n_chunks;
     int64_t events_done;
     size_t footprint;

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -51,6 +52,7 @@ struct Plan {
     // sequence program
     std::vector<Event> ev;
     std::vector<Stretch> st;
+    std::vector<std::array<double, 4>> fam_dk;  // increments of each stretch family
     std::vector<int32_t> inl_k, def_k;  // inline / deferred column -> ADC index
     int64_t n_slots = 0, n_rf = 0, n_runs = 0;
     std::vector<int64_t> snap_event;  // slot -> event index of its EV_SNAP
@@ -133,11 +135,18 @@ struct koma_ctx {
     int64_t n_launch[K_KINDS] = {};
     int64_t work[K_KINDS] = {};
     Plan plan;  // reused by koma_simulate (capacity kept across calls)
-    // pinned host staging for the packed tables (one upload per call) and the
-    // validation flag read-back
-    void *h_stage = nullptr;
-    size_t h_stage_cap = 0;
+    // pinned host staging for the packed tables (one upload per call), two
+    // buffers used in turn so that a call can pack while the upload of the
+    // previous one is still queued, and the validation flag read-back
+    void *h_stage[2] = {nullptr, nullptr};
+    size_t h_stage_cap[2] = {0, 0};
+    hipEvent_t stage_ev[2] = {nullptr, nullptr};  // recorded after each buffer's upload
+    int stage_next = 0;
     int32_t *h_flag = nullptr;
+    // work of koma_simulate_async still queued on async_stream, which later
+    // calls on the context's scratch order themselves after
+    bool async_pending = false;
+    hipEvent_t async_done = nullptr;
     DevMem s_tables;
     // device blocks released by closed requests, reused by later ones (by size)
     std::multimap<size_t, void *> pool;
@@ -193,6 +202,9 @@ static koma_status dev_reserve(koma_ctx *ctx, DevMem &m, size_t bytes) {
     if (bytes == 0) bytes = 16;
     if (m.cap >= bytes) return KOMA_OK;
     if (m.p) {
+        // queued asynchronous work may still use the block
+        if (ctx->async_pending && hipEventSynchronize(ctx->async_done) != hipSuccess)
+            return fail(ctx, KOMA_E_DEVICE, "waiting for queued work failed");
         hipError_t e = hipFree(m.p);
         m.p = nullptr;
         m.cap = 0;
@@ -402,18 +414,20 @@ struct Samples {
 
 // True when samples i..i+len-1 all lie within the tolerances of the straight
 // line through the first and the last of them; the line's increments go to
-// inc. Branch-free compare-and-or loops, so the compiler vectorises them.
-inline bool on_line(const Samples &s, size_t i, size_t len, double *inc) {
+// inc and the largest distance of a sample from the line to dev. Branch-free
+// max loops, so the compiler vectorises them.
+inline bool on_line(const Samples &s, size_t i, size_t len, double *inc, double *dev) {
     for (int c = 0; c < 4; ++c) {
         const double *__restrict v = s.v[c] + i;
         const double v0 = v[0];
         const double d = (v[len - 1] - v0) / (double)(len - 1);
         const double tol = c < 3 ? kStretchTolK : kStretchTolT;
-        int bad = 0;
+        double e = 0.0;
         const int n = (int)len - 1;  // the last sample lies on the line by construction
-        for (int q = 1; q < n; ++q) bad |= std::fabs(v[q] - (v0 + (double)q * d)) > tol;
-        if (bad) return false;
+        for (int q = 1; q < n; ++q) e = std::max(e, std::fabs(v[q] - (v0 + (double)q * d)));
+        if (!(e <= tol)) return false;
         inc[c] = d;
+        dev[c] = e;
     }
     return true;
 }
@@ -426,9 +440,9 @@ void make_stretches(const Samples &s, int max_len, Emit emit) {
     const size_t m = s.size();
     size_t i = 0;
     while (i < m) {
-        double inc[4] = {0, 0, 0, 0};
+        double inc[4] = {0, 0, 0, 0}, dev[4] = {0, 0, 0, 0};
         size_t len = std::min<size_t>((size_t)max_len, m - i);
-        if (len > 1 && !on_line(s, i, len, inc)) {
+        if (len > 1 && !on_line(s, i, len, inc, dev)) {
             // greedy: extend while the next sample stays near the line of the first step
             size_t j = i + 1;
             while (j < m && (j - i + 1) <= (size_t)max_len) {
@@ -443,15 +457,36 @@ void make_stretches(const Samples &s, int max_len, Emit emit) {
                 ++j;
             }
             len = j - i;
-            while (len > 1 && !on_line(s, i, len, inc)) len /= 2;
+            while (len > 1 && !on_line(s, i, len, inc, dev)) len /= 2;
         }
         if (len <= 1) {
             len = 1;
             inc[0] = inc[1] = inc[2] = inc[3] = 0;
+            dev[0] = dev[1] = dev[2] = dev[3] = 0;
         }
-        emit(i, len, inc);
+        emit(i, len, inc, dev);
         i += len;
     }
+}
+
+// Family of a deferred stretch with increments inc, whose samples lie within
+// dev of its own line: the first of the most recent families whose
+// increments F keep every sample within the stretch tolerances,
+// dev + (len - 1) |inc - F| <= tol (so the stretch may use F instead of inc
+// under the same error bound), else a new family with increments inc. The
+// stretch takes its family's increments bitwise, so that the sample-parallel
+// kernel can share the per-sample powers among the stretches of a family.
+int32_t stretch_family(std::vector<std::array<double, 4>> &fams, size_t len, const double *inc, const double *dev) {
+    const double n = (double)(len - 1);
+    const int64_t nf = (int64_t)fams.size();
+    for (int64_t f = nf - 1; f >= 0 && f >= nf - 16; --f) {
+        bool ok = true;
+        for (int c = 0; c < 4 && ok; ++c)
+            ok = dev[c] + n * std::fabs(inc[c] - fams[f][c]) <= (c < 3 ? kStretchTolK : kStretchTolT);
+        if (ok) return (int32_t)f;
+    }
+    fams.push_back({inc[0], inc[1], inc[2], inc[3]});
+    return (int32_t)nf;
 }
 
 }  // namespace
@@ -501,6 +536,7 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     // reset, keeping the vectors' capacity (plans are rebuilt every call)
     P.ev.clear();
     P.st.clear();
+    P.fam_dk.clear();
     P.inl_k.clear();
     P.def_k.clear();
     P.snap_event.clear();
@@ -647,20 +683,23 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
                 e.a0 = slot;
                 P.snap_event.push_back((int64_t)P.ev.size());
                 P.ev.push_back(e);
-                make_stretches(samples, cfg.stretch_max, [&](size_t i, size_t len, const double *inc) {
+                make_stretches(samples, cfg.stretch_max, [&](size_t i, size_t len, const double *inc,
+                                                             const double *dev) {
                     Stretch s{};
                     s.slot = slot;
                     s.d0 = (int32_t)P.def_k.size();
                     s.count = (int32_t)len;
+                    s.fam = stretch_family(P.fam_dk, len, inc, dev);
                     for (int c = 0; c < 4; ++c) {
                         s.k0[c] = samples.v[c][i];
-                        s.dk[c] = inc[c];
+                        s.dk[c] = P.fam_dk[s.fam][c];
                     }
                     P.def_k.insert(P.def_k.end(), samples.k + i, samples.k + i + len);
                     P.st.push_back(s);
                 });
             } else {
-                make_stretches(samples, cfg.stretch_max, [&](size_t i, size_t len, const double *inc) {
+                make_stretches(samples, cfg.stretch_max, [&](size_t i, size_t len, const double *inc,
+                                                             const double *) {
                     Event e{};
                     e.kind = EV_ADC;
                     e.a0 = (int32_t)P.inl_k.size();
@@ -750,6 +789,9 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
 
     // ---- sample-parallel layout: blocks of 4*S tiles of one group
     const int64_t n_st = (int64_t)P.st.size();
+    // the matrix-core kernel takes kMMStretches stretches per workgroup
+    const bool mm = cfg.precision == KOMA_MIXED && cfg.sample_engine == 0;
+    const int64_t st_per_wg = mm ? kMMStretches : 1;
     int spl = cfg.spins_per_lane;
     if (spl == 0) {
         spl = 1;
@@ -759,7 +801,7 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
                 const int64_t nt = P.tile_off[g + 1] - P.tile_off[g];
                 nb += (nt + 4 * cand - 1) / (4 * cand);
             }
-            if (nb * std::max<int64_t>(n_st, 1) >= 2048) {
+            if (nb * std::max<int64_t>((n_st + st_per_wg - 1) / st_per_wg, 1) >= (mm ? 1024 : 2048)) {
                 spl = cand;
                 break;
             }
@@ -781,7 +823,9 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     const int64_t n_blocks = (int64_t)P.blocks.size();
     // stretches per workgroup: keep >= ~16 workgroups per CU, share spin loads beyond that
     P.per_wg = 1;
-    if (n_st > 0) {
+    if (mm) {
+        P.per_wg = kMMStretches;
+    } else if (n_st > 0) {
         const int64_t target = 4096;
         const int64_t wgs = n_blocks * n_st;
         P.per_wg = std::max<int64_t>(1, std::min<int64_t>(16, wgs / target));
@@ -804,7 +848,13 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
             }
             c.s1 = s;
             c.c1 = c.c0 + cols;
-            c.ready = P.snap_event[P.st[s - 1].slot] + 1;  // slots are increasing with the stretch order
+            // families together (each stretch keeps its own columns), so that
+            // the stretches of one workgroup mostly share their increments
+            std::stable_sort(P.st.begin() + c.s0, P.st.begin() + c.s1,
+                             [](const Stretch &x, const Stretch &y) { return x.fam < y.fam; });
+            int32_t last = 0;
+            for (int64_t i = c.s0; i < c.s1; ++i) last = std::max(last, P.st[i].slot);
+            c.ready = P.snap_event[last] + 1;
             P.chunks.push_back(c);
             P.max_cols = std::max(P.max_cols, cols);
         }
@@ -1036,6 +1086,7 @@ void koma_ctx_destroy(koma_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->async_pending) (void)hipEventSynchronize(ctx->async_done);
     DevMem *all[] = {&ctx->s_ev, &ctx->s_st, &ctx->s_tiles, &ctx->s_blocks, &ctx->s_toff, &ctx->s_boff,
                      &ctx->s_inl, &ctx->s_def, &ctx->s_snap, &ctx->s_pa, &ctx->s_pb, &ctx->s_sig,
                      &ctx->s_mxy, &ctx->s_mz, &ctx->s_flags, &ctx->s_mf};
@@ -1046,7 +1097,11 @@ void koma_ctx_destroy(koma_ctx *ctx) {
                      &ctx->l_v, &ctx->l_y, &ctx->l_zp, &ctx->l_z, &ctx->l_basis, &ctx->l_sv, &ctx->l_out};
     for (DevMem *m : mrf) dev_free(*m);
     dev_free(ctx->s_tables);
-    if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+    for (int b = 0; b < 2; ++b) {
+        if (ctx->h_stage[b]) (void)hipHostFree(ctx->h_stage[b]);
+        if (ctx->stage_ev[b]) (void)hipEventDestroy(ctx->stage_ev[b]);
+    }
+    if (ctx->async_done) (void)hipEventDestroy(ctx->async_done);
     if (ctx->h_flag) (void)hipHostFree(ctx->h_flag);
     pool_trim(ctx);
     for (auto &r : ctx->recs) {
@@ -1125,14 +1180,20 @@ koma_status koma_ctx_kernel_stats(koma_ctx *ctx, int kind, double *total_ms, int
     return KOMA_OK;
 }
 
-koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phantom *ph,
-                          const koma_sequence *seq, koma_mem where, void *hip_stream, double *sig,
-                          double *m_final) {
+// Everything of one simulation up to the outputs, enqueued on the stream:
+// validation, packing, upload, kernels, and (device-resident phantoms) the
+// commit of the results if the device-side validation found them clean. With
+// async, the validation bits go to `status` (device) and nothing is waited for.
+static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const koma_phantom *ph,
+                                    const koma_sequence *seq, koma_mem where, void *hip_stream, double *sig,
+                                    double *m_final, bool async, int32_t *status) {
     if (!ctx) return KOMA_E_ARG;
     if (ctx->poisoned) return fail(ctx, KOMA_E_DEVICE, "context poisoned by an earlier device error");
     ctx->err.clear();
     koma_status st;
     if (where != KOMA_HOST && where != KOMA_DEVICE) return fail(ctx, KOMA_E_ARG, "bad koma_mem");
+    if (async && where != KOMA_DEVICE)
+        return fail(ctx, KOMA_E_ARG, "koma_simulate_async takes device-resident inputs and outputs");
     if ((st = check_scanner(ctx, sc)) != KOMA_OK) return st;
     if ((st = check_phantom_shape(ctx, ph)) != KOMA_OK) return st;
     if ((st = check_sequence(ctx, seq)) != KOMA_OK) return st;
@@ -1142,6 +1203,8 @@ koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     const bool fp64 = ctx->cfg.precision == KOMA_FP64;
     const size_t r = fp64 ? 8 : 4;
+    // the context's scratch is reused: order this call after queued work
+    if (ctx->async_pending) HIPCHK(ctx, hipStreamWaitEvent(s, ctx->async_done, 0));
 
     Plan &P = ctx->plan;
     if ((st = build_plan(ctx, ctx->cfg, sc->gamma, ph, seq, P)) != KOMA_OK) return st;
@@ -1182,18 +1245,24 @@ koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
         pt.off = total;
         total += (pt.bytes + 255) & ~(size_t)255;
     }
-    if (ctx->h_stage_cap < total) {
-        if (ctx->h_stage) HIPCHK(ctx, hipHostFree(ctx->h_stage));
-        ctx->h_stage = nullptr;
-        ctx->h_stage_cap = 0;
-        HIPCHK(ctx, hipHostMalloc(&ctx->h_stage, total, hipHostMallocDefault));
-        ctx->h_stage_cap = total;
+    // staging buffer b was last uploaded two calls ago: wait for that copy
+    const int b = ctx->stage_next;
+    ctx->stage_next ^= 1;
+    if (!ctx->stage_ev[b]) HIPCHK(ctx, hipEventCreateWithFlags(&ctx->stage_ev[b], hipEventDisableTiming));
+    else HIPCHK(ctx, hipEventSynchronize(ctx->stage_ev[b]));
+    if (ctx->h_stage_cap[b] < total) {
+        if (ctx->h_stage[b]) HIPCHK(ctx, hipHostFree(ctx->h_stage[b]));
+        ctx->h_stage[b] = nullptr;
+        ctx->h_stage_cap[b] = 0;
+        HIPCHK(ctx, hipHostMalloc(&ctx->h_stage[b], total, hipHostMallocDefault));
+        ctx->h_stage_cap[b] = total;
     }
     if (!ctx->h_flag) HIPCHK(ctx, hipHostMalloc((void **)&ctx->h_flag, 64, hipHostMallocDefault));
     for (auto &pt : parts)
-        if (pt.bytes) memcpy((char *)ctx->h_stage + pt.off, pt.src, pt.bytes);
+        if (pt.bytes) memcpy((char *)ctx->h_stage[b] + pt.off, pt.src, pt.bytes);
     if ((st = dev_reserve(ctx, ctx->s_tables, total)) != KOMA_OK) return st;
-    HIPCHK(ctx, hipMemcpyAsync(ctx->s_tables.p, ctx->h_stage, total, hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->s_tables.p, ctx->h_stage[b], total, hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipEventRecord(ctx->stage_ev[b], s));
     char *tb = (char *)ctx->s_tables.p;
     B.ev = (const Event *)(tb + parts[0].off);
     B.st = (const Stretch *)(tb + parts[1].off);
@@ -1249,12 +1318,20 @@ koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
     if (dev_check) {
         if (sig_n) LAUNCH(ctx, K_AUX, (int64_t)sig_n, s, launch_commit(flag_total, B.sig, sig, (int64_t)sig_n, s));
         if (store) LAUNCH(ctx, K_AUX, ph->n * 3, s, launch_commit(flag_total, mf, m_final, ph->n * 3, s));
+        if (async) {
+            if (status) HIPCHK(ctx, hipMemcpyAsync(status, flag_total, 4, hipMemcpyDeviceToDevice, s));
+            if (!ctx->async_done) HIPCHK(ctx, hipEventCreateWithFlags(&ctx->async_done, hipEventDisableTiming));
+            HIPCHK(ctx, hipEventRecord(ctx->async_done, s));
+            ctx->async_pending = true;
+            return KOMA_OK;
+        }
         HIPCHK(ctx, hipMemcpyAsync(ctx->h_flag, flag_total, 4, hipMemcpyDeviceToHost, s));
     } else {
         if (sig_n) HIPCHK(ctx, hipMemcpyAsync(sig, B.sig, sig_n * 8, hipMemcpyDeviceToHost, s));
         if (store) HIPCHK(ctx, hipMemcpyAsync(m_final, mf, (size_t)ph->n * 24, hipMemcpyDeviceToHost, s));
     }
     HIPCHK(ctx, hipStreamSynchronize(s));
+    ctx->async_pending = false;  // this stream waited for it
     if (dev_check && *ctx->h_flag) {
         const int32_t bad = *ctx->h_flag;
         if (bad & 1) return fail(ctx, KOMA_E_PHANTOM, "non-finite position, velocity, dw or PD in the phantom");
@@ -1263,6 +1340,18 @@ koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
         return fail(ctx, KOMA_E_PHANTOM, "non-finite coil sensitivity in the phantom");
     }
     return KOMA_OK;
+}
+
+koma_status koma_simulate(koma_ctx *ctx, const koma_scanner *sc, const koma_phantom *ph,
+                          const koma_sequence *seq, koma_mem where, void *hip_stream, double *sig,
+                          double *m_final) {
+    return simulate_enqueue(ctx, sc, ph, seq, where, hip_stream, sig, m_final, false, nullptr);
+}
+
+koma_status koma_simulate_async(koma_ctx *ctx, const koma_scanner *sc, const koma_phantom *ph,
+                                const koma_sequence *seq, void *hip_stream, double *sig, double *m_final,
+                                int32_t *status) {
+    return simulate_enqueue(ctx, sc, ph, seq, KOMA_DEVICE, hip_stream, sig, m_final, true, status);
 }
 
 // ---------------------------------------------------------------- requests
@@ -1540,6 +1629,7 @@ static void fill_info(const Plan &P, koma_req_info *info) {
     info->n_inline_adc = (int64_t)P.inl_k.size();
     info->n_deferred_adc = (int64_t)P.def_k.size();
     info->n_stretches = (int64_t)P.st.size();
+    info->n_families = (int64_t)P.fam_dk.size();
     info->n_snapshots = P.n_slots;
     info->n_blocks = (int64_t)P.blocks.size();
     info->spins_per_lane = P.spl;

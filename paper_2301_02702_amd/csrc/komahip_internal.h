@@ -62,7 +62,7 @@ struct alignas(16) Stretch {
     int32_t slot;
     int32_t d0;     // deferred sample index of the first sample
     int32_t count;  // samples (<= 128)
-    int32_t pad;
+    int32_t fam;    // family: stretches of one family have bitwise-equal dk
     double k0[4];   // kx, ky, kz, tau of the first sample
     double dk[4];   // increments between consecutive samples
 };
@@ -96,6 +96,7 @@ constexpr int kWG = 256;            // 4 wavefronts
 constexpr int kWavesPerWG = kWG / kWave;
 constexpr int kBatch = 16;          // samples reduced together by the register transpose
 constexpr int kStretchMax = 128;
+constexpr int kMMStretches = 4;     // stretches whose sums one matrix-core workgroup keeps in registers
 
 struct SeqArgs {  // spin-sequential kernel
     PhantomDev ph;

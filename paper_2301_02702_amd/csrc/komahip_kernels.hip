@@ -633,19 +633,29 @@ __global__ __launch_bounds__(kWG) void k_par(ParArgs a) {
 // per-sample factor). Writing j = 16 q + r (q < 8, r < 16),
 //   S[16 q + r] = sum_s (c_s w_s^(16 q)) (w_s^r) = sum_s A[q][s] B[s][r],
 // a complex product of an 8 x n_spins and an n_spins x 16 matrix: the sum
-// over spins is the contraction. As a real product with rows (Re, Im) x q
-// and the spin's (Re, Im) pair on the contraction axis,
-//   [Re S; Im S] = [Re A, -Im A; Im A, Re A] [Re B; Im B],
-// it runs as v_mfma_f32_16x16x4f32 (FP32 products and sums), two spins per
-// instruction. Each lane forms its spin's 8 values A[q] = c w^(16 q) and 16
-// values B[r] = w^r (23 complex products, fewer roundings than a 127-step
-// recurrence), stages them through LDS, and the wavefront multiplies the 64
-// spins of the tile in 32 instructions. Lane l of the instruction holds
-// A[l % 16][l / 16], B[l / 16][l % 16] and the accumulator rows
-// 4 (l / 16) + i, column l % 16.
+// over spins is the contraction. Two stretches whose B is the same (see
+// below) stack their A into the 16 rows of v_mfma_f32_16x16x4f32 (FP32
+// products and sums, four spins per instruction), and the complex product
+// takes three real ones (Gauss):
+//   P1 = (Re A + Im A) Re B,  P2 = Re A (Im B - Re B),  P3 = Im A (Re B + Im B),
+//   Re S = P1 - P3,  Im S = P1 + P2,
+// so 24 instructions per 64 spins and stretch instead of 32. Lane l of an
+// instruction holds A[l % 16][l / 16] and B[l / 16][l % 16], and accumulates
+// rows 4 (l / 16) + i of column l % 16: lanes l < 32 the first stretch of
+// the pair, lanes l >= 32 the second, each with Re S and Im S of the same
+// samples in its own registers.
+//
+// B depends on the stretch only through its increments, which the host makes
+// bitwise equal within a family of stretches (all lines of one readout
+// polarity, say). A workgroup takes up to kMMStretches stretches and loops
+// over its tiles outside them: per tile and family, each lane forms its
+// spin's w^r (r < 16) and w^(16 q) once, and the wavefront turns the B
+// operands round through LDS into registers; per stretch only the anchor c
+// and its 8 products c w^(16 q) are formed and staged. The sums of all the
+// batch's stretches stay in registers until the workgroup's tiles are done,
+// then the four wavefronts are added in FP64 through LDS.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int kSpinStride = 52;  // floats per staged spin: 16 (A) + 32 (B), padded so that the
-                                 // 16-byte writes of consecutive lanes start 20 banks apart
+constexpr int kStageFloats = 48;  // per spin: 3 A planes of 16 (per pair), or the B operands (32)
 
 // par_factor with the decay rate 1/T2 given.
 __device__ __forceinline__ C2<float> mm_factor(const ParSpin &s, float r2, const double *k) {
@@ -656,78 +666,24 @@ __device__ __forceinline__ C2<float> mm_factor(const ParSpin &s, float r2, const
     return {cs * e2, sn * e2};
 }
 
-// This lane's spin of tile slot j of the block: its anchor c (snapshot times
-// the exact FP64-phase factor, times the coil sensitivity) and per-sample
-// factor w, and the 48 floats it stages: A[q] = c w^(16 q) (q < 8) and
-// B[r] = w^r (r < 16), (Re, Im) interleaved. Powers by a shallow product
-// tree (depth 5 instead of a 23-step chain). Lanes without a spin stage zeros
-// in A.
-__device__ __forceinline__ void mm_operands(const ParArgs &a, const Block &B, int wave, int lane, int j, int slot,
-                                            int64_t n_pad, int64_t coil, bool coils, const double *k0,
-                                            const double *dk, float *vals) {
-    using R = float;
-    const int tl = wave + kWavesPerWG * j;
-    ParSpin spn{0.f, 0.f, 0.f, 0.f, __builtin_inff()};
-    C2<R> mm{R(0), R(0)};
-    if (tl < B.ntiles) {
-        const Tile T = a.tiles[B.tile0 + tl];
-        if (lane < T.count) {
-            const int64_t i = T.spin0 + lane;
-            spn = ParSpin{a.ph.x[i], a.ph.y[i], a.ph.z[i], a.ph.dw[i], a.ph.t2[i]};
-            const float2 v = reinterpret_cast<const float2 *>(a.snap)[(int64_t)slot * n_pad +
-                                                                      (int64_t)(B.tile0 + tl) * kWave + lane];
-            mm = C2<R>{v.x, v.y};
-            if (coils) mm = cmul(mm, C2<R>{a.ph.sre[coil * a.ph.n + i], a.ph.sim[coil * a.ph.n + i]});
-        }
-    }
-    // one reciprocal of T2 for both factors (instead of two divisions)
-    const R r2 = R(1) / spn.t2;  // +inf -> 0: no decay
-    const C2<R> c = cmul(mm, mm_factor(spn, r2, k0));
-    const C2<R> w = mm_factor(spn, r2, dk);
-    C2<R> pw[16];
-    pw[0] = C2<R>{R(1), R(0)};
-    pw[1] = w;
-    pw[2] = cmul(w, w);
-    pw[3] = cmul(pw[2], w);
-    pw[4] = cmul(pw[2], pw[2]);
-#pragma unroll
-    for (int r = 5; r < 8; ++r) pw[r] = cmul(pw[4], pw[r - 4]);
-    const C2<R> w8 = cmul(pw[4], pw[4]);
-    pw[8] = w8;
-#pragma unroll
-    for (int r = 9; r < 16; ++r) pw[r] = cmul(w8, pw[r - 8]);
-    const C2<R> w16 = cmul(w8, w8);
-    const C2<R> w32 = cmul(w16, w16);
-    const C2<R> w64 = cmul(w32, w32);
-    C2<R> aq[8];
-    aq[0] = c;
-    aq[1] = cmul(c, w16);
-    aq[2] = cmul(c, w32);
-    aq[3] = cmul(aq[1], w32);
-#pragma unroll
-    for (int qq = 4; qq < 8; ++qq) aq[qq] = cmul(aq[qq - 4], w64);
-#pragma unroll
-    for (int qq = 0; qq < 8; ++qq) {
-        vals[2 * qq] = aq[qq].re;
-        vals[2 * qq + 1] = aq[qq].im;
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        vals[16 + 2 * r] = pw[r].re;
-        vals[16 + 2 * r + 1] = pw[r].im;
-    }
+// The anchor factor of a stretch start: as mm_factor but without the
+// renormalisation (a single factor, not raised to powers).
+__device__ __forceinline__ C2<float> mm_anchor(const ParSpin &s, float r2, const double *k) {
+    float sn, cs;
+    Mixed::sincos_turns(par_phase<float>(s, k), sn, cs);
+    const float e2 = Mixed::exp_neg(float(k[3]) * r2);
+    return {cs * e2, sn * e2};
 }
 
 template <int S>
-__global__ __launch_bounds__(kWG) void k_par_mm(ParArgs a) {
-    using P = Mixed;
-    using R = float;
-    // per-wavefront operand stages; after a stretch's products the same
-    // memory holds the four wavefronts' sample sums (52 KB: 3 workgroups per CU)
-    __shared__ __attribute__((aligned(16))) float stage[kWavesPerWG][kWave * kSpinStride];
-    static_assert(sizeof(double2) * kWavesPerWG * kStretchMax <= sizeof(float) * kWavesPerWG * kWave * kSpinStride,
-                  "sample sums fit in the stage");
-    double2(*red)[kStretchMax] = reinterpret_cast<double2(*)[kStretchMax]>(&stage[0][0]);
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k_par_mm(ParArgs a) {
+    // per-wavefront stage (12 KB): B operands at a family's start, the three
+    // A planes per stretch pair; after the tiles, the FP64 sums
+    // [wave][stretch of the pair][sample] (16 KB)
+    __shared__ __attribute__((aligned(16))) float stage[kWavesPerWG][kWave * kStageFloats];
+    static_assert(sizeof(double2) * kWavesPerWG * 2 * kStretchMax <= sizeof(stage), "sums fit in the stage");
+    static_assert(kMMStretches == 4, "two stretch pairs per batch");
+    double2(*red)[2][kStretchMax] = reinterpret_cast<double2(*)[2][kStretchMax]>(&stage[0][0]);
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const Block B = a.blocks[blockIdx.x];
@@ -735,78 +691,203 @@ __global__ __launch_bounds__(kWG) void k_par_mm(ParArgs a) {
     const int64_t coil = blockIdx.z;  // 0 without receive coils
     const bool coils = a.ph.n_coils > 0;
     float *my = stage[wave];
-    // this lane's operand positions: row m, contraction index k (spin pair half, re/im)
-    const int m = lane & 15, kq = lane >> 4;
-    const int q = m & 7, hi = m >> 3, comp = kq & 1, sp = kq >> 1;
-    const int a_idx = 2 * q + (hi ^ comp);             // A[m][k] = +-(Re or Im of A[q])
-    const float a_sign = (hi == 0 && comp == 1) ? -1.0f : 1.0f;
-    const int b_idx = 16 + 2 * m + comp;               // B[k][n = m] = Re or Im of w^n
+    // Stage layouts (floats), with XOR-permuted 16-byte chunks so that the
+    // 16-byte writes of 8 consecutive lanes and the operand reads of a
+    // wavefront fall in distinct banks:
+    //   B: spin s, chunk c (w^(2c), w^(2c+1) as re, im, re, im) at 32 s + 4 (c ^ (s & 7));
+    //   A plane p (Re A + Im A, Re A, Im A) at 1024 p: spin s, chunk c (rows 4c .. 4c + 3;
+    //   row 8 h + q is A[q] of stretch h of the pair) at 16 s + 4 (c ^ ((s >> 1) & 3)).
+    const int m = lane & 15, g = lane >> 4;  // row (A) / column (B) m; spin 4u + g of group u
+    // operand read positions for even and odd u (spin 4u + g), plus 64 u (A) or 128 u (B)
+    const int a_rd0 = 16 * g + 4 * ((m >> 2) ^ (g >> 1)) + (m & 3);
+    const int a_rd1 = 16 * g + 4 * ((m >> 2) ^ (2 + (g >> 1))) + (m & 3);
+    const int b_rd0 = 32 * g + 4 * ((m >> 1) ^ g) + 2 * (m & 1);
+    const int b_rd1 = 32 * g + 4 * ((m >> 1) ^ (4 + g)) + 2 * (m & 1);
+    const int a_wr = 16 * lane, a_sw = (lane >> 1) & 3;
+    const int b_wr = 32 * lane, b_sw = lane & 7;
 
     const int64_t st0 = a.s0 + (int64_t)blockIdx.y * a.per_wg;
     const int64_t st1 = min(st0 + a.per_wg, a.s1);
-    for (int64_t st = st0; st < st1; ++st) {
-        const auto &S_ = as_const(a.st)[st];
-        const int cnt = S_.count;
-        const int slot = S_.slot;
-        const int d0 = S_.d0;
-        const double k0[4] = {S_.k0[0], S_.k0[1], S_.k0[2], S_.k0[3]};
-        const double dk[4] = {S_.dk[0], S_.dk[1], S_.dk[2], S_.dk[3]};
-        // four independent accumulator chains keep the matrix pipeline busy
-        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
-        // operands of the next tile are formed while the current tile's
-        // products run (software pipelining over the S tiles)
-        float vals[48];
-        mm_operands(a, B, wave, lane, 0, slot, n_pad, coil, coils, k0, dk, vals);
+    for (int64_t sb = st0; sb < st1; sb += kMMStretches) {
+        const int nb = (int)min<int64_t>(kMMStretches, st1 - sb);  // uniform
+        f32x4 acc[2][3];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) acc[p][0] = acc[p][1] = acc[p][2] = f32x4{0.f, 0.f, 0.f, 0.f};
         for (int j = 0; j < S; ++j) {
-            float4 *dst = reinterpret_cast<float4 *>(my + lane * kSpinStride);
-#pragma unroll
-            for (int v4 = 0; v4 < 12; ++v4)
-                dst[v4] = make_float4(vals[4 * v4], vals[4 * v4 + 1], vals[4 * v4 + 2], vals[4 * v4 + 3]);
-            // the stage is private to this wavefront, and its LDS operations
-            // complete in program order: the writes above are seen by the
-            // reads below, and these reads by the next tile's writes; only
-            // the compiler must not move LDS accesses across these points
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            if (j + 1 < S) mm_operands(a, B, wave, lane, j + 1, slot, n_pad, coil, coils, k0, dk, vals);
-            const float *src = my + sp * kSpinStride;
-#pragma unroll 2
-            for (int u = 0; u < kWave / 2; u += 4) {  // spins 2u .. 2u + 7
-                float av[4], bv[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    av[k] = a_sign * src[(2 * (u + k)) * kSpinStride + a_idx];
-                    bv[k] = src[(2 * (u + k)) * kSpinStride + b_idx];
+            const int tl = wave + kWavesPerWG * j;
+            ParSpin spn{0.f, 0.f, 0.f, 0.f, __builtin_inff()};
+            C2<float> sens{1.f, 0.f};
+            bool valid = false;
+            int64_t pidx = 0;  // padded spin slot of this lane
+            if (tl < B.ntiles) {
+                const Tile T = a.tiles[B.tile0 + tl];
+                pidx = (int64_t)(B.tile0 + tl) * kWave + lane;
+                if (lane < T.count) {
+                    const int64_t i = T.spin0 + lane;
+                    valid = true;
+                    spn = ParSpin{a.ph.x[i], a.ph.y[i], a.ph.z[i], a.ph.dw[i], a.ph.t2[i]};
+                    if (coils) sens = C2<float>{a.ph.sre[coil * a.ph.n + i], a.ph.sim[coil * a.ph.n + i]};
                 }
-                acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0], bv[0], acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1], bv[1], acc1, 0, 0, 0);
-                acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2], bv[2], acc2, 0, 0, 0);
-                acc3 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[3], bv[3], acc3, 0, 0, 0);
             }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+            const float r2 = __builtin_amdgcn_rcpf(spn.t2);  // +inf -> 0: no decay
+            int32_t fam = -1;                                   // family of the operands in registers
+            C2<float> wq[8];                                    // w^(16 q)
+            float b1[16], b2[16], b3[16];                       // Re B, Im B - Re B, Re B + Im B (spin 4u + g, column m)
+            // anchor of a stretch: snapshot x coil sensitivity x exact FP64-phase factor
+            auto anchor = [&](const auto &T_) -> C2<float> {
+                C2<float> mm{0.f, 0.f};
+                if (valid) {
+                    const float2 v = reinterpret_cast<const float2 *>(a.snap)[(int64_t)T_.slot * n_pad + pidx];
+                    mm = C2<float>{v.x, v.y};
+                    if (coils) mm = cmul(mm, sens);
+                }
+                const double k0[4] = {T_.k0[0], T_.k0[1], T_.k0[2], T_.k0[3]};
+                return cmul(mm, mm_anchor(spn, r2, k0));
+            };
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                // a short batch repeats its last stretch (no branch around the
+                // products, so the sums keep their registers); the repeats are
+                // not stored
+                const auto &Sa = as_const(a.st)[sb + min(2 * p, nb - 1)];
+                const auto &Sb = as_const(a.st)[sb + min(2 * p + 1, nb - 1)];
+                // two families in one pair: one pass per stretch, the other half zero
+                const int passes = Sa.fam == Sb.fam ? 1 : 2;  // uniform
+                for (int pass = 0; pass < passes; ++pass) {
+                    const auto &Sf = pass == 0 ? Sa : Sb;
+                    if (Sf.fam != fam) {  // uniform: the first stretch, or a new family
+                        fam = Sf.fam;
+                        const double dk[4] = {Sf.dk[0], Sf.dk[1], Sf.dk[2], Sf.dk[3]};
+                        const C2<float> w = mm_factor(spn, r2, dk);
+                        // powers by a shallow product tree
+                        C2<float> pw[16];
+                        pw[0] = C2<float>{1.f, 0.f};
+                        pw[1] = w;
+                        pw[2] = cmul(w, w);
+                        pw[3] = cmul(pw[2], w);
+                        pw[4] = cmul(pw[2], pw[2]);
+#pragma unroll
+                        for (int r = 5; r < 8; ++r) pw[r] = cmul(pw[4], pw[r - 4]);
+                        pw[8] = cmul(pw[4], pw[4]);
+#pragma unroll
+                        for (int r = 9; r < 16; ++r) pw[r] = cmul(pw[8], pw[r - 8]);
+                        wq[0] = C2<float>{1.f, 0.f};
+                        wq[1] = cmul(pw[8], pw[8]);
+                        wq[2] = cmul(wq[1], wq[1]);
+                        wq[3] = cmul(wq[2], wq[1]);
+                        wq[4] = cmul(wq[2], wq[2]);
+#pragma unroll
+                        for (int q = 5; q < 8; ++q) wq[q] = cmul(wq[4], wq[q - 4]);
+#pragma unroll
+                        for (int c = 0; c < 8; ++c)
+                            *reinterpret_cast<float4 *>(my + b_wr + 4 * (c ^ b_sw)) =
+                                make_float4(pw[2 * c].re, pw[2 * c].im, pw[2 * c + 1].re, pw[2 * c + 1].im);
+                        // the stage is private to this wavefront, and its LDS
+                        // operations complete in program order: only the
+                        // compiler must not move LDS accesses across these points
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                        for (int u = 0; u < 16; ++u) {
+                            const float2 v = *reinterpret_cast<const float2 *>(my + 128 * u + ((u & 1) ? b_rd1 : b_rd0));
+                            b1[u] = v.x;
+                            b2[u] = v.y - v.x;
+                            b3[u] = v.x + v.y;
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                    const C2<float> zero{0.f, 0.f};
+                    const C2<float> ca = (passes == 1 || pass == 0) ? anchor(Sa) : zero;
+                    const C2<float> cb = (passes == 1 || pass == 1) ? anchor(Sb) : zero;
+                    C2<float> aa[8], ab[8];
+                    aa[0] = ca;
+                    ab[0] = cb;
+#pragma unroll
+                    for (int q = 1; q < 8; ++q) {
+                        aa[q] = cmul(ca, wq[q]);
+                        ab[q] = cmul(cb, wq[q]);
+                    }
+                    float *pl = my + a_wr;
+#define KOMA_A4(arr, q0, f) make_float4(f(arr[q0]), f(arr[q0 + 1]), f(arr[q0 + 2]), f(arr[q0 + 3]))
+#define KOMA_SUM(z) ((z).re + (z).im)
+#define KOMA_RE(z) ((z).re)
+#define KOMA_IM(z) ((z).im)
+                    *reinterpret_cast<float4 *>(pl + 4 * (0 ^ a_sw)) = KOMA_A4(aa, 0, KOMA_SUM);
+                    *reinterpret_cast<float4 *>(pl + 4 * (1 ^ a_sw)) = KOMA_A4(aa, 4, KOMA_SUM);
+                    *reinterpret_cast<float4 *>(pl + 4 * (2 ^ a_sw)) = KOMA_A4(ab, 0, KOMA_SUM);
+                    *reinterpret_cast<float4 *>(pl + 4 * (3 ^ a_sw)) = KOMA_A4(ab, 4, KOMA_SUM);
+                    *reinterpret_cast<float4 *>(pl + 1024 + 4 * (0 ^ a_sw)) = KOMA_A4(aa, 0, KOMA_RE);
+                    *reinterpret_cast<float4 *>(pl + 1024 + 4 * (1 ^ a_sw)) = KOMA_A4(aa, 4, KOMA_RE);
+                    *reinterpret_cast<float4 *>(pl + 1024 + 4 * (2 ^ a_sw)) = KOMA_A4(ab, 0, KOMA_RE);
+                    *reinterpret_cast<float4 *>(pl + 1024 + 4 * (3 ^ a_sw)) = KOMA_A4(ab, 4, KOMA_RE);
+                    *reinterpret_cast<float4 *>(pl + 2048 + 4 * (0 ^ a_sw)) = KOMA_A4(aa, 0, KOMA_IM);
+                    *reinterpret_cast<float4 *>(pl + 2048 + 4 * (1 ^ a_sw)) = KOMA_A4(aa, 4, KOMA_IM);
+                    *reinterpret_cast<float4 *>(pl + 2048 + 4 * (2 ^ a_sw)) = KOMA_A4(ab, 0, KOMA_IM);
+                    *reinterpret_cast<float4 *>(pl + 2048 + 4 * (3 ^ a_sw)) = KOMA_A4(ab, 4, KOMA_IM);
+#undef KOMA_A4
+#undef KOMA_SUM
+#undef KOMA_RE
+#undef KOMA_IM
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    // the three planes in two halves of 8 spin groups: reads
+                    // first (one wait), then the products
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        float av[3][8];
+#pragma unroll
+                        for (int pl_ = 0; pl_ < 3; ++pl_)
+#pragma unroll
+                            for (int uu = 0; uu < 8; ++uu) {
+                                const int u = 8 * h + uu;
+                                av[pl_][uu] = my[1024 * pl_ + 64 * u + ((u & 1) ? a_rd1 : a_rd0)];
+                            }
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int uu = 0; uu < 8; ++uu) {
+                            const int u = 8 * h + uu;
+                            acc[p][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0][uu], b1[u], acc[p][0], 0, 0, 0);
+                            acc[p][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1][uu], b2[u], acc[p][1], 0, 0, 0);
+                            acc[p][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2][uu], b3[u], acc[p][2], 0, 0, 0);
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
         }
-        const f32x4 acc = (acc0 + acc1) + (acc2 + acc3);
         __syncthreads();  // every wavefront is done with its stage
-        // acc[i] = row 4 kq + i (q' = row & 7, Re if row < 8 else Im), column m: sample 16 q' + m
+        // lane l holds rows 4 (l / 16) + v: stretch h = l / 32 of the pair,
+        // q = 4 ((l / 16) % 2) + v; column m
+        const int half = lane >> 5;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = 4 * kq + i;
-            const int smp = 16 * (row & 7) + m;
-            double *slot_p = reinterpret_cast<double *>(&red[wave][smp]);
-            slot_p[row >> 3] = (double)acc[i];
-        }
-        __syncthreads();
-        for (int i = threadIdx.x; i < cnt; i += kWG) {
-            double2 t = red[0][i];
+        for (int p = 0; p < 2; ++p) {
+            if (2 * p >= nb) break;
 #pragma unroll
-            for (int wv = 1; wv < kWavesPerWG; ++wv) {
-                t.x += red[wv][i].x;
-                t.y += red[wv][i].y;
+            for (int v = 0; v < 4; ++v) {
+                const int smp = 16 * (4 * (g & 1) + v) + m;
+                const double p1 = (double)acc[p][0][v];
+                red[wave][half][smp] = make_double2(p1 - (double)acc[p][2][v], p1 + (double)acc[p][1][v]);
             }
-            reinterpret_cast<double2 *>(a.pb)[(coil * a.n_blocks + (int64_t)blockIdx.x) * a.cols + (d0 - a.col0) + i] = t;
+            __syncthreads();
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (2 * p + h >= nb) break;
+                const auto &S_ = as_const(a.st)[sb + 2 * p + h];
+                const int cnt = S_.count, d0 = S_.d0;
+                for (int k = threadIdx.x; k < cnt; k += kWG) {
+                    double2 t = red[0][h][k];
+#pragma unroll
+                    for (int wv = 1; wv < kWavesPerWG; ++wv) {
+                        t.x += red[wv][h][k].x;
+                        t.y += red[wv][h][k].y;
+                    }
+                    reinterpret_cast<double2 *>(a.pb)[(coil * a.n_blocks + (int64_t)blockIdx.x) * a.cols + (d0 - a.col0) + k] = t;
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 

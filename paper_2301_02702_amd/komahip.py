@@ -57,7 +57,7 @@ class koma_config(ctypes.Structure):
 class koma_req_info(ctypes.Structure):
     _fields_ = [(k, c_int64) for k in (
         "n_spins", "n_tiles", "n_groups", "n_adc", "n_events", "n_rf", "n_runs", "n_inline_adc",
-        "n_deferred_adc", "n_stretches", "n_snapshots", "n_blocks", "spins_per_lane", "n_chunks",
+        "n_deferred_adc", "n_stretches", "n_families", "n_snapshots", "n_blocks", "spins_per_lane", "n_chunks",
         "events_done")] + [("footprint", c_size_t)]
 
     def as_dict(self):
@@ -98,6 +98,8 @@ EXPORTS = {
                                POINTER(c_size_t)]),
     "koma_simulate": (c_int, [c_void_p, POINTER(koma_scanner), POINTER(koma_phantom),
                               POINTER(koma_sequence), c_int, c_void_p, c_void_p, c_void_p]),
+    "koma_simulate_async": (c_int, [c_void_p, POINTER(koma_scanner), POINTER(koma_phantom),
+                                    POINTER(koma_sequence), c_void_p, c_void_p, c_void_p, c_void_p]),
     "koma_req_open": (c_int, [c_void_p, POINTER(koma_scanner), POINTER(koma_phantom),
                               POINTER(koma_sequence), c_int, POINTER(c_void_p)]),
     "koma_req_advance": (c_int, [c_void_p, c_int64, c_void_p]),
@@ -386,6 +388,40 @@ class Context:
         if not p.n_coils:
             z = z[0]
         return (z, m) if want_m else z
+
+    def bind_async(self, scanner, phantom, seq, sig, stream=None, m_final=None, status=None):
+        """koma_simulate_async with its arguments marshalled once: returns a
+        function of no arguments that enqueues one whole simulation (host
+        packing included) on ``stream`` and returns without waiting. The
+        phantom is device-resident (as for ``simulate(where='device')``),
+        ``sig`` a float64 GPU tensor ``[(n_coils,) n_groups, n_adc, 2]``,
+        ``m_final`` None or a float64 GPU tensor ``[n, 3]``, ``status`` None or
+        an int32 GPU tensor of one element that receives the phantom's
+        validation bits (0: valid; otherwise the outputs are left untouched).
+        The tensors and arrays must stay alive until the work has run."""
+        p, s = _PhantomArgs(phantom, True), _SeqArgs(seq)
+        sc = make_scanner(scanner)
+        if sig.numel() != 2 * p.n_sig * p.n_groups * s.n_adc or not sig.is_contiguous():
+            raise ValueError("sig must be a contiguous [(n_coils,) n_groups, n_adc, 2] tensor")
+        if m_final is not None and (m_final.numel() != 3 * p.n or not m_final.is_contiguous()):
+            raise ValueError("m_final must be a contiguous [n, 3] tensor")
+        if status is not None and (status.numel() < 1 or str(status.dtype) != "torch.int32"):
+            raise ValueError("status must be an int32 tensor")
+        stream_h = None if stream is None else c_void_p(stream if isinstance(stream, int) else stream.cuda_stream)
+        args = (self.h, ctypes.byref(sc), ctypes.byref(p.c), ctypes.byref(s.c), stream_h, _ptr(sig),
+                _ptr(m_final), _ptr(status))
+        fn = lib().koma_simulate_async
+        h = self.h
+        keep = (p, s, sc, sig, m_final, status)
+
+        def enqueue():
+            _check(fn(*args), h)
+            return keep[3]
+        return enqueue
+
+    def simulate_async(self, scanner, phantom, seq, sig, stream=None, m_final=None, status=None):
+        """koma_simulate_async once (see ``bind_async``)."""
+        return self.bind_async(scanner, phantom, seq, sig, stream, m_final, status)()
 
     def mrf_match(self, dictionary, fingerprints, where: str = "host", stream=None, best=None, proj=None):
         """koma_mrf_match. Host: complex ``[n_entries, n_t]`` and ``[n_pix, n_t]``

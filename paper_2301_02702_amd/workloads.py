@@ -450,6 +450,25 @@ def epi_sequence(n: int = 128, fov: float = 0.23, dt: float = 4e-6, rf_int: int 
     return s.build("epi128", fov=fov, n=n)
 
 
+def readout_lines_sequence(amps, n_samples: int = 40, ramp: int = 4, dt: float = 4e-6, fov: float = 0.2,
+                           gamma: float = GAMMA) -> Sequence:
+    """Hard 90 deg, then one flat-top readout line per entry of ``amps``
+    (Gx amplitude in T/m; ``n_samples`` ADC points on the flat top), with a
+    Gy blip of area 1/(gamma_bar FOV) before every line: lines of equal
+    amplitude share their per-sample increments and differ in their start."""
+    gbar = gamma / (2 * np.pi)
+    per_line = 2 * 2 + 1 + 2 * ramp + n_samples
+    n_int = 20 + len(amps) * per_line
+    s = UniformSeq(n_int, dt)
+    p = s.rf(0, hard_pulse(20, dt, np.pi / 2, gamma))
+    for a in amps:
+        p = s.trap_area(1, p, 2, 1, 1.0 / (gbar * fov))
+        s.adc_points(p + ramp, n_samples)
+        p = s.trap(0, p, ramp, n_samples, float(a))
+    assert p <= n_int
+    return s.build("readout_lines", fov=fov, amps=list(map(float, amps)))
+
+
 def seepi_sequence(n: int = 128, fov: float = 0.23, dt: float = 4e-6, ramp: int = 15,
                    n_slices: int = SEEPI_NSLICE, te: float = 60e-3,
                    zs=None, gamma: float = GAMMA) -> Sequence:

@@ -44,9 +44,13 @@ def test_config_defaults(K):
 
 
 @pytest.mark.parametrize("k,expect", [
-    (1, dict(n_rf=6400, n_runs=64, n_deferred_adc=4096, n_inline_adc=0, n_stretches=64, n_snapshots=64)),
-    (2, dict(n_rf=50, n_runs=1, n_deferred_adc=16384, n_inline_adc=0, n_stretches=128, n_snapshots=1)),
-    (4, dict(n_rf=10000, n_runs=1000, n_deferred_adc=0, n_inline_adc=1000, n_stretches=0, n_snapshots=0)),
+    # one readout gradient for every GRE line; two readout polarities in EPI
+    (1, dict(n_rf=6400, n_runs=64, n_deferred_adc=4096, n_inline_adc=0, n_stretches=64, n_families=1,
+             n_snapshots=64)),
+    (2, dict(n_rf=50, n_runs=1, n_deferred_adc=16384, n_inline_adc=0, n_stretches=128, n_families=2,
+             n_snapshots=1)),
+    (4, dict(n_rf=10000, n_runs=1000, n_deferred_adc=0, n_inline_adc=1000, n_stretches=0, n_families=0,
+             n_snapshots=0)),
 ])
 def test_host_plans_of_the_workloads(K, k, expect):
     sc, ph, seq = W.config(k)
@@ -61,9 +65,25 @@ def test_host_plans_of_the_workloads(K, k, expect):
 
 def test_stretches_split_at_the_length_cap(K):
     sc, ph, seq = W.config(2)
-    for smax, want in ((128, 128), (100, 256), (1, 16384)):
+    for smax, want, fams in ((128, 128, 2), (100, 256, 2), (1, 16384, 1)):
         info = K.koma_plan_info(sc, ph, seq, K.make_config(stretch_max=smax))
         assert info["n_stretches"] == want
+        # single samples have no increments: one family takes them all
+        assert info["n_families"] == fams
+
+
+def test_stretches_of_equal_increments_form_families(K):
+    """Lines of equal readout amplitude share their per-sample increments
+    (one family each); single samples join any family."""
+    rng = np.random.default_rng(3)
+    ph = W.random_spins(rng, 100)
+    seq = W.readout_lines_sequence([0.01, -0.01, 0.01, 0.02, -0.01, 0.01, -0.01])
+    info = K.koma_plan_info(W.Scanner(), ph, seq, K.make_config())
+    assert info["n_stretches"] == 7 and info["n_families"] == 3
+    info = K.koma_plan_info(W.Scanner(), ph, seq, K.make_config(stretch_max=16))
+    assert info["n_stretches"] == 7 * 3 and info["n_families"] == 3
+    info = K.koma_plan_info(W.Scanner(), ph, seq, K.make_config(stretch_max=1))
+    assert info["n_families"] == 1
 
 
 def test_defer_threshold_moves_samples_inline(K):

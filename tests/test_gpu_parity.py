@@ -138,6 +138,30 @@ def test_random_sequences_edge_cases(ctx, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_stretch_families_share_operands(ctx, prec):
+    """Readout lines of three gradient amplitudes (3, 3 and 1 lines, in
+    mixed order): the matrix-core kernel shares the per-sample operands
+    within a family of equal increments; a stretch pair whose stretches
+    belong to two families, and a short last batch, take their own paths.
+    Several stretch lengths and tile counts per lane, both sample engines."""
+    import oracle
+    rng = np.random.default_rng(21)
+    sc = W.Scanner()
+    seq = W.readout_lines_sequence([0.01, -0.01, 0.01, 0.02, -0.01, 0.01, -0.01])
+    ph = W.random_spins(rng, 300)
+    ref = oracle.simulate(sc, ph, seq)
+    for smax in (128, 16, 7):
+        for spl in (1, 2, 8):
+            for eng in (0, 1):
+                ctx.set_config(prec, spins_per_lane=spl, sample_engine=eng, stretch_max=smax)
+                got = ctx.simulate(sc, ph, seq)
+                e = float(np.max(nrmse(got, ref)))
+                assert e <= TOL[prec], (smax, spl, eng, e)
+    say(f"[parity] stretch families {prec}: ok")
+    ctx.set_config(prec, spins_per_lane=0, sample_engine=0, stretch_max=128)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_launch_shape_invariance_and_determinism(ctx, prec):
     """Spins per lane and stretch length change only rounding; repeated runs
     are bitwise identical."""
