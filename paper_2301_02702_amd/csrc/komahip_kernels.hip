@@ -714,33 +714,39 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
         for (int p = 0; p < 2; ++p) acc[p][0] = acc[p][1] = acc[p][2] = f32x4{0.f, 0.f, 0.f, 0.f};
         for (int j = 0; j < S; ++j) {
-            const int tl = wave + kWavesPerWG * j;
+            // the wavefront's tile (uniform: read through the scalar cache)
+            const int tl = __builtin_amdgcn_readfirstlane(wave) + kWavesPerWG * j;
+            if (tl >= B.ntiles) break;  // uniform; later slots are empty too
+            const auto &T = as_const(a.tiles)[B.tile0 + tl];
+            const bool valid = lane < T.count;
+            const int64_t pidx = (int64_t)(B.tile0 + tl) * kWave + lane;  // padded spin slot of this lane
+            // every load of the tile issued at once: spin data, sensitivity,
+            // and the snapshots of the batch's stretches
             ParSpin spn{0.f, 0.f, 0.f, 0.f, __builtin_inff()};
             C2<float> sens{1.f, 0.f};
-            bool valid = false;
-            int64_t pidx = 0;  // padded spin slot of this lane
-            if (tl < B.ntiles) {
-                const Tile T = a.tiles[B.tile0 + tl];
-                pidx = (int64_t)(B.tile0 + tl) * kWave + lane;
-                if (lane < T.count) {
-                    const int64_t i = T.spin0 + lane;
-                    valid = true;
-                    spn = ParSpin{a.ph.x[i], a.ph.y[i], a.ph.z[i], a.ph.dw[i], a.ph.t2[i]};
-                    if (coils) sens = C2<float>{a.ph.sre[coil * a.ph.n + i], a.ph.sim[coil * a.ph.n + i]};
-                }
+            float2 snap[kMMStretches];
+            // snapshots of stretch i2 of the batch (zero for empty lanes)
+            auto load_snap = [&](int i2) {
+                snap[i2] = make_float2(0.f, 0.f);
+                if (valid)
+                    snap[i2] = reinterpret_cast<const float2 *>(a.snap)[(int64_t)as_const(a.st)[sb + min(i2, nb - 1)].slot * n_pad + pidx];
+            };
+            if (valid) {
+                const int64_t i = T.spin0 + lane;
+                spn = ParSpin{a.ph.x[i], a.ph.y[i], a.ph.z[i], a.ph.dw[i], a.ph.t2[i]};
+                if (coils) sens = C2<float>{a.ph.sre[coil * a.ph.n + i], a.ph.sim[coil * a.ph.n + i]};
             }
+            load_snap(0);
+            load_snap(1);
             const float r2 = __builtin_amdgcn_rcpf(spn.t2);  // +inf -> 0: no decay
             int32_t fam = -1;                                   // family of the operands in registers
             C2<float> wq[8];                                    // w^(16 q)
             float b1[16], b2[16], b3[16];                       // Re B, Im B - Re B, Re B + Im B (spin 4u + g, column m)
-            // anchor of a stretch: snapshot x coil sensitivity x exact FP64-phase factor
-            auto anchor = [&](const auto &T_) -> C2<float> {
-                C2<float> mm{0.f, 0.f};
-                if (valid) {
-                    const float2 v = reinterpret_cast<const float2 *>(a.snap)[(int64_t)T_.slot * n_pad + pidx];
-                    mm = C2<float>{v.x, v.y};
-                    if (coils) mm = cmul(mm, sens);
-                }
+            // anchor of stretch i2 of the batch: snapshot x coil sensitivity x
+            // exact FP64-phase factor
+            auto anchor = [&](const auto &T_, int i2) -> C2<float> {
+                C2<float> mm{snap[i2].x, snap[i2].y};
+                if (coils) mm = cmul(mm, sens);
                 const double k0[4] = {T_.k0[0], T_.k0[1], T_.k0[2], T_.k0[3]};
                 return cmul(mm, mm_anchor(spn, r2, k0));
             };
@@ -798,8 +804,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
                         __builtin_amdgcn_wave_barrier();
                     }
                     const C2<float> zero{0.f, 0.f};
-                    const C2<float> ca = (passes == 1 || pass == 0) ? anchor(Sa) : zero;
-                    const C2<float> cb = (passes == 1 || pass == 1) ? anchor(Sb) : zero;
+                    const C2<float> ca = (passes == 1 || pass == 0) ? anchor(Sa, 2 * p) : zero;
+                    const C2<float> cb = (passes == 1 || pass == 1) ? anchor(Sb, 2 * p + 1) : zero;
                     C2<float> aa[8], ab[8];
                     aa[0] = ca;
                     ab[0] = cb;
@@ -831,6 +837,11 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
 #undef KOMA_IM
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     __builtin_amdgcn_wave_barrier();
+                    // the next pair's snapshots arrive during these products
+                    if (p == 0 && pass == passes - 1) {
+                        load_snap(2);
+                        load_snap(3);
+                    }
                     // the three planes in two halves of 8 spin groups: reads
                     // first (one wait), then the products
 #pragma unroll
