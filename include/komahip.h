@@ -213,7 +213,8 @@ void koma_req_close(koma_req *req);
 
 typedef struct {
     int64_t n_spins, n_tiles, n_groups, n_adc;
-    int64_t n_events, n_rf, n_runs, n_inline_adc, n_deferred_adc, n_stretches, n_families, n_snapshots;
+    int64_t n_events, n_rf, n_rf_events, n_runs, n_inline_adc, n_deferred_adc, n_stretches, n_families,
+        n_snapshots;
     int64_t n_blocks, spins_per_lane, n_chunks;
     int64_t events_done;
     size_t footprint;

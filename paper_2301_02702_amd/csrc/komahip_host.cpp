@@ -18,6 +18,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <new>
 #include <string>
@@ -54,7 +55,7 @@ struct Plan {
     std::vector<Stretch> st;
     std::vector<std::array<double, 4>> fam_dk;  // increments of each stretch family
     std::vector<int32_t> inl_k, def_k;  // inline / deferred column -> ADC index
-    int64_t n_slots = 0, n_rf = 0, n_runs = 0;
+    int64_t n_slots = 0, n_rf = 0, n_rf_events = 0, n_runs = 0;
     std::vector<int64_t> snap_event;  // slot -> event index of its EV_SNAP
     // spin layout
     int64_t n_spins = 0, n_groups = 1, n_tiles = 0, n_adc = 0;
@@ -545,7 +546,7 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     P.blocks.clear();
     P.blk_off.clear();
     P.chunks.clear();
-    P.n_slots = P.n_rf = P.n_runs = 0;
+    P.n_slots = P.n_rf = P.n_rf_events = P.n_runs = 0;
     P.spl = 1;
     P.per_wg = 1;
     P.max_cols = 0;
@@ -606,6 +607,10 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     // (their phase is not linear in the sample index)
     const int defer_min = P.moving ? -1 : cfg.defer_min_adc;
     const bool moving = P.moving;
+    // the current run of identical excitation intervals: the point it ends
+    // at, its start time and its G t means (moving spins)
+    int64_t rf_run_end = -1;
+    double rf_run_t0 = 0.0, rf_run_gt[3] = {0, 0, 0};
 
     P.def_k.reserve((size_t)q->n_adc);
     const double *__restrict T = q->t;
@@ -730,22 +735,8 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
         // excitation interval b
         {
             const double dt = q->t[b + 1] - q->t[b];
-            const double v[8] = {0.5 * (q->gx[b] + q->gx[b + 1]),
-                                 0.5 * (q->gy[b] + q->gy[b + 1]),
-                                 0.5 * (q->gz[b] + q->gz[b + 1]),
-                                 q->b1_re[b],
-                                 q->b1_im[b],
-                                 q->b1_re[b] * q->b1_re[b] + q->b1_im[b] * q->b1_im[b],
-                                 -gamma * dt / (2.0 * kTwoPi),
-                                 dt};
-            Event e{};
-            e.kind = EV_RF;
-            for (int c = 0; c < 8; ++c) {
-                e.d[c] = v[c];
-                e.f[c] = (float)v[c];
-            }
-            e.b1sq_f32 = (double)e.f[3] * (double)e.f[3] + (double)e.f[4] * (double)e.f[4];
-            e.rot = -1;
+            const double gb[3] = {0.5 * (q->gx[b] + q->gx[b + 1]), 0.5 * (q->gy[b] + q->gy[b + 1]),
+                                  0.5 * (q->gz[b] + q->gz[b + 1])};
             // moving spins: the interval mean of G(t) t, the velocity's share of Bz
             double gt[3] = {0, 0, 0};
             if (moving) {
@@ -753,6 +744,43 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
                 gt[0] = 0.5 * (q->gx[b] * t0 + q->gx[b + 1] * t1);
                 gt[1] = 0.5 * (q->gy[b] * t0 + q->gy[b + 1] * t1);
                 gt[2] = 0.5 * (q->gz[b] * t0 + q->gz[b + 1] * t1);
+            }
+            // A run of excitation intervals with the same field (bitwise) and
+            // lengths equal up to the rounding of the time grid (a hard pulse,
+            // say), with no other event in between, is one event with a count
+            // and the run's mean interval length.
+            Event *prev = nullptr;
+            if (!P.ev.empty() && P.ev.back().kind == EV_RF && b == rf_run_end) prev = &P.ev.back();
+            bool merge = false;
+            if (prev) {
+                const double tol = 8.0 * std::numeric_limits<double>::epsilon() * std::fabs(q->t[b + 1]);
+                merge = prev->count < (1 << 30) && std::fabs(dt - prev->d[7]) <= tol &&
+                        std::memcmp(prev->d, gb, sizeof gb) == 0 && prev->d[3] == q->b1_re[b] &&
+                        prev->d[4] == q->b1_im[b] && std::memcmp(rf_run_gt, gt, sizeof gt) == 0;
+            }
+            int32_t count = 1;
+            double dtr = dt;
+            if (merge) {
+                count = prev->count + 1;
+                dtr = (q->t[b + 1] - rf_run_t0) / (double)count;
+            } else {
+                rf_run_t0 = q->t[b];
+                std::memcpy(rf_run_gt, gt, sizeof gt);
+            }
+            rf_run_end = b + 1;
+            const double v[8] = {gb[0], gb[1], gb[2], q->b1_re[b], q->b1_im[b],
+                                 q->b1_re[b] * q->b1_re[b] + q->b1_im[b] * q->b1_im[b],
+                                 -gamma * dtr / (2.0 * kTwoPi), dtr};
+            Event e{};
+            e.kind = EV_RF;
+            e.count = count;
+            for (int c = 0; c < 8; ++c) {
+                e.d[c] = v[c];
+                e.f[c] = (float)v[c];
+            }
+            e.b1sq_f32 = (double)e.f[3] * (double)e.f[3] + (double)e.f[4] * (double)e.f[4];
+            e.rot = -1;
+            if (moving) {
                 for (int c = 0; c < 3; ++c) {
                     e.c64[c] = gt[c];
                     e.c32[c] = (float)gt[c];
@@ -762,7 +790,7 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
                 // zero gradient: for Bz = 0 the field is (b1, 0) for every spin;
                 // alpha = cos(phi/2), beta = -i (b1/|b1|) sin(phi/2), phi = -gamma |b1| dt
                 const double nb = std::sqrt(v[5]);
-                const double h = -0.5 * gamma * nb * dt;
+                const double h = -0.5 * gamma * nb * dtr;
                 const double ar = std::cos(h), ai = 0.0;
                 const double sn = std::sin(h) / nb;
                 const double br = q->b1_im[b] * sn, bi = -q->b1_re[b] * sn;
@@ -778,7 +806,12 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
                 }
                 e.rot = 1;
             }
-            P.ev.push_back(e);
+            if (merge) {
+                *prev = e;
+            } else {
+                P.ev.push_back(e);
+                ++P.n_rf_events;
+            }
             ++P.n_rf;
         }
         a = b + 1;
@@ -1625,6 +1658,7 @@ static void fill_info(const Plan &P, koma_req_info *info) {
     info->n_adc = P.n_adc;
     info->n_events = (int64_t)P.ev.size();
     info->n_rf = P.n_rf;
+    info->n_rf_events = P.n_rf_events;
     info->n_runs = P.n_runs;
     info->n_inline_adc = (int64_t)P.inl_k.size();
     info->n_deferred_adc = (int64_t)P.def_k.size();

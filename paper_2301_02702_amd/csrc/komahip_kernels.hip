@@ -341,6 +341,80 @@ __device__ __forceinline__ void excite_relax(const SpinP<typename P::R> &s, cons
     mz = fma(-eps1, nz - s.pd, nz);
 }
 
+// The rotation of one excitation interval (Eq. Rot_exc, the spinor as in
+// excite_relax) as a real 3 x 3 matrix on (Mx, My, Mz), row-major.
+template <class P, bool MOV>
+__device__ __forceinline__ void rot_matrix(const SpinP<typename P::R> &s, const typename P::R *q,
+                                           const typename P::R *gt, double b1sq_exact, typename P::R *m) {
+    using R = typename P::R;
+    const R gx = q[0], gy = q[1], gz = q[2], b1r = q[3], b1i = q[4], b1sq = q[5], hs = q[6];
+    R bz0 = s.bz0;
+    if (MOV) bz0 = fma(s.vx, gt[0], fma(s.vy, gt[1], fma(s.vz, gt[2], bz0)));
+    const R bz = fma(s.x, gx, fma(s.y, gy, fma(s.z, gz, bz0)));
+    const R nb2 = fma(bz, bz, b1sq);
+    const R inv = nb2 > R(0) ? P::rsq(nb2) : R(0);
+    const R nb = nb2 * inv;
+    R sn, cs;
+    P::sincos_turns(hs * nb, sn, cs);
+    R sk = sn * inv;
+    {
+        const double B2 = fma((double)bz, (double)bz, b1sq_exact);
+        const double sk2 = (double)sk * (double)sk;
+        const R h = R(-0.5 * fma(sk2, B2, fma((double)cs, (double)cs, -1.0)));
+        cs = fma(cs, h, cs);
+        sk = fma(sk, h, sk);
+    }
+    const R ar = cs, ai = -bz * sk;
+    const R br = b1i * sk, bi = -b1r * sk;
+    const R ur = ar * ar - ai * ai, ui = R(-2) * ar * ai;
+    const R vr = br * br - bi * bi, vi = R(2) * br * bi;
+    const R wr = ar * br + ai * bi, wi = ar * bi - ai * br;
+    const R pr = ar * br - ai * bi, pi = ar * bi + ai * br;
+    m[0] = ur - vr;
+    m[1] = -(ui + vi);
+    m[2] = R(2) * wr;
+    m[3] = ui - vi;
+    m[4] = ur + vr;
+    m[5] = R(2) * wi;
+    m[6] = R(-2) * pr;
+    m[7] = R(-2) * pi;
+    m[8] = (ar * ar + ai * ai) - (br * br + bi * bi);
+}
+
+// k identical excitation intervals (uniform k >= 1): one interval is the
+// affine map M -> A M + b with A the rotation followed by the relaxation
+// factors (rows scaled by 1 - eps2, 1 - eps2, 1 - eps1) and b = (0, 0,
+// eps1 M0); its k-th power is applied by binary powering, the same product
+// of per-interval operators associated differently (log2 k squarings instead
+// of k steps).
+template <class R>
+__device__ __forceinline__ void affine_power(R *p, R b2, int k, R &mr, R &mi, R &mz) {
+    R q[3] = {R(0), R(0), b2};
+    for (;;) {
+        if (k & 1) {
+            const R nr = fma(p[0], mr, fma(p[1], mi, fma(p[2], mz, q[0])));
+            const R ni = fma(p[3], mr, fma(p[4], mi, fma(p[5], mz, q[1])));
+            const R nz = fma(p[6], mr, fma(p[7], mi, fma(p[8], mz, q[2])));
+            mr = nr;
+            mi = ni;
+            mz = nz;
+        }
+        k >>= 1;
+        if (k == 0) break;
+        R p2[9], q2[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) p2[3 * r + c] = fma(p[3 * r], p[c], fma(p[3 * r + 1], p[3 + c], p[3 * r + 2] * p[6 + c]));
+            q2[r] = fma(p[3 * r], q[0], fma(p[3 * r + 1], q[1], fma(p[3 * r + 2], q[2], q[r])));
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) p[i] = p2[i];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) q[i] = q2[i];
+    }
+}
+
 // ---------------------------------------------------------------- k_seq
 
 // The event program and stretch tables are read-only for a whole launch and
@@ -457,7 +531,33 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
                     eps1 = R(-expm1(-dt * (double)s.r1));
                     eps2 = R(-expm1(-dt * (double)s.r2));
                 }
-                if (ev.rot() >= 0 && no_offres) {
+                const int reps = ev.count();  // identical consecutive intervals (uniform)
+                if (reps > 1) {
+                    R m[9];
+                    if (ev.rot() >= 0 && no_offres) {
+                        // the host's coefficients: Mxy_re' = c0 Mz + c1 Mxy_re + c2 Mxy_im, ...
+                        const int perm[9] = {1, 2, 0, 5, 4, 3, 7, 8, 6};
+#pragma unroll
+                        for (int i = 0; i < 9; ++i) m[i] = sizeof(R) == 4 ? R(ev.c32(perm[i])) : R(ev.c64(perm[i]));
+                    } else {
+                        R q[7];
+#pragma unroll
+                        for (int i = 0; i < 7; ++i) q[i] = sizeof(R) == 4 ? R(ev.f(i)) : R(ev.d(i));
+                        R gt[3] = {R(0), R(0), R(0)};
+                        if (MOV && ev.rot() < 0) {
+#pragma unroll
+                            for (int i = 0; i < 3; ++i) gt[i] = sizeof(R) == 4 ? R(ev.c32(i)) : R(ev.c64(i));
+                        }
+                        const double b1sq = sizeof(R) == 4 ? ev.b1sq() : ev.d(5);
+                        rot_matrix<P, MOV>(s, q, gt, b1sq, m);
+                    }
+                    const R k2 = R(1) - eps2, k1 = R(1) - eps1;
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) m[i] *= k2;
+#pragma unroll
+                    for (int i = 6; i < 9; ++i) m[i] *= k1;
+                    affine_power(m, eps1 * s.pd, reps, mr, mi, mz);
+                } else if (ev.rot() >= 0 && no_offres) {
                     R c[9];
 #pragma unroll
                     for (int i = 0; i < 9; ++i) c[i] = sizeof(R) == 4 ? R(ev.c32(i)) : R(ev.c64(i));

@@ -56,7 +56,7 @@ class koma_config(ctypes.Structure):
 
 class koma_req_info(ctypes.Structure):
     _fields_ = [(k, c_int64) for k in (
-        "n_spins", "n_tiles", "n_groups", "n_adc", "n_events", "n_rf", "n_runs", "n_inline_adc",
+        "n_spins", "n_tiles", "n_groups", "n_adc", "n_events", "n_rf", "n_rf_events", "n_runs", "n_inline_adc",
         "n_deferred_adc", "n_stretches", "n_families", "n_snapshots", "n_blocks", "spins_per_lane", "n_chunks",
         "events_done")] + [("footprint", c_size_t)]
 

@@ -45,12 +45,14 @@ def test_config_defaults(K):
 
 @pytest.mark.parametrize("k,expect", [
     # one readout gradient for every GRE line; two readout polarities in EPI
-    (1, dict(n_rf=6400, n_runs=64, n_deferred_adc=4096, n_inline_adc=0, n_stretches=64, n_families=1,
-             n_snapshots=64)),
-    (2, dict(n_rf=50, n_runs=1, n_deferred_adc=16384, n_inline_adc=0, n_stretches=128, n_families=2,
-             n_snapshots=1)),
-    (4, dict(n_rf=10000, n_runs=1000, n_deferred_adc=0, n_inline_adc=1000, n_stretches=0, n_families=0,
-             n_snapshots=0)),
+    # identical consecutive excitation intervals are one event: the two
+    # middle samples of each GRE sinc, the EPI hard pulse, each MRF hard pulse
+    (1, dict(n_rf=6400, n_rf_events=6336, n_runs=64, n_deferred_adc=4096, n_inline_adc=0, n_stretches=64,
+             n_families=1, n_snapshots=64)),
+    (2, dict(n_rf=50, n_rf_events=1, n_runs=1, n_deferred_adc=16384, n_inline_adc=0, n_stretches=128,
+             n_families=2, n_snapshots=1)),
+    (4, dict(n_rf=10000, n_rf_events=1000, n_runs=1000, n_deferred_adc=0, n_inline_adc=1000, n_stretches=0,
+             n_families=0, n_snapshots=0)),
 ])
 def test_host_plans_of_the_workloads(K, k, expect):
     sc, ph, seq = W.config(k)
@@ -60,7 +62,7 @@ def test_host_plans_of_the_workloads(K, k, expect):
     assert info["n_tiles"] == sum(-(-int(b - a) // 64) for a, b in zip(
         *(lambda o: (o[:-1], o[1:]))(ph.group_off if ph.group_off is not None else np.array([0, ph.n]))))
     # one event per excitation interval, block end, snapshot and inline stretch
-    assert info["n_events"] >= expect["n_rf"] + expect["n_runs"] + expect["n_snapshots"]
+    assert info["n_events"] >= expect["n_rf_events"] + expect["n_runs"] + expect["n_snapshots"]
 
 
 def test_stretches_split_at_the_length_cap(K):
@@ -70,6 +72,32 @@ def test_stretches_split_at_the_length_cap(K):
         assert info["n_stretches"] == want
         # single samples have no increments: one family takes them all
         assert info["n_families"] == fams
+
+
+def test_runs_of_identical_excitation_intervals_are_one_event(K):
+    """Equal field values and lengths equal up to the rounding of the time
+    grid merge; a changed field, a sample or a precession interval in between
+    ends the run."""
+    ph = W.random_spins(np.random.default_rng(4), 10)
+    dt = 4e-6
+    b1 = np.full(40, 1e-5 + 0j)
+    b1[17] = 1.1e-5          # one different value: runs 17, 1, 22
+    seq = W.make_sequence(dt * np.arange(41), np.zeros((41, 3)), b1, [])
+    info = K.koma_plan_info(W.Scanner(), ph, seq, K.make_config())
+    assert info["n_rf"] == 40 and info["n_rf_events"] == 3
+    seq = W.make_sequence(dt * np.arange(41), np.zeros((41, 3)), np.full(40, 1e-5 + 0j), [10, 30])
+    info = K.koma_plan_info(W.Scanner(), ph, seq, K.make_config())
+    assert info["n_rf_events"] == 3       # split at the two sampled points
+    g = np.zeros((41, 3))
+    g[20:, 0] = 1e-3                       # the field changes at point 20 (mean G of interval 19)
+    seq = W.make_sequence(dt * np.arange(41), g, np.full(40, 1e-5 + 0j), [])
+    info = K.koma_plan_info(W.Scanner(), ph, seq, K.make_config())
+    assert info["n_rf_events"] == 3       # runs 0..18, 19, 20..39
+    t = dt * np.arange(41)
+    t[25:] += 1e-9                         # one longer interval
+    seq = W.make_sequence(t, np.zeros((41, 3)), np.full(40, 1e-5 + 0j), [])
+    info = K.koma_plan_info(W.Scanner(), ph, seq, K.make_config())
+    assert info["n_rf_events"] == 3
 
 
 def test_stretches_of_equal_increments_form_families(K):
@@ -152,7 +180,7 @@ def test_moving_phantom_plans_every_sample_inline(K):
     assert info["n_deferred_adc"] == 0 and info["n_stretches"] == 0 and info["n_snapshots"] == 0
     assert info["n_inline_adc"] == seq.n_adc
     # one event per sample, per excitation interval and per block end
-    assert info["n_events"] == seq.n_adc + info["n_rf"] + info["n_runs"]
+    assert info["n_events"] == seq.n_adc + info["n_rf_events"] + info["n_runs"]
     f_static = K.koma_footprint(ph, seq, K.make_config())
     f_moving = K.koma_footprint(W.with_velocity(ph), seq, K.make_config())
     assert f_moving > f_static

@@ -137,6 +137,55 @@ def test_random_sequences_edge_cases(ctx, prec):
     ctx.set_config(prec, defer_min_adc=32, sample_engine=0)
 
 
+def _pulse_runs_sequence(with_gradient_rf=False):
+    """Hard pulses of 1, 2, 3, 7, 50 and 1000 identical intervals, each
+    followed by a gradient lobe and a few samples; optionally one pulse
+    played under a gradient."""
+    dt = 4e-6
+    lens = (1, 2, 3, 7, 50, 1000)
+    n_int = sum(lens) + len(lens) * 30 + (50 if with_gradient_rf else 0)
+    s = W.UniformSeq(n_int, dt)
+    p = 0
+    for k, n in enumerate(lens):
+        p = s.rf(p, W.hard_pulse(n, dt, (0.3 + 0.2 * k) * np.pi / 2))
+        s.adc_points(p, 3)
+        q = s.trap(0, p + 4, 3, 6, 2e-3 * (k + 1))
+        s.adc_points(q, 4)
+        p += 30
+    if with_gradient_rf:
+        s.trap(2, p - 1, 2, 38, 5e-3)   # Gz under the last pulse: intervals differ for moving spins
+        p = s.rf(p, W.hard_pulse(40, dt, np.pi / 4))
+    return s.build("pulse_runs")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_runs_of_identical_excitation_intervals(ctx, prec):
+    """Runs of identical excitation intervals are applied by binary powering
+    of one interval's affine map (rotation then relaxation): against the
+    oracle's interval-by-interval steps, for spins with off-resonance (the
+    per-spin spinor) and without (the precomputed zero-gradient rotation),
+    with relaxation and with T = inf, and for moving spins."""
+    import oracle
+    rng = np.random.default_rng(31)
+    sc = W.Scanner()
+    seq = _pulse_runs_sequence()
+    cases = [W.random_spins(rng, 200), W.random_spins(rng, 130, finite_t=False)]
+    still = W.random_spins(rng, 128)
+    still.dw[:] = 0.0                      # whole wavefronts without off-resonance
+    cases.append(still)
+    for ph in cases:
+        ref = oracle.simulate(sc, ph, seq)
+        ctx.set_config(prec)
+        e = float(np.max(nrmse(ctx.simulate(sc, ph, seq), ref)))
+        assert e <= TOL[prec], (ph.name, e)
+    mov_seq = _pulse_runs_sequence(with_gradient_rf=True)
+    ph = W.with_velocity(W.random_spins(rng, 150), v=(0.05, -0.1, 0.2), spread=0.05)
+    ref = oracle.simulate(sc, ph, mov_seq)
+    e = float(np.max(nrmse(ctx.simulate(sc, ph, mov_seq), ref)))
+    assert e <= TOL[prec], ("moving", e)
+    say(f"[parity] excitation runs {prec}: ok")
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_stretch_families_share_operands(ctx, prec):
     """Readout lines of three gradient amplitudes (3, 3 and 1 lines, in
