@@ -551,12 +551,20 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
                         const double b1sq = sizeof(R) == 4 ? ev.b1sq() : ev.d(5);
                         rot_matrix<P, MOV>(s, q, gt, b1sq, m);
                     }
-                    const R k2 = R(1) - eps2, k1 = R(1) - eps1;
+                    // the powers in FP64 (full rate here): every spin with the
+                    // same field shares the matrix, so its rounding would add
+                    // up coherently over the spins of a voxel
+                    const double k2 = 1.0 - (double)eps2, k1 = 1.0 - (double)eps1;
+                    double md[9];
 #pragma unroll
-                    for (int i = 0; i < 6; ++i) m[i] *= k2;
+                    for (int i = 0; i < 6; ++i) md[i] = (double)m[i] * k2;
 #pragma unroll
-                    for (int i = 6; i < 9; ++i) m[i] *= k1;
-                    affine_power(m, eps1 * s.pd, reps, mr, mi, mz);
+                    for (int i = 6; i < 9; ++i) md[i] = (double)m[i] * k1;
+                    double xr = mr, xi = mi, xz = mz;
+                    affine_power(md, (double)eps1 * (double)s.pd, reps, xr, xi, xz);
+                    mr = R(xr);
+                    mi = R(xi);
+                    mz = R(xz);
                 } else if (ev.rot() >= 0 && no_offres) {
                     R c[9];
 #pragma unroll
