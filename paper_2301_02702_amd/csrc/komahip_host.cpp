@@ -958,6 +958,7 @@ struct Bufs {  // device views used by the launch sequence
     double *pb;
     double *sig;
     void *mxy, *mz;
+    const int32_t *gate = nullptr;  // the sums are written only if *gate == 0 (device-checked phantoms)
 };
 
 }  // namespace
@@ -974,9 +975,10 @@ struct Bufs {  // device views used by the launch sequence
     } while (0)
 
 static koma_status run_seq(koma_ctx *ctx, const Plan &P, bool fp64, const Bufs &B, int64_t e0, int64_t e1,
-                           bool init, bool store, hipStream_t s) {
+                           bool init, bool store, hipStream_t s, int32_t *vflags = nullptr) {
     if (e1 <= e0) return KOMA_OK;
     SeqArgs a{};
+    a.vflags = vflags;
     a.ph = B.ph;
     a.tiles = B.tiles;
     a.n_tiles = P.n_tiles;
@@ -1027,6 +1029,7 @@ static koma_status run_chunk(koma_ctx *ctx, const Plan &P, bool fp64, const Bufs
     r.n_groups = P.n_groups;
     r.col_to_adc = B.def + c.c0;
     r.sig = B.sig;
+    r.gate = B.gate;
     r.n_adc = P.n_adc;
     LAUNCH(ctx, K_RED, P.n_sig * (int64_t)P.blocks.size() * (c.c1 - c.c0) * 16, s, launch_reduce(true, r, s));
     return KOMA_OK;
@@ -1043,6 +1046,7 @@ static koma_status run_inline_reduce(koma_ctx *ctx, const Plan &P, bool fp64, co
     r.n_groups = P.n_groups;
     r.col_to_adc = B.inl;
     r.sig = B.sig;
+    r.gate = B.gate;
     r.n_adc = P.n_adc;
     LAUNCH(ctx, K_RED, P.n_sig * P.n_tiles * r.cols * (fp64 ? 16 : 8), s, launch_reduce(fp64, r, s));
     return KOMA_OK;
@@ -1306,18 +1310,17 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
     B.inl = (const int32_t *)(tb + parts[6].off);
     B.def = (const int32_t *)(tb + parts[7].off);
 
-    // device-resident phantom: validation flags reduced on the device; the
-    // results are committed to the caller's buffers only if they are clean,
+    // device-resident phantom: the spin-sequential kernel validates the
+    // values it reads (per-workgroup flags, reduced on the device); the
+    // final sums are written to the caller's buffers only if they are clean,
     // and the host reads the flag after the one synchronisation at the end
     const bool dev_check = where == KOMA_DEVICE;
-    int32_t *flag_total = nullptr;
+    int32_t *flags = nullptr, *flag_total = nullptr;
+    const int64_t nwg_seq = (P.n_tiles + kWavesPerWG - 1) / kWavesPerWG;
     if (dev_check) {
-        const int64_t nwg = (ph->n + kWG - 1) / kWG;
-        if ((st = dev_reserve(ctx, ctx->s_flags, (size_t)(nwg + 1) * 4)) != KOMA_OK) return st;
-        int32_t *flags = (int32_t *)ctx->s_flags.p;
-        flag_total = flags + nwg;
-        LAUNCH(ctx, K_AUX, ph->n, s, launch_validate(B.ph, ph->n, flags, s));
-        LAUNCH(ctx, K_AUX, nwg, s, launch_flags_or(flags, nwg, flag_total, s));
+        if ((st = dev_reserve(ctx, ctx->s_flags, (size_t)(nwg_seq + 1) * 4)) != KOMA_OK) return st;
+        flags = (int32_t *)ctx->s_flags.p;
+        flag_total = flags + nwg_seq;
     }
 
     const size_t n_pad = (size_t)P.n_tiles * kWave;
@@ -1332,25 +1335,32 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
         if ((st = dev_reserve(ctx, ctx->s_mf, (size_t)ph->n * 24)) != KOMA_OK) return st;
     }
     const size_t sig_n = nsig * (size_t)P.n_groups * P.n_adc * 2;  // doubles
-    if ((st = dev_reserve(ctx, ctx->s_sig, sig_n * 8)) != KOMA_OK) return st;
     B.snap = ctx->s_snap.p;
     B.pa = ctx->s_pa.p;
     B.pb = (double *)ctx->s_pb.p;
-    B.sig = (double *)ctx->s_sig.p;
     B.mxy = ctx->s_mxy.p;
     B.mz = ctx->s_mz.p;
+    if (dev_check) {
+        // every sample of every signal plane is written by the final sums,
+        // straight into the caller's buffer, gated by the validation flag
+        B.sig = sig;
+        B.gate = flag_total;
+    } else {
+        if ((st = dev_reserve(ctx, ctx->s_sig, sig_n * 8)) != KOMA_OK) return st;
+        B.sig = (double *)ctx->s_sig.p;
+    }
 
-    if ((st = run_seq(ctx, P, fp64, B, 0, (int64_t)P.ev.size(), true, store, s)) != KOMA_OK) return st;
+    if ((st = run_seq(ctx, P, fp64, B, 0, (int64_t)P.ev.size(), true, store, s, flags)) != KOMA_OK) return st;
+    if (dev_check) LAUNCH(ctx, K_AUX, nwg_seq, s, launch_flags_or(flags, nwg_seq, flag_total, s));
     if (P.n_adc > 0) {
         for (const Chunk &c : P.chunks)
             if ((st = run_chunk(ctx, P, fp64, B, c, s)) != KOMA_OK) return st;
         if ((st = run_inline_reduce(ctx, P, fp64, B, s)) != KOMA_OK) return st;
     }
-    double *mf = store ? (double *)ctx->s_mf.p : nullptr;
-    if (store) LAUNCH(ctx, K_AUX, (int64_t)n_pad, s, launch_export(fp64, B.tiles, P.n_tiles, B.mxy, B.mz, mf, s));
+    double *mf = store ? (dev_check ? m_final : (double *)ctx->s_mf.p) : nullptr;
+    if (store)
+        LAUNCH(ctx, K_AUX, (int64_t)n_pad, s, launch_export(fp64, B.tiles, P.n_tiles, B.mxy, B.mz, mf, B.gate, s));
     if (dev_check) {
-        if (sig_n) LAUNCH(ctx, K_AUX, (int64_t)sig_n, s, launch_commit(flag_total, B.sig, sig, (int64_t)sig_n, s));
-        if (store) LAUNCH(ctx, K_AUX, ph->n * 3, s, launch_commit(flag_total, mf, m_final, ph->n * 3, s));
         if (async) {
             if (status) HIPCHK(ctx, hipMemcpyAsync(status, flag_total, 4, hipMemcpyDeviceToDevice, s));
             if (!ctx->async_done) HIPCHK(ctx, hipEventCreateWithFlags(&ctx->async_done, hipEventDisableTiming));

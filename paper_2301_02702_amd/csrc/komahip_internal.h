@@ -112,6 +112,7 @@ struct SeqArgs {  // spin-sequential kernel
     void *snap;       // [n_slots][n_tiles*64] complex (R2)
     void *pa;         // inline partials [n_sig][n_tiles][n_inline] complex (R2)
     int64_t n_inline;
+    int32_t *vflags;  // nullptr, or per-workgroup validation bits of the phantom values (as k_validate)
 };
 
 struct ParArgs {  // sample-parallel kernel
@@ -138,6 +139,7 @@ struct ReduceArgs {  // cross-workgroup sums into the signal (grid.z = coil)
     int64_t n_groups;
     const int32_t *col_to_adc;  // column c -> ADC index
     double *sig;           // [n_sig][n_groups][n_adc] double2
+    const int32_t *gate;   // nullptr, or a flag: the sums are written only if *gate == 0
     int64_t n_adc;
 };
 
@@ -150,7 +152,6 @@ int launch_par(bool fp64, int spins_per_lane, const ParArgs &a, void *stream);
 int launch_reduce(bool part_fp64, const ReduceArgs &a, void *stream);
 int launch_validate(const PhantomDev &ph, int64_t n, int32_t *flags, void *stream);
 int launch_flags_or(const int32_t *flags, int64_t n, int32_t *out, void *stream);
-int launch_commit(const int32_t *flag, const double *src, double *dst, int64_t n, void *stream);
 int launch_export(bool fp64, const Tile *tiles, int64_t n_tiles, const void *mxy, const void *mz,
-                  double *m_final, void *stream);
+                  double *m_final, const int32_t *gate, void *stream);
 }  // namespace koma

@@ -415,6 +415,22 @@ __device__ __forceinline__ void affine_power(R *p, R b2, int k, R &mr, R &mi, R 
     }
 }
 
+// Validation bits of spin i's phantom values (device-resident phantoms):
+// bit 0 non-finite x, y, z, dw, PD or velocity; bit 1 PD < 0; bit 2 T1 or T2
+// <= 0 or NaN; bit 3 non-finite coil sensitivity.
+__device__ __forceinline__ int32_t spin_flags(const PhantomDev &ph, int64_t i) {
+    int32_t bad = 0;
+    const float x = ph.x[i], y = ph.y[i], z = ph.z[i], dw = ph.dw[i], pd = ph.pd[i];
+    const float t1 = ph.t1[i], t2 = ph.t2[i];
+    if (!isfinite(x) || !isfinite(y) || !isfinite(z) || !isfinite(dw) || !isfinite(pd)) bad |= 1;
+    if (pd < 0.f) bad |= 2;
+    if (!(t1 > 0.f) || !(t2 > 0.f)) bad |= 4;
+    if (ph.vx && (!isfinite(ph.vx[i]) || !isfinite(ph.vy[i]) || !isfinite(ph.vz[i]))) bad |= 1;
+    for (int64_t k = 0; k < ph.n_coils; ++k)
+        if (!isfinite(ph.sre[k * ph.n + i]) || !isfinite(ph.sim[k * ph.n + i])) bad |= 8;
+    return bad;
+}
+
 // ---------------------------------------------------------------- k_seq
 
 // The event program and stretch tables are read-only for a whole launch and
@@ -500,6 +516,15 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
     const SpinP<R> s = load_spin<R, MOV>(a.ph, T, lane, a.inv_gamma);
     const int64_t n_pad = a.n_tiles * kWave;
     const int64_t pidx = tile * kWave + lane;
+    if (a.vflags) {  // uniform: validate the phantom values of this workgroup's spins
+        __shared__ int32_t wg_bad;
+        if (threadIdx.x == 0) wg_bad = 0;
+        __syncthreads();
+        const int32_t bad = lane < T.count ? spin_flags(a.ph, T.spin0 + lane) : 0;
+        if (bad) atomicOr(&wg_bad, bad);
+        __syncthreads();
+        if (threadIdx.x == 0) a.vflags[blockIdx.x] = wg_bad;
+    }
 
     R mr = R(0), mi = R(0), mz = s.pd;
     if (active && !a.init) {
@@ -1019,6 +1044,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
 template <class T2>
 __global__ __launch_bounds__(kWG) void k_reduce(ReduceArgs a) {
     __shared__ double2 red[kWavesPerWG][kWave];
+    if (a.gate && *as_const(a.gate) != 0) return;  // uniform: invalid inputs leave the output untouched
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t col = (int64_t)blockIdx.x * kWave + lane;
     const int64_t k = blockIdx.z;
@@ -1051,9 +1077,11 @@ __global__ __launch_bounds__(kWG) void k_reduce(ReduceArgs a) {
 
 // ---------------------------------------------------------------- k_export
 
+// gate: nullptr, or a flag that must be 0 for anything to be written.
 template <class R, class R2>
 __global__ __launch_bounds__(kWG) void k_export(const Tile *tiles, int64_t n_tiles, const R2 *mxy,
-                                                const R *mz, double *out) {
+                                                const R *mz, double *out, const int32_t *gate) {
+    if (gate && *as_const(gate) != 0) return;
     const int64_t p = (int64_t)blockIdx.x * kWG + threadIdx.x;
     const int64_t tile = p / kWave;
     const int lane = (int)(p % kWave);
@@ -1074,17 +1102,7 @@ __global__ __launch_bounds__(kWG) void k_export(const Tile *tiles, int64_t n_til
 __global__ __launch_bounds__(kWG) void k_validate(PhantomDev ph, int64_t n, int32_t *flags) {
     __shared__ int32_t f[kWG];
     const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    int32_t bad = 0;
-    if (i < n) {
-        const float x = ph.x[i], y = ph.y[i], z = ph.z[i], dw = ph.dw[i], pd = ph.pd[i];
-        const float t1 = ph.t1[i], t2 = ph.t2[i];
-        if (!isfinite(x) || !isfinite(y) || !isfinite(z) || !isfinite(dw) || !isfinite(pd)) bad |= 1;
-        if (pd < 0.f) bad |= 2;
-        if (!(t1 > 0.f) || !(t2 > 0.f)) bad |= 4;
-        if (ph.vx && (!isfinite(ph.vx[i]) || !isfinite(ph.vy[i]) || !isfinite(ph.vz[i]))) bad |= 1;
-        for (int64_t k = 0; k < ph.n_coils; ++k)
-            if (!isfinite(ph.sre[k * ph.n + i]) || !isfinite(ph.sim[k * ph.n + i])) bad |= 8;
-    }
+    const int32_t bad = i < n ? spin_flags(ph, i) : 0;
     f[threadIdx.x] = bad;
     __syncthreads();
     for (int s = kWG / 2; s > 0; s >>= 1) {
@@ -1106,13 +1124,6 @@ __global__ __launch_bounds__(kWG) void k_flags_or(const int32_t *flags, int64_t 
         __syncthreads();
     }
     if (threadIdx.x == 0) out[0] = f[0];
-}
-
-// Copy n doubles from src to dst only if *flag == 0 (the inputs were valid),
-// so a rejected call leaves the caller's output untouched.
-__global__ __launch_bounds__(kWG) void k_commit(const int32_t *flag, const double *src, double *dst, int64_t n) {
-    if (*flag != 0) return;
-    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG) dst[i] = src[i];
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1197,25 +1208,17 @@ int launch_flags_or(const int32_t *flags, int64_t n, int32_t *out, void *stream)
     return check_launch();
 }
 
-int launch_commit(const int32_t *flag, const double *src, double *dst, int64_t n, void *stream) {
-    if (n <= 0) return 0;
-    int64_t g = (n + kWG - 1) / kWG;
-    if (g > 4096) g = 4096;
-    hipLaunchKernelGGL(k_commit, dim3((unsigned)g), dim3(kWG), 0, (hipStream_t)stream, flag, src, dst, n);
-    return check_launch();
-}
-
 int launch_export(bool fp64, const Tile *tiles, int64_t n_tiles, const void *mxy, const void *mz,
-                  double *m_final, void *stream) {
+                  double *m_final, const int32_t *gate, void *stream) {
     if (n_tiles <= 0) return 0;
     const int64_t n = n_tiles * kWave;
     dim3 grid((unsigned)((n + kWG - 1) / kWG));
     if (fp64)
         hipLaunchKernelGGL((k_export<double, double2>), grid, dim3(kWG), 0, (hipStream_t)stream, tiles,
-                           n_tiles, (const double2 *)mxy, (const double *)mz, m_final);
+                           n_tiles, (const double2 *)mxy, (const double *)mz, m_final, gate);
     else
         hipLaunchKernelGGL((k_export<float, float2>), grid, dim3(kWG), 0, (hipStream_t)stream, tiles,
-                           n_tiles, (const float2 *)mxy, (const float *)mz, m_final);
+                           n_tiles, (const float2 *)mxy, (const float *)mz, m_final, gate);
     return check_launch();
 }
 

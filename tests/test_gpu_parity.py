@@ -274,10 +274,11 @@ def test_invalid_device_phantom_is_rejected(ctx, K):
     sc, ph, seq = case("epi_small")
     dph = K.device_phantom(ph)
     dph["t2"][5] = float("nan")
-    sig = torch.zeros((1, seq.n_adc, 2), dtype=torch.float64, device="cuda:0")
+    sig = torch.full((1, seq.n_adc, 2), -3.0, dtype=torch.float64, device="cuda:0")
     with pytest.raises(K.KomaError) as e:
         ctx.simulate(sc, dph, seq, where="device", sig=sig)
     assert e.value.status == -2
+    assert bool(torch.all(sig == -3.0))  # the output is left untouched
     # the context still works afterwards
     assert np.isfinite(ctx.simulate(sc, ph, seq)).all()
 
