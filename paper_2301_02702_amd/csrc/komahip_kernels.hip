@@ -1002,17 +1002,22 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
             }
         }
         __syncthreads();  // every wavefront is done with its stage
+        // The thread's indices formed afresh (an opaque copy of the thread id),
+        // so that nothing derived from them stays live across the tile loop.
+        int tid;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
+        const int e_wave = tid >> 6, e_lane = tid & 63, e_m = e_lane & 15, e_g = e_lane >> 4;
         // lane l holds rows 4 (l / 16) + v: stretch h = l / 32 of the pair,
         // q = 4 ((l / 16) % 2) + v; column m
-        const int half = lane >> 5;
+        const int half = e_lane >> 5;
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
             if (2 * p >= nb) break;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int smp = 16 * (4 * (g & 1) + v) + m;
+                const int smp = 16 * (4 * (e_g & 1) + v) + e_m;
                 const double p1 = (double)acc[p][0][v];
-                red[wave][half][smp] = make_double2(p1 - (double)acc[p][2][v], p1 + (double)acc[p][1][v]);
+                red[e_wave][half][smp] = make_double2(p1 - (double)acc[p][2][v], p1 + (double)acc[p][1][v]);
             }
             __syncthreads();
 #pragma unroll
@@ -1020,7 +1025,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
                 if (2 * p + h >= nb) break;
                 const auto &S_ = as_const(a.st)[sb + 2 * p + h];
                 const int cnt = S_.count, d0 = S_.d0;
-                for (int k = threadIdx.x; k < cnt; k += kWG) {
+                for (int k = tid; k < cnt; k += kWG) {
                     double2 t = red[0][h][k];
 #pragma unroll
                     for (int wv = 1; wv < kWavesPerWG; ++wv) {
