@@ -42,6 +42,9 @@ constexpr double kTwoPi = 6.28318530717958647692;
 // |f| (about the rounding of the time grid itself, ~1e-16 relative).
 constexpr double kStretchTolK = 2e-9;   // cycles/m
 constexpr double kStretchTolT = 1e-12;  // s
+// moving spins: first moments within this of their quadratic model (phase
+// error below 2e-9 turns per m/s of |v|)
+constexpr double kStretchTolK1 = 2e-9;  // cycles s/m
 
 struct Chunk {
     int64_t s0, s1;   // stretch range
@@ -470,6 +473,55 @@ void make_stretches(const Samples &s, int max_len, Emit emit) {
     }
 }
 
+// True when the first moments m[c][i..i+len-1] of a moving spin's samples lie
+// within kStretchTolK1 of the quadratic y0 + j d1 + j (j - 1) / 2 d2 through
+// the first, middle and last of them (exact for a constant gradient and evenly
+// spaced samples: the trapezoidal first moment of G t is quadratic in t).
+inline bool on_quadratic(const double *const m[3], size_t i, size_t len, double *d1, double *d2) {
+    const int n = (int)len - 1;
+    for (int c = 0; c < 3; ++c) {
+        const double *__restrict y = m[c] + i;
+        if (n == 1) {
+            d1[c] = y[1] - y[0];
+            d2[c] = 0.0;
+            continue;
+        }
+        const int mid = n / 2;
+        const double a1 = mid, b1 = 0.5 * mid * (mid - 1.0), a2 = n, b2 = 0.5 * n * (n - 1.0);
+        const double r1 = y[mid] - y[0], r2 = y[n] - y[0];
+        const double det = a1 * b2 - a2 * b1;
+        const double q2 = (a1 * r2 - a2 * r1) / det;
+        const double q1 = (r1 - b1 * q2) / a1;
+        double e = 0.0;
+        for (int q = 1; q <= n; ++q)
+            e = std::max(e, std::fabs(y[q] - (y[0] + q * q1 + 0.5 * q * (q - 1.0) * q2)));
+        if (!(e <= kStretchTolK1)) return false;
+        d1[c] = q1;
+        d2[c] = q2;
+    }
+    return true;
+}
+
+// make_stretches for moving spins: moments linear, first moments quadratic
+// in the sample index (halving a stretch until both hold).
+template <class Emit>
+void make_stretches_moving(const Samples &s, const double *const m[3], int max_len, Emit emit) {
+    const size_t n = s.size();
+    size_t i = 0;
+    while (i < n) {
+        double inc[4] = {0, 0, 0, 0}, dev[4] = {0, 0, 0, 0}, d1[3] = {0, 0, 0}, d2[3] = {0, 0, 0};
+        size_t len = std::min<size_t>((size_t)max_len, n - i);
+        while (len > 1 && !(on_line(s, i, len, inc, dev) && on_quadratic(m, i, len, d1, d2))) len = (len + 1) / 2;
+        if (len <= 1) {
+            len = 1;
+            for (int c = 0; c < 4; ++c) inc[c] = dev[c] = 0.0;
+            for (int c = 0; c < 3; ++c) d1[c] = d2[c] = 0.0;
+        }
+        emit(i, len, inc, dev, d1, d2);
+        i += len;
+    }
+}
+
 // Family of a deferred stretch with increments inc, whose samples lie within
 // dev of its own line: the first of the most recent families whose
 // increments F keep every sample within the stretch tolerances,
@@ -598,15 +650,16 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     // planner scratch lives per thread and only grows: large per-call
     // allocations would be fresh pages (page faults) on every call
     thread_local std::vector<int32_t> smp_k;
-    thread_local std::vector<double> smp_v[4];
+    thread_local std::vector<double> smp_v[4], smp_m[3];
+    const bool moving = P.moving;
     if (smp_k.size() < (size_t)q->n_adc + 1) {
         smp_k.resize((size_t)q->n_adc + 1);
         for (auto &v : smp_v) v.resize((size_t)q->n_adc + 1);
     }
-    // moving spins: no sample-parallel deferral and no sample recurrences
-    // (their phase is not linear in the sample index)
-    const int defer_min = P.moving ? -1 : cfg.defer_min_adc;
-    const bool moving = P.moving;
+    if (moving && smp_m[0].size() < (size_t)q->n_adc + 1)
+        for (auto &v : smp_m) v.resize((size_t)q->n_adc + 1);
+    const double *const smp_m_ptr[3] = {smp_m[0].data(), smp_m[1].data(), smp_m[2].data()};
+    const int defer_min = cfg.defer_min_adc;
     // the current run of identical excitation intervals: the point it ends
     // at, its start time and its G t means (moving spins)
     int64_t rf_run_end = -1;
@@ -645,22 +698,20 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
             ky = k[1];
             kz = k[2];
         } else {
+            // moving spins: the samples' first moments beside their moments
+            double *__restrict m0 = smp_m[0].data(), *__restrict m1 = smp_m[1].data(), *__restrict m2 = smp_m[2].data();
             int64_t p = a;
             for (;;) {
                 if (next == p) {
-                    Event e{};
-                    e.kind = EV_ADC;
-                    e.a0 = (int32_t)P.inl_k.size();
-                    e.count = 1;
-                    e.d[0] = kx;
-                    e.d[1] = ky;
-                    e.d[2] = kz;
-                    e.d[3] = T[p] - ta;
-                    e.c64[0] = k1x;
-                    e.c64[1] = k1y;
-                    e.c64[2] = k1z;
-                    P.inl_k.push_back((int32_t)cursor);
-                    P.ev.push_back(e);
+                    sk[ns] = (int32_t)cursor;
+                    s0[ns] = kx;
+                    s1[ns] = ky;
+                    s2[ns] = kz;
+                    s3[ns] = T[p] - ta;
+                    m0[ns] = k1x;
+                    m1[ns] = k1y;
+                    m2[ns] = k1z;
+                    ++ns;
                     ++cursor;
                     next = cursor < n_adc ? AI[cursor] : -1;
                 }
@@ -680,7 +731,50 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
         const double K1[3] = {k1x, k1y, k1z};
         samples.n = ns;
         const bool defer = defer_min >= 0 && b > a && (int64_t)samples.size() >= std::max(1, defer_min);
-        if (samples.size() > 0) {
+        if (samples.size() > 0 && moving) {
+            if (defer) {
+                // sample-parallel from a snapshot: moments linear and first
+                // moments quadratic in the sample index over every stretch
+                const int32_t slot = (int32_t)P.n_slots++;
+                Event e{};
+                e.kind = EV_SNAP;
+                e.a0 = slot;
+                P.snap_event.push_back((int64_t)P.ev.size());
+                P.ev.push_back(e);
+                make_stretches_moving(samples, smp_m_ptr, cfg.stretch_max,
+                                      [&](size_t i, size_t len, const double *inc, const double *dev,
+                                          const double *d1, const double *d2) {
+                    Stretch s{};
+                    s.slot = slot;
+                    s.d0 = (int32_t)P.def_k.size();
+                    s.count = (int32_t)len;
+                    s.fam = stretch_family(P.fam_dk, len, inc, dev);
+                    for (int c = 0; c < 4; ++c) {
+                        s.k0[c] = samples.v[c][i];
+                        s.dk[c] = P.fam_dk[s.fam][c];
+                    }
+                    for (int c = 0; c < 3; ++c) {
+                        s.k1[c] = smp_m_ptr[c][i];
+                        s.dk1[c] = d1[c];
+                        s.d2k1[c] = d2[c];
+                    }
+                    P.def_k.insert(P.def_k.end(), samples.k + i, samples.k + i + len);
+                    P.st.push_back(s);
+                });
+            } else {
+                // one event per sample, its moments and first moments exact
+                for (size_t i = 0; i < samples.size(); ++i) {
+                    Event e{};
+                    e.kind = EV_ADC;
+                    e.a0 = (int32_t)P.inl_k.size();
+                    e.count = 1;
+                    for (int c = 0; c < 4; ++c) e.d[c] = samples.v[c][i];
+                    for (int c = 0; c < 3; ++c) e.c64[c] = smp_m_ptr[c][i];
+                    P.inl_k.push_back(samples.k[i]);
+                    P.ev.push_back(e);
+                }
+            }
+        } else if (samples.size() > 0) {
             if (defer) {
                 const int32_t slot = (int32_t)P.n_slots++;
                 Event e{};

@@ -65,8 +65,12 @@ struct alignas(16) Stretch {
     int32_t fam;    // family: stretches of one family have bitwise-equal dk
     double k0[4];   // kx, ky, kz, tau of the first sample
     double dk[4];   // increments between consecutive samples
+    // moving spins: first moments of sample j, k1 + j dk1 + j (j - 1) / 2 d2k1
+    // (cycles s/m; quadratic in j on a constant gradient)
+    double k1[3], dk1[3], d2k1[3];
+    double pad;
 };
-static_assert(sizeof(Stretch) == 80, "Stretch layout");
+static_assert(sizeof(Stretch) == 160, "Stretch layout");
 
 // 64 consecutive spin slots of one signal group (one wavefront).
 struct alignas(16) Tile {

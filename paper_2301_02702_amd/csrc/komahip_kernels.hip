@@ -759,6 +759,122 @@ __global__ __launch_bounds__(kWG) void k_par(ParArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- k_par_mov
+//
+// The sample-parallel kernel for moving spins, x(t) = x + v t. Over a stretch
+// of evenly spaced samples on a constant gradient the moments K are linear
+// and the first moments K1 quadratic in the sample index j, so the phase
+// -(x.K(j) + v.K1(j) + f tau(j)) is quadratic in j: the per-sample factor
+// changes by a constant factor U = exp(-i 2 pi v.d2k1) from one sample to the
+// next. Each spin is re-anchored exactly (FP64 phase) at the start of every
+// batch of 16 samples, then c <- c w, w <- w U. Same block and stretch layout
+// as k_par; spin data are re-read per batch (cache-resident).
+template <class P, int S>
+__global__ __launch_bounds__(kWG) void k_par_mov(ParArgs a) {
+    using R = typename P::R;
+    using R2 = typename P::R2;
+    __shared__ double2 red[kWavesPerWG][kStretchMax];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const Block B = a.blocks[blockIdx.x];
+    const int64_t n_pad = a.n_tiles * kWave;
+    const int64_t coil = blockIdx.z;  // 0 without receive coils
+    const bool coils = a.ph.n_coils > 0;
+
+    const int64_t st0 = a.s0 + (int64_t)blockIdx.y * a.per_wg;
+    const int64_t st1 = min(st0 + a.per_wg, a.s1);
+    for (int64_t st = st0; st < st1; ++st) {
+        const auto &S_ = as_const(a.st)[st];
+        const int cnt = S_.count;
+        const int slot = S_.slot;
+        const int d0 = S_.d0;
+        for (int b0 = 0; b0 < cnt; b0 += kBatch) {
+            // moments of sample b0 and the increments at b0 (FP64)
+            const double jb = (double)b0;
+            const double kb[4] = {fma(jb, S_.dk[0], S_.k0[0]), fma(jb, S_.dk[1], S_.k0[1]),
+                                  fma(jb, S_.dk[2], S_.k0[2]), fma(jb, S_.dk[3], S_.k0[3])};
+            const double hb = 0.5 * jb * (jb - 1.0);
+            const double k1b[3] = {fma(hb, S_.d2k1[0], fma(jb, S_.dk1[0], S_.k1[0])),
+                                   fma(hb, S_.d2k1[1], fma(jb, S_.dk1[1], S_.k1[1])),
+                                   fma(hb, S_.d2k1[2], fma(jb, S_.dk1[2], S_.k1[2]))};
+            const double d1b[3] = {fma(jb, S_.d2k1[0], S_.dk1[0]), fma(jb, S_.d2k1[1], S_.dk1[1]),
+                                   fma(jb, S_.d2k1[2], S_.dk1[2])};
+            R are[kBatch], aim[kBatch];
+#pragma unroll
+            for (int i = 0; i < kBatch; ++i) {
+                are[i] = R(0);
+                aim[i] = R(0);
+            }
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                const int tl = wave + kWavesPerWG * j;
+                float x = 0.f, y = 0.f, z = 0.f, dw = 0.f, t2 = __builtin_inff(), vx = 0.f, vy = 0.f, vz = 0.f;
+                C2<R> m{R(0), R(0)};
+                if (tl < B.ntiles) {
+                    const Tile T = a.tiles[B.tile0 + tl];
+                    if (lane < T.count) {
+                        const int64_t i = T.spin0 + lane;
+                        x = a.ph.x[i];
+                        y = a.ph.y[i];
+                        z = a.ph.z[i];
+                        dw = a.ph.dw[i];
+                        t2 = a.ph.t2[i];
+                        vx = a.ph.vx[i];
+                        vy = a.ph.vy[i];
+                        vz = a.ph.vz[i];
+                        const R2 v = reinterpret_cast<const R2 *>(a.snap)[(int64_t)slot * n_pad +
+                                                                          (int64_t)(B.tile0 + tl) * kWave + lane];
+                        m = C2<R>{v.x, v.y};
+                        if (coils) m = cmul(m, C2<R>{R(a.ph.sre[coil * a.ph.n + i]), R(a.ph.sim[coil * a.ph.n + i])});
+                    }
+                }
+                const double f = (double)dw * kInv2Pi;
+                // phase at b0, its increment to b0 + 1, and the increment's change (turns)
+                const double ph0 = -fma((double)x, kb[0], fma((double)y, kb[1], fma((double)z, kb[2],
+                                   fma((double)vx, k1b[0], fma((double)vy, k1b[1], fma((double)vz, k1b[2], f * kb[3]))))));
+                const double ph1 = -fma((double)x, S_.dk[0], fma((double)y, S_.dk[1], fma((double)z, S_.dk[2],
+                                   fma((double)vx, d1b[0], fma((double)vy, d1b[1], fma((double)vz, d1b[2], f * S_.dk[3]))))));
+                const double ph2 = -fma((double)vx, S_.d2k1[0], fma((double)vy, S_.d2k1[1], (double)vz * S_.d2k1[2]));
+                const R r2 = R(1) / R(t2);  // +inf -> 0: no decay
+                R sn, cs;
+                P::sincos_turns(ph0, sn, cs);
+                renorm(cs, sn);
+                const R e0 = P::exp_neg(R(kb[3]) * r2);
+                C2<R> c = cmul(m, C2<R>{cs * e0, sn * e0});
+                P::sincos_turns(ph1, sn, cs);
+                renorm(cs, sn);
+                const R e1 = P::exp_neg(R(S_.dk[3]) * r2);
+                C2<R> w{cs * e1, sn * e1};
+                P::sincos_turns(ph2, sn, cs);
+                renorm(cs, sn);
+                const C2<R> u{cs, sn};
+#pragma unroll
+                for (int i = 0; i < kBatch; ++i) {
+                    are[i] += c.re;
+                    aim[i] += c.im;
+                    c = cmul(c, w);
+                    w = cmul(w, u);
+                }
+            }
+            transpose_sum16(are);
+            transpose_sum16(aim);
+            const int smp = b0 + (lane >> 2);
+            if ((lane & 3) == 0 && smp < cnt) red[wave][smp] = make_double2((double)are[0], (double)aim[0]);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt; i += kWG) {
+            double2 t = red[0][i];
+#pragma unroll
+            for (int wv = 1; wv < kWavesPerWG; ++wv) {
+                t.x += red[wv][i].x;
+                t.y += red[wv][i].y;
+            }
+            reinterpret_cast<double2 *>(a.pb)[(coil * a.n_blocks + (int64_t)blockIdx.x) * a.cols + (d0 - a.col0) + i] = t;
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- k_par_mm
 //
 // The mixed-precision sample-parallel kernel on the matrix cores. For one
@@ -1175,11 +1291,29 @@ static void par_dispatch(int spl, dim3 grid, const ParArgs &a, hipStream_t st) {
     }
 }
 
+template <class P>
+static void par_dispatch_mov(int spl, dim3 grid, const ParArgs &a, hipStream_t st) {
+    switch (spl) {
+        case 1: hipLaunchKernelGGL((k_par_mov<P, 1>), grid, dim3(kWG), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_par_mov<P, 2>), grid, dim3(kWG), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_par_mov<P, 4>), grid, dim3(kWG), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_par_mov<P, 8>), grid, dim3(kWG), 0, st, a); break;
+    }
+}
+
 int launch_par(bool fp64, int spl, const ParArgs &a, void *stream) {
     if (a.n_blocks <= 0 || a.s1 <= a.s0) return 0;
     if (a.ph.n_coils < 0 || a.ph.n_coils > 65535 || (a.ph.n_coils > 0 && (!a.ph.sre || !a.ph.sim))) return -1;
     dim3 grid((unsigned)a.n_blocks, (unsigned)((a.s1 - a.s0 + a.per_wg - 1) / a.per_wg),
               (unsigned)(a.ph.n_coils > 0 ? a.ph.n_coils : 1));
+    if (a.ph.vx) {  // moving spins (all three velocity arrays, checked on the host)
+        if (!a.ph.vy || !a.ph.vz) return -1;
+        if (fp64)
+            par_dispatch_mov<FP64>(spl, grid, a, (hipStream_t)stream);
+        else
+            par_dispatch_mov<Mixed>(spl, grid, a, (hipStream_t)stream);
+        return check_launch();
+    }
     if (fp64)
         par_dispatch<FP64>(spl, grid, a, (hipStream_t)stream);
     else if (a.engine == 0)

@@ -173,13 +173,18 @@ def test_footprint_counts_snapshots_and_partials(K):
     assert f_fp64 > f_mixed > n_pad * (8 + 12)  # snapshot + state at least
 
 
-def test_moving_phantom_plans_every_sample_inline(K):
+def test_moving_phantom_plans(K):
+    """Moving spins: each EPI line is one stretch (moments linear, first
+    moments quadratic in the sample index on the flat top); with deferral
+    off, one event per sample."""
     sc, ph, seq = W.config(2)
     ph = ph.subset(np.arange(0, ph.n, 64))
     info = K.koma_plan_info(sc, W.with_velocity(ph), seq, K.make_config())
+    assert info["n_deferred_adc"] == seq.n_adc and info["n_stretches"] == 128 and info["n_snapshots"] == 1
+    info = K.koma_plan_info(sc, W.with_velocity(ph), seq, K.make_config(defer_min_adc=-1))
     assert info["n_deferred_adc"] == 0 and info["n_stretches"] == 0 and info["n_snapshots"] == 0
     assert info["n_inline_adc"] == seq.n_adc
-    # one event per sample, per excitation interval and per block end
+    # one event per sample, per excitation run and per block end
     assert info["n_events"] == seq.n_adc + info["n_rf_events"] + info["n_runs"]
     f_static = K.koma_footprint(ph, seq, K.make_config())
     f_moving = K.koma_footprint(W.with_velocity(ph), seq, K.make_config())

@@ -42,9 +42,14 @@ def epi_moving():
 def test_moving_epi_matches_oracle(ctx, epi_moving, prec):
     sc, ph, seq, ref = epi_moving
     say(f"[motion] epi_small v_y = 0.1 m/s {prec}")
+    # every sample on its own (spin-sequential), then the lines as stretches
+    # with the quadratic first-moment model (sample-parallel)
+    ctx.set_config(prec, defer_min_adc=-1)
+    e1 = float(np.max(nrmse(ctx.simulate(sc, ph, seq), ref)))
     ctx.set_config(prec)
     got = ctx.simulate(sc, ph, seq)
     e = float(np.max(nrmse(got, ref)))
+    assert e1 <= TOL[prec], e1
     # the motion is visible: the static result differs from the moving one
     static = ctx.simulate(sc, W.Phantom(ph.x, ph.y, ph.z, ph.pd, ph.t1, ph.t2, ph.dw), seq)
     d = float(np.max(nrmse(static, ref)))
@@ -64,11 +69,13 @@ def test_moving_random_sequences(ctx, prec, seed):
     ph = W.random_spins(rng, 130 + 61 * seed, extent=0.05, dw_max=300.0)
     ph = W.with_velocity(ph, rng.uniform(-0.5, 0.5, 3), spread=0.3, seed=seed)
     ref = oracle.simulate(W.Scanner(), ph, seq, mode=oracle.MODE_STEP)
-    ctx.set_config(prec)
-    got = ctx.simulate(W.Scanner(), ph, seq)
-    e = float(np.max(nrmse(got, ref)))
-    say(f"[motion] random seed {seed} {prec}: {ph.n} spins, NRMSE {e:.3e}")
-    assert e <= TOL[prec]
+    for dm, spl in ((32, 0), (-1, 0), (0, 1), (2, 8)):  # inline samples and stretches of every length
+        ctx.set_config(prec, defer_min_adc=dm, spins_per_lane=spl)
+        got = ctx.simulate(W.Scanner(), ph, seq)
+        e = float(np.max(nrmse(got, ref)))
+        say(f"[motion] random seed {seed} {prec} defer {dm}: {ph.n} spins, NRMSE {e:.3e}")
+        assert e <= TOL[prec], (dm, spl, e)
+    ctx.set_config(prec, defer_min_adc=32, spins_per_lane=0)
 
 
 def test_velocity_encoding_phase_on_gpu(ctx, K):
