@@ -19,6 +19,9 @@ HIPCC_FLAGS = [
     # packed FP32 (v_pk_*) stays off: the compiler would otherwise form it
     # from plain float code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # host code (sequence packing): AVX2 and FMA, present on every x86-64
+    # host of this GPU generation
+    "-Xarch_host", "-mavx2", "-Xarch_host", "-mfma",
 ]
 
 

@@ -139,25 +139,33 @@ struct koma_ctx {
     int64_t n_launch[K_KINDS] = {};
     int64_t work[K_KINDS] = {};
     Plan plan;  // reused by koma_simulate (capacity kept across calls)
-    // pinned host staging for the packed tables (one upload per call), two
-    // buffers used in turn so that a call can pack while the upload of the
-    // previous one is still queued, and the validation flag read-back
-    void *h_stage[2] = {nullptr, nullptr};
-    size_t h_stage_cap[2] = {0, 0};
-    hipEvent_t stage_ev[2] = {nullptr, nullptr};  // recorded after each buffer's upload
-    int stage_next = 0;
+    // The packed tables of a call: a ring of pinned host staging buffers and
+    // their device copies, so that a call packs while the uploads and kernels
+    // of earlier calls are still queued. The upload goes on the call's stream
+    // (ordered after the kernels of the previous call on that stream; a
+    // cross-stream wait costs more host time than the copy saves); a slot's
+    // host buffer is reused kStageRing calls later, once its upload is done.
+    struct StageSlot {
+        void *h = nullptr;
+        size_t cap = 0;
+        DevMem d;
+        hipEvent_t copied = nullptr;  // recorded after the upload
+        bool pending = false;
+    };
+    static constexpr int kStageRing = 4;
+    StageSlot ring[kStageRing];
+    int ring_next = 0;
     int32_t *h_flag = nullptr;
     // work of koma_simulate_async still queued on async_stream, which later
     // calls on the context's scratch order themselves after
     bool async_pending = false;
     hipEvent_t async_done = nullptr;
-    DevMem s_tables;
     // device blocks released by closed requests, reused by later ones (by size)
     std::multimap<size_t, void *> pool;
     size_t pool_bytes = 0;
     // scratch reused by koma_simulate (grow-only)
     DevMem s_ev, s_st, s_tiles, s_blocks, s_toff, s_boff, s_inl, s_def, s_snap, s_pa, s_pb, s_sig,
-        s_mxy, s_mz, s_flags, s_mf, s_ph[kPhArrays];
+        s_mxy, s_mz, s_flags, s_vcount, s_mf, s_ph[kPhArrays];
     // MRF matching scratch (grow-only)
     DevMem m_src_d, m_src_x, m_dh, m_xh, m_dexp, m_xexp, m_inv, m_ps, m_pi, m_best, m_proj;
     DevMem l_v, l_y, l_zp, l_z, l_basis, l_sv, l_out;  // dictionary compression scratch
@@ -418,20 +426,26 @@ struct Samples {
 
 // True when samples i..i+len-1 all lie within the tolerances of the straight
 // line through the first and the last of them; the line's increments go to
-// inc and the largest distance of a sample from the line to dev. Branch-free
-// max loops, so the compiler vectorises them.
-inline bool on_line(const Samples &s, size_t i, size_t len, double *inc, double *dev) {
+// inc, and half[c] tells whether component c even lies within half its
+// tolerance (the margin a stretch needs to share the increments of another,
+// see stretch_family). Branch-free compare-and-or loops, so the compiler
+// vectorises them.
+inline bool on_line(const Samples &s, size_t i, size_t len, double *inc, bool *half) {
     for (int c = 0; c < 4; ++c) {
         const double *__restrict v = s.v[c] + i;
         const double v0 = v[0];
         const double d = (v[len - 1] - v0) / (double)(len - 1);
-        const double tol = c < 3 ? kStretchTolK : kStretchTolT;
-        double e = 0.0;
+        const double tol = c < 3 ? kStretchTolK : kStretchTolT, tol2 = 0.5 * tol;
+        int bad = 0, bad2 = 0;
         const int n = (int)len - 1;  // the last sample lies on the line by construction
-        for (int q = 1; q < n; ++q) e = std::max(e, std::fabs(v[q] - (v0 + (double)q * d)));
-        if (!(e <= tol)) return false;
+        for (int q = 1; q < n; ++q) {
+            const double e = std::fabs(v[q] - (v0 + (double)q * d));
+            bad |= e > tol;
+            bad2 |= e > tol2;
+        }
+        if (bad) return false;
         inc[c] = d;
-        dev[c] = e;
+        half[c] = !bad2;
     }
     return true;
 }
@@ -444,9 +458,10 @@ void make_stretches(const Samples &s, int max_len, Emit emit) {
     const size_t m = s.size();
     size_t i = 0;
     while (i < m) {
-        double inc[4] = {0, 0, 0, 0}, dev[4] = {0, 0, 0, 0};
+        double inc[4] = {0, 0, 0, 0};
+        bool half[4] = {true, true, true, true};
         size_t len = std::min<size_t>((size_t)max_len, m - i);
-        if (len > 1 && !on_line(s, i, len, inc, dev)) {
+        if (len > 1 && !on_line(s, i, len, inc, half)) {
             // greedy: extend while the next sample stays near the line of the first step
             size_t j = i + 1;
             while (j < m && (j - i + 1) <= (size_t)max_len) {
@@ -461,14 +476,14 @@ void make_stretches(const Samples &s, int max_len, Emit emit) {
                 ++j;
             }
             len = j - i;
-            while (len > 1 && !on_line(s, i, len, inc, dev)) len /= 2;
+            while (len > 1 && !on_line(s, i, len, inc, half)) len /= 2;
         }
         if (len <= 1) {
             len = 1;
             inc[0] = inc[1] = inc[2] = inc[3] = 0;
-            dev[0] = dev[1] = dev[2] = dev[3] = 0;
+            half[0] = half[1] = half[2] = half[3] = true;
         }
-        emit(i, len, inc, dev);
+        emit(i, len, inc, half);
         i += len;
     }
 }
@@ -509,33 +524,39 @@ void make_stretches_moving(const Samples &s, const double *const m[3], int max_l
     const size_t n = s.size();
     size_t i = 0;
     while (i < n) {
-        double inc[4] = {0, 0, 0, 0}, dev[4] = {0, 0, 0, 0}, d1[3] = {0, 0, 0}, d2[3] = {0, 0, 0};
+        double inc[4] = {0, 0, 0, 0}, d1[3] = {0, 0, 0}, d2[3] = {0, 0, 0};
+        bool half[4] = {true, true, true, true};
         size_t len = std::min<size_t>((size_t)max_len, n - i);
-        while (len > 1 && !(on_line(s, i, len, inc, dev) && on_quadratic(m, i, len, d1, d2))) len = (len + 1) / 2;
+        while (len > 1 && !(on_line(s, i, len, inc, half) && on_quadratic(m, i, len, d1, d2))) len = (len + 1) / 2;
         if (len <= 1) {
             len = 1;
-            for (int c = 0; c < 4; ++c) inc[c] = dev[c] = 0.0;
+            for (int c = 0; c < 4; ++c) {
+                inc[c] = 0.0;
+                half[c] = true;
+            }
             for (int c = 0; c < 3; ++c) d1[c] = d2[c] = 0.0;
         }
-        emit(i, len, inc, dev, d1, d2);
+        emit(i, len, inc, half, d1, d2);
         i += len;
     }
 }
 
-// Family of a deferred stretch with increments inc, whose samples lie within
-// dev of its own line: the first of the most recent families whose
-// increments F keep every sample within the stretch tolerances,
-// dev + (len - 1) |inc - F| <= tol (so the stretch may use F instead of inc
-// under the same error bound), else a new family with increments inc. The
+// Family of a deferred stretch with increments inc: the first of the most
+// recent families whose increments F keep every sample within the stretch
+// tolerances, else a new family with increments inc. A component c qualifies
+// if inc[c] == F[c], or if its samples lie within half the tolerance of their
+// own line (half[c]) and (len - 1) |inc[c] - F[c]| is within the other half
+// (so the stretch may use F instead of inc under the same error bound). The
 // stretch takes its family's increments bitwise, so that the sample-parallel
 // kernel can share the per-sample powers among the stretches of a family.
-int32_t stretch_family(std::vector<std::array<double, 4>> &fams, size_t len, const double *inc, const double *dev) {
+int32_t stretch_family(std::vector<std::array<double, 4>> &fams, size_t len, const double *inc, const bool *half) {
     const double n = (double)(len - 1);
     const int64_t nf = (int64_t)fams.size();
     for (int64_t f = nf - 1; f >= 0 && f >= nf - 16; --f) {
         bool ok = true;
         for (int c = 0; c < 4 && ok; ++c)
-            ok = dev[c] + n * std::fabs(inc[c] - fams[f][c]) <= (c < 3 ? kStretchTolK : kStretchTolT);
+            ok = inc[c] == fams[f][c] ||
+                 (half[c] && n * std::fabs(inc[c] - fams[f][c]) <= 0.5 * (c < 3 ? kStretchTolK : kStretchTolT));
         if (ok) return (int32_t)f;
     }
     fams.push_back({inc[0], inc[1], inc[2], inc[3]});
@@ -742,13 +763,13 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
                 P.snap_event.push_back((int64_t)P.ev.size());
                 P.ev.push_back(e);
                 make_stretches_moving(samples, smp_m_ptr, cfg.stretch_max,
-                                      [&](size_t i, size_t len, const double *inc, const double *dev,
+                                      [&](size_t i, size_t len, const double *inc, const bool *half,
                                           const double *d1, const double *d2) {
                     Stretch s{};
                     s.slot = slot;
                     s.d0 = (int32_t)P.def_k.size();
                     s.count = (int32_t)len;
-                    s.fam = stretch_family(P.fam_dk, len, inc, dev);
+                    s.fam = stretch_family(P.fam_dk, len, inc, half);
                     for (int c = 0; c < 4; ++c) {
                         s.k0[c] = samples.v[c][i];
                         s.dk[c] = P.fam_dk[s.fam][c];
@@ -783,12 +804,12 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
                 P.snap_event.push_back((int64_t)P.ev.size());
                 P.ev.push_back(e);
                 make_stretches(samples, cfg.stretch_max, [&](size_t i, size_t len, const double *inc,
-                                                             const double *dev) {
+                                                             const bool *half) {
                     Stretch s{};
                     s.slot = slot;
                     s.d0 = (int32_t)P.def_k.size();
                     s.count = (int32_t)len;
-                    s.fam = stretch_family(P.fam_dk, len, inc, dev);
+                    s.fam = stretch_family(P.fam_dk, len, inc, half);
                     for (int c = 0; c < 4; ++c) {
                         s.k0[c] = samples.v[c][i];
                         s.dk[c] = P.fam_dk[s.fam][c];
@@ -798,7 +819,7 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
                 });
             } else {
                 make_stretches(samples, cfg.stretch_max, [&](size_t i, size_t len, const double *inc,
-                                                             const double *) {
+                                                             const bool *) {
                     Event e{};
                     e.kind = EV_ADC;
                     e.a0 = (int32_t)P.inl_k.size();
@@ -1069,10 +1090,13 @@ struct Bufs {  // device views used by the launch sequence
     } while (0)
 
 static koma_status run_seq(koma_ctx *ctx, const Plan &P, bool fp64, const Bufs &B, int64_t e0, int64_t e1,
-                           bool init, bool store, hipStream_t s, int32_t *vflags = nullptr) {
+                           bool init, bool store, hipStream_t s, int32_t *vflags = nullptr,
+                           int32_t *vtotal = nullptr, uint32_t *vcount = nullptr) {
     if (e1 <= e0) return KOMA_OK;
     SeqArgs a{};
     a.vflags = vflags;
+    a.vtotal = vtotal;
+    a.vcount = vcount;
     a.ph = B.ph;
     a.tiles = B.tiles;
     a.n_tiles = P.n_tiles;
@@ -1220,17 +1244,18 @@ void koma_ctx_destroy(koma_ctx *ctx) {
     if (ctx->async_pending) (void)hipEventSynchronize(ctx->async_done);
     DevMem *all[] = {&ctx->s_ev, &ctx->s_st, &ctx->s_tiles, &ctx->s_blocks, &ctx->s_toff, &ctx->s_boff,
                      &ctx->s_inl, &ctx->s_def, &ctx->s_snap, &ctx->s_pa, &ctx->s_pb, &ctx->s_sig,
-                     &ctx->s_mxy, &ctx->s_mz, &ctx->s_flags, &ctx->s_mf};
+                     &ctx->s_mxy, &ctx->s_mz, &ctx->s_flags, &ctx->s_vcount, &ctx->s_mf};
     for (DevMem *m : all) dev_free(*m);
     for (DevMem &m : ctx->s_ph) dev_free(m);
     DevMem *mrf[] = {&ctx->m_src_d, &ctx->m_src_x, &ctx->m_dh, &ctx->m_xh, &ctx->m_dexp, &ctx->m_xexp,
                      &ctx->m_inv, &ctx->m_ps, &ctx->m_pi, &ctx->m_best, &ctx->m_proj,
                      &ctx->l_v, &ctx->l_y, &ctx->l_zp, &ctx->l_z, &ctx->l_basis, &ctx->l_sv, &ctx->l_out};
     for (DevMem *m : mrf) dev_free(*m);
-    dev_free(ctx->s_tables);
-    for (int b = 0; b < 2; ++b) {
-        if (ctx->h_stage[b]) (void)hipHostFree(ctx->h_stage[b]);
-        if (ctx->stage_ev[b]) (void)hipEventDestroy(ctx->stage_ev[b]);
+    for (auto &sl : ctx->ring) {
+        if (sl.copied) (void)hipEventSynchronize(sl.copied);
+        dev_free(sl.d);
+        if (sl.h) (void)hipHostFree(sl.h);
+        if (sl.copied) (void)hipEventDestroy(sl.copied);
     }
     if (ctx->async_done) (void)hipEventDestroy(ctx->async_done);
     if (ctx->h_flag) (void)hipHostFree(ctx->h_flag);
@@ -1376,25 +1401,27 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
         pt.off = total;
         total += (pt.bytes + 255) & ~(size_t)255;
     }
-    // staging buffer b was last uploaded two calls ago: wait for that copy
-    const int b = ctx->stage_next;
-    ctx->stage_next ^= 1;
-    if (!ctx->stage_ev[b]) HIPCHK(ctx, hipEventCreateWithFlags(&ctx->stage_ev[b], hipEventDisableTiming));
-    else HIPCHK(ctx, hipEventSynchronize(ctx->stage_ev[b]));
-    if (ctx->h_stage_cap[b] < total) {
-        if (ctx->h_stage[b]) HIPCHK(ctx, hipHostFree(ctx->h_stage[b]));
-        ctx->h_stage[b] = nullptr;
-        ctx->h_stage_cap[b] = 0;
-        HIPCHK(ctx, hipHostMalloc(&ctx->h_stage[b], total, hipHostMallocDefault));
-        ctx->h_stage_cap[b] = total;
+    koma_ctx::StageSlot &sl = ctx->ring[ctx->ring_next];
+    ctx->ring_next = (ctx->ring_next + 1) % koma_ctx::kStageRing;
+    if (!sl.copied) HIPCHK(ctx, hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming));
+    if (sl.pending) HIPCHK(ctx, hipEventSynchronize(sl.copied));  // the host staging is free again
+    if (sl.h && sl.cap < total) {
+        HIPCHK(ctx, hipHostFree(sl.h));
+        sl.h = nullptr;
+        sl.cap = 0;
+    }
+    if (!sl.h) {
+        HIPCHK(ctx, hipHostMalloc(&sl.h, total, hipHostMallocDefault));
+        sl.cap = total;
     }
     if (!ctx->h_flag) HIPCHK(ctx, hipHostMalloc((void **)&ctx->h_flag, 64, hipHostMallocDefault));
     for (auto &pt : parts)
-        if (pt.bytes) memcpy((char *)ctx->h_stage[b] + pt.off, pt.src, pt.bytes);
-    if ((st = dev_reserve(ctx, ctx->s_tables, total)) != KOMA_OK) return st;
-    HIPCHK(ctx, hipMemcpyAsync(ctx->s_tables.p, ctx->h_stage[b], total, hipMemcpyHostToDevice, s));
-    HIPCHK(ctx, hipEventRecord(ctx->stage_ev[b], s));
-    char *tb = (char *)ctx->s_tables.p;
+        if (pt.bytes) memcpy((char *)sl.h + pt.off, pt.src, pt.bytes);
+    if ((st = dev_reserve(ctx, sl.d, total)) != KOMA_OK) return st;
+    HIPCHK(ctx, hipMemcpyAsync(sl.d.p, sl.h, total, hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipEventRecord(sl.copied, s));
+    sl.pending = true;
+    char *tb = (char *)sl.d.p;
     B.ev = (const Event *)(tb + parts[0].off);
     B.st = (const Stretch *)(tb + parts[1].off);
     B.tiles = (const Tile *)(tb + parts[2].off);
@@ -1410,11 +1437,17 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
     // and the host reads the flag after the one synchronisation at the end
     const bool dev_check = where == KOMA_DEVICE;
     int32_t *flags = nullptr, *flag_total = nullptr;
+    uint32_t *flag_count = nullptr;
     const int64_t nwg_seq = (P.n_tiles + kWavesPerWG - 1) / kWavesPerWG;
     if (dev_check) {
-        if ((st = dev_reserve(ctx, ctx->s_flags, (size_t)(nwg_seq + 1) * 4)) != KOMA_OK) return st;
+        if (!ctx->s_vcount.p) {  // [0] the OR of the flags, [1] the workgroup count, zero between launches
+            if ((st = dev_reserve(ctx, ctx->s_vcount, 256)) != KOMA_OK) return st;
+            HIPCHK(ctx, hipMemset(ctx->s_vcount.p, 0, 256));
+        }
+        if ((st = dev_reserve(ctx, ctx->s_flags, (size_t)nwg_seq * 4)) != KOMA_OK) return st;
         flags = (int32_t *)ctx->s_flags.p;
-        flag_total = flags + nwg_seq;
+        flag_total = (int32_t *)ctx->s_vcount.p;
+        flag_count = (uint32_t *)ctx->s_vcount.p + 1;
     }
 
     const size_t n_pad = (size_t)P.n_tiles * kWave;
@@ -1444,8 +1477,9 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
         B.sig = (double *)ctx->s_sig.p;
     }
 
-    if ((st = run_seq(ctx, P, fp64, B, 0, (int64_t)P.ev.size(), true, store, s, flags)) != KOMA_OK) return st;
-    if (dev_check) LAUNCH(ctx, K_AUX, nwg_seq, s, launch_flags_or(flags, nwg_seq, flag_total, s));
+    if ((st = run_seq(ctx, P, fp64, B, 0, (int64_t)P.ev.size(), true, store, s, flags, flag_total, flag_count)) !=
+        KOMA_OK)
+        return st;
     if (P.n_adc > 0) {
         for (const Chunk &c : P.chunks)
             if ((st = run_chunk(ctx, P, fp64, B, c, s)) != KOMA_OK) return st;

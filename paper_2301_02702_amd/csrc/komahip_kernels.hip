@@ -518,12 +518,31 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
     const int64_t pidx = tile * kWave + lane;
     if (a.vflags) {  // uniform: validate the phantom values of this workgroup's spins
         __shared__ int32_t wg_bad;
+        __shared__ int32_t wg_last;
         if (threadIdx.x == 0) wg_bad = 0;
         __syncthreads();
         const int32_t bad = lane < T.count ? spin_flags(a.ph, T.spin0 + lane) : 0;
         if (bad) atomicOr(&wg_bad, bad);
         __syncthreads();
-        if (threadIdx.x == 0) a.vflags[blockIdx.x] = wg_bad;
+        // the last workgroup to get here ORs every workgroup's bits and
+        // resets the count for the next launch
+        if (threadIdx.x == 0) {
+            a.vflags[blockIdx.x] = wg_bad;
+            __threadfence();
+            wg_last = atomicAdd(a.vcount, 1u) == gridDim.x - 1;
+        }
+        __syncthreads();
+        if (wg_last) {  // uniform per workgroup
+            __threadfence();
+            int32_t v = 0;
+            for (unsigned i = threadIdx.x; i < gridDim.x; i += kWG) v |= *(volatile const int32_t *)(a.vflags + i);
+            if (v) atomicOr(&wg_bad, v);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                *a.vtotal = wg_bad;
+                *a.vcount = 0u;
+            }
+        }
     }
 
     R mr = R(0), mi = R(0), mz = s.pd;
@@ -1233,20 +1252,6 @@ __global__ __launch_bounds__(kWG) void k_validate(PhantomDev ph, int64_t n, int3
     if (threadIdx.x == 0) flags[blockIdx.x] = f[0];
 }
 
-// OR of n per-workgroup validation flags into out[0] (one workgroup).
-__global__ __launch_bounds__(kWG) void k_flags_or(const int32_t *flags, int64_t n, int32_t *out) {
-    __shared__ int32_t f[kWG];
-    int32_t v = 0;
-    for (int64_t i = threadIdx.x; i < n; i += kWG) v |= flags[i];
-    f[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = kWG / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) f[threadIdx.x] |= f[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[0] = f[0];
-}
-
 // ---------------------------------------------------------------- launchers
 
 static int check_launch() { return hipGetLastError() == hipSuccess ? 0 : -1; }
@@ -1339,11 +1344,6 @@ int launch_validate(const PhantomDev &ph, int64_t n, int32_t *flags, void *strea
     if (n <= 0) return 0;
     dim3 grid((unsigned)((n + kWG - 1) / kWG));
     hipLaunchKernelGGL(k_validate, grid, dim3(kWG), 0, (hipStream_t)stream, ph, n, flags);
-    return check_launch();
-}
-
-int launch_flags_or(const int32_t *flags, int64_t n, int32_t *out, void *stream) {
-    hipLaunchKernelGGL(k_flags_or, dim3(1), dim3(kWG), 0, (hipStream_t)stream, flags, n, out);
     return check_launch();
 }
 
