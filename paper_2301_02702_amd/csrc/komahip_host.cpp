@@ -1418,7 +1418,10 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
     for (auto &pt : parts)
         if (pt.bytes) memcpy((char *)sl.h + pt.off, pt.src, pt.bytes);
     if ((st = dev_reserve(ctx, sl.d, total)) != KOMA_OK) return st;
-    HIPCHK(ctx, hipMemcpyAsync(sl.d.p, sl.h, total, hipMemcpyHostToDevice, s));
+    // copied by a kernel that reads the pinned staging directly (no DMA copy)
+    void *hdev = nullptr;
+    HIPCHK(ctx, hipHostGetDevicePointer(&hdev, sl.h, 0));
+    LAUNCH(ctx, K_AUX, (int64_t)(total / 16), s, launch_upload(hdev, sl.d.p, total, s));
     HIPCHK(ctx, hipEventRecord(sl.copied, s));
     sl.pending = true;
     char *tb = (char *)sl.d.p;

@@ -156,6 +156,7 @@ namespace koma {
 int launch_seq(bool fp64, bool moving, const SeqArgs &a, void *stream);
 int launch_par(bool fp64, int spins_per_lane, const ParArgs &a, void *stream);
 int launch_reduce(bool part_fp64, const ReduceArgs &a, void *stream);
+int launch_upload(const void *src, void *dst, size_t bytes, void *stream);
 int launch_validate(const PhantomDev &ph, int64_t n, int32_t *flags, void *stream);
 int launch_export(bool fp64, const Tile *tiles, int64_t n_tiles, const void *mxy, const void *mz,
                   double *m_final, const int32_t *gate, void *stream);

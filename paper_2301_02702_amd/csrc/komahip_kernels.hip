@@ -1252,6 +1252,17 @@ __global__ __launch_bounds__(kWG) void k_validate(PhantomDev ph, int64_t n, int3
     if (threadIdx.x == 0) flags[blockIdx.x] = f[0];
 }
 
+// ---------------------------------------------------------------- k_upload
+
+// Copy n 16-byte words from pinned host memory (mapped into the device's
+// address space) to device memory, on the compute queue: the packed tables
+// of a call reach the device without a DMA-engine copy, whose ordering with
+// the kernels around it costs tens of microseconds per call.
+__global__ __launch_bounds__(kWG) void k_upload(const uint4 *src, uint4 *dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG)
+        dst[i] = src[i];
+}
+
 // ---------------------------------------------------------------- launchers
 
 static int check_launch() { return hipGetLastError() == hipSuccess ? 0 : -1; }
@@ -1337,6 +1348,17 @@ int launch_reduce(bool part_fp64, const ReduceArgs &a, void *stream) {
         hipLaunchKernelGGL(k_reduce<double2>, grid, dim3(kWG), 0, (hipStream_t)stream, a);
     else
         hipLaunchKernelGGL(k_reduce<float2>, grid, dim3(kWG), 0, (hipStream_t)stream, a);
+    return check_launch();
+}
+
+int launch_upload(const void *src, void *dst, size_t bytes, void *stream) {
+    if (bytes == 0) return 0;
+    if ((bytes & 15) || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15)) return -1;
+    const int64_t n = (int64_t)(bytes / 16);
+    int64_t g = (n + kWG - 1) / kWG;
+    if (g > 256) g = 256;
+    hipLaunchKernelGGL(k_upload, dim3((unsigned)g), dim3(kWG), 0, (hipStream_t)stream, (const uint4 *)src,
+                       (uint4 *)dst, n);
     return check_launch();
 }
 
