@@ -566,11 +566,11 @@ int32_t stretch_family(std::vector<std::array<double, 4>> &fams, size_t len, con
 }  // namespace
 
 // Moments of one precession block (points [a, b]): K = gamma_bar sum of
-// (G_n + G_{n+1}) dt_n / 2 from the block start, accumulated in order, and at
-// every ADC point of the block (cursor into the increasing ADC indices) the
-// sample's ADC index, K and elapsed time into the sample arrays. Returns the
-// number of samples written; k receives K at point b. A function of its own so
-// that the running sums stay in registers.
+// (G_n + G_{n+1}) dt_n / 2 from the block start, and at every ADC point of
+// the block (cursor into the increasing ADC indices) the sample's ADC index, K
+// and elapsed time into the sample arrays. Returns the number of samples
+// written; k receives K at point b. A function of its own so that the running
+// sums stay in registers.
 static size_t block_moments(const double *__restrict T, const double *__restrict GX, const double *__restrict GY,
                             const double *__restrict GZ, int64_t a, int64_t b, double gbar,
                             const int64_t *__restrict AI, int64_t n_adc, int64_t &cursor, int32_t *__restrict sk,
@@ -603,6 +603,25 @@ static size_t block_moments(const double *__restrict T, const double *__restrict
     k[1] = ky;
     k[2] = kz;
     return ns;
+}
+
+// First interval i >= a with B1 != 0 (n_int if none): 8 intervals at a time
+// by OR-ing the bit patterns without their sign bits (-0.0 counts as zero).
+static int64_t next_excitation(const double *__restrict br, const double *__restrict bi, int64_t a,
+                               int64_t n_int) {
+    int64_t b = a;
+    for (; b + 8 <= n_int; b += 8) {
+        uint64_t m = 0;
+        for (int j = 0; j < 8; ++j) {
+            uint64_t ur, ui;
+            memcpy(&ur, br + b + j, 8);
+            memcpy(&ui, bi + b + j, 8);
+            m |= (ur | ui) << 1;
+        }
+        if (m) break;
+    }
+    while (b < n_int && br[b] == 0.0 && bi[b] == 0.0) ++b;
+    return b;
 }
 
 static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamma, const koma_phantom *ph,
@@ -700,8 +719,7 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     Samples samples{smp_k.data(), {smp_v[0].data(), smp_v[1].data(), smp_v[2].data(), smp_v[3].data()}, 0};
     for (;;) {
         // precession block: points [a, b], intervals [a, b)
-        int64_t b = a;
-        while (b < n_int && BR[b] == 0.0 && BI[b] == 0.0) ++b;
+        const int64_t b = next_excitation(BR, BI, a, n_int);
         size_t ns = 0;
         const double ta = T[a];
         int64_t next = cursor < n_adc ? AI[cursor] : -1;
