@@ -128,6 +128,7 @@ struct ProfRec {
 
 struct koma_ctx {
     int device = 0;
+    int n_cu = 256;  // compute units of the device (the planner sizes grids by it)
     koma_config cfg{};
     hipStream_t stream = nullptr;
     std::string err;
@@ -958,16 +959,41 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     // the matrix-core kernel takes kMMStretches stretches per workgroup
     const bool mm = cfg.precision == KOMA_MIXED && cfg.sample_engine == 0;
     const int64_t st_per_wg = mm ? kMMStretches : 1;
+    auto n_blocks_for = [&](int cand) {
+        int64_t nb = 0;
+        for (int64_t g = 0; g < P.n_groups; ++g) {
+            const int64_t nt = P.tile_off[g + 1] - P.tile_off[g];
+            nb += (nt + 4 * cand - 1) / (4 * cand);
+        }
+        return nb;
+    };
     int spl = cfg.spins_per_lane;
-    if (spl == 0) {
+    if (spl == 0 && mm && !P.moving && n_st > 0) {
+        // The matrix-core kernel takes any number of tiles per wavefront:
+        // size the grid to whole rounds of resident workgroups (kMMResident
+        // per CU), so that the last round does not run a few workgroups on an
+        // otherwise idle chip: the S whose rounds are fullest, and among those
+        // within 2 % of it the largest (fewest partial rows).
+        const int64_t slots = (int64_t)kMMResident * std::max(1, ctx->n_cu);
+        const int64_t batches = (n_st + kMMStretches - 1) / kMMStretches * std::max<int64_t>(1, P.n_coils);
+        double eff[17] = {};
+        double best_eff = 0.0;
+        for (int cand = 1; cand <= 16; ++cand) {
+            const int64_t w = n_blocks_for(cand) * batches;
+            const int64_t rounds = (w + slots - 1) / slots;
+            eff[cand] = (double)w / (double)(rounds * slots);
+            best_eff = std::max(best_eff, eff[cand]);
+        }
+        spl = 1;
+        for (int cand = 16; cand >= 1; --cand)
+            if (eff[cand] >= best_eff - 0.02) {
+                spl = cand;
+                break;
+            }
+    } else if (spl == 0) {
         spl = 1;
         for (int cand : {8, 4, 2}) {  // largest S that still gives >= 8 workgroups per CU
-            int64_t nb = 0;
-            for (int64_t g = 0; g < P.n_groups; ++g) {
-                const int64_t nt = P.tile_off[g + 1] - P.tile_off[g];
-                nb += (nt + 4 * cand - 1) / (4 * cand);
-            }
-            if (nb * std::max<int64_t>((n_st + st_per_wg - 1) / st_per_wg, 1) >= (mm ? 1024 : 2048)) {
+            if (n_blocks_for(cand) * std::max<int64_t>((n_st + st_per_wg - 1) / st_per_wg, 1) >= (mm ? 1024 : 2048)) {
                 spl = cand;
                 break;
             }
@@ -1148,6 +1174,11 @@ static koma_status run_chunk(koma_ctx *ctx, const Plan &P, bool fp64, const Bufs
     a.col0 = c.c0;
     a.cols = c.c1 - c.c0;
     a.engine = ctx->cfg.sample_engine;
+    // a plan laid out for the matrix-core kernel (any tiles per wavefront) run
+    // with a vector-ALU kernel (1, 2, 4 or 8) after a configuration change
+    if ((fp64 || a.engine != 0 || P.moving) && !(P.spl == 1 || P.spl == 2 || P.spl == 4 || P.spl == 8))
+        return fail(ctx, KOMA_E_STATE, "the plan was laid out for the matrix-core sample sums; "
+                                       "set sample_engine back to 0 or open the request again");
     const int64_t max_st = 65535 * P.per_wg;  // grid.y limit
     for (int64_t s0 = c.s0; s0 < c.s1; s0 += max_st) {
         a.s0 = s0;
@@ -1246,6 +1277,11 @@ koma_status koma_ctx_create(int device, const koma_config *cfg, koma_ctx **out) 
     koma_ctx *ctx = new (std::nothrow) koma_ctx();
     if (!ctx) return fail(nullptr, KOMA_E_NOMEM, "out of host memory");
     ctx->device = device;
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+            ctx->n_cu = cus;
+    }
     ctx->cfg = c;
     if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess) {
         delete ctx;

@@ -101,6 +101,7 @@ constexpr int kWavesPerWG = kWG / kWave;
 constexpr int kBatch = 16;          // samples reduced together by the register transpose
 constexpr int kStretchMax = 128;
 constexpr int kMMStretches = 4;     // stretches whose sums one matrix-core workgroup keeps in registers
+constexpr int kMMResident = 3;      // matrix-core workgroups resident per CU (LDS 48 KB, 168 VGPRs)
 
 struct SeqArgs {  // spin-sequential kernel
     PhantomDev ph;
@@ -134,6 +135,7 @@ struct ParArgs {  // sample-parallel kernel
     double *pb;            // [n_sig][n_blocks][cols] double2 (grid.z = coil)
     int64_t col0, cols;    // deferred sample index of column 0, columns
     int engine;            // mixed precision: 0 matrix cores (k_par_mm), 1 vector ALU (k_par)
+    int spl;               // tiles per wavefront (set by the launcher)
 };
 
 struct ReduceArgs {  // cross-workgroup sums into the signal (grid.z = coil)

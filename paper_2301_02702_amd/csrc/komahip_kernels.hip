@@ -943,8 +943,10 @@ __device__ __forceinline__ C2<float> mm_anchor(const ParSpin &s, float r2, const
     return {cs * e2, sn * e2};
 }
 
-template <int S>
+// Tiles per wavefront: a.spl (a block is 4 a.spl tiles), a run-time value so
+// that the planner can size the grid to whole rounds of resident workgroups.
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k_par_mm(ParArgs a) {
+    const int S = a.spl;
     // per-wavefront stage (12 KB): B operands at a family's start, the three
     // A planes per stretch pair; after the tiles, the FP64 sums
     // [wave][stretch of the pair][sample] (16 KB)
@@ -1289,12 +1291,9 @@ int launch_seq(bool fp64, bool moving, const SeqArgs &a, void *stream) {
 }
 
 static void par_dispatch_mm(int spl, dim3 grid, const ParArgs &a, hipStream_t st) {
-    switch (spl) {
-        case 1: hipLaunchKernelGGL((k_par_mm<1>), grid, dim3(kWG), 0, st, a); break;
-        case 2: hipLaunchKernelGGL((k_par_mm<2>), grid, dim3(kWG), 0, st, a); break;
-        case 4: hipLaunchKernelGGL((k_par_mm<4>), grid, dim3(kWG), 0, st, a); break;
-        default: hipLaunchKernelGGL((k_par_mm<8>), grid, dim3(kWG), 0, st, a); break;
-    }
+    ParArgs b = a;
+    b.spl = spl;
+    hipLaunchKernelGGL(k_par_mm, grid, dim3(kWG), 0, st, b);
 }
 
 template <class P>
@@ -1322,6 +1321,10 @@ int launch_par(bool fp64, int spl, const ParArgs &a, void *stream) {
     if (a.ph.n_coils < 0 || a.ph.n_coils > 65535 || (a.ph.n_coils > 0 && (!a.ph.sre || !a.ph.sim))) return -1;
     dim3 grid((unsigned)a.n_blocks, (unsigned)((a.s1 - a.s0 + a.per_wg - 1) / a.per_wg),
               (unsigned)(a.ph.n_coils > 0 ? a.ph.n_coils : 1));
+    // the vector-ALU kernels are instantiated for 1, 2, 4 and 8 tiles per wavefront
+    const bool pow2 = spl == 1 || spl == 2 || spl == 4 || spl == 8;
+    if ((fp64 || a.engine != 0 || a.ph.vx) && !pow2) return -1;
+    if (spl < 1 || spl > 64) return -1;
     if (a.ph.vx) {  // moving spins (all three velocity arrays, checked on the host)
         if (!a.ph.vy || !a.ph.vz) return -1;
         if (fp64)

@@ -100,6 +100,20 @@ def test_runs_of_identical_excitation_intervals_are_one_event(K):
     assert info["n_rf_events"] == 3
 
 
+def test_matrix_core_grid_fills_whole_rounds(K):
+    """The mixed form's sample-parallel grid is sized to whole rounds of
+    resident workgroups (3 per CU, 256 CUs when there is no device): epi256
+    gets 11 tiles per wavefront, 24 spin blocks x 32 batches = 768
+    workgroups; the vector-ALU forms keep 1, 2, 4 or 8."""
+    sc, ph, seq = W.config(2)
+    i = K.koma_plan_info(sc, ph, seq, K.make_config())
+    assert i["spins_per_lane"] == 11 and i["n_blocks"] == 24
+    for cfg in (K.make_config("fp64"), K.make_config(sample_engine=1)):
+        assert K.koma_plan_info(sc, ph, seq, cfg)["spins_per_lane"] in (1, 2, 4, 8)
+    assert K.koma_plan_info(sc, W.with_velocity(ph.subset(np.arange(0, ph.n, 8))), seq,
+                            K.make_config())["spins_per_lane"] in (1, 2, 4, 8)
+
+
 def test_stretches_of_equal_increments_form_families(K):
     """Lines of equal readout amplitude share their per-sample increments
     (one family each); single samples join any family."""
@@ -214,8 +228,10 @@ def test_coil_plans_and_validation(K):
     pc = W.with_coils(ph, 8)
     f8 = K.koma_footprint(pc, seq, K.make_config())
     assert f8 > f1 + 8 * ph.n * 8  # sensitivities at least
-    i1 = K.koma_plan_info(sc, ph, seq, K.make_config(partial_budget=1 << 20))
-    i8 = K.koma_plan_info(sc, pc, seq, K.make_config(partial_budget=1 << 20))
+    # (the same spin blocks in both: the planner's own choice also weighs the coils)
+    i1 = K.koma_plan_info(sc, ph, seq, K.make_config(partial_budget=1 << 20, spins_per_lane=2))
+    i8 = K.koma_plan_info(sc, pc, seq, K.make_config(partial_budget=1 << 20, spins_per_lane=2))
+    assert i1["n_blocks"] == i8["n_blocks"]
     assert i8["n_chunks"] >= 4 * i1["n_chunks"]  # the partial budget is shared by the coils
     p = K._PhantomArgs(pc, False)
     info = K.koma_req_info()
