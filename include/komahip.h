@@ -112,7 +112,8 @@ typedef struct {
 
 typedef struct {
     koma_precision precision;
-    int spins_per_lane;    /* spins summed per lane in the sample-parallel kernel: 0 = auto, or 1, 2, 4, 8 */
+    int spins_per_lane;    /* spins summed per lane in the sample-parallel kernel: 0 = the planner's
+                              choice, or 1 .. 16 (the vector-ALU kernels round down to 1, 2, 4 or 8) */
     int wg_size;           /* 256 (reserved: other values are rejected) */
     int64_t chunk_events;  /* events per launch of the spin-sequential kernel for requests; >= 1 */
     size_t hbm_budget;     /* bytes a request may hold on the device; 0 = no limit */

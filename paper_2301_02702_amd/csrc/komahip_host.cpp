@@ -307,9 +307,8 @@ static koma_status check_config(koma_ctx *ctx, const koma_config *c) {
     if (!c) return fail(ctx, KOMA_E_ARG, "config is NULL");
     if (c->precision != KOMA_FP64 && c->precision != KOMA_MIXED)
         return fail(ctx, KOMA_E_ARG, "precision must be KOMA_FP64 or KOMA_MIXED");
-    if (!(c->spins_per_lane == 0 || c->spins_per_lane == 1 || c->spins_per_lane == 2 ||
-          c->spins_per_lane == 4 || c->spins_per_lane == 8))
-        return fail(ctx, KOMA_E_ARG, "spins_per_lane must be 0, 1, 2, 4 or 8");
+    if (c->spins_per_lane < 0 || c->spins_per_lane > 16)
+        return fail(ctx, KOMA_E_ARG, "spins_per_lane must be 0 (planner's choice) or 1 .. 16");
     if (c->wg_size != 256) return fail(ctx, KOMA_E_ARG, "wg_size must be 256");
     if (c->chunk_events < 1) return fail(ctx, KOMA_E_ARG, "chunk_events must be >= 1");
     if (c->partial_budget < ((size_t)1 << 20)) return fail(ctx, KOMA_E_ARG, "partial_budget must be >= 1 MiB");
@@ -968,6 +967,9 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
         return nb;
     };
     int spl = cfg.spins_per_lane;
+    // the vector-ALU kernels take 1, 2, 4 or 8 tiles per wavefront (the
+    // largest of those not above a requested value); the matrix-core one any
+    if (spl > 0 && !(mm && !P.moving)) spl = spl >= 8 ? 8 : spl >= 4 ? 4 : spl >= 2 ? 2 : 1;
     if (spl == 0 && mm && !P.moving && n_st > 0) {
         // The matrix-core kernel takes any number of tiles per wavefront:
         // size the grid to whole rounds of resident workgroups (kMMResident

@@ -169,7 +169,7 @@ def test_phantom_and_config_validation(K):
         K.koma_plan_info(W.Scanner(), ph, seq, K.make_config())
     assert e.value.status == -2
     ph.group_off = None
-    for bad in (dict(spins_per_lane=3), dict(wg_size=128), dict(stretch_max=0), dict(stretch_max=129),
+    for bad in (dict(spins_per_lane=17), dict(spins_per_lane=-1), dict(wg_size=128), dict(stretch_max=0), dict(stretch_max=129),
                 dict(chunk_events=0), dict(partial_budget=1000)):
         with pytest.raises(K.KomaError) as e:
             K.koma_plan_info(W.Scanner(), ph, seq, K.make_config(**bad))
