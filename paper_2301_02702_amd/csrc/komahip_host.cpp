@@ -1501,7 +1501,7 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
     if (dev_check) {
         if (!ctx->s_vcount.p) {  // [0] the OR of the flags, [1] the workgroup count, zero between launches
             if ((st = dev_reserve(ctx, ctx->s_vcount, 256)) != KOMA_OK) return st;
-            HIPCHK(ctx, hipMemset(ctx->s_vcount.p, 0, 256));
+            HIPCHK(ctx, hipMemsetAsync(ctx->s_vcount.p, 0, 256, s));  // ordered before the kernels
         }
         if ((st = dev_reserve(ctx, ctx->s_flags, (size_t)nwg_seq * 4)) != KOMA_OK) return st;
         flags = (int32_t *)ctx->s_flags.p;
