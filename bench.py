@@ -63,6 +63,15 @@ def time_steps(fn, steps, warmup, torch):
     return (time.perf_counter() - t0) / steps
 
 
+_STREAM = []
+
+
+def _bench_stream(torch):
+    if not _STREAM:
+        _STREAM.append(torch.cuda.Stream())
+    return _STREAM[0]
+
+
 def run_workload(K, ctx, torch, sc, ph, seq, prec, steps, warmup, profile=False, pipelined=False):
     """Time `steps` device-resident simulations; return (seconds per step, signal, kernel stats).
 
@@ -76,7 +85,10 @@ def run_workload(K, ctx, torch, sc, ph, seq, prec, steps, warmup, profile=False,
     ctx.set_config(prec)
     dph = K.device_phantom(ph)
     sig = torch.zeros((ph.n_groups, seq.n_adc, 2), dtype=torch.float64, device="cuda:0")
-    stream = torch.cuda.current_stream()
+    # a stream of its own (default priority): launches on the legacy default
+    # stream synchronise with the other blocking streams of the process
+    stream = _bench_stream(torch)
+    torch.cuda.synchronize()  # the phantom and the signal buffer are made on the default stream
     if pipelined:
         step = ctx.bind_async(sc, dph, seq, sig, stream=stream)
     else:
@@ -218,8 +230,8 @@ def load_traffic(khash):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-serving", action="store_true")

@@ -1136,13 +1136,10 @@ struct Bufs {  // device views used by the launch sequence
     } while (0)
 
 static koma_status run_seq(koma_ctx *ctx, const Plan &P, bool fp64, const Bufs &B, int64_t e0, int64_t e1,
-                           bool init, bool store, hipStream_t s, int32_t *vflags = nullptr,
-                           int32_t *vtotal = nullptr, uint32_t *vcount = nullptr) {
+                           bool init, bool store, hipStream_t s, int32_t *vbits = nullptr) {
     if (e1 <= e0) return KOMA_OK;
     SeqArgs a{};
-    a.vflags = vflags;
-    a.vtotal = vtotal;
-    a.vcount = vcount;
+    a.vbits = vbits;
     a.ph = B.ph;
     a.tiles = B.tiles;
     a.n_tiles = P.n_tiles;
@@ -1440,6 +1437,18 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
     }
     B.ph = ph_dev(dptr, P.moving, ph->n, P.n_coils);
 
+    // device-resident phantom: the spin-sequential kernel validates the
+    // values it reads (their bits ORed into one word, which the upload
+    // zeroes first); the final sums are written to the caller's buffers only
+    // if they are clean, and the host reads the word after the one
+    // synchronisation at the end
+    const bool dev_check = where == KOMA_DEVICE;
+    int32_t *flag_total = nullptr;
+    if (dev_check) {
+        if ((st = dev_reserve(ctx, ctx->s_vcount, 256)) != KOMA_OK) return st;
+        flag_total = (int32_t *)ctx->s_vcount.p;
+    }
+
     // packed tables: one pinned staging buffer, one upload
     struct Part {
         const void *src;
@@ -1459,7 +1468,11 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
     }
     koma_ctx::StageSlot &sl = ctx->ring[ctx->ring_next];
     ctx->ring_next = (ctx->ring_next + 1) % koma_ctx::kStageRing;
-    if (!sl.copied) HIPCHK(ctx, hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming));
+    // the host only learns from it that the upload kernel has read the
+    // staging: no memory fence when it is reached (a system-scope fence
+    // writes back and invalidates the caches ahead of the following kernels)
+    if (!sl.copied)
+        HIPCHK(ctx, hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming | hipEventDisableSystemFence));
     if (sl.pending) HIPCHK(ctx, hipEventSynchronize(sl.copied));  // the host staging is free again
     if (sl.h && sl.cap < total) {
         HIPCHK(ctx, hipHostFree(sl.h));
@@ -1477,7 +1490,7 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
     // copied by a kernel that reads the pinned staging directly (no DMA copy)
     void *hdev = nullptr;
     HIPCHK(ctx, hipHostGetDevicePointer(&hdev, sl.h, 0));
-    LAUNCH(ctx, K_AUX, (int64_t)(total / 16), s, launch_upload(hdev, sl.d.p, total, s));
+    LAUNCH(ctx, K_AUX, (int64_t)(total / 16), s, launch_upload(hdev, sl.d.p, total, flag_total, s));
     HIPCHK(ctx, hipEventRecord(sl.copied, s));
     sl.pending = true;
     char *tb = (char *)sl.d.p;
@@ -1489,25 +1502,6 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
     B.boff = (const int32_t *)(tb + parts[5].off);
     B.inl = (const int32_t *)(tb + parts[6].off);
     B.def = (const int32_t *)(tb + parts[7].off);
-
-    // device-resident phantom: the spin-sequential kernel validates the
-    // values it reads (per-workgroup flags, reduced on the device); the
-    // final sums are written to the caller's buffers only if they are clean,
-    // and the host reads the flag after the one synchronisation at the end
-    const bool dev_check = where == KOMA_DEVICE;
-    int32_t *flags = nullptr, *flag_total = nullptr;
-    uint32_t *flag_count = nullptr;
-    const int64_t nwg_seq = (P.n_tiles + kWavesPerWG - 1) / kWavesPerWG;
-    if (dev_check) {
-        if (!ctx->s_vcount.p) {  // [0] the OR of the flags, [1] the workgroup count, zero between launches
-            if ((st = dev_reserve(ctx, ctx->s_vcount, 256)) != KOMA_OK) return st;
-            HIPCHK(ctx, hipMemsetAsync(ctx->s_vcount.p, 0, 256, s));  // ordered before the kernels
-        }
-        if ((st = dev_reserve(ctx, ctx->s_flags, (size_t)nwg_seq * 4)) != KOMA_OK) return st;
-        flags = (int32_t *)ctx->s_flags.p;
-        flag_total = (int32_t *)ctx->s_vcount.p;
-        flag_count = (uint32_t *)ctx->s_vcount.p + 1;
-    }
 
     const size_t n_pad = (size_t)P.n_tiles * kWave;
     if ((st = dev_reserve(ctx, ctx->s_snap, (size_t)P.n_slots * n_pad * 2 * r)) != KOMA_OK) return st;
@@ -1536,7 +1530,7 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
         B.sig = (double *)ctx->s_sig.p;
     }
 
-    if ((st = run_seq(ctx, P, fp64, B, 0, (int64_t)P.ev.size(), true, store, s, flags, flag_total, flag_count)) !=
+    if ((st = run_seq(ctx, P, fp64, B, 0, (int64_t)P.ev.size(), true, store, s, flag_total)) !=
         KOMA_OK)
         return st;
     if (P.n_adc > 0) {
@@ -1550,7 +1544,11 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
     if (dev_check) {
         if (async) {
             if (status) HIPCHK(ctx, hipMemcpyAsync(status, flag_total, 4, hipMemcpyDeviceToDevice, s));
-            if (!ctx->async_done) HIPCHK(ctx, hipEventCreateWithFlags(&ctx->async_done, hipEventDisableTiming));
+            // waited for by later calls on other streams (device-side
+            // consumers: a device-scope release suffices) and by the host
+            // before it frees or reuses scratch (completion only)
+            if (!ctx->async_done)
+                HIPCHK(ctx, hipEventCreateWithFlags(&ctx->async_done, hipEventDisableTiming | hipEventReleaseToDevice));
             HIPCHK(ctx, hipEventRecord(ctx->async_done, s));
             ctx->async_pending = true;
             return KOMA_OK;

@@ -117,9 +117,8 @@ struct SeqArgs {  // spin-sequential kernel
     void *snap;       // [n_slots][n_tiles*64] complex (R2)
     void *pa;         // inline partials [n_sig][n_tiles][n_inline] complex (R2)
     int64_t n_inline;
-    int32_t *vflags;  // nullptr, or per-workgroup validation bits of the phantom values (as k_validate),
-    int32_t *vtotal;  // their OR (written by the last workgroup to finish validating),
-    uint32_t *vcount; // and the count of workgroups done (zero between launches)
+    int32_t *vbits;   // nullptr, or a word (zero at the launch) that receives the OR of the
+                      // validation bits (as k_validate) of every spin's phantom values
 };
 
 struct ParArgs {  // sample-parallel kernel
@@ -158,7 +157,7 @@ namespace koma {
 int launch_seq(bool fp64, bool moving, const SeqArgs &a, void *stream);
 int launch_par(bool fp64, int spins_per_lane, const ParArgs &a, void *stream);
 int launch_reduce(bool part_fp64, const ReduceArgs &a, void *stream);
-int launch_upload(const void *src, void *dst, size_t bytes, void *stream);
+int launch_upload(const void *src, void *dst, size_t bytes, int32_t *zero, void *stream);  // *zero = 0 first (if set)
 int launch_validate(const PhantomDev &ph, int64_t n, int32_t *flags, void *stream);
 int launch_export(bool fp64, const Tile *tiles, int64_t n_tiles, const void *mxy, const void *mz,
                   double *m_final, const int32_t *gate, void *stream);

@@ -516,33 +516,12 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
     const SpinP<R> s = load_spin<R, MOV>(a.ph, T, lane, a.inv_gamma);
     const int64_t n_pad = a.n_tiles * kWave;
     const int64_t pidx = tile * kWave + lane;
-    if (a.vflags) {  // uniform: validate the phantom values of this workgroup's spins
-        __shared__ int32_t wg_bad;
-        __shared__ int32_t wg_last;
-        if (threadIdx.x == 0) wg_bad = 0;
-        __syncthreads();
-        const int32_t bad = lane < T.count ? spin_flags(a.ph, T.spin0 + lane) : 0;
-        if (bad) atomicOr(&wg_bad, bad);
-        __syncthreads();
-        // the last workgroup to get here ORs every workgroup's bits and
-        // resets the count for the next launch
-        if (threadIdx.x == 0) {
-            a.vflags[blockIdx.x] = wg_bad;
-            __threadfence();
-            wg_last = atomicAdd(a.vcount, 1u) == gridDim.x - 1;
-        }
-        __syncthreads();
-        if (wg_last) {  // uniform per workgroup
-            __threadfence();
-            int32_t v = 0;
-            for (unsigned i = threadIdx.x; i < gridDim.x; i += kWG) v |= *(volatile const int32_t *)(a.vflags + i);
-            if (v) atomicOr(&wg_bad, v);
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                *a.vtotal = wg_bad;
-                *a.vcount = 0u;
-            }
-        }
+    // validate the phantom values of this lane's spin: its bits (as
+    // k_validate) are ORed into one word, zeroed by the upload before this
+    // launch; only lanes with an invalid spin touch it
+    if (a.vbits && lane < T.count) {
+        const int32_t bad = spin_flags(a.ph, T.spin0 + lane);
+        if (bad) atomicOr(a.vbits, bad);
     }
 
     R mr = R(0), mi = R(0), mz = s.pd;
@@ -1260,7 +1239,8 @@ __global__ __launch_bounds__(kWG) void k_validate(PhantomDev ph, int64_t n, int3
 // address space) to device memory, on the compute queue: the packed tables
 // of a call reach the device without a DMA-engine copy, whose ordering with
 // the kernels around it costs tens of microseconds per call.
-__global__ __launch_bounds__(kWG) void k_upload(const uint4 *src, uint4 *dst, int64_t n) {
+__global__ __launch_bounds__(kWG) void k_upload(const uint4 *src, uint4 *dst, int64_t n, int32_t *zero) {
+    if (zero && blockIdx.x == 0 && threadIdx.x == 0) *zero = 0;
     for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG)
         dst[i] = src[i];
 }
@@ -1354,14 +1334,15 @@ int launch_reduce(bool part_fp64, const ReduceArgs &a, void *stream) {
     return check_launch();
 }
 
-int launch_upload(const void *src, void *dst, size_t bytes, void *stream) {
-    if (bytes == 0) return 0;
+int launch_upload(const void *src, void *dst, size_t bytes, int32_t *zero, void *stream) {
+    if (bytes == 0 && !zero) return 0;
     if ((bytes & 15) || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15)) return -1;
     const int64_t n = (int64_t)(bytes / 16);
     int64_t g = (n + kWG - 1) / kWG;
     if (g > 256) g = 256;
+    if (g < 1) g = 1;
     hipLaunchKernelGGL(k_upload, dim3((unsigned)g), dim3(kWG), 0, (hipStream_t)stream, (const uint4 *)src,
-                       (uint4 *)dst, n);
+                       (uint4 *)dst, n, zero);
     return check_launch();
 }
 
