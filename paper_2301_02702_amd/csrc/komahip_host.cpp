@@ -12,6 +12,8 @@
 // update over tau.
 #include <hip/hip_runtime.h>
 
+#include <immintrin.h>
+
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -335,6 +337,12 @@ static koma_status check_sequence(koma_ctx *ctx, const koma_sequence *q) {
         return fail(ctx, KOMA_E_ARG, "sequence array is NULL");
     if (q->n_adc < 0) return fail(ctx, KOMA_E_SEQUENCE, "n_adc must be >= 0");
     if (q->n_adc > 0 && !q->adc_idx) return fail(ctx, KOMA_E_ARG, "adc_idx is NULL");
+    // branch-free pass (vectorised); the slow one below only names the index
+    const int64_t *__restrict ai = q->adc_idx;
+    int bad = 0;
+    if (q->n_adc > 0) bad = (ai[0] < 0) | (ai[q->n_adc - 1] >= q->n_t);
+    for (int64_t k = 1; k < q->n_adc; ++k) bad |= ai[k] <= ai[k - 1];
+    if (!bad) return KOMA_OK;
     for (int64_t k = 0; k < q->n_adc; ++k) {
         if (q->adc_idx[k] < 0 || q->adc_idx[k] >= q->n_t)
             return fail(ctx, KOMA_E_SEQUENCE, "adc_idx[%lld] = %lld out of [0, n_t)", (long long)k,
@@ -424,28 +432,56 @@ struct Samples {
     size_t size() const { return n; }
 };
 
+// Largest |v[q] - (v0 + q d)| over q = 1 .. n - 1 (NaN if any term is NaN).
+inline double line_dev(const double *__restrict v, int n, double v0, double d) {
+    double e = 0.0;
+    int q = 1;
+#if defined(__AVX2__) && defined(__FMA__)
+    {
+        // eight samples per step in two independent maxima; the sample index
+        // kept as exact doubles
+        const __m256d a = _mm256_set1_pd(v0), b = _mm256_set1_pd(d), step = _mm256_set1_pd(8.0);
+        const __m256d absm = _mm256_castsi256_pd(_mm256_set1_epi64x(0x7fffffffffffffffLL));
+        __m256d q0 = _mm256_setr_pd(1.0, 2.0, 3.0, 4.0), q1 = _mm256_setr_pd(5.0, 6.0, 7.0, 8.0);
+        __m256d e0 = _mm256_setzero_pd(), e1 = _mm256_setzero_pd(), nan = _mm256_setzero_pd();
+        for (; q + 8 <= n; q += 8) {
+            const __m256d x0 = _mm256_sub_pd(_mm256_loadu_pd(v + q), _mm256_fmadd_pd(q0, b, a));
+            const __m256d x1 = _mm256_sub_pd(_mm256_loadu_pd(v + q + 4), _mm256_fmadd_pd(q1, b, a));
+            e0 = _mm256_max_pd(e0, _mm256_and_pd(x0, absm));
+            e1 = _mm256_max_pd(e1, _mm256_and_pd(x1, absm));
+            nan = _mm256_or_pd(nan, _mm256_cmp_pd(x0, x1, _CMP_UNORD_Q));
+            q0 = _mm256_add_pd(q0, step);
+            q1 = _mm256_add_pd(q1, step);
+        }
+        double t[4];
+        _mm256_storeu_pd(t, _mm256_max_pd(e0, e1));
+        e = std::max(std::max(t[0], t[1]), std::max(t[2], t[3]));
+        if (_mm256_movemask_pd(nan)) return std::numeric_limits<double>::quiet_NaN();
+    }
+#endif
+    for (; q < n; ++q) {
+        const double x = std::fabs(v[q] - std::fma((double)q, d, v0));
+        if (!(x <= e)) e = x;  // a NaN term makes e NaN
+    }
+    return e;
+}
+
 // True when samples i..i+len-1 all lie within the tolerances of the straight
 // line through the first and the last of them; the line's increments go to
 // inc, and half[c] tells whether component c even lies within half its
 // tolerance (the margin a stretch needs to share the increments of another,
-// see stretch_family). Branch-free compare-and-or loops, so the compiler
-// vectorises them.
+// see stretch_family).
 inline bool on_line(const Samples &s, size_t i, size_t len, double *inc, bool *half) {
     for (int c = 0; c < 4; ++c) {
         const double *__restrict v = s.v[c] + i;
         const double v0 = v[0];
         const double d = (v[len - 1] - v0) / (double)(len - 1);
-        const double tol = c < 3 ? kStretchTolK : kStretchTolT, tol2 = 0.5 * tol;
-        int bad = 0, bad2 = 0;
-        const int n = (int)len - 1;  // the last sample lies on the line by construction
-        for (int q = 1; q < n; ++q) {
-            const double e = std::fabs(v[q] - (v0 + (double)q * d));
-            bad |= e > tol;
-            bad2 |= e > tol2;
-        }
-        if (bad) return false;
+        const double tol = c < 3 ? kStretchTolK : kStretchTolT;
+        // the last sample lies on the line by construction
+        const double e = line_dev(v, (int)len - 1, v0, d);
+        if (!(e <= tol)) return false;
         inc[c] = d;
-        half[c] = !bad2;
+        half[c] = e <= 0.5 * tol;
     }
     return true;
 }
