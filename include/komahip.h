@@ -122,11 +122,12 @@ typedef struct {
                               summed by the sample-parallel kernel; < 0 disables it */
     int stretch_max;       /* longest run of evenly spaced samples evaluated by recurrence
                               after one exact FP64 anchor; 1..128 */
-    int sample_engine;     /* KOMA_MIXED sums of deferred samples: 0 = matrix cores (FP32
-                              MFMA: the sum over spins of c w^j as a product of an
-                              [8 x spins] and a [spins x 16] matrix per 128 samples),
-                              1 = vector ALU (complex recurrence and a register
-                              transpose). KOMA_FP64 always uses the vector ALU. */
+    int sample_engine;     /* sums of deferred samples: 0 = matrix cores (the sum over
+                              spins of c w^j as a product of an [8 x spins] and a
+                              [spins x 16] matrix per 128 samples; FP32 MFMA for
+                              KOMA_MIXED, FP64 MFMA for KOMA_FP64), 1 = vector ALU
+                              (complex recurrence and a register transpose). Moving
+                              spins always use the vector ALU. */
 } koma_config;
 
 typedef struct koma_ctx koma_ctx;

@@ -991,8 +991,8 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
 
     // ---- sample-parallel layout: blocks of 4*S tiles of one group
     const int64_t n_st = (int64_t)P.st.size();
-    // the matrix-core kernel takes kMMStretches stretches per workgroup
-    const bool mm = cfg.precision == KOMA_MIXED && cfg.sample_engine == 0;
+    // the matrix-core kernels take kMMStretches stretches per workgroup
+    const bool mm = cfg.sample_engine == 0;
     const int64_t st_per_wg = mm ? kMMStretches : 1;
     auto n_blocks_for = [&](int cand) {
         int64_t nb = 0;
@@ -1007,12 +1007,13 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     // largest of those not above a requested value); the matrix-core one any
     if (spl > 0 && !(mm && !P.moving)) spl = spl >= 8 ? 8 : spl >= 4 ? 4 : spl >= 2 ? 2 : 1;
     if (spl == 0 && mm && !P.moving && n_st > 0) {
-        // The matrix-core kernel takes any number of tiles per wavefront:
+        // The matrix-core kernels take any number of tiles per wavefront:
         // size the grid to whole rounds of resident workgroups (kMMResident
-        // per CU), so that the last round does not run a few workgroups on an
+        // per CU in FP32, kMMResident64 in FP64), so that the last round does not run a few workgroups on an
         // otherwise idle chip: the S whose rounds are fullest, and among those
         // within 2 % of it the largest (fewest partial rows).
-        const int64_t slots = (int64_t)kMMResident * std::max(1, ctx->n_cu);
+        const int64_t slots =
+            (int64_t)(cfg.precision == KOMA_FP64 ? kMMResident64 : kMMResident) * std::max(1, ctx->n_cu);
         const int64_t batches = (n_st + kMMStretches - 1) / kMMStretches * std::max<int64_t>(1, P.n_coils);
         double eff[17] = {};
         double best_eff = 0.0;
@@ -1211,7 +1212,7 @@ static koma_status run_chunk(koma_ctx *ctx, const Plan &P, bool fp64, const Bufs
     a.engine = ctx->cfg.sample_engine;
     // a plan laid out for the matrix-core kernel (any tiles per wavefront) run
     // with a vector-ALU kernel (1, 2, 4 or 8) after a configuration change
-    if ((fp64 || a.engine != 0 || P.moving) && !(P.spl == 1 || P.spl == 2 || P.spl == 4 || P.spl == 8))
+    if ((a.engine != 0 || P.moving) && !(P.spl == 1 || P.spl == 2 || P.spl == 4 || P.spl == 8))
         return fail(ctx, KOMA_E_STATE, "the plan was laid out for the matrix-core sample sums; "
                                        "set sample_engine back to 0 or open the request again");
     const int64_t max_st = 65535 * P.per_wg;  // grid.y limit

@@ -102,6 +102,7 @@ constexpr int kBatch = 16;          // samples reduced together by the register 
 constexpr int kStretchMax = 128;
 constexpr int kMMStretches = 4;     // stretches whose sums one matrix-core workgroup keeps in registers
 constexpr int kMMResident = 3;      // matrix-core workgroups resident per CU (LDS 48 KB, 168 VGPRs)
+constexpr int kMMResident64 = 1;    // the same in FP64 (LDS 96 KB)
 
 struct SeqArgs {  // spin-sequential kernel
     PhantomDev ph;

@@ -1156,6 +1156,224 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
     }
 }
 
+// ---------------------------------------------------------------- k_par_mm64
+//
+// The FP64 form of k_par_mm: the same factorisation S[16 q + r] =
+// sum_s (c_s w_s^(16 q)) (w_s^r), two stretches of a family stacked in the 16
+// rows, Gauss's three real products, now on v_mfma_f64_16x16x4f64 (FP64
+// products and sums). That instruction takes its operands as the FP32 one
+// (lane l: A[l % 16][l / 16], B[l / 16][l % 16]) but returns row 4 v + l / 16
+// of column l % 16 in its element v. Every factor is formed in FP64 (exact
+// FP64 phase, FP64 sincos and exp), the powers by the same shallow product
+// trees. To keep the registers for the FP64 values, the operands stay in LDS
+// as complex numbers (B for the whole family, A per stretch pair) and each
+// product's Re + Im, Im - Re sums are formed as it is read; 32 KB of stage
+// per wavefront (one workgroup per CU), so the next tile's spin data and
+// snapshots are loaded during the current tile's products.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int kStage64 = 64;  // doubles per spin: B (16 complex) + A (16 rows, Re and Im planes)
+
+// par_factor in FP64 with the decay rate 1/T2 given.
+__device__ __forceinline__ C2<double> mm64_factor(const ParSpin &s, double r2, const double *k) {
+    double sn, cs;
+    FP64::sincos_turns(par_phase<double>(s, k), sn, cs);
+    renorm(cs, sn);
+    const double e2 = FP64::exp_neg(k[3] * r2);
+    return {cs * e2, sn * e2};
+}
+
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(1))) void k_par_mm64(ParArgs a) {
+    const int S = a.spl;
+    // per-wavefront stage: B operands of the current family (complex, 2048
+    // doubles), then the A rows of the current stretch pair in a Re and an Im
+    // plane (1024 doubles each); after the tiles, the FP64 sums
+    // [wave][stretch of the pair][sample]
+    __shared__ __attribute__((aligned(16))) double stage[kWavesPerWG][kWave * kStage64];
+    static_assert(sizeof(double2) * kWavesPerWG * 2 * kStretchMax <= sizeof(stage), "sums fit in the stage");
+    static_assert(kMMStretches == 4, "two stretch pairs per batch");
+    double2(*red)[2][kStretchMax] = reinterpret_cast<double2(*)[2][kStretchMax]>(&stage[0][0]);
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const Block B = a.blocks[blockIdx.x];
+    const int64_t n_pad = a.n_tiles * kWave;
+    const int64_t coil = blockIdx.z;  // 0 without receive coils
+    const bool coils = a.ph.n_coils > 0;
+    double *my = stage[wave];
+    // Stage layouts (doubles), 16-byte chunks XOR-permuted by the spin so
+    // that the chunk writes of consecutive lanes fall in distinct banks:
+    //   B: spin s, complex r at 32 s + 2 (r ^ (s & 15));
+    //   A plane p (Re A, Im A) at 2048 + 1024 p: spin s, rows 2c, 2c + 1 (row
+    //   8 h + q is A[q] of stretch h of the pair) at 16 s + 2 (c ^ (s & 7)).
+    const int m = lane & 15, g = lane >> 4;  // row (A) / column (B) m; spin 4u + g of group u
+
+    const int64_t st0 = a.s0 + (int64_t)blockIdx.y * a.per_wg;
+    const int64_t st1 = min(st0 + a.per_wg, a.s1);
+    for (int64_t sb = st0; sb < st1; sb += kMMStretches) {
+        const int nb = (int)min<int64_t>(kMMStretches, st1 - sb);  // uniform
+        f64x4 acc[2][3];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) acc[p][0] = acc[p][1] = acc[p][2] = f64x4{0.0, 0.0, 0.0, 0.0};
+        // the inputs of tile slot j of this wavefront (zero for empty lanes)
+        ParSpin spn;
+        C2<double> sens;
+        double2 snap[kMMStretches];
+        auto load_tile = [&](int j, ParSpin &sp, C2<double> &se, double2 *sn) {
+            sp = ParSpin{0.f, 0.f, 0.f, 0.f, __builtin_inff()};
+            se = C2<double>{1.0, 0.0};
+#pragma unroll
+            for (int i2 = 0; i2 < kMMStretches; ++i2) sn[i2] = make_double2(0.0, 0.0);
+            const int tl = __builtin_amdgcn_readfirstlane(wave) + kWavesPerWG * j;
+            if (j >= S || tl >= B.ntiles) return;  // uniform
+            const auto &T = as_const(a.tiles)[B.tile0 + tl];
+            if (lane >= T.count) return;
+            const int64_t i = T.spin0 + lane;
+            const int64_t pidx = (int64_t)(B.tile0 + tl) * kWave + lane;
+            sp = ParSpin{a.ph.x[i], a.ph.y[i], a.ph.z[i], a.ph.dw[i], a.ph.t2[i]};
+            if (coils) se = C2<double>{(double)a.ph.sre[coil * a.ph.n + i], (double)a.ph.sim[coil * a.ph.n + i]};
+#pragma unroll
+            for (int i2 = 0; i2 < kMMStretches; ++i2)
+                sn[i2] = reinterpret_cast<const double2 *>(a.snap)[(int64_t)as_const(a.st)[sb + min(i2, nb - 1)].slot * n_pad + pidx];
+        };
+        load_tile(0, spn, sens, snap);
+        for (int j = 0; j < S; ++j) {
+            const int tl = __builtin_amdgcn_readfirstlane(wave) + kWavesPerWG * j;
+            if (tl >= B.ntiles) break;  // uniform; later slots are empty too
+            // the next tile's inputs arrive during this tile's products
+            ParSpin spn_n;
+            C2<double> sens_n;
+            double2 snap_n[kMMStretches];
+            load_tile(j + 1, spn_n, sens_n, snap_n);
+            const double r2 = 1.0 / (double)spn.t2;  // +inf -> 0: no decay
+            int32_t fam = -1;  // family of the operands in the stage
+            C2<double> wq[8];  // w^(16 q)
+            auto anchor = [&](const auto &T_, int i2) -> C2<double> {
+                C2<double> mm{snap[i2].x, snap[i2].y};
+                if (coils) mm = cmul(mm, sens);
+                const double k0[4] = {T_.k0[0], T_.k0[1], T_.k0[2], T_.k0[3]};
+                return cmul(mm, mm64_factor(spn, r2, k0));
+            };
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const auto &Sa = as_const(a.st)[sb + min(2 * p, nb - 1)];
+                const auto &Sb = as_const(a.st)[sb + min(2 * p + 1, nb - 1)];
+                const int passes = Sa.fam == Sb.fam ? 1 : 2;  // uniform
+                for (int pass = 0; pass < passes; ++pass) {
+                    const auto &Sf = pass == 0 ? Sa : Sb;
+                    if (Sf.fam != fam) {  // uniform: the first stretch, or a new family
+                        fam = Sf.fam;
+                        const double dk[4] = {Sf.dk[0], Sf.dk[1], Sf.dk[2], Sf.dk[3]};
+                        const C2<double> w = mm64_factor(spn, r2, dk);
+                        C2<double> pw[16];
+                        pw[0] = C2<double>{1.0, 0.0};
+                        pw[1] = w;
+                        pw[2] = cmul(w, w);
+                        pw[3] = cmul(pw[2], w);
+                        pw[4] = cmul(pw[2], pw[2]);
+#pragma unroll
+                        for (int r = 5; r < 8; ++r) pw[r] = cmul(pw[4], pw[r - 4]);
+                        pw[8] = cmul(pw[4], pw[4]);
+#pragma unroll
+                        for (int r = 9; r < 16; ++r) pw[r] = cmul(pw[8], pw[r - 8]);
+                        wq[0] = C2<double>{1.0, 0.0};
+                        wq[1] = cmul(pw[8], pw[8]);
+                        wq[2] = cmul(wq[1], wq[1]);
+                        wq[3] = cmul(wq[2], wq[1]);
+                        wq[4] = cmul(wq[2], wq[2]);
+#pragma unroll
+                        for (int q = 5; q < 8; ++q) wq[q] = cmul(wq[4], wq[q - 4]);
+                        // the stage is private to this wavefront, and its LDS
+                        // operations complete in program order: only the
+                        // compiler must not move LDS accesses across these points
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                        for (int r = 0; r < 16; ++r)
+                            *reinterpret_cast<double2 *>(my + 32 * lane + 2 * (r ^ (lane & 15))) =
+                                make_double2(pw[r].re, pw[r].im);
+                    }
+                    const C2<double> zero{0.0, 0.0};
+                    const C2<double> ca = (passes == 1 || pass == 0) ? anchor(Sa, 2 * p) : zero;
+                    const C2<double> cb = (passes == 1 || pass == 1) ? anchor(Sb, 2 * p + 1) : zero;
+                    double *pl = my + 2048 + 16 * lane;
+                    const int sw = lane & 7;
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        // rows 2c, 2c + 1: stretch a (c < 4) or b, q = 2c % 8 and 2c % 8 + 1
+                        const C2<double> base = c < 4 ? ca : cb;
+                        const int q0 = (2 * c) & 7;
+                        const C2<double> x0 = q0 == 0 ? base : cmul(base, wq[q0]);
+                        const C2<double> x1 = cmul(base, wq[q0 + 1]);
+                        *reinterpret_cast<double2 *>(pl + 2 * (c ^ sw)) = make_double2(x0.re, x1.re);
+                        *reinterpret_cast<double2 *>(pl + 1024 + 2 * (c ^ sw)) = make_double2(x0.im, x1.im);
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    // four quarters of 4 spin groups: reads first (one wait),
+                    // then the operand sums and the products
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) {
+                        double are[4], aim[4];
+                        double2 bv[4];
+#pragma unroll
+                        for (int uu = 0; uu < 4; ++uu) {
+                            const int sp_ = 4 * (4 * h + uu) + g;
+                            const int ai = 2048 + 16 * sp_ + 2 * ((m >> 1) ^ (sp_ & 7)) + (m & 1);
+                            are[uu] = my[ai];
+                            aim[uu] = my[ai + 1024];
+                            bv[uu] = *reinterpret_cast<const double2 *>(my + 32 * sp_ + 2 * (m ^ (sp_ & 15)));
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int uu = 0; uu < 4; ++uu) {
+                            acc[p][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[uu] + aim[uu], bv[uu].x, acc[p][0], 0, 0, 0);
+                            acc[p][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[uu], bv[uu].y - bv[uu].x, acc[p][1], 0, 0, 0);
+                            acc[p][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[uu], bv[uu].x + bv[uu].y, acc[p][2], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+            spn = spn_n;
+            sens = sens_n;
+#pragma unroll
+            for (int i2 = 0; i2 < kMMStretches; ++i2) snap[i2] = snap_n[i2];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();  // every wavefront is done with its stage
+        // element v of lane l: row 4 v + l / 16 = 8 h + q of column l % 16, so
+        // stretch h = v / 2 of the pair and q = 4 (v % 2) + l / 16
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            if (2 * p >= nb) break;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int smp = 16 * (4 * (v & 1) + g) + m;
+                const double p1 = acc[p][0][v];
+                red[wave][v >> 1][smp] = make_double2(p1 - acc[p][2][v], p1 + acc[p][1][v]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (2 * p + h >= nb) break;
+                const auto &S_ = as_const(a.st)[sb + 2 * p + h];
+                const int cnt = S_.count, d0 = S_.d0;
+                for (int k = threadIdx.x; k < cnt; k += kWG) {
+                    double2 t = red[0][h][k];
+#pragma unroll
+                    for (int wv = 1; wv < kWavesPerWG; ++wv) {
+                        t.x += red[wv][h][k].x;
+                        t.y += red[wv][h][k].y;
+                    }
+                    reinterpret_cast<double2 *>(a.pb)[(coil * a.n_blocks + (int64_t)blockIdx.x) * a.cols + (d0 - a.col0) + k] = t;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // ---------------------------------------------------------------- k_reduce
 
 // sig[k][g][adc(c)] = sum over rows r of group g (in order) of part[k][r][c],
@@ -1276,6 +1494,12 @@ static void par_dispatch_mm(int spl, dim3 grid, const ParArgs &a, hipStream_t st
     hipLaunchKernelGGL(k_par_mm, grid, dim3(kWG), 0, st, b);
 }
 
+static void par_dispatch_mm64(int spl, dim3 grid, const ParArgs &a, hipStream_t st) {
+    ParArgs b = a;
+    b.spl = spl;
+    hipLaunchKernelGGL(k_par_mm64, grid, dim3(kWG), 0, st, b);
+}
+
 template <class P>
 static void par_dispatch(int spl, dim3 grid, const ParArgs &a, hipStream_t st) {
     switch (spl) {
@@ -1301,9 +1525,10 @@ int launch_par(bool fp64, int spl, const ParArgs &a, void *stream) {
     if (a.ph.n_coils < 0 || a.ph.n_coils > 65535 || (a.ph.n_coils > 0 && (!a.ph.sre || !a.ph.sim))) return -1;
     dim3 grid((unsigned)a.n_blocks, (unsigned)((a.s1 - a.s0 + a.per_wg - 1) / a.per_wg),
               (unsigned)(a.ph.n_coils > 0 ? a.ph.n_coils : 1));
-    // the vector-ALU kernels are instantiated for 1, 2, 4 and 8 tiles per wavefront
+    // the vector-ALU kernels are instantiated for 1, 2, 4 and 8 tiles per
+    // wavefront; the matrix-core ones take any number
     const bool pow2 = spl == 1 || spl == 2 || spl == 4 || spl == 8;
-    if ((fp64 || a.engine != 0 || a.ph.vx) && !pow2) return -1;
+    if ((a.engine != 0 || a.ph.vx) && !pow2) return -1;
     if (spl < 1 || spl > 64) return -1;
     if (a.ph.vx) {  // moving spins (all three velocity arrays, checked on the host)
         if (!a.ph.vy || !a.ph.vz) return -1;
@@ -1313,12 +1538,16 @@ int launch_par(bool fp64, int spl, const ParArgs &a, void *stream) {
             par_dispatch_mov<Mixed>(spl, grid, a, (hipStream_t)stream);
         return check_launch();
     }
-    if (fp64)
+    if (a.engine == 0) {
+        if (fp64)
+            par_dispatch_mm64(spl, grid, a, (hipStream_t)stream);
+        else
+            par_dispatch_mm(spl, grid, a, (hipStream_t)stream);
+    } else if (fp64) {
         par_dispatch<FP64>(spl, grid, a, (hipStream_t)stream);
-    else if (a.engine == 0)
-        par_dispatch_mm(spl, grid, a, (hipStream_t)stream);
-    else
+    } else {
         par_dispatch<Mixed>(spl, grid, a, (hipStream_t)stream);
+    }
     return check_launch();
 }
 

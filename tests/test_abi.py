@@ -101,14 +101,18 @@ def test_runs_of_identical_excitation_intervals_are_one_event(K):
 
 
 def test_matrix_core_grid_fills_whole_rounds(K):
-    """The mixed form's sample-parallel grid is sized to whole rounds of
-    resident workgroups (3 per CU, 256 CUs when there is no device): epi256
-    gets 11 tiles per wavefront, 24 spin blocks x 32 batches = 768
-    workgroups; the vector-ALU forms keep 1, 2, 4 or 8."""
+    """The matrix-core sample-parallel grids are sized to whole rounds of
+    resident workgroups (256 CUs when there is no device): in the mixed form
+    (3 per CU) epi256 gets 11 tiles per wavefront, 24 spin blocks x 32
+    batches = 768 workgroups; in FP64 (1 per CU, 96 KB of LDS) every S fills
+    whole rounds and the largest, 16, gives 16 blocks x 32 = 512 (two
+    rounds); the vector-ALU forms keep 1, 2, 4 or 8."""
     sc, ph, seq = W.config(2)
     i = K.koma_plan_info(sc, ph, seq, K.make_config())
     assert i["spins_per_lane"] == 11 and i["n_blocks"] == 24
-    for cfg in (K.make_config("fp64"), K.make_config(sample_engine=1)):
+    i = K.koma_plan_info(sc, ph, seq, K.make_config("fp64"))
+    assert i["spins_per_lane"] == 16 and i["n_blocks"] == 16
+    for cfg in (K.make_config("fp64", sample_engine=1), K.make_config(sample_engine=1)):
         assert K.koma_plan_info(sc, ph, seq, cfg)["spins_per_lane"] in (1, 2, 4, 8)
     assert K.koma_plan_info(sc, W.with_velocity(ph.subset(np.arange(0, ph.n, 8))), seq,
                             K.make_config())["spins_per_lane"] in (1, 2, 4, 8)
@@ -181,8 +185,9 @@ def test_phantom_and_config_validation(K):
 
 def test_footprint_counts_snapshots_and_partials(K):
     sc, ph, seq = W.config(2)
-    f_mixed = K.koma_footprint(ph, seq, K.make_config("mixed"))
-    f_fp64 = K.koma_footprint(ph, seq, K.make_config("fp64"))
+    # the same launch shape in both forms (the planner's choices differ)
+    f_mixed = K.koma_footprint(ph, seq, K.make_config("mixed", spins_per_lane=8))
+    f_fp64 = K.koma_footprint(ph, seq, K.make_config("fp64", spins_per_lane=8))
     n_pad = 1024 * 64
     assert f_fp64 > f_mixed > n_pad * (8 + 12)  # snapshot + state at least
 

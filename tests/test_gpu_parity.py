@@ -340,20 +340,21 @@ def test_minimal_grid_on_gpu_matches_raster_oracle(ctx, K, prec, which):
     assert e <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("key", ["epi_small", "gre", "seepi_subset"])
-def test_sample_engines_agree(ctx, key):
-    """Mixed precision with the deferred sample sums on the matrix cores
-    (FP32 MFMA) and on the vector ALU: both within the parity bar of the
-    oracle and of each other."""
+def test_sample_engines_agree(ctx, key, prec):
+    """The deferred sample sums on the matrix cores (FP32 MFMA in the mixed
+    form, FP64 MFMA in the FP64 form) and on the vector ALU: both within the
+    parity bar of the oracle and of each other."""
     ref = oracle_cached(key)
     out = {}
     for eng in (0, 1):
-        ctx.set_config("mixed", sample_engine=eng)
+        ctx.set_config(prec, sample_engine=eng)
         sc, ph, seq = case(key)
         out[eng] = ctx.simulate(sc, ph, seq)
-    ctx.set_config("mixed", sample_engine=0)
+    ctx.set_config(prec, sample_engine=0)
     e0 = float(np.max(nrmse(out[0], ref)))
     e1 = float(np.max(nrmse(out[1], ref)))
     e01 = float(np.max(nrmse(out[0], out[1])))
-    say(f"[engine] {key}: matrix cores {e0:.3e}, vector ALU {e1:.3e} vs oracle; between {e01:.3e}")
-    assert e0 <= TOL["mixed"] and e1 <= TOL["mixed"] and e01 <= TOL["mixed"]
+    say(f"[engine] {key} {prec}: matrix cores {e0:.3e}, vector ALU {e1:.3e} vs oracle; between {e01:.3e}")
+    assert e0 <= TOL[prec] and e1 <= TOL[prec] and e01 <= TOL[prec]
