@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "G spin-steps/s (mixed vs FP64 GPU) + serving p50/p99 latency at NRMSE<=1e-4"
 PEAK_FP32 = 157.3  # TFLOP/s, MI355X FP32 (vector and dense matrix; published)
+PEAK_FP64 = 78.6   # TFLOP/s, MI355X FP64 (vector and dense matrix; published)
 PEAK_HBM = 8000.0  # GB/s
 PEAK_FP16 = 2500.0  # TFLOP/s, MI355X dense FP16 matrix (published)
 # Algorithmic work of one (spin, sample) term of a precession block summed by
@@ -286,6 +287,14 @@ def main():
                 "unit_def": "one (spin, ADC sample) term of a precession block",
                 "kernel_hash": khash}
 
+    # the FP64 form's sample sums (k_par_mm64) against the FP64 matrix peak
+    par64 = st_64["par"]
+    par64_ms = par64["total_ms"] / max(par64["launches"], 1)
+    ach64 = FLOP_PER_TERM * n_terms / (par64_ms * 1e-3) / 1e12 / (par64["launches"] / args.steps)
+    roofline_fp64 = {"bound": "mfma", "kernel": "k_par_mm64 (sample-parallel block sums on FP64 MFMA)",
+                     "achieved": round(ach64, 3), "peak": PEAK_FP64, "unit": "TFLOP/s",
+                     "frac": round(ach64 / PEAK_FP64, 4), "avg_launch_ms": round(par64_ms, 5)}
+
     out = {
         "metric": METRIC, "value": round(spin_steps / t_mix / 1e9, 3), "unit": "G spin-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -300,7 +309,8 @@ def main():
                             "step while the device runs the current one"},
         "one_call_at_a_time": {"value": round(spin_steps / t_mix1 / 1e9, 3), "ms_per_step": round(t_mix1 * 1e3, 4),
                                "fp64_ms_per_step": round(t_641 * 1e3, 4)},
-        "fp64": {"value": round(spin_steps / t_64 / 1e9, 3), "ms_per_step": round(t_64 * 1e3, 4)},
+        "fp64": {"value": round(spin_steps / t_64 / 1e9, 3), "ms_per_step": round(t_64 * 1e3, 4),
+                 "roofline": roofline_fp64},
         "mixed_over_fp64": round(t_64 / t_mix, 3),
         "mixed_valu": {"value": round(spin_steps / t_vm / 1e9, 3), "ms_per_step": round(t_vm * 1e3, 4),
                        "par_ms": round(st_vm["par"]["total_ms"] / max(st_vm["par"]["launches"], 1), 5),
