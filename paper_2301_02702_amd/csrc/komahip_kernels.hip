@@ -68,68 +68,15 @@ struct Mixed {
     }
 };
 
-// FP64 sine/cosine and exponential of this file's own: the library routines
-// cover every argument range with branches and special cases (about 90 and
-// 55 instructions), while the phases here are reduced to turns first and the
-// exponents are never positive. Both are Taylor polynomials on a reduced
-// argument; on the CPU against 80-bit references their largest errors are
-// 1.5e-16 absolute (sin, cos) and 1.4e-16 relative (exp).
-//   sin, cos of 2 pi h: y = 4 (h - rint(h)) and f = y - rint(y) are exact,
-//   |f| <= 1/2; sin(pi f / 2) to degree 17 and cos(pi f / 2) to degree 18
-//   (truncation below 1e-19), then the quadrant rint(y) mod 4 swaps and
-//   negates them.
-//   exp(-x), x >= 0: n = rint(-x log2 e), r = -x - n ln 2 with ln 2 split
-//   in two (n ln2_hi exact), |r| <= ln 2 / 2; exp(r) to degree 13
-//   (truncation 4e-18), scaled by 2^n.
-constexpr double kSinPi2[9] = {  // (-1)^k (pi/2)^(2k+1) / (2k+1)!
-    1.5707963267948966, -0.6459640975062463, 0.07969262624616705, -0.004681754135318688,
-    0.00016044118478735983, -3.598843235212085e-06, 5.692172921967927e-08, -6.688035109811468e-10,
-    6.0669357311061955e-12};
-constexpr double kCosPi2[10] = {  // (-1)^k (pi/2)^(2k) / (2k)!
-    1.0, -1.2337005501361697, 0.25366950790104803, -0.02086348076335296, 0.0009192602748394266,
-    -2.5202042373060607e-05, 4.710874778818172e-07, -6.386603083791852e-09, 6.565963114979473e-11,
-    -5.294400200734623e-13};
-constexpr double kExpTaylor[14] = {  // 1 / k!
-    1.0, 1.0, 0.5, 0.16666666666666666, 0.041666666666666664, 0.008333333333333333, 0.001388888888888889,
-    0.0001984126984126984, 2.48015873015873e-05, 2.7557319223985893e-06, 2.755731922398589e-07,
-    2.505210838544172e-08, 2.08767569878681e-09, 1.6059043836821613e-10};
-constexpr double kLn2Hi = 0.6931467056274414;       // ln 2 to 21 bits
-constexpr double kLn2Lo = 4.7493250390316726e-07;   // ln 2 - kLn2Hi
-constexpr double kLog2eD = 1.4426950408889634;
-
 struct FP64 {
     using R = double;
     using R2 = double2;
     static __device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
     static __device__ __forceinline__ void sincos_turns(double h, double &s, double &c) {
-        const double y = 4.0 * (h - rint(h));
-        const double q = rint(y);
-        const double f = y - q, f2 = f * f;
-        double ps = kSinPi2[8];
-#pragma unroll
-        for (int k = 7; k >= 0; --k) ps = fma(ps, f2, kSinPi2[k]);
-        const double a = f * ps;
-        double b = kCosPi2[9];
-#pragma unroll
-        for (int k = 8; k >= 0; --k) b = fma(b, f2, kCosPi2[k]);
-        // quadrant: sin(pi/2 (q + f)) = a, b, -a, -b and cos = b, -a, -b, a
-        const int iq = (int)q & 3;
-        s = (iq & 1) ? b : a;
-        c = (iq & 1) ? a : b;
-        if (iq & 2) s = -s;
-        if ((iq + 1) & 2) c = -c;
+        double r = h - rint(h);
+        sincospi(2.0 * r, &s, &c);
     }
-    static __device__ __forceinline__ double exp_neg(double x) {  // exp(-x), x >= 0 (NaN stays NaN)
-        if (x > 746.0) return 0.0;
-        const double y = -x;
-        const double n = rint(y * kLog2eD);
-        double r = fma(-n, kLn2Hi, y);
-        r = fma(-n, kLn2Lo, r);
-        double p = kExpTaylor[13];
-#pragma unroll
-        for (int k = 12; k >= 0; --k) p = fma(p, r, kExpTaylor[k]);
-        return ldexp(p, (int)n);
-    }
+    static __device__ __forceinline__ double exp_neg(double x) { return exp(-x); }
 };
 
 template <class R>
