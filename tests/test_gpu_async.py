@@ -104,3 +104,34 @@ def test_invalid_device_phantom_sets_status_and_leaves_outputs(K):
             ctx.simulate_async(sc, K.device_phantom(ph), bad, _sig(torch, ph, seq))
     finally:
         ctx.close()
+
+
+def test_validation_word_is_cleared_for_every_call(K):
+    """The phantom-check word is zeroed by each call's upload: a valid call
+    right after an invalid one (queued behind it, and synchronous) reports 0
+    and writes its outputs, bit for bit the reference."""
+    import torch
+    ctx = K.Context(0, "mixed")
+    try:
+        sc, ph, seq = case("epi_small")
+        good = K.device_phantom(ph)
+        ref = _z(ctx.simulate(sc, good, seq, where="device", sig=_sig(torch, ph, seq)))
+        bad = K.device_phantom(ph)
+        bad["t1"][3] = -1.0
+        outs = []
+        for dph in (bad, good, bad, good):
+            sig = _sig(torch, ph, seq)
+            st = torch.full((1,), -1, dtype=torch.int32, device="cuda:0")
+            ctx.simulate_async(sc, dph, seq, sig, status=st)
+            outs.append((sig, st))
+        torch.cuda.synchronize()
+        for k, (sig, st) in enumerate(outs):
+            if k % 2 == 0:
+                assert int(st.cpu()[0]) == 4 and bool(torch.all(sig == -7.0)), k
+            else:
+                assert int(st.cpu()[0]) == 0 and np.array_equal(_z(sig), ref), k
+        with pytest.raises(K.KomaError):
+            ctx.simulate(sc, bad, seq, where="device", sig=_sig(torch, ph, seq))
+        assert np.array_equal(_z(ctx.simulate(sc, good, seq, where="device", sig=_sig(torch, ph, seq))), ref)
+    finally:
+        ctx.close()
