@@ -210,6 +210,44 @@ def test_stretch_families_share_operands(ctx, prec):
     ctx.set_config(prec, spins_per_lane=0, sample_engine=0, stretch_max=128)
 
 
+def test_random_readouts_every_engine_and_shape(ctx):
+    """Seeded random cases: 1-8 readout lines of four amplitudes (so pairs of
+    stretches of two families and short last batches occur), 8-199 samples
+    per line, 1-699 spins in up to three groups, receive coils in some; each
+    form on both sample engines with a random number of tiles per lane
+    (1 .. 16, rounded down to 1, 2, 4 or 8 on the vector ALU) and stretch
+    length, against the oracle."""
+    import oracle
+    rng = np.random.default_rng(777)
+    sc = W.Scanner()
+    worst = {"fp64": 0.0, "mixed": 0.0}
+    for trial in range(8):
+        amps = list(rng.choice([0.01, -0.01, 0.02, -0.015], size=int(rng.integers(1, 9))))
+        seq = W.readout_lines_sequence(amps, n_samples=int(rng.integers(8, 200)))
+        n = int(rng.integers(1, 700))
+        ph = W.random_spins(rng, n)
+        if rng.random() < 0.5:
+            cuts = np.sort(rng.integers(0, n + 1, 2))
+            ph.group_off = np.concatenate([[0], cuts, [n]])
+        if rng.random() < 0.3:
+            ph = W.with_coils(ph, int(rng.integers(1, 4)))
+        ref = oracle.simulate(sc, ph, seq)
+        r2 = ref.reshape(-1, ref.shape[-1])
+        mask = np.abs(r2).max(axis=1) > 0
+        for prec in ("fp64", "mixed"):
+            for eng in (0, 1):
+                spl = int(rng.choice([0, 1, 2, 3, 5, 8, 16]))
+                smax = int(rng.choice([128, 37, 16, 5]))
+                ctx.set_config(prec, sample_engine=eng, spins_per_lane=spl, stretch_max=smax)
+                got = ctx.simulate(sc, ph, seq).reshape(-1, ref.shape[-1])
+                e = float(np.max(nrmse(got[mask], r2[mask]))) if mask.any() else 0.0
+                assert np.all(got[~mask] == 0)
+                assert e <= TOL[prec], (trial, n, prec, eng, spl, smax, e)
+                worst[prec] = max(worst[prec], e)
+    ctx.set_config("mixed", sample_engine=0, spins_per_lane=0, stretch_max=128)
+    say(f"[parity] random readouts: worst NRMSE fp64 {worst['fp64']:.2e}, mixed {worst['mixed']:.2e}")
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_launch_shape_invariance_and_determinism(ctx, prec):
     """Spins per lane and stretch length change only rounding; repeated runs
