@@ -241,7 +241,7 @@ def main():
                     help="also run a plain 1 GiB device copy (counter calibration runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the simulator runs on one GPU (spins would shard across GPUs with one final signal sum, not implemented); --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
