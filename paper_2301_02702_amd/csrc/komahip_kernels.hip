@@ -1223,6 +1223,24 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(1))) void k
     const int64_t st1 = min(st0 + a.per_wg, a.s1);
     for (int64_t sb = st0; sb < st1; sb += kMMStretches) {
         const int nb = (int)min<int64_t>(kMMStretches, st1 - sb);  // uniform
+        // the batch's stretch parameters, read once into registers (with one
+        // wavefront per SIMD a scalar reload per tile would wait in full)
+        struct SP {
+            double k0[4], dk[4];
+            int fam, slot;
+        } sprm[kMMStretches];
+#pragma unroll
+        for (int i2 = 0; i2 < kMMStretches; ++i2) {
+            const auto &S_ = as_const(a.st)[sb + min(i2, nb - 1)];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                sprm[i2].k0[c] = S_.k0[c];
+                sprm[i2].dk[c] = S_.dk[c];
+                asm volatile("" : "+v"(sprm[i2].k0[c]), "+v"(sprm[i2].dk[c]));
+            }
+            sprm[i2].fam = S_.fam;
+            sprm[i2].slot = S_.slot;
+        }
         f64x4 acc[2][3];
 #pragma unroll
         for (int p = 0; p < 2; ++p) acc[p][0] = acc[p][1] = acc[p][2] = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -1245,7 +1263,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(1))) void k
             if (coils) se = C2<double>{(double)a.ph.sre[coil * a.ph.n + i], (double)a.ph.sim[coil * a.ph.n + i]};
 #pragma unroll
             for (int i2 = 0; i2 < kMMStretches; ++i2)
-                sn[i2] = reinterpret_cast<const double2 *>(a.snap)[(int64_t)as_const(a.st)[sb + min(i2, nb - 1)].slot * n_pad + pidx];
+                sn[i2] = reinterpret_cast<const double2 *>(a.snap)[(int64_t)sprm[i2].slot * n_pad + pidx];
         };
         load_tile(0, spn, sens, snap);
         for (int j = 0; j < S; ++j) {
@@ -1259,23 +1277,21 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(1))) void k
             const double r2 = 1.0 / (double)spn.t2;  // +inf -> 0: no decay
             int32_t fam = -1;  // family of the operands in the stage
             C2<double> wq[8];  // w^(16 q)
-            auto anchor = [&](const auto &T_, int i2) -> C2<double> {
+            auto anchor = [&](const SP &T_, int i2) -> C2<double> {
                 C2<double> mm{snap[i2].x, snap[i2].y};
                 if (coils) mm = cmul(mm, sens);
-                const double k0[4] = {T_.k0[0], T_.k0[1], T_.k0[2], T_.k0[3]};
-                return cmul(mm, mm64_factor(spn, r2, k0));
+                return cmul(mm, mm64_factor(spn, r2, T_.k0));
             };
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
-                const auto &Sa = as_const(a.st)[sb + min(2 * p, nb - 1)];
-                const auto &Sb = as_const(a.st)[sb + min(2 * p + 1, nb - 1)];
+                const SP &Sa = sprm[2 * p];
+                const SP &Sb = sprm[2 * p + 1];
                 const int passes = Sa.fam == Sb.fam ? 1 : 2;  // uniform
                 for (int pass = 0; pass < passes; ++pass) {
-                    const auto &Sf = pass == 0 ? Sa : Sb;
+                    const SP &Sf = pass == 0 ? Sa : Sb;
                     if (Sf.fam != fam) {  // uniform: the first stretch, or a new family
                         fam = Sf.fam;
-                        const double dk[4] = {Sf.dk[0], Sf.dk[1], Sf.dk[2], Sf.dk[3]};
-                        const C2<double> w = mm64_factor(spn, r2, dk);
+                        const C2<double> w = mm64_factor(spn, r2, Sf.dk);
                         C2<double> pw[16];
                         pw[0] = C2<double>{1.0, 0.0};
                         pw[1] = w;
