@@ -1186,12 +1186,65 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kStage64 = 64;  // doubles per spin: B (16 complex) + A (16 rows, Re and Im planes)
 
+// sin and cos of 2 pi h (h in turns) and exp(-x) for x >= 0 in FP64, shorter
+// than the library routines (which cover every argument with branches):
+// Taylor polynomials on exactly reduced arguments. sin, cos: y = 4 (h -
+// rint(h)) and f = y - rint(y) are exact, |f| <= 1/2; sin(pi f / 2) to degree
+// 17 and cos(pi f / 2) to degree 18 (truncation below 1e-19), then the
+// quadrant rint(y) mod 4. exp: n = rint(-x log2 e), r = -x - n ln 2 with ln 2
+// in two parts, |r| <= ln 2 / 2, exp(r) to degree 13 (truncation 4e-18),
+// times 2^n. Against 80-bit references on the CPU: 1.5e-16 absolute (sin,
+// cos), 1.4e-16 relative (exp).
+constexpr double kSinPi2[9] = {  // (-1)^k (pi/2)^(2k+1) / (2k+1)!
+    1.5707963267948966, -0.6459640975062463, 0.07969262624616705, -0.004681754135318688,
+    0.00016044118478735983, -3.598843235212085e-06, 5.692172921967927e-08, -6.688035109811468e-10,
+    6.0669357311061955e-12};
+constexpr double kCosPi2[10] = {  // (-1)^k (pi/2)^(2k) / (2k)!
+    1.0, -1.2337005501361697, 0.25366950790104803, -0.02086348076335296, 0.0009192602748394266,
+    -2.5202042373060607e-05, 4.710874778818172e-07, -6.386603083791852e-09, 6.565963114979473e-11,
+    -5.294400200734623e-13};
+constexpr double kExpTaylor[14] = {  // 1 / k!
+    1.0, 1.0, 0.5, 0.16666666666666666, 0.041666666666666664, 0.008333333333333333, 0.001388888888888889,
+    0.0001984126984126984, 2.48015873015873e-05, 2.7557319223985893e-06, 2.755731922398589e-07,
+    2.505210838544172e-08, 2.08767569878681e-09, 1.6059043836821613e-10};
+
+__device__ __forceinline__ void mm64_sincos_turns(double h, double &s, double &c) {
+    const double y = 4.0 * (h - rint(h));
+    const double q = rint(y);
+    const double f = y - q, f2 = f * f;
+    double ps = kSinPi2[8];
+#pragma unroll
+    for (int k = 7; k >= 0; --k) ps = fma(ps, f2, kSinPi2[k]);
+    const double sa = f * ps;
+    double cb = kCosPi2[9];
+#pragma unroll
+    for (int k = 8; k >= 0; --k) cb = fma(cb, f2, kCosPi2[k]);
+    // sin(pi/2 (q + f)) = sa, cb, -sa, -cb and cos = cb, -sa, -cb, sa for q mod 4 = 0 .. 3
+    const int iq = (int)q & 3;
+    s = (iq & 1) ? cb : sa;
+    c = (iq & 1) ? sa : cb;
+    if (iq & 2) s = -s;
+    if ((iq + 1) & 2) c = -c;
+}
+
+__device__ __forceinline__ double mm64_exp_neg(double x) {  // exp(-x), x >= 0 (NaN stays NaN)
+    if (x > 746.0) return 0.0;
+    const double y = -x;
+    const double n = rint(y * 1.4426950408889634);
+    double r = fma(-n, 0.6931467056274414, y);   // ln 2 to 21 bits: n ln2_hi exact
+    r = fma(-n, 4.7493250390316726e-07, r);      // ln 2 - ln2_hi
+    double p = kExpTaylor[13];
+#pragma unroll
+    for (int k = 12; k >= 0; --k) p = fma(p, r, kExpTaylor[k]);
+    return ldexp(p, (int)n);
+}
+
 // par_factor in FP64 with the decay rate 1/T2 given.
 __device__ __forceinline__ C2<double> mm64_factor(const ParSpin &s, double r2, const double *k) {
     double sn, cs;
-    FP64::sincos_turns(par_phase<double>(s, k), sn, cs);
+    mm64_sincos_turns(par_phase<double>(s, k), sn, cs);
     renorm(cs, sn);
-    const double e2 = FP64::exp_neg(k[3] * r2);
+    const double e2 = mm64_exp_neg(k[3] * r2);
     return {cs * e2, sn * e2};
 }
 
