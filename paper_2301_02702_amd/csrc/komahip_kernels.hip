@@ -1181,8 +1181,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
 // trees. To keep the registers for the FP64 values, the operands stay in LDS
 // as complex numbers (B for the whole family, A per stretch pair) and each
 // product's Re + Im, Im - Re sums are formed as it is read; 32 KB of stage
-// per wavefront (one workgroup per CU), so the next tile's spin data and
-// snapshots are loaded during the current tile's products.
+// per wavefront (one workgroup per CU, one wavefront per SIMD).
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kStage64 = 64;  // doubles per spin: B (16 complex) + A (16 rows, Re and Im planes)
 
@@ -1297,36 +1296,28 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(1))) void k
         f64x4 acc[2][3];
 #pragma unroll
         for (int p = 0; p < 2; ++p) acc[p][0] = acc[p][1] = acc[p][2] = f64x4{0.0, 0.0, 0.0, 0.0};
-        // the inputs of tile slot j of this wavefront (zero for empty lanes)
-        ParSpin spn;
-        C2<double> sens;
-        double2 snap[kMMStretches];
-        auto load_tile = [&](int j, ParSpin &sp, C2<double> &se, double2 *sn) {
-            sp = ParSpin{0.f, 0.f, 0.f, 0.f, __builtin_inff()};
-            se = C2<double>{1.0, 0.0};
-#pragma unroll
-            for (int i2 = 0; i2 < kMMStretches; ++i2) sn[i2] = make_double2(0.0, 0.0);
-            const int tl = __builtin_amdgcn_readfirstlane(wave) + kWavesPerWG * j;
-            if (j >= S || tl >= B.ntiles) return;  // uniform
-            const auto &T = as_const(a.tiles)[B.tile0 + tl];
-            if (lane >= T.count) return;
-            const int64_t i = T.spin0 + lane;
-            const int64_t pidx = (int64_t)(B.tile0 + tl) * kWave + lane;
-            sp = ParSpin{a.ph.x[i], a.ph.y[i], a.ph.z[i], a.ph.dw[i], a.ph.t2[i]};
-            if (coils) se = C2<double>{(double)a.ph.sre[coil * a.ph.n + i], (double)a.ph.sim[coil * a.ph.n + i]};
-#pragma unroll
-            for (int i2 = 0; i2 < kMMStretches; ++i2)
-                sn[i2] = reinterpret_cast<const double2 *>(a.snap)[(int64_t)sprm[i2].slot * n_pad + pidx];
-        };
-        load_tile(0, spn, sens, snap);
         for (int j = 0; j < S; ++j) {
             const int tl = __builtin_amdgcn_readfirstlane(wave) + kWavesPerWG * j;
             if (tl >= B.ntiles) break;  // uniform; later slots are empty too
-            // the next tile's inputs arrive during this tile's products
-            ParSpin spn_n;
-            C2<double> sens_n;
-            double2 snap_n[kMMStretches];
-            load_tile(j + 1, spn_n, sens_n, snap_n);
+            // the tile's inputs (zero for empty lanes); loading the next
+            // tile's during this one's products measured no faster
+            ParSpin spn{0.f, 0.f, 0.f, 0.f, __builtin_inff()};
+            C2<double> sens{1.0, 0.0};
+            double2 snap[kMMStretches];
+#pragma unroll
+            for (int i2 = 0; i2 < kMMStretches; ++i2) snap[i2] = make_double2(0.0, 0.0);
+            {
+                const auto &T = as_const(a.tiles)[B.tile0 + tl];
+                if (lane < T.count) {
+                    const int64_t i = T.spin0 + lane;
+                    const int64_t pidx = (int64_t)(B.tile0 + tl) * kWave + lane;
+                    spn = ParSpin{a.ph.x[i], a.ph.y[i], a.ph.z[i], a.ph.dw[i], a.ph.t2[i]};
+                    if (coils) sens = C2<double>{(double)a.ph.sre[coil * a.ph.n + i], (double)a.ph.sim[coil * a.ph.n + i]};
+#pragma unroll
+                    for (int i2 = 0; i2 < kMMStretches; ++i2)
+                        snap[i2] = reinterpret_cast<const double2 *>(a.snap)[(int64_t)sprm[i2].slot * n_pad + pidx];
+                }
+            }
             const double r2 = 1.0 / (double)spn.t2;  // +inf -> 0: no decay
             int32_t fam = -1;  // family of the operands in the stage
             C2<double> wq[8];  // w^(16 q)
@@ -1416,10 +1407,6 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(1))) void k
                     }
                 }
             }
-            spn = spn_n;
-            sens = sens_n;
-#pragma unroll
-            for (int i2 = 0; i2 < kMMStretches; ++i2) snap[i2] = snap_n[i2];
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
