@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the Bloch-simulation hot path on one MI355X.
 
-A step is one whole simulation of the 2D single-shot EPI workload
-(256 x 256 head-like phantom, 65,536 spins; 128 x 128 EPI at dt = 4 us,
-20,374 intervals, 16,384 ADC samples) through ``koma_simulate``: host
-packing of the sequence into the event program, its upload, every kernel
-(excitation, block ends, sample sums, cross-workgroup reduction), with the
-phantom and the signal in HBM. ``value`` is grid spin-steps per second
-(spins x intervals / time) of the mixed-precision form; the all-FP64 form,
-NRMSE against the FP64 oracle, the other workloads, serving latency, the
-roofline of the dominant kernel and the oracle's CPU rate are reported
-beside it in the same JSON line.
+Headline: the large 2D multi-slice spin-echo EPI (5e6 spins in 20 slices
+of 500 x 500; per slice a 100-interval sinc 90 deg, a 200-interval sinc
+180 deg and a 128 x 128 EPI readout with k_y = 0 at TE = 60 ms; dt = 4 us,
+563,900 intervals, 327,680 ADC samples), the largest configuration of the
+measured set that one GPU holds. A step is one whole simulation through
+``koma_simulate_async``: host packing of the sequence into the event
+program, its upload, every kernel, with the phantom and the signal in HBM.
+``value`` is grid spin-steps per second (spins x intervals / time) of the
+mixed-precision form; beside it in the same JSON line: the all-FP64 form,
+events/s, the roofline of every kernel of the step (the dominant one as
+``roofline``), the error against the FP64 oracle, the oracle's own CPU rate
+on a seeded spin subset, the other workloads (each with its error against
+the oracle), the sequence-aware grids, motion and coils, MRF dictionary
+matching, and the serving figures.
 """
 from __future__ import annotations
 
@@ -27,14 +31,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "G spin-steps/s (mixed vs FP64 GPU) + serving p50/p99 latency at NRMSE<=1e-4"
-PEAK_FP32 = 157.3  # TFLOP/s, MI355X FP32 (vector and dense matrix; published)
-PEAK_FP64 = 78.6   # TFLOP/s, MI355X FP64 (vector and dense matrix; published)
-PEAK_HBM = 8000.0  # GB/s
-PEAK_FP16 = 2500.0  # TFLOP/s, MI355X dense FP16 matrix (published)
-# Algorithmic work of one (spin, sample) term of a precession block summed by
-# the sample-parallel kernel: one complex multiply (rotation and decay by the
-# per-sample factor, 6 FLOP) and one complex add into the sample (2 FLOP).
-FLOP_PER_TERM = 8
+# Published MI355X peaks
+PEAK_FP32 = 157.3      # TFLOP/s FP32 (packed vector / dense matrix)
+PEAK_FP32_VALU = 78.6  # TFLOP/s FP32 vector without packed instructions: 256 CU x 64 lanes x 2 x 2.4 GHz
+PEAK_FP64 = 78.6       # TFLOP/s FP64 (vector and dense matrix)
+PEAK_HBM = 8000.0      # GB/s
+PEAK_FP16 = 2500.0     # TFLOP/s dense FP16 matrix
+# Algorithmic work per unit (see the measurement section of the design notes)
+FLOP_PER_TERM = 8      # (spin, sample) of a deferred block: complex multiply (6) + add (2)
+FLOP_PER_RF = 65       # (spin, excitation interval): field, spinor, Eq. Rot_exc, relaxation
+FLOP_PER_END = 17      # (spin, block end): FP64 phase (8), complex rotate (6), Mz relaxation (3)
+FLOP_PER_INLINE = 8    # (spin, inline sample): factor (6) + accumulate (2)
+TRANS_PER_RF = 3       # rsqrt, sin, cos
+TRANS_PER_END = 3      # sin, cos, exp
 
 
 def log(*a):
@@ -49,8 +58,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def nrmse(got, ref):
-    return float(np.sqrt(np.mean(np.abs(got - ref) ** 2)) / np.max(np.abs(ref)))
+def err(got, ref):
+    """(NRMSE, max sample error, MAE), each over rows of the last axis and
+    normalised by the row's max|ref|; the worst row."""
+    r = np.asarray(ref).reshape(-1, np.shape(ref)[-1])
+    g = np.asarray(got).reshape(r.shape)
+    s = np.max(np.abs(r), axis=1)
+    nz = s > 0
+    d = np.abs(g - r)[nz]
+    return {"nrmse": float(np.max(np.sqrt(np.mean(d ** 2, axis=1)) / s[nz])),
+            "max_err": float(np.max(np.max(d, axis=1) / s[nz])),
+            "mae": float(np.max(np.mean(d, axis=1) / s[nz]))}
 
 
 def time_steps(fn, steps, warmup, torch):
@@ -73,7 +91,7 @@ def _bench_stream(torch):
     return _STREAM[0]
 
 
-def run_workload(K, ctx, torch, sc, ph, seq, prec, steps, warmup, profile=False, pipelined=False):
+def run_workload(K, ctx, torch, sc, ph, seq, prec, steps, warmup, profile_steps=0, pipelined=False):
     """Time `steps` device-resident simulations; return (seconds per step, signal, kernel stats).
 
     A step is one whole simulation: host packing of the sequence, upload of
@@ -81,11 +99,13 @@ def run_workload(K, ctx, torch, sc, ph, seq, prec, steps, warmup, profile=False,
     for its stream (the latency of one call). Pipelined: koma_simulate_async
     on one stream, so the host packs step k + 1 while the device runs step k
     (the throughput of a stream of simulations). Kernel statistics come from
-    a separate profiled pass (the profiler records HIP events around every
-    launch, which is kept out of the timed steps)."""
+    a separate profiled pass of `profile_steps` steps (the profiler records
+    HIP events around every launch on the stream it is launched on, which is
+    kept out of the timed steps)."""
     ctx.set_config(prec)
     dph = K.device_phantom(ph)
-    sig = torch.zeros((ph.n_groups, seq.n_adc, 2), dtype=torch.float64, device="cuda:0")
+    nsig = getattr(ph, "n_coils", 0) or 1
+    sig = torch.zeros((nsig, ph.n_groups, seq.n_adc, 2), dtype=torch.float64, device="cuda:0")
     # a stream of its own (default priority): launches on the legacy default
     # stream synchronise with the other blocking streams of the process
     stream = _bench_stream(torch)
@@ -97,25 +117,276 @@ def run_workload(K, ctx, torch, sc, ph, seq, prec, steps, warmup, profile=False,
             ctx.simulate(sc, dph, seq, where="device", sig=sig, stream=stream)
     t = time_steps(step, steps, warmup, torch)
     stats = None
-    if profile:
+    if profile_steps:
         ctx.profile(True)
-        time_steps(step, steps, 0, torch)
+        time_steps(step, profile_steps, 0, torch)
         stats = {k: ctx.kernel_stats(k) for k in ("seq", "par", "reduce", "aux")}
+        stats["steps"] = profile_steps
         ctx.profile(False)
     s = sig.cpu().numpy()
-    return t, s[..., 0] + 1j * s[..., 1], stats
+    out = s[..., 0] + 1j * s[..., 1]
+    del dph, sig
+    return t, (out if nsig > 1 else out[0]), stats
 
 
-def cpu_baseline(sc, ph, seq):
+def per_launch(st, kind):
+    k = st[kind]
+    return k["total_ms"] / max(k["launches"], 1), k["launches"] / st["steps"]
+
+
+def rooflines(info, st, prec, n_spins):
+    """Roofline of every kernel of a step from the live HIP-event timing.
+    Units and per-unit work: the measurement section of the design notes."""
+    out = {}
+    fp64 = prec == "fp64"
+    # sample-parallel sums: dense contraction on the matrix cores
+    if st["par"]["launches"]:
+        ms, lps = per_launch(st, "par")
+        units = n_spins * info["n_deferred_adc"]
+        ach = FLOP_PER_TERM * units / lps / (ms * 1e-3) / 1e12
+        peak = PEAK_FP64 if fp64 else PEAK_FP32
+        out["k_par_mm64" if fp64 else "k_par_mm"] = {
+            "bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(ach / peak, 4), "avg_launch_ms": round(ms, 5), "launches_per_step": lps,
+            "flop_per_unit": FLOP_PER_TERM, "units_per_step": units,
+            "unit_def": "one (spin, ADC sample) term of a deferred precession block",
+            "peak_def": "FP64 dense matrix" if fp64 else "FP32 dense matrix"}
+    # spin-sequential kernel: vector ALU
+    if st["seq"]["launches"]:
+        ms, lps = per_launch(st, "seq")
+        rf_single = info["n_rf_events"] - (info["n_runs"] if info["n_rf_in_runs"] else 0)
+        flop = n_spins * (FLOP_PER_RF * info["n_rf_events"] + FLOP_PER_END * info["n_ends"]
+                          + FLOP_PER_INLINE * info["n_inline_adc"])
+        trans = n_spins * (TRANS_PER_RF * info["n_rf_events"] + TRANS_PER_END * info["n_ends"])
+        ach = flop / lps / (ms * 1e-3) / 1e12
+        peak = PEAK_FP64 if fp64 else PEAK_FP32_VALU
+        out["k_seq"] = {
+            "bound": "alu", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(ach / peak, 4),
+            "frac_of_published_fp32": None if fp64 else round(ach / PEAK_FP32, 4),
+            "transcendentals_per_s": round(trans / lps / (ms * 1e-3), 1),
+            "avg_launch_ms": round(ms, 5), "launches_per_step": lps, "flop_per_step": flop,
+            "units": {"excitation_event": [FLOP_PER_RF, info["n_rf_events"]], "block_end": [FLOP_PER_END, info["n_ends"]],
+                      "inline_sample": [FLOP_PER_INLINE, info["n_inline_adc"]]},
+            "single_interval_events": rf_single,
+            "peak_def": "FP64 vector" if fp64 else "FP32 vector, non-packed (packed FP32 is not used)"}
+    # fixed-order FP64 sums of the workgroup partials: HBM
+    if st["reduce"]["launches"]:
+        ms, lps = per_launch(st, "reduce")
+        out["k_reduce"] = {"bound": "hbm", "avg_launch_ms": round(ms, 5), "launches_per_step": lps}
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(sc, ph, seq, n_multi, n_single, seed=5050):
+    """The oracle (per-interval FP64 splitting, as it stands) on seeded spin
+    subsets of the workload: n_multi spins on every thread the process may
+    use (at most 16, the host share of one GPU), n_single spins on one
+    thread. Returns (subset index, oracle signal of the multi-thread subset,
+    report)."""
     import oracle
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(ph.n, n_multi, replace=False))
+    sub = ph.subset(idx)
     th = oracle.default_threads()
     t0 = time.perf_counter()
-    ref = oracle.simulate(sc, ph, seq, mode=oracle.MODE_STEP, threads=th)
+    ref = oracle.simulate(sc, sub, seq, mode=oracle.MODE_STEP, threads=th)
     dt = time.perf_counter() - t0
-    return ref, {"value": ph.n * seq.n_int / dt / 1e9, "unit": "G spin-steps/s", "cores": th,
-                 "kind": "oracle", "wall_s": round(dt, 3),
-                 "sample": f"the whole workload ({ph.n} spins x {seq.n_int} intervals), "
-                           "per-interval splitting in FP64, one signal matrix per thread"}
+    sub1 = ph.subset(idx[:n_single])
+    t0 = time.perf_counter()
+    oracle.simulate(sc, sub1, seq, mode=oracle.MODE_STEP, threads=1)
+    dt1 = time.perf_counter() - t0
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        avail = os.cpu_count()
+    rep = {"value": round(n_multi * seq.n_int / dt / 1e9, 4), "unit": "G spin-steps/s", "cores": th,
+           "kind": "oracle", "wall_s": round(dt, 3),
+           "sample": f"{n_multi} seeded spins of the {ph.n} (all slices) x the full {seq.n_int}-interval "
+                     "sequence, per-interval FP64 splitting, one signal matrix per thread",
+           "one_thread": {"value": round(n_single * seq.n_int / dt1 / 1e9, 5), "wall_s": round(dt1, 3),
+                          "sample": f"the first {n_single} spins of that subset"},
+           "cpu_model": cpu_model(), "cpus_available": avail}
+    return idx, ref, rep
+
+
+def load_stored(name, khash):
+    """A counter figure taken by rocprofv3 and committed under profiles/ with
+    the kernel source hash it was taken with; None once the kernels changed."""
+    p = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_hash") != khash:
+        return None
+    d["source"] = f"stored: profiles/{name}"
+    return d
+
+
+def oracle_entries(sc, ph, seq, entries):
+    import oracle
+    return np.stack([oracle.simulate(sc, ph.groups(int(e), int(e) + 1), seq, mode=oracle.MODE_BLOCK)[0, 0]
+                     for e in entries])
+
+
+def bench_headline(K, ctx, torch, W, args, khash):
+    sc, ph, seq = W.config(5)
+    info = K.koma_plan_info(sc, ph, seq, K.make_config("mixed"))
+    spin_steps = ph.n * seq.n_int
+    prof = min(args.steps, 5)
+    log(f"[bench] headline seepi: {ph.n} spins x {seq.n_int} intervals, {seq.n_adc} ADC")
+    t_mix, s_mix, st_mix = run_workload(K, ctx, torch, sc, ph, seq, "mixed", args.steps, args.warmup, prof, True)
+    log(f"[bench] seepi mixed, pipelined: {t_mix * 1e3:.2f} ms/step")
+    t_64, s_64, st_64 = run_workload(K, ctx, torch, sc, ph, seq, "fp64", args.steps, args.warmup, prof, True)
+    log(f"[bench] seepi fp64, pipelined: {t_64 * 1e3:.2f} ms/step")
+    events = ph.n * (info["n_rf_events"] + info["n_ends"] + info["n_adc"])
+    rl_mix = rooflines(info, st_mix, "mixed", ph.n)
+    rl_64 = rooflines(info, st_64, "fp64", ph.n)
+    kms = {p: {k: round(v["total_ms"] / st["steps"], 3) for k, v in st.items() if k != "steps"}
+           for p, st in (("mixed", st_mix), ("fp64", st_64))}
+    dom = max(("k_par_mm", "par"), ("k_seq", "seq"), key=lambda kv: kms["mixed"][kv[1]])[0]
+    roofline = dict(rl_mix[dom], kernel=dom)
+    traffic = load_stored(f"traffic_{dom}_seepi.json", khash)
+    roofline["traffic"] = traffic["bytes_per_launch"] if traffic else None
+    if traffic:
+        roofline["traffic_source"] = traffic["source"]
+    flops = load_stored("flops_seepi.json", khash)
+    out = {
+        "metric": METRIC, "value": round(spin_steps / t_mix / 1e9, 3), "unit": "G spin-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t_mix * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "seepi20x500_mixed: multi-slice spin-echo EPI, 5e6 spins (20 slices of "
+                               "500x500 seeded head phantoms, 100 Hz smooth off-resonance), per slice sinc 90 "
+                               "(100 int) + sinc 180 (200 int) + 128x128 EPI readout, TE 60 ms, dt 4 us, "
+                               f"{seq.n_int} intervals, {seq.n_adc} ADC samples",
+                   "spins": ph.n, "intervals": seq.n_int, "adc": seq.n_adc, "spin_steps": spin_steps,
+                   "phantom_in": "HBM", "signal_out": "HBM", "sequence_packing": "host, every step",
+                   "steps": "pipelined: koma_simulate_async on one stream"},
+        "fp64": {"value": round(spin_steps / t_64 / 1e9, 3), "ms_per_step": round(t_64 * 1e3, 4),
+                 "roofline": rl_64},
+        "mixed_over_fp64": round(t_64 / t_mix, 3),
+        "events_per_s": {"mixed": round(events / t_mix, 1), "fp64": round(events / t_64, 1),
+                         "events_per_spin": info["n_rf_events"] + info["n_ends"] + info["n_adc"],
+                         "def": "per spin: excitation events + block ends + ADC samples evaluated"},
+        "kernel_ms_per_step": kms,
+        "roofline": roofline,
+        "rooflines": {"mixed": rl_mix, "fp64": rl_64},
+        "rocprof_flops": flops,
+    }
+    # error against the FP64 oracle: the oracle on a seeded spin subset (the
+    # CPU baseline run); FP64 by linearity at full size (full - rest =
+    # subset); mixed on the subset directly and against FP64 at full size
+    out["nrmse_mixed_vs_fp64"] = err(s_mix, s_64)
+    if not args.no_cpu:
+        log("[bench] oracle CPU baseline on a seeded subset of the seepi spins ...")
+        idx, ref, cpu = cpu_baseline(sc, ph, seq, args.cpu_spins, args.cpu_spins_1t)
+        out["cpu_baseline"] = cpu
+        log(f"[bench] oracle {cpu['wall_s']} s on {cpu['cores']} threads ({cpu['value']} G spin-steps/s); "
+            f"1 thread {cpu['one_thread']['value']}")
+        keep = np.ones(ph.n, dtype=bool)
+        keep[idx] = False
+        rest = ph.subset(np.nonzero(keep)[0])
+        _, s_rest, _ = run_workload(K, ctx, torch, sc, rest, seq, "fp64", 1, 0)
+        del rest
+        sub = ph.subset(idx)
+        _, s_sub_mix, _ = run_workload(K, ctx, torch, sc, sub, seq, "mixed", 1, 0)
+        _, s_sub_64, _ = run_workload(K, ctx, torch, sc, sub, seq, "fp64", 1, 0)
+        out["error_vs_oracle"] = {
+            "fp64_full_size_by_linearity": err(s_64 - s_rest, ref),
+            "fp64_subset": err(s_sub_64, ref), "mixed_subset": err(s_sub_mix, ref),
+            "subset_spins": int(len(idx)),
+            "def": "oracle on the seeded subset; fp64_full_size_by_linearity = FP64(all spins) - "
+                   "FP64(all but the subset) against it; *_subset = the GPU run on the subset alone"}
+        log(f"[bench] seepi error vs oracle: {out['error_vs_oracle']}")
+    else:
+        out["cpu_baseline"] = None
+    return out
+
+
+def bench_secondary(K, ctx, torch, W, args, out):
+    import oracle
+    # epi256: the 256 x 256 head, 128 x 128 single-shot EPI (65,536 spins)
+    sc, ph, seq = W.config(2)
+    ss = ph.n * seq.n_int
+    info = K.koma_plan_info(sc, ph, seq, K.make_config("mixed"))
+    t_m, s_m, st_m = run_workload(K, ctx, torch, sc, ph, seq, "mixed", args.epi_steps, 20, 50, True)
+    t_m1, _, _ = run_workload(K, ctx, torch, sc, ph, seq, "mixed", args.epi_steps, 20)
+    t_6, s_6, st_6 = run_workload(K, ctx, torch, sc, ph, seq, "fp64", args.epi_steps, 20, 50, True)
+    ctx.set_config("mixed", sample_engine=1)  # the same sums on the vector ALU, for comparison
+    t_v, s_v, st_v = run_workload(K, ctx, torch, sc, ph, seq, "mixed", args.epi_steps, 20, 50, True)
+    ctx.set_config("mixed", sample_engine=0)
+    ref = oracle.simulate(sc, ph, seq, mode=oracle.MODE_BLOCK)[0]
+    rl_m = rooflines(info, st_m, "mixed", ph.n)
+    par_v, lps_v = per_launch(st_v, "par")
+    ach_v = FLOP_PER_TERM * ph.n * info["n_deferred_adc"] / lps_v / (par_v * 1e-3) / 1e12
+    w = {"spins": ph.n, "intervals": seq.n_int, "spin_steps": ss,
+         "mixed_gsps": round(ss / t_m / 1e9, 3), "mixed_ms": round(t_m * 1e3, 4),
+         "mixed_one_call_ms": round(t_m1 * 1e3, 4),
+         "fp64_gsps": round(ss / t_6 / 1e9, 3), "fp64_ms": round(t_6 * 1e3, 4),
+         "rooflines": {"mixed": rl_m, "fp64": rooflines(info, st_6, "fp64", ph.n)},
+         "mixed_valu_sums": {"ms": round(t_v * 1e3, 4), "par_ms": round(par_v, 5),
+                             "roofline": {"bound": "alu", "kernel": "k_par (vector ALU)",
+                                          "achieved": round(ach_v, 3), "peak": PEAK_FP32_VALU,
+                                          "frac": round(ach_v / PEAK_FP32_VALU, 4)},
+                             "vs_mfma": err(s_v, s_m)},
+         "error_vs_oracle": {"mixed": err(s_m, ref), "fp64": err(s_6, ref)},
+         "traffic_k_par_mm": load_stored("traffic_k_par_mm_epi256.json", out["kernel_hash"])}
+    log(f"[bench] epi256: mixed {w['mixed_gsps']}, fp64 {w['fp64_gsps']} G spin-steps/s; vs oracle "
+        f"{w['error_vs_oracle']}")
+    wl = {"epi256": w}
+    dictionary = None
+    # gre64 (whole oracle) and the MRF batch (oracle on 48 seeded entries)
+    for k in (1, 4):
+        sck, phk, seqk = W.config(k)
+        ss = phk.n * seqk.n_int
+        infok = K.koma_plan_info(sck, phk, seqk, K.make_config("mixed"))
+        tm, sm, km = run_workload(K, ctx, torch, sck, phk, seqk, "mixed", 3, 1, 3)
+        t6, s6, k6 = run_workload(K, ctx, torch, sck, phk, seqk, "fp64", 3, 1, 3)
+        name = W.WORKLOAD_NAMES[k].split(" ")[0]
+        w = {"spins": phk.n, "intervals": seqk.n_int, "spin_steps": ss,
+             "mixed_gsps": round(ss / tm / 1e9, 3), "fp64_gsps": round(ss / t6 / 1e9, 3),
+             "mixed_ms": round(tm * 1e3, 3), "fp64_ms": round(t6 * 1e3, 3),
+             "events_per_spin": infok["n_rf_events"] + infok["n_ends"] + infok["n_adc"],
+             "kernel_ms": {p: {kk: round(v["total_ms"] / st["steps"], 3) for kk, v in st.items() if kk != "steps"}
+                           for p, st in (("mixed", km), ("fp64", k6))},
+             "rooflines": {"mixed": rooflines(infok, km, "mixed", phk.n), "fp64": rooflines(infok, k6, "fp64", phk.n)}}
+        if k == 1:
+            ref = oracle.simulate(sck, phk, seqk, mode=oracle.MODE_BLOCK)
+            w["error_vs_oracle"] = {"mixed": err(sm, ref), "fp64": err(s6, ref)}
+        else:
+            dictionary = sm.astype(np.complex64)  # 10,000 simulated fingerprints x 1,000 TRs
+            rng = np.random.default_rng(4004)
+            entries = np.sort(rng.choice(phk.n_groups, 48, replace=False))
+            ref = oracle_entries(sck, phk, seqk, entries)
+            per = {}
+            for p, s in (("mixed", sm), ("fp64", s6)):
+                d = np.abs(s[entries] - ref)
+                sc_ = np.max(np.abs(ref), axis=1)
+                e = np.sqrt(np.mean(d ** 2, axis=1)) / sc_
+                worst = int(np.argmax(e))
+                per[p] = {"nrmse_max": float(e.max()), "nrmse_p99": float(np.percentile(e, 99)),
+                          "nrmse_median": float(np.median(e)),
+                          "max_err": float(np.max(np.max(d, axis=1) / sc_)),
+                          "worst_entry_t1_t2": [float(phk.t1[phk.group_off[entries[worst]]]),
+                                                float(phk.t2[phk.group_off[entries[worst]]])]}
+            w["error_vs_oracle_per_entry"] = dict(per, entries=48)
+            e = np.sqrt(np.mean(np.abs(sm - s6) ** 2, axis=1)) / np.max(np.abs(s6), axis=1)
+            w["nrmse_mixed_vs_fp64_all_entries"] = {"max": float(e.max()), "median": float(np.median(e))}
+        log(f"[bench] {name}: mixed {w['mixed_gsps']}, fp64 {w['fp64_gsps']} G spin-steps/s")
+        wl[name] = w
+        del phk
+    out["workloads"] = wl
+    return dictionary
 
 
 def bench_mrf_match(K, ctx, torch, dictionary, no_cpu, n_pix=65536, reps=5):
@@ -157,22 +428,20 @@ def bench_mrf_match(K, ctx, torch, dictionary, no_cpu, n_pix=65536, reps=5):
                         "achieved": round(achieved, 2), "peak": PEAK_FP16, "unit": "TFLOP/s",
                         "frac": round(achieved / PEAK_FP16, 4)},
            "recovered_fraction": float(np.mean(b == truth.cpu().numpy()))}
-    if not no_cpu:  # reference on the same rounded operands, a sample of pixels
+    if not no_cpu:  # against the FP64 definition on the caller's inputs, a seeded sample of pixels
         from oracle import mrf_match as M
-        idx = np.arange(0, n_pix, n_pix // 256)
+        idx = np.sort(np.random.default_rng(4141).choice(n_pix, 512, replace=False))
         xs = x[idx].cpu().numpy()
-        xs = xs[..., 0] + 1j * xs[..., 1]
+        xs = (xs[..., 0] + 1j * xs[..., 1]).astype(np.complex64)
         t0 = time.perf_counter()
-        rb, _, rs, scores = M.match_rounded(dictionary, xs.astype(np.complex64))
+        j = M.judge_picks(b[idx], dictionary, xs)
         t_ref = time.perf_counter() - t0
-        srt = np.sort(scores, axis=1)
-        clear = (rs - srt[:, -2]) > 1e-4 * rs
-        out["parity_sample"] = {"pixels": int(len(idx)), "identical": int(np.sum(b[idx] == rb)),
-                                "clear_gap": int(np.sum(clear)),
-                                "clear_gap_identical": int(np.sum((b[idx] == rb) & clear))}
+        rr = M.match_rounded(dictionary, xs)[0]
+        j["identical_to_binary16_argmax"] = int(np.sum(b[idx] == rr))
+        out["parity_vs_definition"] = j
         out["cpu_reference_ms_per_pixel"] = round(t_ref / len(idx) * 1e3, 3)
     log(f"[bench] mrf match {n_pix} px x {n_e} entries x {n_t} TR: kernel {k_ms:.3f} ms, "
-        f"{achieved:.1f} TFLOP/s, recovered {out['recovered_fraction']:.4f}")
+        f"{achieved:.1f} TFLOP/s, recovered {out['recovered_fraction']:.4f}; parity {out.get('parity_vs_definition')}")
     # rank-5 compression (the paper's LRTV dictionary rank), then matching in the
     # compressed domain
     rank = 5
@@ -204,6 +473,39 @@ def bench_mrf_match(K, ctx, torch, dictionary, no_cpu, n_pix=65536, reps=5):
     return out
 
 
+def bench_extras(K, ctx, torch, W, out):
+    # sequence-aware time stepping: the same sequences from their block
+    # form, discretised by the library to the minimal grid
+    seqaware = {}
+    for k, blocks_fn in ((1, W.gre_blocks), (2, W.epi_blocks)):
+        sck, phk, seqk = W.config(k)
+        blocks = blocks_fn()
+        t0 = time.perf_counter()
+        m = K.koma_discretize(blocks)
+        t_disc = time.perf_counter() - t0
+        rep = 5 if k == 1 else 50
+        tr, sr, _ = run_workload(K, ctx, torch, sck, phk, seqk, "mixed", rep, 1)
+        tm, sm, _ = run_workload(K, ctx, torch, sck, phk, m, "mixed", rep, 1)
+        name = W.WORKLOAD_NAMES[k].split(" ")[0]
+        seqaware[name] = {
+            "blocks": len(blocks), "raster_intervals": seqk.n_int, "minimal_intervals": m.n_int,
+            "discretise_ms": round(t_disc * 1e3, 3),
+            "raster_ms": round(tr * 1e3, 3), "minimal_ms": round(tm * 1e3, 3),
+            "speedup": round(tr / tm, 3), "minimal_vs_raster": err(sm, sr)}
+        log(f"[bench] minimal grid {name}: {m.n_int} vs {seqk.n_int} intervals, "
+            f"{tm * 1e3:.3f} vs {tr * 1e3:.3f} ms")
+    out["sequence_aware"] = seqaware
+    # motion (the paper's u_y = v_y t, v_y = 0.1 m/s) and 8 receive coils on epi256
+    sc, ph, seq = W.config(2)
+    ext = {}
+    for tag, phx in (("motion_vy0.1", W.with_velocity(ph, (0.0, 0.1, 0.0))), ("coils8", W.with_coils(ph, 8))):
+        tx, _, _ = run_workload(K, ctx, torch, sc, phx, seq, "mixed", 5, 1)
+        ext[tag] = {"ms": round(tx * 1e3, 3), "gsps": round(ph.n * seq.n_int / tx / 1e9, 3),
+                    "signals": phx.n_coils or 1}
+        log(f"[bench] epi256 {tag}: {tx * 1e3:.3f} ms")
+    out["extensions"] = ext
+
+
 def gpu_clocks():
     """Shader clock levels of the GPU as the driver reports them (sysfs,
     read-only), to put box-to-box differences in context; None if absent."""
@@ -218,30 +520,25 @@ def gpu_clocks():
     return None
 
 
-def load_traffic(khash):
-    p = os.path.join(ROOT, "profiles", "traffic_k_par_epi256.json")
-    if not os.path.exists(p):
-        return None
-    d = json.load(open(p))
-    if d.get("kernel_hash") != khash:
-        return None
-    return d.get("bytes_per_launch")
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=20, help="timed headline steps")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--epi-steps", type=int, default=200, help="timed steps of the epi256 workload")
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline and oracle errors")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--serving-requests", type=int, default=1000)
+    ap.add_argument("--serving-warmup", type=int, default=50)
+    ap.add_argument("--cpu-spins", type=int, default=16384, help="oracle subset on every thread")
+    ap.add_argument("--cpu-spins-1t", type=int, default=1024, help="oracle subset on one thread")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "the simulator runs on one GPU (spins would shard across GPUs with one final signal sum, not implemented); --gpus must be 1",
+        print(json.dumps({"error": "this build runs on one GPU: spins would shard across GPUs with one "
+                                   "final signal sum, which is not implemented; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
@@ -251,169 +548,26 @@ def main():
 
     K.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    ctx = K.Context(0, "mixed")
-    sc, ph, seq = W.config(2)
-    spin_steps = ph.n * seq.n_int
-    log(f"[bench] workload epi256: {ph.n} spins x {seq.n_int} intervals, {seq.n_adc} ADC")
-
-    # headline: mixed precision, a stream of pipelined simulations; the
-    # kernels' live HIP-event timing from a separate profiled pass
-    t_mix, s_mix, st_mix = run_workload(K, ctx, torch, sc, ph, seq, "mixed", args.steps, args.warmup, True, True)
-    log(f"[bench] mixed, pipelined: {t_mix * 1e3:.3f} ms/step")
-    t_mix1, s_mix1, _ = run_workload(K, ctx, torch, sc, ph, seq, "mixed", args.steps, args.warmup)
-    log(f"[bench] mixed, one call at a time: {t_mix1 * 1e3:.3f} ms/step")
-    assert np.array_equal(s_mix, s_mix1), "pipelined and synchronous calls must agree bitwise"
-    t_64, s_64, st_64 = run_workload(K, ctx, torch, sc, ph, seq, "fp64", args.steps, args.warmup, True, True)
-    log(f"[bench] fp64, pipelined:  {t_64 * 1e3:.3f} ms/step")
-    t_641, _, _ = run_workload(K, ctx, torch, sc, ph, seq, "fp64", args.steps, args.warmup)
-    log(f"[bench] fp64, one call at a time:  {t_641 * 1e3:.3f} ms/step")
-    ctx.set_config("mixed", sample_engine=1)  # the same sums on the vector ALU, for comparison
-    t_vm, s_vm, st_vm = run_workload(K, ctx, torch, sc, ph, seq, "mixed", args.steps, args.warmup, True, True)
-    ctx.set_config("mixed", sample_engine=0)
-    log(f"[bench] mixed, vector-ALU sums, pipelined: {t_vm * 1e3:.3f} ms/step")
-
-    info = K.koma_plan_info(sc, ph, seq, K.make_config("mixed"))
-    n_terms = ph.n * info["n_deferred_adc"]
-    par = st_mix["par"]
-    par_ms = par["total_ms"] / max(par["launches"], 1)
-    achieved = FLOP_PER_TERM * n_terms / (par_ms * 1e-3) / 1e12 / (par["launches"] / args.steps)
     khash = kernel_source_hash()
-    traffic = load_traffic(khash)
-    roofline = {"bound": "mfma", "kernel": "k_par_mm (sample-parallel block sums on FP32 MFMA)",
-                "achieved": round(achieved, 3), "peak": PEAK_FP32, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32, 4), "traffic": traffic,
-                "avg_launch_ms": round(par_ms, 5), "launches_per_step": par["launches"] / args.steps,
-                "flop_per_unit": FLOP_PER_TERM, "units_per_step": n_terms,
-                "unit_def": "one (spin, ADC sample) term of a precession block",
-                "kernel_hash": khash}
-
-    # the FP64 form's sample sums (k_par_mm64) against the FP64 matrix peak
-    par64 = st_64["par"]
-    par64_ms = par64["total_ms"] / max(par64["launches"], 1)
-    ach64 = FLOP_PER_TERM * n_terms / (par64_ms * 1e-3) / 1e12 / (par64["launches"] / args.steps)
-    roofline_fp64 = {"bound": "mfma", "kernel": "k_par_mm64 (sample-parallel block sums on FP64 MFMA)",
-                     "achieved": round(ach64, 3), "peak": PEAK_FP64, "unit": "TFLOP/s",
-                     "frac": round(ach64 / PEAK_FP64, 4), "avg_launch_ms": round(par64_ms, 5)}
-
-    out = {
-        "metric": METRIC, "value": round(spin_steps / t_mix / 1e9, 3), "unit": "G spin-steps/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(t_mix * 1e3, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": "epi256_mixed: 256x256 head phantom (65536 spins, 3 tissue classes, "
-                               "50 Hz smooth off-resonance), 128x128 single-shot EPI, dt 4 us, "
-                               f"{seq.n_int} intervals, {seq.n_adc} ADC samples",
-                   "spins": ph.n, "intervals": seq.n_int, "adc": seq.n_adc, "spin_steps": spin_steps,
-                   "phantom_in": "HBM", "signal_out": "HBM", "sequence_packing": "host, every step",
-                   "steps": "pipelined: koma_simulate_async on one stream, the host packs the next "
-                            "step while the device runs the current one"},
-        "one_call_at_a_time": {"value": round(spin_steps / t_mix1 / 1e9, 3), "ms_per_step": round(t_mix1 * 1e3, 4),
-                               "fp64_ms_per_step": round(t_641 * 1e3, 4)},
-        "fp64": {"value": round(spin_steps / t_64 / 1e9, 3), "ms_per_step": round(t_64 * 1e3, 4),
-                 "roofline": roofline_fp64},
-        "mixed_over_fp64": round(t_64 / t_mix, 3),
-        "mixed_valu": {"value": round(spin_steps / t_vm / 1e9, 3), "ms_per_step": round(t_vm * 1e3, 4),
-                       "par_ms": round(st_vm["par"]["total_ms"] / max(st_vm["par"]["launches"], 1), 5),
-                       "nrmse_vs_mfma": nrmse(s_vm[0], s_mix[0])},
-        "kernel_ms_per_step": {p: {k: round(v["total_ms"] / args.steps, 4) for k, v in st.items()}
-                               for p, st in (("mixed", st_mix), ("fp64", st_64))},
-        "roofline": roofline,
-    }
-
-    if not args.no_cpu:
-        log("[bench] oracle CPU baseline (whole workload, per-interval FP64) ...")
-        ref, cpu = cpu_baseline(sc, ph, seq)
-        out["cpu_baseline"] = cpu
-        out["nrmse_vs_oracle"] = {"mixed": nrmse(s_mix[0], ref[0]), "fp64": nrmse(s_64[0], ref[0])}
-        log(f"[bench] oracle {cpu['wall_s']} s on {cpu['cores']} threads; NRMSE {out['nrmse_vs_oracle']}")
-    else:
-        out["cpu_baseline"] = None
-        out["nrmse_vs_oracle"] = None
-    out["nrmse_mixed_vs_fp64"] = nrmse(s_mix[0], s_64[0])
-
+    ctx = K.Context(0, "mixed")
+    out = bench_headline(K, ctx, torch, W, args, khash)
+    out["kernel_hash"] = khash
     if not args.no_extra:
-        extra = {}
-        dictionary = None
-        for k in (1, 4, 5):
-            sck, phk, seqk = W.config(k)
-            ss = phk.n * seqk.n_int
-            rep = 3 if k != 5 else 2
-            tm, sm, km = run_workload(K, ctx, torch, sck, phk, seqk, "mixed", rep, 1, True)
-            if k == 4:
-                dictionary = sm.astype(np.complex64)  # 10,000 simulated fingerprints x 1,000 TRs
-            t6, s6, k6 = run_workload(K, ctx, torch, sck, phk, seqk, "fp64", rep, 1, True)
-            e = np.sqrt(np.mean(np.abs(sm - s6) ** 2, axis=1)) / np.max(np.abs(s6), axis=1)
-            extra[W.WORKLOAD_NAMES[k].split(" ")[0]] = {
-                "spins": phk.n, "intervals": seqk.n_int, "spin_steps": ss,
-                "mixed_gsps": round(ss / tm / 1e9, 3), "fp64_gsps": round(ss / t6 / 1e9, 3),
-                "mixed_ms": round(tm * 1e3, 3), "fp64_ms": round(t6 * 1e3, 3),
-                "kernel_ms": {p: {kk: round(v["total_ms"] / rep, 3) for kk, v in st.items()}
-                              for p, st in (("mixed", km), ("fp64", k6))},
-                "nrmse_mixed_vs_fp64_max": float(np.max(e))}
-            log(f"[bench] {W.WORKLOAD_NAMES[k]}: mixed {ss / tm / 1e9:.2f}, fp64 {ss / t6 / 1e9:.2f} G spin-steps/s")
-            del phk
-        out["workloads"] = extra
-
-    if not args.no_extra:
-        # sequence-aware time stepping: the same sequences from their block
-        # form, discretised by the library to the minimal grid
-        seqaware = {}
-        for k, blocks_fn in ((1, W.gre_blocks), (2, W.epi_blocks)):
-            sck, phk, seqk = W.config(k) if k != 2 else (sc, ph, seq)
-            blocks = blocks_fn()
-            t0 = time.perf_counter()
-            m = K.koma_discretize(blocks)
-            t_disc = time.perf_counter() - t0
-            rep = 5 if k == 1 else args.steps
-            tr, sr, _ = run_workload(K, ctx, torch, sck, phk, seqk, "mixed", rep, 1)
-            tm, sm, km = run_workload(K, ctx, torch, sck, phk, m, "mixed", rep, 1, True)
-            name = W.WORKLOAD_NAMES[k].split(" ")[0]
-            seqaware[name] = {
-                "blocks": len(blocks), "raster_intervals": seqk.n_int, "minimal_intervals": m.n_int,
-                "discretise_ms": round(t_disc * 1e3, 3),
-                "raster_ms": round(tr * 1e3, 3), "minimal_ms": round(tm * 1e3, 3),
-                "speedup": round(tr / tm, 3),
-                "nrmse_minimal_vs_raster": float(np.max(np.sqrt(np.mean(np.abs(sm - sr) ** 2, axis=1))
-                                                        / np.max(np.abs(sr), axis=1)))}
-            log(f"[bench] minimal grid {name}: {m.n_int} vs {seqk.n_int} intervals, "
-                f"{tm * 1e3:.3f} vs {tr * 1e3:.3f} ms")
-        out["sequence_aware"] = seqaware
-
-        # motion (the paper's u_y = v_y t, v_y = 0.1 m/s) and 8 receive coils on epi256
-        ext = {}
-        for tag, phx in (("motion_vy0.1", W.with_velocity(ph, (0.0, 0.1, 0.0))), ("coils8", W.with_coils(ph, 8))):
-            nsig = phx.n_coils or 1
-            dphx = K.device_phantom(phx)
-            sigx = torch.zeros((nsig, ph.n_groups, seq.n_adc, 2), dtype=torch.float64, device="cuda:0")
-            ctx.set_config("mixed")
-
-            def stepx():
-                ctx.simulate(sc, dphx, seq, where="device", sig=sigx)
-
-            tx = time_steps(stepx, 5, 1, torch)
-            ext[tag] = {"ms": round(tx * 1e3, 3), "gsps": round(spin_steps / tx / 1e9, 3), "signals": nsig}
-            log(f"[bench] epi256 {tag}: {tx * 1e3:.3f} ms, {spin_steps / tx / 1e9:.1f} G spin-steps/s")
-            del dphx, sigx
-        out["extensions"] = ext
-
-        if dictionary is not None:
-            out["mrf_match"] = bench_mrf_match(K, ctx, torch, dictionary, args.no_cpu)
-
+        dictionary = bench_secondary(K, ctx, torch, W, args, out)
+        bench_extras(K, ctx, torch, W, out)
+        out["mrf_match"] = bench_mrf_match(K, ctx, torch, dictionary, args.no_cpu)
     if not args.no_serving:
         from paper_2301_02702_amd import serve
-        log(f"[bench] serving: {args.serving_requests} requests ...")
-        out["serving"] = serve.benchmark(ctx_device=0, n_requests=args.serving_requests, rho=0.8,
-                                         log=log)
-
+        log(f"[bench] serving: {args.serving_requests} requests (+{args.serving_warmup} warm-up) ...")
+        out["serving"] = serve.benchmark(ctx_device=0, n_requests=args.serving_requests,
+                                         n_warm=args.serving_warmup, log=log)
     out["gpu_sclk"] = gpu_clocks()
-
     if args.calib_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0")
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = 2 * a.numel() * 4
-
     ctx.close()
     print(json.dumps(out), flush=True)
 

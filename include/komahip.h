@@ -116,7 +116,10 @@ typedef struct {
                               choice, or 1 .. 16 (the vector-ALU kernels round down to 1, 2, 4 or 8) */
     int wg_size;           /* 256 (reserved: other values are rejected) */
     int64_t chunk_events;  /* events per launch of the spin-sequential kernel for requests; >= 1 */
-    size_t hbm_budget;     /* bytes a request may hold on the device; 0 = no limit */
+    size_t hbm_budget;     /* device bytes: the footprint one call may need, and the total that the
+                              open requests of the context hold together with the blocks it keeps
+                              cached for reuse (koma_req_open fails with KOMA_E_BUDGET rather
+                              than exceed it); 0 = no limit */
     size_t partial_budget; /* bytes for cross-workgroup signal partials per launch; >= 1 MiB */
     int defer_min_adc;     /* precession blocks with at least this many ADC samples are
                               summed by the sample-parallel kernel; < 0 disables it */
@@ -220,12 +223,20 @@ typedef struct {
     int64_t n_blocks, spins_per_lane, n_chunks;
     int64_t events_done;
     size_t footprint;
+    int64_t n_ends;        /* precession-block ends every spin evaluates */
+    int64_t n_rf_in_runs;  /* excitation intervals inside runs of identical ones */
 } koma_req_info;
 koma_status koma_req_info_get(const koma_req *req, koma_req_info *info);
 /* The same figures for a plan built on the host only (no device work);
  * footprint is what koma_req_open would hold. */
 koma_status koma_plan_info(const koma_scanner *sc, const koma_phantom *ph, const koma_sequence *seq,
                            const koma_config *cfg, koma_req_info *info);
+
+/* Device memory of the context's requests: bytes held by open requests,
+ * bytes of closed requests' blocks cached for reuse, and the largest
+ * held + cached total since the context was created. Any pointer may be
+ * NULL. */
+koma_status koma_ctx_mem(const koma_ctx *ctx, size_t *held, size_t *cached, size_t *peak);
 
 /* ---- measurement ---------------------------------------------------------
  * With profiling on, every kernel launch of the context is bracketed by HIP

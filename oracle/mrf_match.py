@@ -12,13 +12,15 @@ being normalised: best(x) = argmax_e |<d_e, x>| / ||d_e||, with
 the pixel's complex proton-density scale (relative to the entry's own
 scale).
 
-The paper does not fix a precision. The library takes the decision on
+The paper does not fix a precision. ``match`` is the definition on the
+caller's inputs in FP64, and ``judge_picks`` checks a pick against it with
+the error bound of ``decision_bound``. The library takes the decision on
 half-precision operands: every row (dictionary entry or fingerprint) is
 scaled by an exact power of two so that its largest component magnitude
 lies in [0.5, 1), and each real and imaginary part is rounded to the
 nearest IEEE binary16 value (ties to even). ``match_rounded`` applies that
-same rounding and then evaluates the definition in FP64; ``match`` is the
-definition on the unrounded inputs.
+same rounding and then evaluates the definition in FP64 (a diagnostic of
+where a pick differs from the definition, not the parity reference).
 """
 from __future__ import annotations
 
@@ -37,6 +39,71 @@ def match(dictionary, x):
     rows = np.arange(x.shape[0])
     proj = ip[rows, best] / np.sqrt(norm2[best])
     return best.astype(np.int64), proj, score[rows, best]
+
+
+def cosines(dictionary, x):
+    """FP64 |<d_e, x>| / (||d_e|| ||x||) for every pixel and entry [n_p, n_e]
+    (0 where either row is zero): the definition's score, normalised so that
+    it lies in [0, 1] and its argmax over e is the definition's pick."""
+    d = np.asarray(dictionary, dtype=np.complex128)
+    x = np.asarray(x, dtype=np.complex128)
+    nd = np.sqrt(np.sum(np.abs(d) ** 2, axis=1))
+    nx = np.sqrt(np.sum(np.abs(x) ** 2, axis=1))
+    ip = np.abs(x @ d.conj().T)
+    den = nx[:, None] * nd[None, :]
+    return np.where(den > 0, ip / np.where(den > 0, den, 1.0), 0.0)
+
+
+def decision_bound(n_t):
+    """Bound beta on |c'_e - c_e| for every entry e, where c_e is the FP64
+    cosine of the unrounded inputs and c'_e the cosine the library ranks by
+    (binary16 rows, FP32 accumulation of exact products, FP32 norm).
+
+    * Rounding a row to binary16 after the exact power-of-two scaling (largest
+      |Re|, |Im| in [0.5, 1), so ||row|| >= 0.5): each normal component moves
+      by at most u16 = 2^-11 of itself, each subnormal one by at most 2^-25,
+      so ||delta row|| <= eps ||row|| with eps = u16 + 2^-24 sqrt(2 n_t).
+    * |<d', x'> - <d, x>| <= (2 eps + eps^2) ||d|| ||x|| (Cauchy-Schwarz).
+    * Re and Im of <d', x'> are sums of 2 n_t exact products in FP32: error
+      <= gamma ||d'|| ||x'|| each, gamma = m u32 / (1 - m u32), m = 2 n_t,
+      u32 = 2^-24; sqrt(2) gamma for the modulus.
+    * ||d'|| is within eps of ||d||, and its FP32 square within gamma.
+    * A few FP32 roundings of the score itself (|.|^2, 1/||d'||^2, product).
+    To first order beta = 3 eps + (sqrt(2) + 1/2) gamma; the value returned
+    rounds the constants up. If c_best - c_second > 2 beta the library must
+    pick the definition's entry; otherwise its pick must have c >= c_best -
+    2 beta."""
+    u16 = 2.0 ** -11
+    u32 = 2.0 ** -24
+    eps = u16 + u32 * np.sqrt(2.0 * n_t)
+    gam = 2.0 * n_t * u32 / (1.0 - 2.0 * n_t * u32)
+    return 3.0 * eps + 3.0 * eps ** 2 + 2.0 * gam + 4.0 * u32
+
+
+def judge_picks(best, dictionary, x):
+    """The library's picks `best` against the definition. Returns a dict:
+    identical (picks equal to the FP64 argmax), clear (pixels whose best and
+    second-best cosines differ by more than 2 beta), clear_identical,
+    valid (every pick within 2 beta of the best cosine, and identical where
+    the gap is clear), worst_shortfall (largest c_best - c_pick)."""
+    c = cosines(dictionary, x)
+    n_p, n_e = c.shape
+    rows = np.arange(n_p)
+    ref = np.argmax(c, axis=1)
+    cb = c[rows, ref]
+    if n_e > 1:
+        second = np.partition(c, n_e - 2, axis=1)[:, n_e - 2]
+    else:
+        second = np.full(n_p, -np.inf)
+    beta = decision_bound(np.shape(dictionary)[1])
+    clear = (cb - second) > 2.0 * beta
+    best = np.asarray(best)
+    same = best == ref
+    short = cb - c[rows, best]
+    valid = bool(np.all(same[clear]) and np.all(short <= 2.0 * beta))
+    return {"pixels": int(n_p), "identical": int(np.sum(same)), "clear": int(np.sum(clear)),
+            "clear_identical": int(np.sum(same & clear)), "valid": valid,
+            "worst_shortfall": float(np.max(short)) if n_p else 0.0, "bound_2beta": float(2.0 * beta)}
 
 
 def round_rows_half(a):

@@ -166,6 +166,10 @@ struct koma_ctx {
     // device blocks released by closed requests, reused by later ones (by size)
     std::multimap<size_t, void *> pool;
     size_t pool_bytes = 0;
+    // device bytes held by open requests (block capacities), and the largest
+    // held + pooled total seen since the context was created
+    size_t held_bytes = 0;
+    size_t mem_peak = 0;
     // scratch reused by koma_simulate (grow-only)
     DevMem s_ev, s_st, s_tiles, s_blocks, s_toff, s_boff, s_inl, s_def, s_snap, s_pa, s_pb, s_sig,
         s_mxy, s_mz, s_flags, s_vcount, s_mf, s_ph[kPhArrays];
@@ -243,8 +247,14 @@ static void dev_free(DevMem &m) {
 
 // Caching allocator for request buffers: hipFree can synchronise the whole
 // device, which would stall every other request in flight, so blocks of
-// closed requests are kept and reused (smallest fit within 2x), and only
-// released when an allocation fails or the context is destroyed.
+// closed requests are kept and reused (smallest fit within 2x). With an HBM
+// budget, the blocks held by open requests plus the cached ones never exceed
+// it: a reused block must fit beside the held ones, and cached blocks are
+// released (largest first) before an allocation that would not fit. Every
+// block is a multiple of 256 bytes; plan_footprint counts the same sizes, so
+// a request whose footprint fits beside the held bytes always gets its memory.
+static size_t pool_round(size_t bytes) { return (std::max<size_t>(bytes, 16) + 255) & ~(size_t)255; }
+
 static void pool_trim(koma_ctx *ctx) {
     for (auto &kv : ctx->pool) (void)hipFree(kv.second);
     ctx->pool.clear();
@@ -252,14 +262,27 @@ static void pool_trim(koma_ctx *ctx) {
 }
 
 static koma_status pool_get(koma_ctx *ctx, DevMem &m, size_t bytes) {
-    bytes = (std::max<size_t>(bytes, 16) + 255) & ~(size_t)255;
+    bytes = pool_round(bytes);
+    const size_t budget = ctx->cfg.hbm_budget;
     auto it = ctx->pool.lower_bound(bytes);
-    if (it != ctx->pool.end() && it->first <= 2 * bytes) {
+    if (it != ctx->pool.end() && it->first <= 2 * bytes && (!budget || ctx->held_bytes + it->first <= budget)) {
         m.p = it->second;
         m.cap = it->first;
         ctx->pool_bytes -= it->first;
         ctx->pool.erase(it);
+        ctx->held_bytes += m.cap;
         return KOMA_OK;
+    }
+    if (budget) {
+        if (ctx->held_bytes + bytes > budget)
+            return fail(ctx, KOMA_E_BUDGET, "device memory of open requests would exceed hbm_budget (%zu + %zu > %zu)",
+                        ctx->held_bytes, bytes, budget);
+        while (!ctx->pool.empty() && ctx->held_bytes + ctx->pool_bytes + bytes > budget) {
+            auto last = std::prev(ctx->pool.end());
+            (void)hipFree(last->second);
+            ctx->pool_bytes -= last->first;
+            ctx->pool.erase(last);
+        }
     }
     hipError_t e = hipMalloc(&m.p, bytes);
     if (e == hipErrorOutOfMemory && !ctx->pool.empty()) {
@@ -273,6 +296,8 @@ static koma_status pool_get(koma_ctx *ctx, DevMem &m, size_t bytes) {
         return fail(ctx, KOMA_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     }
     m.cap = bytes;
+    ctx->held_bytes += bytes;
+    ctx->mem_peak = std::max(ctx->mem_peak, ctx->held_bytes + ctx->pool_bytes);
     return KOMA_OK;
 }
 
@@ -280,6 +305,7 @@ static void pool_put(koma_ctx *ctx, DevMem &m) {
     if (m.p) {
         ctx->pool.insert({m.cap, m.p});
         ctx->pool_bytes += m.cap;
+        ctx->held_bytes -= m.cap;
     }
     m.p = nullptr;
     m.cap = 0;
@@ -1093,20 +1119,27 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     return KOMA_OK;
 }
 
+// Device bytes of a simulation of plan P: every buffer rounded up as the
+// request allocator rounds it (koma_req_open allocates exactly this list).
 static size_t plan_footprint(const Plan &P, bool fp64, bool with_state, bool with_phantom) {
     const size_t r = fp64 ? 8 : 4;
     const size_t n_pad = (size_t)P.n_tiles * kWave;
-    size_t b = 0;
-    b += P.ev.size() * sizeof(Event) + P.st.size() * sizeof(Stretch);
-    b += P.tiles.size() * sizeof(Tile) + P.blocks.size() * sizeof(Block);
-    b += (P.tile_off.size() + P.blk_off.size() + P.inl_k.size() + P.def_k.size()) * 4;
-    b += (size_t)P.n_slots * n_pad * 2 * r;                       // snapshots
     const size_t ns = (size_t)P.n_sig;
-    b += ns * (size_t)P.n_tiles * P.inl_k.size() * 2 * r;              // inline partials
-    b += ns * (size_t)P.blocks.size() * (size_t)P.max_cols * 16;       // cross-workgroup partials
-    b += ns * (size_t)P.n_groups * (size_t)P.n_adc * 16;               // signal
-    if (with_state) b += n_pad * 3 * r;
-    if (with_phantom) b += (size_t)P.n_spins * (7 + (P.moving ? 3 : 0) + 2 * (size_t)P.n_coils) * 4;
+    size_t b = 0;
+    b += pool_round(P.ev.size() * sizeof(Event)) + pool_round(P.st.size() * sizeof(Stretch));
+    b += pool_round(P.tiles.size() * sizeof(Tile)) + pool_round(P.blocks.size() * sizeof(Block));
+    b += pool_round(P.tile_off.size() * 4) + pool_round(P.blk_off.size() * 4);
+    b += pool_round(P.inl_k.size() * 4) + pool_round(P.def_k.size() * 4);
+    b += pool_round((size_t)P.n_slots * n_pad * 2 * r);                         // snapshots
+    b += pool_round(ns * (size_t)P.n_tiles * P.inl_k.size() * 2 * r);            // inline partials
+    b += pool_round(ns * (size_t)P.blocks.size() * (size_t)P.max_cols * 16);     // cross-workgroup partials
+    b += pool_round(ns * (size_t)P.n_groups * (size_t)P.n_adc * 16);             // signal
+    if (with_state) b += pool_round(n_pad * 2 * r) + pool_round(n_pad * r);
+    if (with_phantom) {
+        const size_t arr = pool_round((size_t)P.n_spins * 4);
+        b += arr * (7 + (P.moving ? 3 : 0)) + 2 * pool_round((size_t)P.n_spins * (size_t)P.n_coils * 4) *
+                                                   (P.n_coils > 0 ? 1 : 0);
+    }
     return b;
 }
 
@@ -1385,6 +1418,14 @@ koma_status koma_footprint(const koma_phantom *ph, const koma_sequence *seq, con
     Plan P;
     if ((st = build_plan(&tmp, c, 2.6752218744e8, ph, seq, P)) != KOMA_OK) return st;
     *bytes = plan_footprint(P, c.precision == KOMA_FP64, true, true);
+    return KOMA_OK;
+}
+
+koma_status koma_ctx_mem(const koma_ctx *ctx, size_t *held, size_t *cached, size_t *peak) {
+    if (!ctx) return KOMA_E_ARG;
+    if (held) *held = ctx->held_bytes;
+    if (cached) *cached = ctx->pool_bytes;
+    if (peak) *peak = ctx->mem_peak;
     return KOMA_OK;
 }
 
@@ -1902,6 +1943,12 @@ static void fill_info(const Plan &P, koma_req_info *info) {
     info->n_chunks = (int64_t)P.chunks.size();
     info->events_done = 0;
     info->footprint = 0;
+    info->n_ends = 0;
+    info->n_rf_in_runs = 0;
+    for (const Event &e : P.ev) {
+        if (e.kind == EV_END) ++info->n_ends;
+        if (e.kind == EV_RF && e.count > 1) info->n_rf_in_runs += e.count;
+    }
 }
 
 koma_status koma_req_info_get(const koma_req *q, koma_req_info *info) {

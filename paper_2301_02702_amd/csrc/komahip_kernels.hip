@@ -32,8 +32,9 @@
 //   k_reduce fixed-order FP64 sum of per-wavefront / per-workgroup partials.
 //   k_export state to the caller's (Mx, My, Mz) layout.
 //
-// No atomics anywhere: every sum has a fixed order, so results are bitwise
-// reproducible for a fixed launch configuration.
+// No atomics in any sum: every sum has a fixed order, so results are bitwise
+// reproducible for a fixed launch configuration. (The one atomic is the OR of
+// a device-resident phantom's validation bits into a status word.)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

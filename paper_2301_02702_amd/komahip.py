@@ -58,7 +58,7 @@ class koma_req_info(ctypes.Structure):
     _fields_ = [(k, c_int64) for k in (
         "n_spins", "n_tiles", "n_groups", "n_adc", "n_events", "n_rf", "n_rf_events", "n_runs", "n_inline_adc",
         "n_deferred_adc", "n_stretches", "n_families", "n_snapshots", "n_blocks", "spins_per_lane", "n_chunks",
-        "events_done")] + [("footprint", c_size_t)]
+        "events_done")] + [("footprint", c_size_t), ("n_ends", c_int64), ("n_rf_in_runs", c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -112,6 +112,7 @@ EXPORTS = {
     "koma_plan_info": (c_int, [POINTER(koma_scanner), POINTER(koma_phantom), POINTER(koma_sequence),
                                POINTER(koma_config), POINTER(koma_req_info)]),
     "koma_ctx_profile": (c_int, [c_void_p, c_int]),
+    "koma_ctx_mem": (c_int, [c_void_p, POINTER(c_size_t), POINTER(c_size_t), POINTER(c_size_t)]),
     "koma_ctx_kernel_stats": (c_int, [c_void_p, c_int, POINTER(c_double), POINTER(c_int64),
                                       POINTER(c_int64)]),
     "koma_discretize": (c_int, [POINTER(koma_block), c_int64, c_double, c_double, POINTER(c_int64),
@@ -480,6 +481,13 @@ class Context:
 
     def open(self, scanner, phantom, seq, where: str = "host") -> "Request":
         return Request(self, scanner, phantom, seq, where)
+
+    def mem(self) -> dict:
+        """koma_ctx_mem: device bytes held by open requests, cached for reuse,
+        and the peak of their sum."""
+        h, c, p = c_size_t(0), c_size_t(0), c_size_t(0)
+        _check(lib().koma_ctx_mem(self.h, ctypes.byref(h), ctypes.byref(c), ctypes.byref(p)), self.h)
+        return {"held": h.value, "cached": c.value, "peak": p.value}
 
     def profile(self, on: bool = True):
         _check(lib().koma_ctx_profile(self.h, 1 if on else 0), self.h)

@@ -1,15 +1,23 @@
 """Continuous-batching server over the komahip request API.
 
 Requests (scanner, phantom, sequence) arrive over time. The scheduler admits
-queued requests in arrival order while a slot is free and the request's
-device footprint fits the HBM budget; an admitted request copies its phantom
-to the device once and keeps phantom and spin state there, and is advanced
-by chunks of events on a HIP stream of its own, so chunks of different
-requests run on the GPU at the same time. A finished request returns its
-signal, releases its device memory and frees its slot for the queue.
-Latency is measured from arrival to the signal in host memory.
+queued requests while a slot is free and the request's device footprint fits
+the HBM budget beside the bytes the open requests hold; an admitted request
+copies its phantom to the device once and keeps phantom and spin state
+there, and is advanced by chunks of events on a HIP stream of its own, so
+chunks of different requests run on the GPU at the same time. A finished
+request returns its signal, releases its device memory and frees its slot
+for the queue. Latency is measured from arrival to the signal in host
+memory.
 
-All device work is in the HIP library; this module only orders calls.
+Admission order: ``fifo`` takes the queue in arrival order (the head waits
+until it fits); ``small_first`` takes the queued request with the least work
+(spins x intervals) that fits, unless the oldest one has waited longer than
+``max_wait`` seconds, which then goes first (no starvation).
+
+All device work is in the HIP library; this module only orders calls. The
+library also enforces the budget on the memory it really holds (cached
+blocks of closed requests included).
 """
 from __future__ import annotations
 
@@ -50,17 +58,21 @@ class Server:
 
     def __init__(self, device: int = 0, precision: str = "mixed", max_slots: int = 8,
                  hbm_budget: Optional[int] = None, chunk_events: int = 1024, keep_signal: bool = False,
-                 backend=None):
+                 backend=None, policy: str = "fifo", max_wait: float = 0.05):
         """``backend`` = (context, stream factory, event factory) replaces the
         HIP context and torch streams/events (used to test the scheduler on the CPU)."""
         self.max_slots = int(max_slots)
         self.chunk_events = int(chunk_events)
+        if policy not in ("fifo", "small_first"):
+            raise ValueError(policy)
+        self.policy = policy
+        self.max_wait = float(max_wait)
         if backend is None:
             import torch
-            self.ctx = K.Context(device, precision, chunk_events=int(chunk_events))
             if hbm_budget is None:
                 free, _ = torch.cuda.mem_get_info(device)
                 hbm_budget = int(0.8 * free)
+            self.ctx = K.Context(device, precision, chunk_events=int(chunk_events), hbm_budget=int(hbm_budget))
             # streams at the default priority
             self.streams = [torch.cuda.Stream(device=device) for _ in range(self.max_slots)]
             self.new_event = torch.cuda.Event
@@ -72,6 +84,23 @@ class Server:
         self.peak_used = 0  # largest sum of admitted footprints seen
         self.peak_active = 0
         self.admit_order = []
+
+    def _held(self, used: int) -> int:
+        """Device bytes the open requests hold: the library's count where the
+        context reports one, else the sum of admitted footprints."""
+        mem = getattr(self.ctx, "mem", None)
+        return max(used, mem()["held"]) if mem else used
+
+    def _next(self, queue, now: float, used: int):
+        """Index in ``queue`` of the request to admit now, or None."""
+        held = self._held(used)
+        if self.policy == "fifo" or now - queue[0].arrival > self.max_wait:
+            return 0 if held + queue[0].footprint <= self.hbm_budget else None
+        best = None
+        for i, j in enumerate(queue):
+            if held + j.footprint <= self.hbm_budget and (best is None or j.spin_steps < queue[best].spin_steps):
+                best = i
+        return best
 
     def close(self):
         self.ctx.close()
@@ -97,18 +126,19 @@ class Server:
             now = time.perf_counter() - t0
             while pending and (not realtime or pending[0].arrival <= now):
                 queue.append(pending.popleft())
-            # admission: arrival order, free slot, footprint within budget
+            # requests that can never fit are rejected on arrival
+            for job in [j for j in queue if j.footprint > self.hbm_budget]:
+                queue.remove(job)
+                job.status, job.error = "rejected", "footprint exceeds the HBM budget"
+                job.finish = time.perf_counter() - t0
+                done.append(job)
+            # admission: free slot, footprint within budget, in policy order
             while queue and len(active) < self.max_slots:
-                job = queue[0]
-                if job.footprint > self.hbm_budget:
-                    queue.popleft()
-                    job.status, job.error = "rejected", "footprint exceeds the HBM budget"
-                    job.finish = time.perf_counter() - t0
-                    done.append(job)
-                    continue
-                if used + job.footprint > self.hbm_budget:
+                k = self._next(queue, now, used)
+                if k is None:
                     break
-                queue.popleft()
+                job = queue[k]
+                del queue[k]
                 job.admit = time.perf_counter() - t0
                 try:
                     req = self.ctx.open(job.scanner, job.phantom, job.seq, "host")
@@ -185,58 +215,80 @@ def make_jobs(n: int, seed: int, scale: float, lo: float = 3.0, hi: float = 6.0,
     return jobs[:warm], jobs[warm:]
 
 
-def benchmark(ctx_device: int = 0, n_requests: int = 200, rho: float = 0.8, seed: int = 3000,
-              max_slots: int = 8, log=None) -> dict:
-    """Serving figures: the service capacity of FIFO one-at-a-time, then the
-    same Poisson stream at load ``rho`` of that capacity served FIFO and with
-    continuous batching."""
+def _reset(jobs, arrivals=None):
+    for k, j in enumerate(jobs):
+        if arrivals is not None:
+            j.arrival = arrivals[k]
+        j.admit = j.finish = float("nan")
+        j.status = "queued"
+        j.error = ""
+
+
+def benchmark(ctx_device: int = 0, n_requests: int = 1000, n_warm: int = 50, rhos=(0.5, 0.8, 0.95),
+              seed: int = 3000, max_slots: int = 8, forced_budget: int = 256 << 20, log=None) -> dict:
+    """Serving figures on one seeded stream of ``n_requests`` requests (after
+    ``n_warm`` warm-up requests): the saturated capacity mu (requests/s with
+    every request queued at t = 0) of the batched server and of FIFO one at a
+    time; then Poisson arrivals at rate rho * mu(batched) for every rho,
+    served by continuous batching (arrival order and small-first) and by FIFO;
+    and the batched server at rho = 0.8 under a forced HBM budget."""
     import torch
-    srv1 = Server(ctx_device, "mixed", max_slots=1)
-    warm, jobs = make_jobs(n_requests, seed, 1.0, warm=10)  # unit-mean gaps, scaled below
+    warm, jobs = make_jobs(n_requests, seed, 1.0, warm=n_warm)  # unit-mean gaps, scaled below
+    unit = [j.arrival - jobs[0].arrival for j in jobs]
+    servers = {"batched": Server(ctx_device, "mixed", max_slots=max_slots),
+               "small_first": Server(ctx_device, "mixed", max_slots=max_slots, policy="small_first"),
+               "fifo": Server(ctx_device, "mixed", max_slots=1)}
     for j in warm + jobs:
-        srv1.prepare(j)
-    srv1.run(warm, realtime=False)
-    # saturated FIFO capacity: everything queued at t = 0
-    arrivals = [j.arrival for j in jobs]
-    t = time.perf_counter()
-    srv1.run(jobs, realtime=False)
-    torch.cuda.synchronize()
-    t_fifo_sat = time.perf_counter() - t
-    mu = len(jobs) / t_fifo_sat  # requests/s one at a time
-    gap = 1.0 / (rho * mu)
-    t_first = arrivals[0]
-    for j, a in zip(jobs, arrivals):
-        j.arrival = (a - t_first) * gap
-        j.admit = j.finish = float("nan")
-        j.status = "queued"
-    out = {"requests": len(jobs), "rho_of_fifo_capacity": rho, "fifo_capacity_req_s": mu,
-           "arrival_rate_req_s": rho * mu, "max_slots": max_slots}
-    t = time.perf_counter()
-    res = srv1.run(jobs, realtime=True)
-    out["fifo"] = summarize(res, time.perf_counter() - t)
-    srv1.close()
-    for j in jobs:
-        j.admit = j.finish = float("nan")
-        j.status = "queued"
-    srv = Server(ctx_device, "mixed", max_slots=max_slots)
-    srv.run(warm, realtime=False)
+        servers["fifo"].prepare(j)
+    for srv in servers.values():
+        _reset(warm, [0.0] * len(warm))
+        srv.run(warm, realtime=False)
+    out = {"requests": len(jobs), "warmup_requests": len(warm), "max_slots": max_slots,
+           "spins_per_request": {"min": int(min(j.phantom.n for j in jobs)),
+                                 "median": float(np.median([j.phantom.n for j in jobs])),
+                                 "max": int(max(j.phantom.n for j in jobs))}}
+    cap = {}
+    for name in ("batched", "fifo"):
+        _reset(jobs, [0.0] * len(jobs))
+        t = time.perf_counter()
+        res = servers[name].run(jobs, realtime=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        cap[name] = len(jobs) / wall
+        out[f"saturated_{name}"] = summarize(res, wall)
+    mu = cap["batched"]
+    out["mu_req_s"] = {"batched": mu, "fifo": cap["fifo"]}
+    loads = {}
+    for rho in rhos:
+        r = {"rho": rho, "arrival_rate_req_s": rho * mu}
+        for name in ("batched", "small_first", "fifo"):
+            _reset(jobs, [u / (rho * mu) for u in unit])
+            t = time.perf_counter()
+            res = servers[name].run(jobs, realtime=True)
+            r[name] = summarize(res, time.perf_counter() - t)
+        loads[str(rho)] = r
+        if log:
+            log(f"[serve] rho {rho}: batched p50/p99 {r['batched']['p50_ms']:.2f}/{r['batched']['p99_ms']:.2f} ms, "
+                f"small-first {r['small_first']['p50_ms']:.2f}/{r['small_first']['p99_ms']:.2f}, "
+                f"FIFO {r['fifo']['p50_ms']:.2f}/{r['fifo']['p99_ms']:.2f}")
+    out["loads"] = loads
+    for srv in servers.values():
+        srv.close()
+    # a forced budget: requests queue for memory; those larger than it are rejected
+    srv = Server(ctx_device, "mixed", max_slots=max_slots, hbm_budget=forced_budget)
+    _reset(jobs, [u / (0.8 * mu) for u in unit])
     t = time.perf_counter()
     res = srv.run(jobs, realtime=True)
-    out["batched"] = summarize(res, time.perf_counter() - t)
-    # saturated throughput of the batched server (everything queued at t = 0)
-    for j in jobs:
-        j.arrival = 0.0
-        j.admit = j.finish = float("nan")
-        j.status = "queued"
-    t = time.perf_counter()
-    res = srv.run(jobs, realtime=False)
-    out["batched_saturated"] = summarize(res, time.perf_counter() - t)
+    fb = summarize(res, time.perf_counter() - t)
+    fb.update(budget_bytes=forced_budget, rho=0.8, peak_footprint_sum=srv.peak_used,
+              peak_device_bytes=srv.ctx.mem()["peak"],
+              rejected=int(sum(j.status == "rejected" for j in res)))
+    out["forced_budget"] = fb
     srv.close()
-    out["p50_ms"] = out["batched"]["p50_ms"]
-    out["p99_ms"] = out["batched"]["p99_ms"]
+    out["p50_ms"] = loads["0.8"]["batched"]["p50_ms"] if "0.8" in loads else None
+    out["p99_ms"] = loads["0.8"]["batched"]["p99_ms"] if "0.8" in loads else None
     if log:
-        log(f"[serve] FIFO capacity {mu:.1f} req/s; at rho={rho}: FIFO p50/p99 "
-            f"{out['fifo']['p50_ms']:.2f}/{out['fifo']['p99_ms']:.2f} ms, batched "
-            f"{out['p50_ms']:.2f}/{out['p99_ms']:.2f} ms; saturated batched "
-            f"{out['batched_saturated']['throughput_req_s']:.1f} req/s")
+        log(f"[serve] capacity batched {mu:.1f} req/s, FIFO {cap['fifo']:.1f}; forced {forced_budget >> 20} MB "
+            f"budget: p50/p99 {fb['p50_ms']:.2f}/{fb['p99_ms']:.2f} ms, {fb['rejected']} rejected, "
+            f"peak device bytes {fb['peak_device_bytes']}")
     return out

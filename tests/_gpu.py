@@ -1,10 +1,20 @@
-"""Helpers shared by the GPU tests (parity metrics, cached oracle runs)."""
+"""Helpers shared by the GPU tests (parity metrics, cached oracle runs).
+
+Parity bar: per row of the
+last axis (a signal group's samples, per receive coil), normalised by that
+row's max |oracle|,
+* FP64 form: NRMSE <= 1e-10 and every sample within 1e-10;
+* mixed form: NRMSE <= 1e-4 and every sample within 1e-4.
+Rows whose oracle signal is exactly zero must be exactly zero.
+"""
 import functools
 import sys
 
 import numpy as np
 
 from paper_2301_02702_amd import workloads as W
+
+TOL = {"fp64": 1e-10, "mixed": 1e-4}
 
 
 def nrmse(got, ref):
@@ -18,6 +28,34 @@ def nrmse(got, ref):
 
 def mae(got, ref):
     return float(np.mean(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def errors(got, ref):
+    """(worst NRMSE, worst max-sample error, rows with zero reference exactly
+    zero) over the rows of the last axis, each normalised by its row's
+    max |ref|."""
+    r = np.asarray(ref).reshape(-1, np.shape(ref)[-1])
+    g = np.asarray(got).reshape(r.shape)
+    scale = np.max(np.abs(r), axis=1)
+    nz = scale > 0
+    d = np.abs(g - r)
+    if not nz.any():
+        return 0.0, 0.0, bool(np.all(g == 0))
+    e_rms = np.sqrt(np.mean(d[nz] ** 2, axis=1)) / scale[nz]
+    e_max = np.max(d[nz], axis=1) / scale[nz]
+    return float(np.max(e_rms)), float(np.max(e_max)), bool(np.all(g[~nz] == 0))
+
+
+def check(got, ref, prec, what, tol=None):
+    """Assert the parity bar of `prec` (or `tol` for both measures); print
+    the measured values; return (NRMSE, max-sample error)."""
+    tol = TOL[prec] if tol is None else tol
+    assert np.shape(got) == np.shape(ref), (what, np.shape(got), np.shape(ref))
+    e, m, zero_ok = errors(got, ref)
+    say(f"[{what}] {prec}: NRMSE {e:.3e}, max sample error {m:.3e} (of max|ref|, bar {tol:.0e})")
+    assert zero_ok, (what, prec, "rows with a zero reference must be zero")
+    assert e <= tol and m <= tol, (what, prec, e, m)
+    return e, m
 
 
 def say(*a):

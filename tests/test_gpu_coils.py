@@ -3,18 +3,16 @@
 Coil c's signal is the sum over a group's spins of sens_c * Mxy. The
 sample-parallel kernel folds sens_c into each spin's anchor (one grid plane
 per coil); the spin-sequential kernel weights every inline sample per coil.
-Tolerances as in the static parity tests: FP64 1e-9, mixed 1e-4 NRMSE, per
-coil and group.
+Parity bar as in the static parity tests (tests/_gpu.py): NRMSE and the
+largest sample error <= 1e-10 (FP64) and 1e-4 (mixed), per coil and group.
 """
 import numpy as np
 import pytest
 
 from paper_2301_02702_amd import workloads as W
-from tests._gpu import case, nrmse, say
+from tests._gpu import TOL, case, check, nrmse, say
 
 pytestmark = pytest.mark.gpu
-
-TOL = {"fp64": 1e-9, "mixed": 1e-4}
 
 
 @pytest.fixture(scope="module")
@@ -64,9 +62,7 @@ def test_coils_match_oracle(ctx, prec, key, n_coils, moving):
     ctx.set_config(prec)
     got = ctx.simulate(sc, ph, seq)
     assert got.shape == ref.shape == (n_coils, ph.n_groups, seq.n_adc)
-    e = worst(got, ref)
-    say(f"[coils] {key} x {n_coils} coils{' moving' if moving else ''} {prec}: worst NRMSE {e:.3e}")
-    assert e <= TOL[prec]
+    check(got, ref, prec, f"coils {key} x {n_coils}{' moving' if moving else ''}")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])

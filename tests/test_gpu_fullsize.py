@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from paper_2301_02702_amd import workloads as W
-from tests._gpu import nrmse, say
+from tests._gpu import check, say
 
 pytestmark = pytest.mark.gpu
 
@@ -42,16 +42,14 @@ def test_mrf_full_batch_sampled_entries(K):
     entries = np.sort(rng.choice(ph.n_groups, 48, replace=False))
     ctx = K.Context(0, "mixed")
     try:
-        for prec, tol in (("fp64", 1e-12), ("mixed", 1e-4)):
+        ref = np.stack([oracle.simulate(sc, ph.groups(int(e), int(e) + 1), seq, mode=oracle.MODE_BLOCK)[0, 0]
+                        for e in entries])
+        for prec in ("fp64", "mixed"):
             say(f"[full] mrf {prec}")
             ctx.set_config(prec)
             got = run_device(K, ctx, sc, ph, seq)
-            worst = 0.0
-            for e in entries:
-                ref = oracle.simulate(sc, ph.groups(int(e), int(e) + 1), seq, mode=oracle.MODE_BLOCK)[0]
-                worst = max(worst, nrmse(got[e], ref))
-            say(f"[full] mrf {prec}: worst per-entry NRMSE over {len(entries)} sampled entries {worst:.3e}")
-            assert worst <= tol
+            # per entry: NRMSE and largest sample error, normalised by the entry's max|oracle|
+            check(got[entries], ref, prec, f"full mrf, {len(entries)} sampled entries")
     finally:
         ctx.close()
 
@@ -71,14 +69,12 @@ def test_seepi_full_linearity_against_oracle_subset(K):
         say("[full] seepi fp64 without the subset")
         rest64 = run_device(K, ctx, sc, rest, seq)[0]
         ref = oracle.simulate(sc, ph.subset(idx), seq, mode=oracle.MODE_BLOCK)[0]
-        e = nrmse(full64 - rest64, ref)
-        say(f"[full] seepi: (full - rest) vs oracle(subset) NRMSE {e:.3e}")
-        assert e <= 1e-8
+        # the difference cancels 2,500x in magnitude, so FP64 rounding of the
+        # full sums (~1e-16 relative) shows at ~3e-13 here
+        check(full64 - rest64, ref, "fp64", "full seepi, (full - rest) vs oracle(subset)")
         ctx.set_config("mixed")
         say("[full] seepi mixed full")
         mixed = run_device(K, ctx, sc, ph, seq)[0]
-        e2 = nrmse(mixed, full64)
-        say(f"[full] seepi: mixed vs fp64 at full size NRMSE {e2:.3e}")
-        assert e2 <= 1e-4
+        check(mixed, full64, "mixed", "full seepi, mixed vs fp64 at full size")
     finally:
         ctx.close()

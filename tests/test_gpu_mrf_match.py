@@ -1,13 +1,15 @@
 """GPU parity of MRF dictionary matching (MFMA contraction + fused argmax)
-against the reference matching on the same binary16 operands.
+against the definition: the maximum normalised dot product in FP64 on the
+caller's FP32 dictionary and fingerprints (oracle/mrf_match.py, ``match``).
 
-The decision is an argmax taken in floating point, so both sides take it on
-the same rounded operands (the library's binary16 rows); they then differ
-only in the accumulation (FP32 on the matrix cores, FP64 in the reference).
-Where the reference's best and second-best scores are further apart than a
-bound on that accumulation error the indices must be identical; inside the
-bound the library's pick must score within it of the best. The projection
-<d, x>/||d|| is compared to 1e-5 relative.
+The library takes the argmax on binary16 rows with FP32 accumulation, so
+its cosine of each entry lies within beta (``decision_bound``, derived in
+its docstring) of the definition's. Where the definition's best and
+second-best cosines are more than 2 beta apart the picks must be identical;
+elsewhere the library's pick must have a cosine within 2 beta of the best.
+The projection <d, x>/||d|| of identical picks must agree within the same
+rounding (3.1 eps ||x||). ``match_rounded`` (the definition on the
+library's own binary16 operands) is printed as a diagnostic only.
 """
 import numpy as np
 import pytest
@@ -16,8 +18,6 @@ from paper_2301_02702_amd import workloads as W
 from tests._gpu import say
 
 pytestmark = pytest.mark.gpu
-
-GAP = 1e-4  # relative score bound of the FP32 accumulation (kp <= 2048 terms of binary16 products)
 
 
 @pytest.fixture(scope="module")
@@ -36,18 +36,18 @@ def ctx(K):
 
 def check(best, proj, d, x, tag):
     from oracle import mrf_match as M
-    rb, rp, rs, scores = M.match_rounded(d, x)
-    srt = np.sort(scores, axis=1)
-    second = srt[:, -2] if scores.shape[1] > 1 else np.zeros(len(rb))
-    clear = (rs - second) > GAP * rs
-    assert np.array_equal(best[clear], rb[clear]), (tag, np.nonzero(best[clear] != rb[clear])[0][:5])
-    rows = np.arange(len(rb))
-    near = ~clear
-    if np.any(near):
-        assert np.all(scores[rows[near], best[near]] >= rs[near] * (1 - GAP)), tag
+    j = M.judge_picks(best, d, x)
+    rb, rp, _ = M.match(d, x)
+    rr = M.match_rounded(d, x)[0]
+    say(f"[mrf match] {tag}: {j['identical']}/{j['pixels']} picks equal to the definition's, "
+        f"{j['clear_identical']}/{j['clear']} where the gap exceeds 2 beta = {j['bound_2beta']:.2e}; "
+        f"worst cosine shortfall {j['worst_shortfall']:.2e}; "
+        f"{int(np.sum(best == rr))} equal to the argmax on the library's binary16 operands")
+    assert j["valid"], (tag, j)
     same = best == rb
-    assert np.allclose(proj[same], rp[same], rtol=1e-5, atol=1e-6 * np.max(np.abs(rp))), tag
-    say(f"[mrf match] {tag}: {int(np.sum(same))}/{len(rb)} identical picks, {int(np.sum(near))} within the bound")
+    eps = 2.0 ** -11 + 2.0 ** -24 * np.sqrt(2.0 * d.shape[1])
+    nx = np.linalg.norm(np.asarray(x, dtype=np.complex128), axis=1)
+    assert np.all(np.abs(proj[same] - rp[same]) <= 3.1 * eps * nx[same] + 1e-300), tag
 
 
 def rnd(rng, shape):

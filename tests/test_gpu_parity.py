@@ -1,22 +1,20 @@
 """GPU parity of the HIP path (through the C-ABI) against the FP64 CPU oracle.
 
-Tolerances:
-* KOMA_FP64: NRMSE <= 1e-9 of max|oracle|. Differences come from rounding
-  order, FMA contraction and the linear model of evenly spaced samples,
-  whose deviation from the exact moments is bounded at 2e-9 cycles/m and
-  1e-12 s (phase error <= ~1e-9 rad for |x| <= 0.1 m, |f| <= 100 Hz).
-* KOMA_MIXED: NRMSE <= 1e-4 of max|oracle| (the target accuracy), with the
-  measured value printed; per dictionary entry for the MRF batch.
+Tolerances (tests/_gpu.py, per signal row, normalised by its max|oracle|):
+* KOMA_FP64: NRMSE and the largest sample error <= 1e-10. Differences come
+  from rounding order, FMA contraction and the linear model of evenly spaced
+  samples (measured ~1e-13).
+* KOMA_MIXED: NRMSE and the largest sample error <= 1e-4 (the target
+  accuracy), with the measured values printed; per dictionary entry for the
+  MRF batch.
 """
 import numpy as np
 import pytest
 
 from paper_2301_02702_amd import workloads as W
-from tests._gpu import case, mae, nrmse, oracle_cached, say
+from tests._gpu import TOL, case, check, errors, mae, nrmse, oracle_cached, say
 
 pytestmark = pytest.mark.gpu
-
-TOL = {"fp64": 1e-9, "mixed": 1e-4}
 
 
 @pytest.fixture(scope="module")
@@ -47,10 +45,9 @@ def test_parity_against_oracle(ctx, prec, key):
     got = run(ctx, prec, key)
     assert got.shape == ref.shape
     e = nrmse(got, ref)
-    e_max = float(np.max(e))
-    say(f"[parity] {key} {prec}: NRMSE max {e_max:.3e} (median {float(np.median(e)):.3e}), "
+    say(f"[parity] {key} {prec}: NRMSE median {float(np.median(e)):.3e}, "
         f"MAE {mae(got.ravel(), ref.ravel()):.3e}")
-    assert e_max <= TOL[prec]
+    check(got, ref, prec, f"parity {key}")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -60,9 +57,7 @@ def test_parity_epi_full_size(ctx, prec):
     say(f"[parity] epi full {prec}")
     ref = oracle_cached("epi")
     got = run(ctx, prec, "epi")
-    e = nrmse(got[0], ref[0])
-    say(f"[parity] epi full {prec}: NRMSE {e:.3e}")
-    assert e <= TOL[prec]
+    check(got, ref, prec, "parity epi full")
 
 
 def test_closed_forms_on_gpu(ctx):
@@ -108,7 +103,7 @@ def test_magnitude_preserved_on_gpu(ctx):
         ctx.set_config(prec)
         _, m = ctx.simulate(W.Scanner(), ph, seq, want_m=True)
         err = np.max(np.abs(np.linalg.norm(m, axis=1) / ph.pd - 1))
-        say(f"[|M|] {prec}: max relative drift {err:.3e} over 20000 intervals")
+        say(f"[|M|] {prec}: max relative drift {err:.3e} over 20000 intervals (bar {tol:.0e})")
         assert err < tol
 
 
@@ -131,9 +126,7 @@ def test_random_sequences_edge_cases(ctx, prec):
         for dm, eng in ((-1, 0), (0, 0), (3, 0), (0, 1)):  # short stretches on both sample engines
             ctx.set_config(prec, defer_min_adc=dm, sample_engine=eng)
             got = ctx.simulate(sc, ph, seq)
-            e = np.max(nrmse(got[np.abs(ref).max(axis=1) > 0], ref[np.abs(ref).max(axis=1) > 0]))
-            assert e <= TOL[prec], (trial, dm, eng, e)
-            assert np.all(got[np.abs(ref).max(axis=1) == 0] == 0)
+            check(got, ref, prec, f"random grid {trial} defer {dm} engine {eng}")
     ctx.set_config(prec, defer_min_adc=32, sample_engine=0)
 
 
@@ -176,13 +169,11 @@ def test_runs_of_identical_excitation_intervals(ctx, prec):
     for ph in cases:
         ref = oracle.simulate(sc, ph, seq)
         ctx.set_config(prec)
-        e = float(np.max(nrmse(ctx.simulate(sc, ph, seq), ref)))
-        assert e <= TOL[prec], (ph.name, e)
+        check(ctx.simulate(sc, ph, seq), ref, prec, f"excitation runs {ph.name}")
     mov_seq = _pulse_runs_sequence(with_gradient_rf=True)
     ph = W.with_velocity(W.random_spins(rng, 150), v=(0.05, -0.1, 0.2), spread=0.05)
     ref = oracle.simulate(sc, ph, mov_seq)
-    e = float(np.max(nrmse(ctx.simulate(sc, ph, mov_seq), ref)))
-    assert e <= TOL[prec], ("moving", e)
+    check(ctx.simulate(sc, ph, mov_seq), ref, prec, "excitation runs, moving spins")
     say(f"[parity] excitation runs {prec}: ok")
 
 
@@ -204,8 +195,8 @@ def test_stretch_families_share_operands(ctx, prec):
             for eng in (0, 1):
                 ctx.set_config(prec, spins_per_lane=spl, sample_engine=eng, stretch_max=smax)
                 got = ctx.simulate(sc, ph, seq)
-                e = float(np.max(nrmse(got, ref)))
-                assert e <= TOL[prec], (smax, spl, eng, e)
+                e, m, z = errors(got, ref)
+                assert z and e <= TOL[prec] and m <= TOL[prec], (smax, spl, eng, e, m)
     say(f"[parity] stretch families {prec}: ok")
     ctx.set_config(prec, spins_per_lane=0, sample_engine=0, stretch_max=128)
 
@@ -240,12 +231,12 @@ def test_random_readouts_every_engine_and_shape(ctx):
                 smax = int(rng.choice([128, 37, 16, 5]))
                 ctx.set_config(prec, sample_engine=eng, spins_per_lane=spl, stretch_max=smax)
                 got = ctx.simulate(sc, ph, seq).reshape(-1, ref.shape[-1])
-                e = float(np.max(nrmse(got[mask], r2[mask]))) if mask.any() else 0.0
-                assert np.all(got[~mask] == 0)
-                assert e <= TOL[prec], (trial, n, prec, eng, spl, smax, e)
-                worst[prec] = max(worst[prec], e)
+                e, m, z = errors(got, r2)
+                assert z, (trial, n, prec, eng)
+                assert e <= TOL[prec] and m <= TOL[prec], (trial, n, prec, eng, spl, smax, e, m)
+                worst[prec] = max(worst[prec], m)
     ctx.set_config("mixed", sample_engine=0, spins_per_lane=0, stretch_max=128)
-    say(f"[parity] random readouts: worst NRMSE fp64 {worst['fp64']:.2e}, mixed {worst['mixed']:.2e}")
+    say(f"[parity] random readouts: worst max sample error fp64 {worst['fp64']:.2e}, mixed {worst['mixed']:.2e}")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -261,7 +252,8 @@ def test_launch_shape_invariance_and_determinism(ctx, prec):
             a = ctx.simulate(sc, ph, seq)
             b = ctx.simulate(sc, ph, seq)
             assert np.array_equal(a, b)
-            assert nrmse(a[0], ref[0]) <= TOL[prec]
+            e, m, _ = errors(a, ref)
+            assert e <= TOL[prec] and m <= TOL[prec], (spl, smax, e, m)
             outs.append(a)
     ctx.set_config(prec, spins_per_lane=0, stretch_max=128)
 
@@ -338,6 +330,8 @@ def test_precomputed_zero_gradient_rotation_matches_general_path(ctx):
         say(f"[rot] {prec}: fast vs per-spin path NRMSE {e:.3e}; vs oracle "
             f"{float(np.max(nrmse(fast, ref))):.3e} / {float(np.max(nrmse(slow, ref))):.3e}")
         assert e <= tol
+        check(fast, ref, prec, "zero-gradient rotation, precomputed")
+        check(slow, ref, prec, "zero-gradient rotation, per-spin spinor")
 
 
 def test_magnitude_preserved_by_repeated_hard_pulses(ctx):
@@ -373,9 +367,8 @@ def test_minimal_grid_on_gpu_matches_raster_oracle(ctx, K, prec, which):
     ref = oracle_cached(which)
     ctx.set_config(prec)
     got = ctx.simulate(sc, ph, m)
-    e = float(np.max(nrmse(got, ref)))
-    say(f"[minimal grid] {which} {prec}: {m.n_int} vs {ref_seq.n_int} intervals, NRMSE vs raster oracle {e:.3e}")
-    assert e <= TOL[prec]
+    say(f"[minimal grid] {which} {prec}: {m.n_int} vs {ref_seq.n_int} intervals")
+    check(got, ref, prec, f"minimal grid {which} vs raster oracle")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -391,8 +384,6 @@ def test_sample_engines_agree(ctx, key, prec):
         sc, ph, seq = case(key)
         out[eng] = ctx.simulate(sc, ph, seq)
     ctx.set_config(prec, sample_engine=0)
-    e0 = float(np.max(nrmse(out[0], ref)))
-    e1 = float(np.max(nrmse(out[1], ref)))
-    e01 = float(np.max(nrmse(out[0], out[1])))
-    say(f"[engine] {key} {prec}: matrix cores {e0:.3e}, vector ALU {e1:.3e} vs oracle; between {e01:.3e}")
-    assert e0 <= TOL[prec] and e1 <= TOL[prec] and e01 <= TOL[prec]
+    check(out[0], ref, prec, f"engine {key} matrix cores")
+    check(out[1], ref, prec, f"engine {key} vector ALU")
+    check(out[0], out[1], prec, f"engine {key} matrix cores vs vector ALU")

@@ -1,10 +1,11 @@
-"""Continuous batching on the GPU: results do not depend on the mix,
-admission respects the HBM budget, a bad request fails alone."""
+"""Continuous batching on the GPU: every served result matches the FP64
+oracle and is the same alone and in the mix, admission respects the HBM
+budget, a bad request fails alone."""
 import numpy as np
 import pytest
 
 from paper_2301_02702_amd import workloads as W
-from tests._gpu import say
+from tests._gpu import check, say
 
 pytestmark = pytest.mark.gpu
 
@@ -28,9 +29,12 @@ def test_each_result_is_the_same_alone_and_in_the_mix(serve):
     done = srv.run(jobs, realtime=False)
     assert all(j.status == "done" for j in done)
     assert srv.peak_active > 1  # requests really overlapped
+    import oracle
     for j in done:
         alone = srv.ctx.simulate(j.scanner, j.phantom, j.seq)
         assert np.array_equal(j.signal, alone), j.tag
+        ref = oracle.simulate(j.scanner, j.phantom, j.seq, mode=oracle.MODE_BLOCK)
+        check(j.signal, ref, "mixed", f"served {j.tag} vs oracle")
     srv.close()
 
 
@@ -40,11 +44,18 @@ def test_admission_respects_a_small_hbm_budget(serve):
     jobs = [probe.prepare(j) for j in small_jobs(serve, 12, 3200)]
     probe.close()
     budget = int(max(j.footprint for j in jobs) * 1.5)
-    srv = serve.Server(0, "mixed", max_slots=8, hbm_budget=budget)
-    done = srv.run(jobs, realtime=False)
-    assert all(j.status == "done" for j in done)
-    assert srv.peak_used <= budget
-    srv.close()
+    for policy in ("fifo", "small_first"):
+        srv = serve.Server(0, "mixed", max_slots=8, hbm_budget=budget, policy=policy)
+        done = srv.run(jobs, realtime=False)
+        assert all(j.status == "done" for j in done)
+        mem = srv.ctx.mem()
+        say(f"[serving] {policy}: budget {budget}, peak footprint sum {srv.peak_used}, "
+            f"peak device bytes (held + cached) {mem['peak']}")
+        assert srv.peak_used <= budget
+        assert mem["peak"] <= budget and mem["held"] == 0  # the memory the library really held
+        srv.close()
+        for j in jobs:
+            j.status, j.admit, j.finish = "queued", float("nan"), float("nan")
 
 
 def test_oversized_and_invalid_requests_fail_alone(serve):

@@ -129,3 +129,77 @@ def test_projection_preserves_inner_products_in_the_span(M):
     c = M.project(rows, q)
     assert np.allclose(c, coef, atol=1e-12)
     assert np.allclose(rows @ rows.conj().T, c @ c.conj().T, atol=1e-12)
+
+
+def _emulated_library_cosines(d, x):
+    """Brute-force emulation of a half-precision decision: rows scaled by a
+    power of two and rounded to binary16 (numpy's own float16 conversion),
+    products formed exactly and summed one by one in float32, the entry's
+    squared norm summed the same way; cosine against the exact ||x||."""
+    def half_rows(a):
+        a = np.asarray(a, dtype=np.complex64)
+        out = []
+        for row in a:
+            m = max(np.max(np.abs(row.real)), np.max(np.abs(row.imag)))
+            k = -np.frexp(m)[1] if m > 0 else 0
+            s = np.float32(2.0 ** k)
+            out.append(((row.real * s).astype(np.float16), (row.imag * s).astype(np.float16), k))
+        return out
+    dh, xh = half_rows(d), half_rows(x)
+    nx = np.linalg.norm(np.asarray(x, dtype=np.complex128), axis=1)
+    c = np.zeros((len(xh), len(dh)))
+    for p, (xr, xi, kx) in enumerate(xh):
+        for e, (dr, di, kd) in enumerate(dh):
+            re = np.float32(0)
+            im = np.float32(0)
+            n2 = np.float32(0)
+            for t in range(len(dr)):
+                a, b = np.float32(dr[t]), np.float32(di[t])
+                u, v = np.float32(xr[t]), np.float32(xi[t])
+                re = np.float32(np.float32(re + a * u) + b * v)
+                im = np.float32(np.float32(im + a * v) - b * u)
+                n2 = np.float32(np.float32(n2 + a * a) + b * b)
+            if n2 > 0 and nx[p] > 0:
+                # back to the caller's units: x' carries 2^kx
+                c[p, e] = np.sqrt(float(re) ** 2 + float(im) ** 2) * 2.0 ** -kx / (np.sqrt(float(n2)) * nx[p])
+    return c
+
+
+@pytest.mark.parametrize("seed,n_t,tiny", [(0, 40, False), (1, 300, False), (2, 64, True)])
+def test_decision_bound_covers_an_emulated_half_precision_decision(M, seed, n_t, tiny):
+    """decision_bound against brute force: every emulated binary16/FP32
+    cosine lies within beta of the FP64 cosine of the unrounded inputs
+    (including rows whose small components fall into binary16's subnormal
+    range); and judge_picks accepts the emulated argmax while rejecting a
+    pick that is clearly worse."""
+    rng = np.random.default_rng(300 + seed)
+    d = random_dict(rng, 12, n_t).astype(np.complex64)
+    if tiny:  # components spanning 1e-9 .. 1 of the row maximum
+        d = (d * np.exp(rng.uniform(-20, 0, d.shape))).astype(np.complex64)
+    e = rng.integers(0, 12, 9)
+    x = (d[e] * (0.3 - 0.6j) + 0.2 * random_dict(rng, 9, n_t)).astype(np.complex64)
+    c = M.cosines(d, x)
+    ce = _emulated_library_cosines(d, x)
+    beta = M.decision_bound(n_t)
+    gap = float(np.max(np.abs(ce - c)))
+    assert gap <= beta, (gap, beta)
+    assert gap > 1e-7  # the emulation really rounds
+    j = M.judge_picks(np.argmax(ce, axis=1), d, x)
+    assert j["valid"]
+    worst = np.argmin(c, axis=1)
+    assert not M.judge_picks(worst, d, x)["valid"]
+
+
+def test_cosines_are_the_definition(M):
+    """argmax of the cosines is the definition's pick; a noise-free scaled
+    copy has cosine 1; Cauchy-Schwarz bounds every cosine by 1."""
+    rng = np.random.default_rng(12)
+    d = random_dict(rng, 20, 30)
+    x = np.concatenate([d[[3, 7]] * (2 - 1j), random_dict(rng, 5, 30)])
+    c = M.cosines(d, x)
+    best, _, score = M.match(d, x)
+    assert np.array_equal(np.argmax(c, axis=1), best)
+    assert abs(c[0, 3] - 1) < 1e-14 and abs(c[1, 7] - 1) < 1e-14
+    assert np.all(c <= 1 + 1e-14)
+    nx2 = np.sum(np.abs(x) ** 2, axis=1)
+    assert np.allclose(c[np.arange(len(x)), best] ** 2 * nx2, score, rtol=1e-12)

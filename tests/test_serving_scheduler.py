@@ -99,3 +99,33 @@ def test_realtime_arrivals_are_honoured():
     done = s.run(js, realtime=True)
     for j in done:
         assert j.admit >= j.arrival - 1e-3 and j.finish >= j.admit
+
+
+def test_small_first_admits_the_least_work_and_ages_the_oldest():
+    s = serve.Server(max_slots=1, hbm_budget=100, keep_signal=True, backend=(FakeCtx(), FakeStream, FakeEvent),
+                     policy="small_first", max_wait=1e9)
+    js = jobs([10, 11, 12, 13, 14], [10, 10, 10, 10, 10])
+    for j, w in zip(js, (50, 40, 30, 20, 10)):
+        j.spin_steps = w
+    s.run(js, realtime=False)
+    assert s.admit_order == [4, 3, 2, 1, 0]  # least work first
+    # a request older than max_wait goes first: with max_wait = 0 the order is the arrival order
+    s = serve.Server(max_slots=1, hbm_budget=100, keep_signal=True, backend=(FakeCtx(), FakeStream, FakeEvent),
+                     policy="small_first", max_wait=0.0)
+    js = jobs([10, 11, 12], [10, 10, 10])
+    for j, w, a in zip(js, (50, 40, 30), (0.0, 1e-4, 2e-4)):
+        j.spin_steps, j.arrival = w, a
+    s.run(js, realtime=False)
+    assert s.admit_order == [0, 1, 2]
+
+
+def test_small_first_skips_a_request_that_does_not_fit_yet():
+    s = serve.Server(max_slots=4, hbm_budget=100, keep_signal=True, backend=(FakeCtx(), FakeStream, FakeEvent),
+                     policy="small_first", max_wait=1e9)
+    js = jobs([10, 11, 12], [60, 70, 30])
+    for j, w in zip(js, (5, 6, 7)):
+        j.spin_steps = w
+    done = s.run(js, realtime=False)
+    assert all(j.status == "done" for j in done)
+    assert s.admit_order[:2] == [0, 2]  # 1 (70) does not fit beside 0 (60); 2 (30) does
+    assert s.peak_used <= 100
