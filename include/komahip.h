@@ -131,6 +131,15 @@ typedef struct {
                               KOMA_MIXED, FP64 MFMA for KOMA_FP64), 1 = vector ALU
                               (complex recurrence and a register transpose). Moving
                               spins always use the vector ALU. */
+    int tile_packing;      /* 1: when no sample is deferred and every non-empty signal group has
+                              >= 64 spins, wavefronts take 64 consecutive spins across group
+                              boundaries (a wavefront then holds at most two groups, whose
+                              samples it sums apart); 0: every wavefront within one group */
+    int lanes_per_spin;    /* lanes per spin of the spin-sequential kernel: 0 = the planner's
+                              choice (several when the spins fill few wavefronts), 1, 2, 4, 8 or
+                              16 (the events between two observations of the state are affine
+                              maps; each lane composes a share of them, the lanes' products are
+                              combined, the same operators associated differently) */
 } koma_config;
 
 typedef struct koma_ctx koma_ctx;
@@ -194,7 +203,9 @@ koma_status koma_simulate_async(koma_ctx *ctx, const koma_scanner *sc, const kom
  * the packed sequence into request-owned device buffers and initialises the
  * spin state; nothing of the caller's is kept. koma_req_advance enqueues the
  * next chunk of at most `max_events` events (<= 0: the configured
- * chunk_events) on `hip_stream` without waiting; the signal of every
+ * chunk_events; with several lanes per spin the chunk ends at a segment
+ * end, so it may exceed `max_events` by up to one segment of 8 x lanes map
+ * events plus its observation) on `hip_stream` without waiting; the signal of every
  * precession block finished so far is summed at the same time. koma_req_done
  * reports whether all events have been enqueued. koma_req_result enqueues
  * the final cross-workgroup sums and copies the signal ([n_sig][n_groups]
@@ -225,6 +236,9 @@ typedef struct {
     size_t footprint;
     int64_t n_ends;        /* precession-block ends every spin evaluates */
     int64_t n_rf_in_runs;  /* excitation intervals inside runs of identical ones */
+    int64_t n_rows;        /* rows of per-wavefront sample partials (a wavefront holding two
+                              groups has two) */
+    int64_t lanes_per_spin; /* lanes per spin of the spin-sequential kernel */
 } koma_req_info;
 koma_status koma_req_info_get(const koma_req *req, koma_req_info *info);
 /* The same figures for a plan built on the host only (no device work);

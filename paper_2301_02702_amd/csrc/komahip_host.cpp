@@ -64,6 +64,10 @@ struct Plan {
     std::vector<int64_t> snap_event;  // slot -> event index of its EV_SNAP
     // spin layout
     int64_t n_spins = 0, n_groups = 1, n_tiles = 0, n_adc = 0;
+    int64_t n_rows = 0;  // rows of inline partials (tiles, plus one per tile holding two groups)
+    bool packed = false; // tiles cross group boundaries (no deferred samples)
+    int lanes = 1;       // lanes per spin of the spin-sequential kernel
+    std::vector<SegEv> segs;  // segments of the event program (lanes > 1)
     std::vector<Tile> tiles;
     std::vector<int32_t> tile_off;  // [n_groups + 1]
     std::vector<Block> blocks;
@@ -183,7 +187,7 @@ struct koma_req {
     Plan plan;
     bool fp64 = false;
     // request-owned device memory
-    DevMem ph[kPhArrays], ev, st, tiles, blocks, toff, boff, inl, def, snap, pa, pb, sig, mxy, mz;
+    DevMem ph[kPhArrays], ev, st, tiles, blocks, toff, boff, inl, def, snap, pa, pb, sig, mxy, mz, segs;
     hipStream_t last_stream = nullptr;  // stream of the last enqueued work
     int64_t cursor = 0;
     size_t next_chunk = 0;
@@ -344,6 +348,10 @@ static koma_status check_config(koma_ctx *ctx, const koma_config *c) {
         return fail(ctx, KOMA_E_ARG, "stretch_max must be in [1, %d]", kStretchMax);
     if (c->sample_engine != 0 && c->sample_engine != 1)
         return fail(ctx, KOMA_E_ARG, "sample_engine must be 0 (matrix cores) or 1 (vector ALU)");
+    if (c->tile_packing != 0 && c->tile_packing != 1) return fail(ctx, KOMA_E_ARG, "tile_packing must be 0 or 1");
+    if (c->lanes_per_spin != 0 && c->lanes_per_spin != 1 && c->lanes_per_spin != 2 && c->lanes_per_spin != 4 &&
+        c->lanes_per_spin != 8 && c->lanes_per_spin != 16)
+        return fail(ctx, KOMA_E_ARG, "lanes_per_spin must be 0 (planner's choice), 1, 2, 4, 8 or 16");
     return KOMA_OK;
 }
 
@@ -701,6 +709,9 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     P.blk_off.clear();
     P.chunks.clear();
     P.n_slots = P.n_rf = P.n_rf_events = P.n_runs = 0;
+    P.packed = false;
+    P.lanes = 1;
+    P.segs.clear();
     P.spl = 1;
     P.per_wg = 1;
     P.max_cols = 0;
@@ -722,16 +733,19 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
         const int64_t b = ph->group_off ? ph->group_off[g + 1] : ph->n;
         P.tile_off[g] = (int32_t)P.tiles.size();
         for (int64_t s = a; s < b; s += kWave) {
-            Tile t;
+            Tile t{};
             t.spin0 = s;
             t.count = (int32_t)std::min<int64_t>(kWave, b - s);
             t.group = (int32_t)g;
+            t.split = t.count;
+            t.seg = (int32_t)P.tiles.size();
             P.tiles.push_back(t);
             if (P.tiles.size() >= (size_t)1 << 30) return fail(ctx, KOMA_E_PHANTOM, "too many spins");
         }
     }
     P.tile_off[P.n_groups] = (int32_t)P.tiles.size();
     P.n_tiles = (int64_t)P.tiles.size();
+    P.n_rows = P.n_tiles;
 
     // ---- event program
     // values first: one branch-free pass (vectorised) over every array; the
@@ -1015,6 +1029,94 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     if ((int64_t)P.inl_k.size() + (int64_t)P.def_k.size() != q->n_adc)
         return fail(ctx, KOMA_E_SEQUENCE, "internal: ADC samples lost in packing");
 
+    // ---- packed tiles: with no deferred samples the only per-tile sums are
+    // the inline ones, so wavefronts may take 64 consecutive spins across
+    // group boundaries. With every non-empty group >= 64 spins a tile holds
+    // at most two groups: lanes [0, split) and [split, count), summed into
+    // partial rows seg and seg + 1; group g then owns rows tile_off[g] ..
+    // tile_off[g + 1] (the rows are in spin order). Saves the partly empty
+    // last wavefront of every group (400-spin groups: 7 -> 6.25 per group).
+    if (cfg.tile_packing && P.def_k.empty() && P.n_groups > 1 && ph->group_off) {
+        const int64_t *go = ph->group_off;
+        const int64_t n = ph->n;
+        bool ok = n > 0;
+        for (int64_t g = 0; ok && g < P.n_groups; ++g) {
+            const int64_t sz = go[g + 1] - go[g];
+            if (sz != 0 && sz < kWave) ok = false;
+        }
+        const int64_t n_packed = (n + kWave - 1) / kWave;
+        if (ok && n_packed < P.n_tiles) {
+            P.tiles.clear();
+            int64_t g = 0;     // group of the tile's first spin
+            int64_t row = 0;
+            for (int64_t s0 = 0; s0 < n; s0 += kWave) {
+                while (go[g + 1] <= s0) ++g;  // skips empty groups
+                Tile t{};
+                t.spin0 = s0;
+                t.count = (int32_t)std::min<int64_t>(kWave, n - s0);
+                t.group = (int32_t)g;
+                t.split = t.count;
+                if (go[g + 1] < s0 + t.count) t.split = (int32_t)(go[g + 1] - s0);  // next group starts inside
+                t.seg = (int32_t)row;
+                row += t.split < t.count ? 2 : 1;
+                P.tiles.push_back(t);
+            }
+            P.n_tiles = (int64_t)P.tiles.size();
+            P.n_rows = row;
+            P.packed = true;
+            // first row of every group: its first spin's tile, second row if it starts mid-tile
+            P.tile_off[P.n_groups] = (int32_t)row;
+            for (int64_t gg = P.n_groups - 1; gg >= 0; --gg) {
+                if (go[gg + 1] == go[gg]) {
+                    P.tile_off[gg] = P.tile_off[gg + 1];  // empty: no rows
+                } else {
+                    const Tile &t = P.tiles[(size_t)(go[gg] / kWave)];
+                    P.tile_off[gg] = t.seg + (go[gg] % kWave != 0 ? 1 : 0);
+                }
+            }
+        }
+    }
+
+    // ---- lanes per spin of the spin-sequential kernel. With few tiles one
+    // lane per spin leaves most SIMDs idle and each wavefront walks the whole
+    // program as one dependent chain; G lanes per spin share every segment of
+    // map events (composition of affine maps, then a butterfly over the
+    // lanes). The planner takes the largest G in {16, 8, 4, 2} that keeps the
+    // grid within two wavefronts per SIMD (kSeqgWaves), at most 8 in FP64;
+    // packed tiles keep one.
+    {
+        int G = cfg.lanes_per_spin;
+        if (G == 0) {
+            G = 1;
+            if (!P.packed)
+                for (int cand : {16, 8, 4, 2})
+                    if (P.n_tiles * cand <= kSeqgWaves) {
+                        G = cand;
+                        break;
+                    }
+        }
+        if (P.packed) G = 1;
+        // FP64 maps need twice the registers: at most 8 lanes (512-lane workgroups)
+        if (cfg.precision == KOMA_FP64 && G > 8) G = 8;
+        P.lanes = G;
+        if (G > 1) {
+            const int64_t cap = (int64_t)kSegPerLane * G;
+            const int64_t ne = (int64_t)P.ev.size();
+            int64_t e = 0;
+            while (e < ne) {
+                SegEv g{};
+                g.e0 = (int32_t)e;
+                while (e < ne && (P.ev[e].kind == EV_RF || P.ev[e].kind == EV_END) && e - g.e0 < cap) ++e;
+                g.e1 = (int32_t)e;
+                if (e < ne && (P.ev[e].kind == EV_SNAP || P.ev[e].kind == EV_ADC)) {
+                    g.obs = 1;
+                    ++e;
+                }
+                P.segs.push_back(g);
+            }
+        }
+    }
+
     // ---- sample-parallel layout: blocks of 4*S tiles of one group
     const int64_t n_st = (int64_t)P.st.size();
     // the matrix-core kernels take kMMStretches stretches per workgroup
@@ -1066,7 +1168,7 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     }
     P.spl = spl;
     P.blk_off.assign(P.n_groups + 1, 0);
-    for (int64_t g = 0; g < P.n_groups; ++g) {
+    for (int64_t g = 0; g < P.n_groups && !P.packed; ++g) {
         P.blk_off[g] = (int32_t)P.blocks.size();
         for (int32_t t = P.tile_off[g]; t < P.tile_off[g + 1]; t += 4 * spl) {
             Block bl{};
@@ -1130,8 +1232,9 @@ static size_t plan_footprint(const Plan &P, bool fp64, bool with_state, bool wit
     b += pool_round(P.tiles.size() * sizeof(Tile)) + pool_round(P.blocks.size() * sizeof(Block));
     b += pool_round(P.tile_off.size() * 4) + pool_round(P.blk_off.size() * 4);
     b += pool_round(P.inl_k.size() * 4) + pool_round(P.def_k.size() * 4);
+    b += pool_round(P.segs.size() * sizeof(SegEv));
     b += pool_round((size_t)P.n_slots * n_pad * 2 * r);                         // snapshots
-    b += pool_round(ns * (size_t)P.n_tiles * P.inl_k.size() * 2 * r);            // inline partials
+    b += pool_round(ns * (size_t)P.n_rows * P.inl_k.size() * 2 * r);             // inline partials
     b += pool_round(ns * (size_t)P.blocks.size() * (size_t)P.max_cols * 16);     // cross-workgroup partials
     b += pool_round(ns * (size_t)P.n_groups * (size_t)P.n_adc * 16);             // signal
     if (with_state) b += pool_round(n_pad * 2 * r) + pool_round(n_pad * r);
@@ -1190,6 +1293,7 @@ struct Bufs {  // device views used by the launch sequence
     double *sig;
     void *mxy, *mz;
     const int32_t *gate = nullptr;  // the sums are written only if *gate == 0 (device-checked phantoms)
+    const SegEv *segs = nullptr;
 };
 
 }  // namespace
@@ -1223,7 +1327,19 @@ static koma_status run_seq(koma_ctx *ctx, const Plan &P, bool fp64, const Bufs &
     a.mz = B.mz;
     a.snap = B.snap;
     a.pa = B.pa;
+    a.n_rows = P.n_rows;
     a.n_inline = (int64_t)P.inl_k.size();
+    a.lanes = P.lanes;
+    if (P.lanes > 1) {
+        // segments that reach into [e0, e1): the first whose events end
+        // after e0, up to the first that starts at or after e1
+        const auto &S = P.segs;
+        auto first = std::partition_point(S.begin(), S.end(), [&](const SegEv &g) { return g.e1 + g.obs <= e0; });
+        auto last = std::partition_point(S.begin(), S.end(), [&](const SegEv &g) { return g.e0 < e1; });
+        a.segs = B.segs;
+        a.s0 = first - S.begin();
+        a.s1 = last - S.begin();
+    }
     LAUNCH(ctx, K_SEQ, P.n_tiles * kWave * (e1 - e0), s, launch_seq(fp64, P.moving, a, s));
     return KOMA_OK;
 }
@@ -1275,7 +1391,7 @@ static koma_status run_inline_reduce(koma_ctx *ctx, const Plan &P, bool fp64, co
     if (P.inl_k.empty()) return KOMA_OK;
     ReduceArgs r{};
     r.n_sig = P.n_sig;
-    r.part_stride = P.n_tiles * (int64_t)P.inl_k.size();
+    r.part_stride = P.n_rows * (int64_t)P.inl_k.size();
     r.part = B.pa;
     r.cols = (int64_t)P.inl_k.size();
     r.row_off = B.toff;
@@ -1284,7 +1400,7 @@ static koma_status run_inline_reduce(koma_ctx *ctx, const Plan &P, bool fp64, co
     r.sig = B.sig;
     r.gate = B.gate;
     r.n_adc = P.n_adc;
-    LAUNCH(ctx, K_RED, P.n_sig * P.n_tiles * r.cols * (fp64 ? 16 : 8), s, launch_reduce(fp64, r, s));
+    LAUNCH(ctx, K_RED, P.n_sig * P.n_rows * r.cols * (fp64 ? 16 : 8), s, launch_reduce(fp64, r, s));
     return KOMA_OK;
 }
 
@@ -1326,6 +1442,8 @@ void koma_config_default(koma_config *cfg) {
     cfg->defer_min_adc = 32;
     cfg->stretch_max = 128;
     cfg->sample_engine = 0;
+    cfg->tile_packing = 1;
+    cfg->lanes_per_spin = 0;
 }
 
 koma_status koma_ctx_create(int device, const koma_config *cfg, koma_ctx **out) {
@@ -1531,14 +1649,15 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
     struct Part {
         const void *src;
         size_t bytes, off;
-    } parts[8] = {{P.ev.data(), P.ev.size() * sizeof(Event), 0},
+    } parts[9] = {{P.ev.data(), P.ev.size() * sizeof(Event), 0},
                   {P.st.data(), P.st.size() * sizeof(Stretch), 0},
                   {P.tiles.data(), P.tiles.size() * sizeof(Tile), 0},
                   {P.blocks.data(), P.blocks.size() * sizeof(Block), 0},
                   {P.tile_off.data(), P.tile_off.size() * 4, 0},
                   {P.blk_off.data(), P.blk_off.size() * 4, 0},
                   {P.inl_k.data(), P.inl_k.size() * 4, 0},
-                  {P.def_k.data(), P.def_k.size() * 4, 0}};
+                  {P.def_k.data(), P.def_k.size() * 4, 0},
+                  {P.segs.data(), P.segs.size() * sizeof(SegEv), 0}};
     size_t total = 0;
     for (auto &pt : parts) {
         pt.off = total;
@@ -1580,11 +1699,12 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
     B.boff = (const int32_t *)(tb + parts[5].off);
     B.inl = (const int32_t *)(tb + parts[6].off);
     B.def = (const int32_t *)(tb + parts[7].off);
+    B.segs = (const SegEv *)(tb + parts[8].off);
 
     const size_t n_pad = (size_t)P.n_tiles * kWave;
     if ((st = dev_reserve(ctx, ctx->s_snap, (size_t)P.n_slots * n_pad * 2 * r)) != KOMA_OK) return st;
     const size_t nsig = (size_t)P.n_sig;
-    if ((st = dev_reserve(ctx, ctx->s_pa, nsig * (size_t)P.n_tiles * P.inl_k.size() * 2 * r)) != KOMA_OK) return st;
+    if ((st = dev_reserve(ctx, ctx->s_pa, nsig * (size_t)P.n_rows * P.inl_k.size() * 2 * r)) != KOMA_OK) return st;
     if ((st = dev_reserve(ctx, ctx->s_pb, nsig * P.blocks.size() * (size_t)P.max_cols * 16)) != KOMA_OK) return st;
     const bool store = m_final != nullptr;
     if (store) {
@@ -1668,6 +1788,7 @@ static Bufs req_bufs(koma_req *q) {
     for (int i = 0; i < kPhArrays; ++i) d[i] = (const float *)q->ph[i].p;
     B.ph = ph_dev(d, q->plan.moving, q->plan.n_spins, q->plan.n_coils);
     B.ev = (const Event *)q->ev.p;
+    B.segs = (const SegEv *)q->segs.p;
     B.st = (const Stretch *)q->st.p;
     B.tiles = (const Tile *)q->tiles.p;
     B.blocks = (const Block *)q->blocks.p;
@@ -1687,7 +1808,7 @@ static Bufs req_bufs(koma_req *q) {
 static void req_free(koma_req *q) {
     for (DevMem &m : q->ph) pool_put(q->ctx, m);
     DevMem *all[] = {&q->ev, &q->st, &q->tiles, &q->blocks, &q->toff, &q->boff, &q->inl, &q->def,
-                     &q->snap, &q->pa, &q->pb, &q->sig, &q->mxy, &q->mz};
+                     &q->snap, &q->pa, &q->pb, &q->sig, &q->mxy, &q->mz, &q->segs};
     for (DevMem *m : all) pool_put(q->ctx, *m);
 }
 
@@ -1745,9 +1866,10 @@ koma_status koma_req_open(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
     if ((st = pool_upload(ctx, q->boff, P.blk_off, s)) != KOMA_OK) return bail(st);
     if ((st = pool_upload(ctx, q->inl, P.inl_k, s)) != KOMA_OK) return bail(st);
     if ((st = pool_upload(ctx, q->def, P.def_k, s)) != KOMA_OK) return bail(st);
+    if ((st = pool_upload(ctx, q->segs, P.segs, s)) != KOMA_OK) return bail(st);
     if ((st = pool_get(ctx, q->snap, (size_t)P.n_slots * n_pad * 2 * r)) != KOMA_OK) return bail(st);
     const size_t nsig = (size_t)P.n_sig;
-    if ((st = pool_get(ctx, q->pa, nsig * (size_t)P.n_tiles * P.inl_k.size() * 2 * r)) != KOMA_OK) return bail(st);
+    if ((st = pool_get(ctx, q->pa, nsig * (size_t)P.n_rows * P.inl_k.size() * 2 * r)) != KOMA_OK) return bail(st);
     if ((st = pool_get(ctx, q->pb, nsig * P.blocks.size() * (size_t)P.max_cols * 16)) != KOMA_OK) return bail(st);
     if ((st = pool_get(ctx, q->sig, nsig * (size_t)P.n_groups * P.n_adc * 16)) != KOMA_OK) return bail(st);
     if ((st = pool_get(ctx, q->mxy, n_pad * 2 * r)) != KOMA_OK) return bail(st);
@@ -1774,7 +1896,17 @@ koma_status koma_req_advance(koma_req *q, int64_t max_events, void *hip_stream) 
     const Plan &P = q->plan;
     const int64_t n_ev = (int64_t)P.ev.size();
     const int64_t step = max_events > 0 ? max_events : ctx->cfg.chunk_events;
-    const int64_t e1 = std::min(n_ev, q->cursor + step);
+    int64_t e1 = std::min(n_ev, q->cursor + step);
+    if (P.lanes > 1 && e1 < n_ev) {
+        // whole segments only (the cursor is always at a segment end), so a
+        // chunked request composes exactly the maps of one whole run: the
+        // last segment end within the step, or one segment beyond it
+        const auto &S = P.segs;
+        auto it = std::partition_point(S.begin(), S.end(), [&](const SegEv &g) { return g.e1 + g.obs <= e1; });
+        int64_t end = it == S.begin() ? -1 : (int64_t)(it - 1)->e1 + (it - 1)->obs;
+        if (end <= q->cursor) end = (int64_t)it->e1 + it->obs;
+        e1 = end;
+    }
     Bufs B = req_bufs(q);
     koma_status st;
     if (e1 > q->cursor || q->cursor == 0) {
@@ -1847,7 +1979,7 @@ static void ckpt_sizes(const koma_req *q, CkptHeader &h) {
     h.bytes_mxy = n_pad * 2 * r;
     h.bytes_mz = n_pad * r;
     h.bytes_snap = (size_t)P.n_slots * n_pad * 2 * r;
-    h.bytes_pa = (size_t)P.n_sig * P.n_tiles * P.inl_k.size() * 2 * r;
+    h.bytes_pa = (size_t)P.n_sig * P.n_rows * P.inl_k.size() * 2 * r;
     h.bytes_sig = (size_t)P.n_sig * P.n_groups * P.n_adc * 16;
 }
 
@@ -1945,6 +2077,8 @@ static void fill_info(const Plan &P, koma_req_info *info) {
     info->footprint = 0;
     info->n_ends = 0;
     info->n_rf_in_runs = 0;
+    info->n_rows = P.n_rows;
+    info->lanes_per_spin = P.lanes;
     for (const Event &e : P.ev) {
         if (e.kind == EV_END) ++info->n_ends;
         if (e.kind == EV_RF && e.count > 1) info->n_rf_in_runs += e.count;

@@ -72,12 +72,19 @@ struct alignas(16) Stretch {
 };
 static_assert(sizeof(Stretch) == 160, "Stretch layout");
 
-// 64 consecutive spin slots of one signal group (one wavefront).
+// 64 consecutive spin slots (one wavefront): of one signal group, or with
+// packed tiles of two, lanes [0, split) in one and [split, count) in the next
+// non-empty one. Inline sample sums go to partial row `seg` (lanes below
+// split) and `seg + 1` (the others).
 struct alignas(16) Tile {
     int64_t spin0;
     int32_t count;  // valid lanes (1..64)
-    int32_t group;
+    int32_t group;  // group of lane 0
+    int32_t split;  // count: one group
+    int32_t seg;    // first partial row
+    int32_t pad[2];
 };
+static_assert(sizeof(Tile) == 32, "Tile layout");
 
 // Consecutive tiles of one group summed into one cross-workgroup partial.
 struct alignas(16) Block {
@@ -104,6 +111,16 @@ constexpr int kMMStretches = 4;     // stretches whose sums one matrix-core work
 constexpr int kMMResident = 3;      // matrix-core workgroups resident per CU (LDS 48 KB, 168 VGPRs)
 constexpr int kMMResident64 = 1;    // the same in FP64 (LDS 96 KB)
 
+// A segment of the event program for the several-lanes-per-spin kernel:
+// map events (EV_RF, EV_END) [e0, e1), then, if obs, the observation event
+// at e1 (EV_SNAP or EV_ADC), which needs the state itself. At most
+// kSegPerLane * lanes map events per segment.
+struct alignas(16) SegEv {
+    int32_t e0, e1, obs, pad;
+};
+constexpr int kSegPerLane = 8;
+constexpr int64_t kSeqgWaves = 2048;  // several lanes per spin while tiles x lanes stays within this
+
 struct SeqArgs {  // spin-sequential kernel
     PhantomDev ph;
     const Tile *tiles;
@@ -116,11 +133,18 @@ struct SeqArgs {  // spin-sequential kernel
     void *mxy;        // state: [n_tiles*64] complex (R2)
     void *mz;         // [n_tiles*64] R
     void *snap;       // [n_slots][n_tiles*64] complex (R2)
-    void *pa;         // inline partials [n_sig][n_tiles][n_inline] complex (R2)
+    void *pa;         // inline partials [n_sig][n_rows][n_inline] complex (R2)
+    int64_t n_rows;
     int64_t n_inline;
     int32_t *vbits;   // nullptr, or a word (zero at the launch) that receives the OR of the
                       // validation bits (as k_validate) of every spin's phantom values
+    // several lanes per spin (k_seqg): lanes > 1 splits each segment's map
+    // events over `lanes` lanes of a spin; segments [s0, s1) cover [e0, e1)
+    int lanes;
+    const SegEv *segs;
+    int64_t s0, s1;
 };
+
 
 struct ParArgs {  // sample-parallel kernel
     PhantomDev ph;

@@ -67,6 +67,8 @@ struct Mixed {
     static __device__ __forceinline__ float exp_neg(float x) {  // exp(-x)
         return __builtin_amdgcn_exp2f(-x * kLog2e);
     }
+    // 1 - exp(-x), accurate to a few ulp also for tiny x (dt / T ~ 1e-6)
+    static __device__ __forceinline__ float one_minus_exp_neg(float x) { return -expm1f(-x); }
 };
 
 struct FP64 {
@@ -78,6 +80,7 @@ struct FP64 {
         sincospi(2.0 * r, &s, &c);
     }
     static __device__ __forceinline__ double exp_neg(double x) { return exp(-x); }
+    static __device__ __forceinline__ double one_minus_exp_neg(double x) { return -expm1(-x); }
 };
 
 template <class R>
@@ -92,12 +95,18 @@ __device__ __forceinline__ C2<R> cmul(C2<R> a, C2<R> b) {
 
 // Unit phasor (c, s) renormalised by one Newton step towards |.| = 1, so
 // repeated products of hardware sines/cosines do not drift in magnitude. In
-// FP32 the defect c^2 + s^2 - 1 is formed exactly in FP64 (products of floats
-// are exact there) and applied with one FP32 fma: a correction factor rounded
-// to FP32 near 1.0 would be quantised unevenly and bias every step.
+// FP32 the defect c^2 + s^2 - 1 is formed to within a few ulp of itself with
+// FP32 operations only: with a = max(|c|, |s|) (a^2 >= 1/2) and b the other,
+// a^2 = p + e exactly (e by an fma), p - 1 is exact (Sterbenz), and
+// fma(b, b, p - 1) rounds a value of the size of the defect once. The
+// correction is applied as c + c h (one fma): a factor 1 + h rounded to FP32
+// near 1.0 would be quantised unevenly and bias every step.
 __device__ __forceinline__ void renorm(float &c, float &s) {
-    const double d = fma((double)c, (double)c, fma((double)s, (double)s, -1.0));
-    const float h = (float)(-0.5 * d);
+    const float a = fmaxf(fabsf(c), fabsf(s)), b = fminf(fabsf(c), fabsf(s));
+    const float p = a * a;
+    const float e = fmaf(a, a, -p);
+    const float d = fmaf(b, b, p - 1.0f) + e;
+    const float h = -0.5f * d;
     c = fmaf(c, h, c);
     s = fmaf(s, h, s);
 }
@@ -292,6 +301,27 @@ __device__ __forceinline__ C2<typename P::R> block_factor(const SpinP<typename P
     return {cs * e2, sn * e2};
 }
 
+// One Newton step of the spinor towards |alpha|^2 + |beta|^2 = cs^2 + sk^2
+// |B|^2 = 1 (sk = sin(phi/2) / |B|), which keeps the rotation orthogonal
+// whatever the errors of the hardware sine, cosine and reciprocal square
+// root. FP32: the defect from the FP32 |B|^2 (nb2), formed as
+// fma(sk^2, nb2, fma(cs, cs, -1)): fma(cs, cs, -1) ~ -sin^2(phi/2) is rounded
+// once at its own size, so the defect is good to ~3 ulp of sin^2(phi/2)
+// (tiny for the small angles of an excitation interval) and its rounding is
+// unbiased; FP64: from the exact |B|^2 of the interval's FP64 values.
+__device__ __forceinline__ void spinor_normalise(float &cs, float &sk, float bz, float nb2, double) {
+    const float d = fmaf(sk * sk, nb2, fmaf(cs, cs, -1.0f));
+    const float h = -0.5f * d;
+    cs = fmaf(cs, h, cs);
+    sk = fmaf(sk, h, sk);
+}
+__device__ __forceinline__ void spinor_normalise(double &cs, double &sk, double bz, double, double b1sq) {
+    const double B2 = fma(bz, bz, b1sq);
+    const double h = -0.5 * fma(sk * sk, B2, fma(cs, cs, -1.0));
+    cs = fma(cs, h, cs);
+    sk = fma(sk, h, sk);
+}
+
 // One excitation interval (Eq. Rot_exc) followed by relaxation with the
 // cached eps = 1 - exp(-dt/T) (applied as M - eps*M, exact in the factor).
 // For moving spins gt holds the interval mean of G(t) t: Bz gains v . gt.
@@ -313,16 +343,8 @@ __device__ __forceinline__ void excite_relax(const SpinP<typename P::R> &s, cons
     R sn, cs;
     P::sincos_turns(hs * nb, sn, cs);  // sin, cos of phi/2
     R sk = sn * inv;                   // sin(phi/2) / |B|
-    // normalise the spinor, |alpha|^2 + |beta|^2 = cs^2 + sk^2 |B|^2 -> 1, with
-    // the defect formed exactly in FP64 (see renorm)
-    {
-        // b1sq_exact = b1r^2 + b1i^2 of the very values used below, exact in FP64
-        const double B2 = fma((double)bz, (double)bz, b1sq_exact);
-        const double sk2 = (double)sk * (double)sk;
-        const R h = R(-0.5 * fma(sk2, B2, fma((double)cs, (double)cs, -1.0)));
-        cs = fma(cs, h, cs);
-        sk = fma(sk, h, sk);
-    }
+    // normalise the spinor, |alpha|^2 + |beta|^2 = cs^2 + sk^2 |B|^2 -> 1
+    spinor_normalise(cs, sk, bz, nb2, b1sq_exact);
     const R ar = cs, ai = -bz * sk;        // alpha = cos - i n_z sin
     const R br = b1i * sk, bi = -b1r * sk;  // beta = -i (b1/|B|) sin
     // conj(alpha)^2, beta^2, conj(alpha) beta, alpha beta
@@ -358,13 +380,7 @@ __device__ __forceinline__ void rot_matrix(const SpinP<typename P::R> &s, const 
     R sn, cs;
     P::sincos_turns(hs * nb, sn, cs);
     R sk = sn * inv;
-    {
-        const double B2 = fma((double)bz, (double)bz, b1sq_exact);
-        const double sk2 = (double)sk * (double)sk;
-        const R h = R(-0.5 * fma(sk2, B2, fma((double)cs, (double)cs, -1.0)));
-        cs = fma(cs, h, cs);
-        sk = fma(sk, h, sk);
-    }
+    spinor_normalise(cs, sk, bz, nb2, b1sq_exact);
     const R ar = cs, ai = -bz * sk;
     const R br = b1i * sk, bi = -b1r * sk;
     const R ur = ar * ar - ai * ai, ui = R(-2) * ar * ai;
@@ -485,16 +501,35 @@ struct EvL {  // view of one staged event
     }
 };
 
+// The wavefront's sum of v into inline partial row `row` of signal plane k;
+// a tile holding two groups sums lanes [0, split) into its first row and
+// the others into the next one.
+template <class R, class R2>
+__device__ __forceinline__ void inline_rows(const SeqArgs &a, const Tile &T, int lane, int64_t k, int col,
+                                            C2<R> v) {
+    R2 *pa = reinterpret_cast<R2 *>(a.pa);
+    if (T.split >= T.count) {  // uniform: one group
+        const R sr = wave_allsum(v.re);
+        const R si = wave_allsum(v.im);
+        if (lane == 0) pa[(k * a.n_rows + T.seg) * a.n_inline + col] = R2{sr, si};
+        return;
+    }
+    const bool lo = lane < T.split;
+    const R ar = wave_allsum(lo ? v.re : R(0)), ai = wave_allsum(lo ? v.im : R(0));
+    const R br = wave_allsum(lo ? R(0) : v.re), bi = wave_allsum(lo ? R(0) : v.im);
+    if (lane == 0) {
+        pa[(k * a.n_rows + T.seg) * a.n_inline + col] = R2{ar, ai};
+        pa[(k * a.n_rows + T.seg + 1) * a.n_inline + col] = R2{br, bi};
+    }
+}
+
 // One inline ADC sample: the wavefront's sum of Mxy (c), or of sens_k * Mxy
 // for every receive coil k, into the per-wavefront partials.
 template <class R, class R2>
-__device__ __forceinline__ void inline_sample(const SeqArgs &a, const Tile &T, int64_t tile, int lane,
-                                              int col, C2<R> c) {
+__device__ __forceinline__ void inline_sample(const SeqArgs &a, const Tile &T, int lane, int col, C2<R> c) {
     const int64_t n_coils = a.ph.n_coils;  // uniform
     if (n_coils == 0) {
-        const R sr = wave_allsum(c.re);
-        const R si = wave_allsum(c.im);
-        if (lane == 0) reinterpret_cast<R2 *>(a.pa)[tile * a.n_inline + col] = R2{sr, si};
+        inline_rows<R, R2>(a, T, lane, 0, col, c);
         return;
     }
     const bool valid = lane < T.count;
@@ -502,10 +537,7 @@ __device__ __forceinline__ void inline_sample(const SeqArgs &a, const Tile &T, i
     for (int64_t k = 0; k < n_coils; ++k) {
         C2<R> sk{R(0), R(0)};
         if (valid) sk = C2<R>{R(a.ph.sre[k * a.ph.n + i]), R(a.ph.sim[k * a.ph.n + i])};
-        const C2<R> v = cmul(sk, c);
-        const R sr = wave_allsum(v.re);
-        const R si = wave_allsum(v.im);
-        if (lane == 0) reinterpret_cast<R2 *>(a.pa)[(k * a.n_tiles + tile) * a.n_inline + col] = R2{sr, si};
+        inline_rows<R, R2>(a, T, lane, k, col, cmul(sk, c));
     }
 }
 
@@ -526,6 +558,8 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
         T.spin0 = 0;
         T.count = 0;
         T.group = 0;
+        T.split = 0;
+        T.seg = 0;
     }
     const SpinP<R> s = load_spin<R, MOV>(a.ph, T, lane, a.inv_gamma);
     const int64_t n_pad = a.n_tiles * kWave;
@@ -565,8 +599,8 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
                 const double dt = ev.d(7);
                 if (dt != dt_cached) {  // uniform: same interval length for every spin
                     dt_cached = dt;
-                    eps1 = R(-expm1(-dt * (double)s.r1));
-                    eps2 = R(-expm1(-dt * (double)s.r2));
+                    eps1 = P::one_minus_exp_neg(R(dt) * s.r1);
+                    eps2 = P::one_minus_exp_neg(R(dt) * s.r2);
                 }
                 const int reps = ev.count();  // identical consecutive intervals (uniform)
                 if (reps > 1) {
@@ -588,20 +622,13 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
                         const double b1sq = sizeof(R) == 4 ? ev.b1sq() : ev.d(5);
                         rot_matrix<P, MOV>(s, q, gt, b1sq, m);
                     }
-                    // the powers in FP64 (full rate here): every spin with the
-                    // same field shares the matrix, so its rounding would add
-                    // up coherently over the spins of a voxel
-                    const double k2 = 1.0 - (double)eps2, k1 = 1.0 - (double)eps1;
-                    double md[9];
+                    // the interval's affine map: rotation rows scaled by the
+                    // relaxation factors (m - eps m, never a rounded 1 - eps)
 #pragma unroll
-                    for (int i = 0; i < 6; ++i) md[i] = (double)m[i] * k2;
+                    for (int i = 0; i < 6; ++i) m[i] = fma(-eps2, m[i], m[i]);
 #pragma unroll
-                    for (int i = 6; i < 9; ++i) md[i] = (double)m[i] * k1;
-                    double xr = mr, xi = mi, xz = mz;
-                    affine_power(md, (double)eps1 * (double)s.pd, reps, xr, xi, xz);
-                    mr = R(xr);
-                    mi = R(xi);
-                    mz = R(xz);
+                    for (int i = 6; i < 9; ++i) m[i] = fma(-eps1, m[i], m[i]);
+                    affine_power(m, eps1 * s.pd, reps, mr, mi, mz);
                 } else if (ev.rot() >= 0 && no_offres) {
                     R c[9];
 #pragma unroll
@@ -644,7 +671,7 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
                 const double k0[4] = {ev.d(0), ev.d(1), ev.d(2), ev.d(3)};
                 const double k1[3] = {ev.c64(0), ev.c64(1), ev.c64(2)};
                 const C2<R> c = cmul(C2<R>{mr, mi}, block_factor<P>(s, block_phase(s, k0, k1), k0[3]));
-                inline_sample<R, R2>(a, T, tile, lane, ev.a0(), c);
+                inline_sample<R, R2>(a, T, lane, ev.a0(), c);
             } else if (kind == EV_ADC) {
                 const double k0[4] = {ev.d(0), ev.d(1), ev.d(2), ev.d(3)};
                 const double dk[4] = {ev.d(4), ev.d(5), ev.d(6), ev.d(7)};
@@ -653,7 +680,7 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
                 C2<R> w{R(1), R(0)};
                 if (cnt > 1) w = block_factor<P>(s, block_phase(s, dk), dk[3]);
                 for (int i = 0; i < cnt; ++i) {
-                    inline_sample<R, R2>(a, T, tile, lane, ev.a0() + i, c);
+                    inline_sample<R, R2>(a, T, lane, ev.a0() + i, c);
                     c = cmul(c, w);
                 }
             } else {  // EV_SNAP
@@ -662,6 +689,310 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
         }
     }
     if (active && a.store) {
+        reinterpret_cast<R2 *>(a.mxy)[pidx] = R2{mr, mi};
+        reinterpret_cast<R *>(a.mz)[pidx] = mz;
+    }
+}
+
+// ---------------------------------------------------------------- k_seqg
+
+// Several lanes per spin. With few spins, one lane per spin leaves most of
+// the chip idle and every wavefront walks the whole event program as one
+// dependent chain. Every event between two observations of the state (a
+// snapshot or an inline sample) is an affine map of (Mx, My, Mz): an
+// excitation interval is its rotation (Eq. Rot_exc) followed by the
+// relaxation update, a run of k identical ones the k-th power of that map,
+// a precession-block end the rotation by the block phase with the decay
+// over the block. The G lanes of a spin each compose the maps of a
+// contiguous share of a segment's events; the G products are combined by a
+// butterfly over the lanes (the later product after the earlier one, so
+// every lane ends with the same composite), which is applied to the state.
+// The same operators as the one-lane kernel, associated differently.
+template <class R>
+struct Aff {
+    R a[9];  // row-major, on (Mx, My, Mz)
+    R b[3];
+};
+
+template <class R>
+__device__ __forceinline__ Aff<R> aff_identity() {
+    Aff<R> m;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) m.a[i] = (i % 4 == 0) ? R(1) : R(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) m.b[i] = R(0);
+    return m;
+}
+
+// the map of `second` after `first`
+template <class R>
+__device__ __forceinline__ Aff<R> aff_then(const Aff<R> &second, const Aff<R> &first) {
+    Aff<R> c;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const R x = second.a[3 * r], y = second.a[3 * r + 1], z = second.a[3 * r + 2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) c.a[3 * r + k] = fma(x, first.a[k], fma(y, first.a[3 + k], z * first.a[6 + k]));
+        c.b[r] = fma(x, first.b[0], fma(y, first.b[1], fma(z, first.b[2], second.b[r])));
+    }
+    return c;
+}
+
+template <class R>
+__device__ __forceinline__ void aff_apply(const Aff<R> &m, R &mr, R &mi, R &mz) {
+    const R nr = fma(m.a[0], mr, fma(m.a[1], mi, fma(m.a[2], mz, m.b[0])));
+    const R ni = fma(m.a[3], mr, fma(m.a[4], mi, fma(m.a[5], mz, m.b[1])));
+    const R nz = fma(m.a[6], mr, fma(m.a[7], mi, fma(m.a[8], mz, m.b[2])));
+    mr = nr;
+    mi = ni;
+    mz = nz;
+}
+
+// k-th power (k >= 1) by binary powering (powers of one map commute)
+template <class R>
+__device__ __forceinline__ Aff<R> aff_power(Aff<R> p, int k) {
+    Aff<R> r = p;
+    bool have = false;
+    for (;;) {
+        if (k & 1) {
+            r = have ? aff_then(p, r) : p;
+            have = true;
+        }
+        k >>= 1;
+        if (k == 0) break;
+        p = aff_then(p, p);
+    }
+    return r;
+}
+
+template <class R>
+__device__ __forceinline__ Aff<R> aff_shfl_xor(const Aff<R> &m, int d) {
+    Aff<R> o;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) o.a[i] = __shfl_xor(m.a[i], d, kWave);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) o.b[i] = __shfl_xor(m.b[i], d, kWave);
+    return o;
+}
+
+// The map of one EV_RF or EV_END event for spin s. eps1/eps2 and dt_cached
+// are the lane's relaxation cache (1 - exp(-dt/T) for the last dt seen).
+template <class P, bool MOV>
+__device__ __forceinline__ Aff<typename P::R> event_map(const EvL &ev, const SpinP<typename P::R> &s,
+                                                        bool no_offres, double &dt_cached,
+                                                        typename P::R &eps1, typename P::R &eps2) {
+    using R = typename P::R;
+    Aff<R> m;
+    if (ev.kind() == EV_END) {
+        const double k4[4] = {ev.d(0), ev.d(1), ev.d(2), ev.d(3)};
+        double th;
+        if (MOV) {
+            const double k1[3] = {ev.d(4), ev.d(5), ev.d(6)};
+            th = block_phase(s, k4, k1);
+        } else {
+            th = block_phase(s, k4);
+        }
+        const C2<R> f = block_factor<P>(s, th, k4[3]);
+        const R e1 = P::exp_neg(R(k4[3]) * s.r1);
+        m.a[0] = f.re;
+        m.a[1] = -f.im;
+        m.a[2] = R(0);
+        m.a[3] = f.im;
+        m.a[4] = f.re;
+        m.a[5] = R(0);
+        m.a[6] = R(0);
+        m.a[7] = R(0);
+        m.a[8] = e1;
+        m.b[0] = R(0);
+        m.b[1] = R(0);
+        m.b[2] = fma(-e1, s.pd, s.pd);
+        return m;
+    }
+    const double dt = ev.d(7);
+    if (dt != dt_cached) {
+        dt_cached = dt;
+        eps1 = P::one_minus_exp_neg(R(dt) * s.r1);
+        eps2 = P::one_minus_exp_neg(R(dt) * s.r2);
+    }
+    if (ev.rot() >= 0 && no_offres) {
+        // the host's coefficients: Mxy_re' = c0 Mz + c1 Mxy_re + c2 Mxy_im, ...
+        const int perm[9] = {1, 2, 0, 5, 4, 3, 7, 8, 6};
+#pragma unroll
+        for (int i = 0; i < 9; ++i) m.a[i] = sizeof(R) == 4 ? R(ev.c32(perm[i])) : R(ev.c64(perm[i]));
+    } else {
+        R q[7];
+#pragma unroll
+        for (int i = 0; i < 7; ++i) q[i] = sizeof(R) == 4 ? R(ev.f(i)) : R(ev.d(i));
+        R gt[3] = {R(0), R(0), R(0)};
+        if (MOV && ev.rot() < 0) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) gt[i] = sizeof(R) == 4 ? R(ev.c32(i)) : R(ev.c64(i));
+        }
+        const double b1sq = sizeof(R) == 4 ? ev.b1sq() : ev.d(5);
+        rot_matrix<P, MOV>(s, q, gt, b1sq, m.a);
+    }
+    // relaxation after the rotation: rows scaled by 1 - eps (as m - eps m)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) m.a[i] = fma(-eps2, m.a[i], m.a[i]);
+#pragma unroll
+    for (int i = 6; i < 9; ++i) m.a[i] = fma(-eps1, m.a[i], m.a[i]);
+    m.b[0] = R(0);
+    m.b[1] = R(0);
+    m.b[2] = eps1 * s.pd;
+    const int reps = ev.count();
+    return reps > 1 ? aff_power(m, reps) : m;
+}
+
+// Staged events: kSegStride dwords apart (odd, so that lanes reading
+// different events of one segment hit different LDS banks).
+constexpr int kSegStride = kEvWords + 1;
+
+// One tile (64 spins) per workgroup of 64 G lanes: lane t holds spin t / G,
+// share t % G of every segment. Segments are staged through LDS, the next
+// one read from memory into registers while the current one is composed.
+template <class P, bool MOV, int G>
+__global__ __launch_bounds__(kWave * G) void k_seqg(SeqArgs a) {
+    using R = typename P::R;
+    using R2 = typename P::R2;
+    constexpr int NT = kWave * G;
+    constexpr int C = kSegPerLane * G + 1;              // events staged per segment at most
+    constexpr int kPre = (C * kEvWords + NT - 1) / NT;  // dwords per thread in flight
+    __shared__ uint32_t lds[2][C * kSegStride];
+    __shared__ double red[G][2];
+    const int tid = threadIdx.x;
+    const int wave = tid / kWave, lane = tid % kWave;
+    const int sl = tid / G;  // spin slot of the tile
+    const int j = tid % G;   // share of each segment
+    const int64_t tile = blockIdx.x;
+    const Tile T = a.tiles[tile];
+    const SpinP<R> s = load_spin<R, MOV>(a.ph, T, sl, a.inv_gamma);
+    const int64_t pidx = tile * kWave + sl;
+    if (a.vbits && j == 0 && sl < T.count) {
+        const int32_t bad = spin_flags(a.ph, T.spin0 + sl);
+        if (bad) atomicOr(a.vbits, bad);
+    }
+    R mr = R(0), mi = R(0), mz = s.pd;
+    if (!a.init) {
+        R2 m = reinterpret_cast<const R2 *>(a.mxy)[pidx];
+        mr = m.x;
+        mi = m.y;
+        mz = reinterpret_cast<const R *>(a.mz)[pidx];
+    }
+    R eps1 = R(0), eps2 = R(0);
+    double dt_cached = -1.0;
+    const bool no_offres = __ballot(s.bz0 != R(0)) == 0;  // per wavefront, as in k_seq
+    const uint32_t *gev = reinterpret_cast<const uint32_t *>(a.ev);
+
+    // events [first, last) of segment si within this launch's range, and
+    // whether its observation event is in the range
+    auto clip = [&](int64_t si, int64_t &first, int64_t &mid, bool &obs) {
+        const SegEv g = a.segs[si];
+        first = g.e0 > a.e0 ? (int64_t)g.e0 : a.e0;
+        mid = g.e1 < a.e1 ? (int64_t)g.e1 : a.e1;
+        if (mid < first) mid = first;
+        obs = g.obs && g.e1 >= a.e0 && g.e1 < a.e1;
+    };
+    uint32_t pre[kPre];
+    auto fetch = [&](int64_t si) {
+        int64_t f, m;
+        bool o;
+        clip(si, f, m, o);
+        const int n = (int)(m - f) + (o ? 1 : 0);
+#pragma unroll
+        for (int r = 0; r < kPre; ++r) {
+            const int w = tid + r * NT;
+            pre[r] = w < n * kEvWords ? gev[f * kEvWords + w] : 0u;
+        }
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < kPre; ++r) {
+            const int w = tid + r * NT;
+            if (w < C * kEvWords) lds[buf][(w / kEvWords) * kSegStride + w % kEvWords] = pre[r];
+        }
+    };
+    if (a.s0 < a.s1) {
+        fetch(a.s0);
+        stage(0);
+    }
+    __syncthreads();
+    for (int64_t si = a.s0; si < a.s1; ++si) {
+        const int buf = (int)((si - a.s0) & 1);
+        if (si + 1 < a.s1) fetch(si + 1);  // in flight while this segment is composed
+        int64_t first, mid;
+        bool obs;
+        clip(si, first, mid, obs);
+        const int L = (int)(mid - first);
+        const uint32_t *base = lds[buf];
+        if (L > 0) {  // uniform
+            const int lo = (j * L) / G, hi = ((j + 1) * L) / G;
+            Aff<R> m = aff_identity<R>();
+            for (int k = lo; k < hi; ++k) {
+                const EvL ev{base + k * kSegStride};
+                const Aff<R> e = event_map<P, MOV>(ev, s, no_offres, dt_cached, eps1, eps2);
+                m = k == lo ? e : aff_then(e, m);
+            }
+#pragma unroll
+            for (int d = 1; d < G; d <<= 1) {
+                const Aff<R> o = aff_shfl_xor(m, d);
+                m = (j & d) ? aff_then(m, o) : aff_then(o, m);  // the later share after the earlier
+            }
+            aff_apply(m, mr, mi, mz);
+        }
+        if (obs) {  // uniform
+            const EvL ev{base + L * kSegStride};
+            const int kind = ev.kind();
+            if (kind == EV_SNAP) {
+                if (j == 0) reinterpret_cast<R2 *>(a.snap)[(int64_t)ev.a0() * (a.n_tiles * kWave) + pidx] = R2{mr, mi};
+            } else {  // EV_ADC: inline samples, the tile's 64 spins summed once each
+                const double k0[4] = {ev.d(0), ev.d(1), ev.d(2), ev.d(3)};
+                C2<R> c, w{R(1), R(0)};
+                int cnt = 1;
+                if (MOV) {
+                    const double k1[3] = {ev.c64(0), ev.c64(1), ev.c64(2)};
+                    c = cmul(C2<R>{mr, mi}, block_factor<P>(s, block_phase(s, k0, k1), k0[3]));
+                } else {
+                    const double dk[4] = {ev.d(4), ev.d(5), ev.d(6), ev.d(7)};
+                    c = cmul(C2<R>{mr, mi}, block_factor<P>(s, block_phase(s, k0), k0[3]));
+                    cnt = ev.count();
+                    if (cnt > 1) w = block_factor<P>(s, block_phase(s, dk), dk[3]);
+                }
+                const int64_t n_planes = a.ph.n_coils > 0 ? a.ph.n_coils : 1;
+                for (int i = 0; i < cnt; ++i) {
+                    for (int64_t k = 0; k < n_planes; ++k) {
+                        C2<R> v = c;
+                        if (a.ph.n_coils > 0) {
+                            C2<R> sk{R(0), R(0)};
+                            if (sl < T.count)
+                                sk = C2<R>{R(a.ph.sre[k * a.ph.n + T.spin0 + sl]), R(a.ph.sim[k * a.ph.n + T.spin0 + sl])};
+                            v = cmul(sk, c);
+                        }
+                        if (j != 0) v = C2<R>{R(0), R(0)};
+                        const R sr = wave_allsum(v.re);
+                        const R sim = wave_allsum(v.im);
+                        if (lane == 0) {
+                            red[wave][0] = (double)sr;
+                            red[wave][1] = (double)sim;
+                        }
+                        __syncthreads();
+                        if (tid == 0) {
+                            double tr = 0.0, ti = 0.0;
+                            for (int q = 0; q < G; ++q) {
+                                tr += red[q][0];
+                                ti += red[q][1];
+                            }
+                            reinterpret_cast<R2 *>(a.pa)[(k * a.n_rows + T.seg) * a.n_inline + ev.a0() + i] = R2{R(tr), R(ti)};
+                        }
+                        __syncthreads();
+                    }
+                    c = cmul(c, w);
+                }
+            }
+        }
+        if (si + 1 < a.s1) stage(buf ^ 1);
+        __syncthreads();
+    }
+    if (a.store && j == 0) {
         reinterpret_cast<R2 *>(a.mxy)[pidx] = R2{mr, mi};
         reinterpret_cast<R *>(a.mz)[pidx] = mz;
     }
@@ -1537,13 +1868,44 @@ __global__ __launch_bounds__(kWG) void k_upload(const uint4 *src, uint4 *dst, in
 
 static int check_launch() { return hipGetLastError() == hipSuccess ? 0 : -1; }
 
+// FP32 maps: up to 16 lanes per spin (1024-lane workgroups, 128 registers);
+// FP64 maps: up to 8 (their registers do not fit beside 1024 lanes).
+template <class P, bool MOV>
+static int launch_seqg(const SeqArgs &a, hipStream_t st) {
+    constexpr bool f32 = sizeof(typename P::R) == 4;
+    const dim3 grid((unsigned)a.n_tiles);
+    switch (a.lanes) {
+        case 2: hipLaunchKernelGGL((k_seqg<P, MOV, 2>), grid, dim3(kWave * 2), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_seqg<P, MOV, 4>), grid, dim3(kWave * 4), 0, st, a); break;
+        case 8: hipLaunchKernelGGL((k_seqg<P, MOV, 8>), grid, dim3(kWave * 8), 0, st, a); break;
+        case 16:
+            if constexpr (f32) {
+                hipLaunchKernelGGL((k_seqg<P, MOV, 16>), grid, dim3(kWave * 16), 0, st, a);
+                break;
+            }
+            return -1;
+        default: return -1;
+    }
+    return 0;
+}
+
 int launch_seq(bool fp64, bool moving, const SeqArgs &a, void *stream) {
     if (a.n_tiles <= 0 || a.e1 <= a.e0) return 0;
     // moving spins need all three velocity arrays (checked on the host)
     if (moving && (!a.ph.vx || !a.ph.vy || !a.ph.vz)) return -1;
     if (a.ph.n_coils < 0 || (a.ph.n_coils > 0 && (!a.ph.sre || !a.ph.sim))) return -1;
-    dim3 grid((unsigned)((a.n_tiles + kWavesPerWG - 1) / kWavesPerWG));
     hipStream_t st = (hipStream_t)stream;
+    if (a.lanes > 1) {
+        if (!a.segs || a.s1 < a.s0) return -1;
+        if (a.s1 == a.s0) return 0;
+        int r;
+        if (fp64)
+            r = moving ? launch_seqg<FP64, true>(a, st) : launch_seqg<FP64, false>(a, st);
+        else
+            r = moving ? launch_seqg<Mixed, true>(a, st) : launch_seqg<Mixed, false>(a, st);
+        return r != 0 ? r : check_launch();
+    }
+    dim3 grid((unsigned)((a.n_tiles + kWavesPerWG - 1) / kWavesPerWG));
     if (fp64) {
         if (moving)
             hipLaunchKernelGGL((k_seq<FP64, true>), grid, dim3(kWG), 0, st, a);

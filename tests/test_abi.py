@@ -41,6 +41,7 @@ def test_config_defaults(K):
     c = K.make_config()
     assert c.precision == K.KOMA_MIXED and c.wg_size == 256 and c.spins_per_lane == 0
     assert c.defer_min_adc == 32 and c.stretch_max == 128 and c.partial_budget == 1 << 30
+    assert c.tile_packing == 1
 
 
 @pytest.mark.parametrize("k,expect", [
@@ -56,7 +57,7 @@ def test_config_defaults(K):
 ])
 def test_host_plans_of_the_workloads(K, k, expect):
     sc, ph, seq = W.config(k)
-    info = K.koma_plan_info(sc, ph, seq, K.make_config())
+    info = K.koma_plan_info(sc, ph, seq, K.make_config(tile_packing=0))
     for key, v in expect.items():
         assert info[key] == v, (key, info[key], v)
     assert info["n_tiles"] == sum(-(-int(b - a) // 64) for a, b in zip(
@@ -251,3 +252,57 @@ def test_coil_plans_and_validation(K):
                                     ctypes.byref(info))
         assert st == -1
     assert p.n_coils == 8
+
+
+def _plan_tiles(K, ph, seq, **cfg):
+    i = K.koma_plan_info(W.Scanner(), ph, seq, K.make_config(**cfg))
+    return i["n_tiles"], i["n_rows"]
+
+
+def test_packed_tiles_cross_group_boundaries(K):
+    """Without deferred samples and with every non-empty group >= 64 spins,
+    wavefronts take 64 consecutive spins across groups: ceil(n / 64) tiles,
+    one more partial row for every tile a group boundary cuts."""
+    sc, ph, seq = W.config(4)  # 10,000 groups of 400 spins, one inline sample per TR
+    assert _plan_tiles(K, ph, seq, tile_packing=0) == (70000, 70000)
+    # boundaries at 400 g: inside a tile unless 400 g is a multiple of 64 (g % 4 == 0)
+    assert _plan_tiles(K, ph, seq) == (62500, 62500 + 7500)
+    rng = np.random.default_rng(5)
+    sizes = rng.integers(64, 300, 40)
+    sizes[[3, 17, 18]] = 0  # empty groups
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    n = int(off[-1])
+    sp = W.random_spins(rng, n)
+    sp.group_off = off
+    rseq = W.random_sequence(rng, 60, p_rf=0.3, p_adc=0.5)
+    cuts = sum(1 for b in off[1:-1] if b % 64 != 0 and b < n)
+    cut_tiles = len({int(b) // 64 for b in off[1:-1] if b % 64 != 0})
+    assert cuts >= cut_tiles > 0
+    assert _plan_tiles(K, sp, rseq, defer_min_adc=-1) == (-(-n // 64), -(-n // 64) + cut_tiles)
+    # a group below 64 spins, or deferred samples: per-group tiles
+    sizes2 = sizes.copy()
+    sizes2[5] = 10
+    sp.group_off = np.concatenate([[0], np.cumsum(sizes2)])
+    sp2 = W.random_spins(rng, int(sp.group_off[-1]))
+    sp2.group_off = sp.group_off
+    per_group = sum(-(-int(z) // 64) for z in sizes2)
+    assert _plan_tiles(K, sp2, rseq, defer_min_adc=-1) == (per_group, per_group)
+    _, eph, eseq = W.config(2)
+    eph.group_off = np.array([0, 30000, eph.n])
+    t, r = _plan_tiles(K, eph, eseq)
+    assert t == r == -(-30000 // 64) + -(-(eph.n - 30000) // 64)
+
+
+def test_lanes_per_spin_of_the_planner(K):
+    """Several lanes per spin while the tiles fill few wavefronts: the GRE
+    phantom (64 tiles) gets 16 in FP32 and 8 in FP64, the 1024-tile EPI two,
+    the 5e6-spin SE-EPI and the packed MRF batch one; a request for 1 or
+    another valid count is honoured, others are rejected."""
+    def lanes(k, prec="mixed", **kw):
+        sc, ph, seq = W.config(k)
+        return K.koma_plan_info(sc, ph, seq, K.make_config(prec, **kw))["lanes_per_spin"]
+    assert lanes(1) == 16 and lanes(1, "fp64") == 8
+    assert lanes(2) == 2 and lanes(4) == 1
+    assert lanes(1, lanes_per_spin=1) == 1 and lanes(1, lanes_per_spin=4) == 4
+    with pytest.raises(K.KomaError):
+        lanes(1, lanes_per_spin=3)

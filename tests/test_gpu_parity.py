@@ -387,3 +387,81 @@ def test_sample_engines_agree(ctx, key, prec):
     check(out[0], ref, prec, f"engine {key} matrix cores")
     check(out[1], ref, prec, f"engine {key} vector ALU")
     check(out[0], out[1], prec, f"engine {key} matrix cores vs vector ALU")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_packed_tiles_match_oracle(ctx, prec):
+    """Wavefronts across signal-group boundaries (packed tiles) sum each
+    group's lanes apart: the 40-entry MRF batch (400-spin groups) packed and
+    per group, and through the chunked request path; random groups of >= 64
+    spins with empty groups among them, with and without receive coils."""
+    import oracle
+    ref = oracle_cached("mrf40")
+    sc, ph, seq = case("mrf40")
+    out = {}
+    for packing in (1, 0):
+        ctx.set_config(prec, tile_packing=packing)
+        out[packing] = ctx.simulate(sc, ph, seq)
+        check(out[packing], ref, prec, f"mrf40 tile packing {packing}")
+    ctx.set_config(prec, tile_packing=1)
+    r = ctx.open(sc, ph, seq)
+    while not r.done():
+        r.advance(333)
+    assert np.array_equal(r.result(), out[1])
+    r.close()
+    rng = np.random.default_rng(61)
+    sizes = rng.integers(64, 200, 12)
+    sizes[[2, 7]] = 0
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    sp = W.random_spins(rng, int(off[-1]))
+    sp.group_off = off
+    rseq = W.random_sequence(rng, 200, p_rf=0.3, p_adc=0.5)
+    for n_coils in (0, 3):
+        phx = W.with_coils(sp, n_coils) if n_coils else sp
+        ref = oracle.simulate(sc, phx, rseq)
+        for packing in (1, 0):
+            ctx.set_config(prec, tile_packing=packing, defer_min_adc=-1)
+            check(ctx.simulate(sc, phx, rseq), ref, prec, f"random groups, {n_coils} coils, packing {packing}")
+    ctx.set_config(prec, tile_packing=1, defer_min_adc=32)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_several_lanes_per_spin_match_oracle(ctx, prec):
+    """Several lanes per spin: each lane composes the affine maps of a share
+    of every segment of excitation intervals and block ends, the lanes'
+    products are combined and applied. Every lane count against the oracle
+    on the GRE workload (sinc excitations, one lane per spin otherwise
+    latency-bound), random grids with inline samples, coils and moving spins;
+    the chunked request path (chunks end at segment ends) gives the bits of
+    one whole run."""
+    import oracle
+    sc, ph, seq = case("gre")
+    ref = oracle_cached("gre")
+    lanes = (1, 2, 4, 8) + ((16,) if prec == "mixed" else ())
+    for g in lanes:
+        ctx.set_config(prec, lanes_per_spin=g)
+        check(ctx.simulate(sc, ph, seq), ref, prec, f"gre, {g} lanes per spin")
+    rng = np.random.default_rng(71)
+    for trial in range(3):
+        rseq = W.random_sequence(rng, int(rng.integers(100, 500)), p_rf=0.5, p_adc=0.2)
+        sp = W.random_spins(rng, int(rng.integers(1, 200)))
+        if trial == 1:
+            sp = W.with_coils(sp, 2)
+        if trial == 2:
+            sp = W.with_velocity(sp, rng.uniform(-0.3, 0.3, 3), spread=0.2, seed=3)
+        rref = oracle.simulate(sc, sp, rseq)
+        for g in lanes:
+            for dm in (-1, 32):
+                ctx.set_config(prec, lanes_per_spin=g, defer_min_adc=dm)
+                check(ctx.simulate(sc, sp, rseq), rref, prec, f"random grid {trial}, {g} lanes, defer {dm}")
+    ph1 = ph.subset(np.arange(700))
+    for g in lanes[1:]:
+        ctx.set_config(prec, lanes_per_spin=g)
+        whole = ctx.simulate(sc, ph1, seq)
+        for chunk in (1, 37, 1000):
+            r = ctx.open(sc, ph1, seq)
+            while not r.done():
+                r.advance(chunk)
+            assert np.array_equal(r.result(), whole), (g, chunk)
+            r.close()
+    ctx.set_config(prec, lanes_per_spin=0, defer_min_adc=32)
