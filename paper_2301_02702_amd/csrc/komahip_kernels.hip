@@ -325,6 +325,15 @@ __device__ __forceinline__ void spinor_normalise(double &cs, double &sk, double 
 // One excitation interval (Eq. Rot_exc) followed by relaxation with the
 // cached eps = 1 - exp(-dt/T) (applied as M - eps*M, exact in the factor).
 // For moving spins gt holds the interval mean of G(t) t: Bz gains v . gt.
+//
+// The spinor of Eq. Rot_exc, alpha = cos(phi/2) - i n_z sin(phi/2), beta =
+// -i n_xy sin(phi/2), rotates M about n = B/|B| by phi. Its product is
+// applied in the equivalent Rodrigues form (the same matrix, fewer
+// operations): M' = cos(phi) M + sin(phi)/|B| (B x M) + (1 - cos phi)/|B|^2
+// B (B . M), with cos(phi) = cs^2 - sk^2 |B|^2, sin(phi)/|B| = 2 cs sk and
+// (1 - cos phi)/|B|^2 = 2 sk^2 from the normalised half-angle spinor
+// (cs = cos(phi/2), sk = sin(phi/2)/|B|), so the matrix stays orthogonal to
+// rounding whatever the errors of the hardware sine and square root.
 template <class P, bool MOV>
 __device__ __forceinline__ void excite_relax(const SpinP<typename P::R> &s, const typename P::R *q,
                                              const typename P::R *gt, double b1sq_exact,
@@ -345,27 +354,26 @@ __device__ __forceinline__ void excite_relax(const SpinP<typename P::R> &s, cons
     R sk = sn * inv;                   // sin(phi/2) / |B|
     // normalise the spinor, |alpha|^2 + |beta|^2 = cs^2 + sk^2 |B|^2 -> 1
     spinor_normalise(cs, sk, bz, nb2, b1sq_exact);
-    const R ar = cs, ai = -bz * sk;        // alpha = cos - i n_z sin
-    const R br = b1i * sk, bi = -b1r * sk;  // beta = -i (b1/|B|) sin
-    // conj(alpha)^2, beta^2, conj(alpha) beta, alpha beta
-    const R ur = ar * ar - ai * ai, ui = R(-2) * ar * ai;
-    const R vr = br * br - bi * bi, vi = R(2) * br * bi;
-    const R wr = ar * br + ai * bi, wi = ar * bi - ai * br;
-    const R pr = ar * br - ai * bi, pi = ar * bi + ai * br;
-    const R dz = (ar * ar + ai * ai) - (br * br + bi * bi);
-    // Mxy+ = 2 conj(a) b Mz + conj(a)^2 Mxy - b^2 conj(Mxy)
-    const R nr = R(2) * wr * mz + (ur - vr) * mr - (ui + vi) * mi;
-    const R ni = R(2) * wi * mz + (ur + vr) * mi + (ui - vi) * mr;
-    // Mz+ = (|a|^2 - |b|^2) Mz - 2 Re(a b conj(Mxy))
-    const R nz = dz * mz - R(2) * (pr * mr + pi * mi);
+    const R sk2 = sk * sk;
+    const R c = fma(-sk2, nb2, cs * cs);  // cos(phi)
+    const R sg = R(2) * cs * sk;          // sin(phi) / |B|
+    const R u = R(2) * sk2 * fma(b1r, mr, fma(b1i, mi, bz * mz));  // (1 - cos phi)/|B|^2 (B . M)
+    // B x M
+    const R xr = fma(b1i, mz, -bz * mi);
+    const R xi = fma(bz, mr, -b1r * mz);
+    const R xz = fma(b1r, mi, -b1i * mr);
+    const R nr = fma(c, mr, fma(sg, xr, u * b1r));
+    const R ni = fma(c, mi, fma(sg, xi, u * b1i));
+    const R nz = fma(c, mz, fma(sg, xz, u * bz));
     // relaxation: Mxy (1 - eps2), Mz - eps1 (Mz - M0)
     mr = fma(-eps2, nr, nr);
     mi = fma(-eps2, ni, ni);
     mz = fma(-eps1, nz - s.pd, nz);
 }
 
-// The rotation of one excitation interval (Eq. Rot_exc, the spinor as in
-// excite_relax) as a real 3 x 3 matrix on (Mx, My, Mz), row-major.
+// The rotation of one excitation interval (Eq. Rot_exc, in the Rodrigues
+// form of excite_relax) as a real 3 x 3 matrix on (Mx, My, Mz), row-major:
+// cos(phi) I + sin(phi)/|B| [B]x + (1 - cos phi)/|B|^2 B B^T.
 template <class P, bool MOV>
 __device__ __forceinline__ void rot_matrix(const SpinP<typename P::R> &s, const typename P::R *q,
                                            const typename P::R *gt, double b1sq_exact, typename P::R *m) {
@@ -381,21 +389,21 @@ __device__ __forceinline__ void rot_matrix(const SpinP<typename P::R> &s, const 
     P::sincos_turns(hs * nb, sn, cs);
     R sk = sn * inv;
     spinor_normalise(cs, sk, bz, nb2, b1sq_exact);
-    const R ar = cs, ai = -bz * sk;
-    const R br = b1i * sk, bi = -b1r * sk;
-    const R ur = ar * ar - ai * ai, ui = R(-2) * ar * ai;
-    const R vr = br * br - bi * bi, vi = R(2) * br * bi;
-    const R wr = ar * br + ai * bi, wi = ar * bi - ai * br;
-    const R pr = ar * br - ai * bi, pi = ar * bi + ai * br;
-    m[0] = ur - vr;
-    m[1] = -(ui + vi);
-    m[2] = R(2) * wr;
-    m[3] = ui - vi;
-    m[4] = ur + vr;
-    m[5] = R(2) * wi;
-    m[6] = R(-2) * pr;
-    m[7] = R(-2) * pi;
-    m[8] = (ar * ar + ai * ai) - (br * br + bi * bi);
+    const R sk2 = sk * sk;
+    const R c = fma(-sk2, nb2, cs * cs);
+    const R sg = R(2) * cs * sk;
+    const R t = R(2) * sk2;
+    const R tr = t * b1r, ti = t * b1i, tz = t * bz;
+    const R sr = sg * b1r, si = sg * b1i, sz = sg * bz;
+    m[0] = fma(tr, b1r, c);
+    m[1] = fma(tr, b1i, -sz);
+    m[2] = fma(tr, bz, si);
+    m[3] = fma(ti, b1r, sz);
+    m[4] = fma(ti, b1i, c);
+    m[5] = fma(ti, bz, -sr);
+    m[6] = fma(tz, b1r, -si);
+    m[7] = fma(tz, b1i, sr);
+    m[8] = fma(tz, bz, c);
 }
 
 // k identical excitation intervals (uniform k >= 1): one interval is the
