@@ -234,7 +234,7 @@ def load_stored(name, khash):
 
 def oracle_entries(sc, ph, seq, entries):
     import oracle
-    return np.stack([oracle.simulate(sc, ph.groups(int(e), int(e) + 1), seq, mode=oracle.MODE_BLOCK)[0, 0]
+    return np.stack([oracle.simulate(sc, ph.groups(int(e), int(e) + 1), seq, mode=oracle.MODE_BLOCK)[0]
                      for e in entries])
 
 

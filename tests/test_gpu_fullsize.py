@@ -42,7 +42,7 @@ def test_mrf_full_batch_sampled_entries(K):
     entries = np.sort(rng.choice(ph.n_groups, 48, replace=False))
     ctx = K.Context(0, "mixed")
     try:
-        ref = np.stack([oracle.simulate(sc, ph.groups(int(e), int(e) + 1), seq, mode=oracle.MODE_BLOCK)[0, 0]
+        ref = np.stack([oracle.simulate(sc, ph.groups(int(e), int(e) + 1), seq, mode=oracle.MODE_BLOCK)[0]
                         for e in entries])
         for prec in ("fp64", "mixed"):
             say(f"[full] mrf {prec}")

@@ -359,16 +359,30 @@ def test_minimal_grid_on_gpu_matches_raster_oracle(ctx, K, prec, which):
     """Sequence-aware time stepping end to end: the library discretises the
     block form of the sequence to its minimal grid (gradient vertices, RF
     samples, ADC points only) and the GPU simulates it; the result matches
-    the oracle on the raster grid of the same sequence."""
+    the oracle on the same minimal grid at the parity bar, and the oracle on
+    the raster grid of the same sequence within the bound of two FP64 phase
+    sums over different grids (64 eps x the largest accumulated phase, the
+    bound the discretiser's own pin uses) in the FP64 form, at the mixed bar
+    in the mixed form."""
+    import oracle
+    from tests.test_discretize import phase_scale
     sc, ph, ref_seq = case(which)
     blocks = W.gre_blocks() if which == "gre" else W.epi_blocks(n=64, ramp=8)
     m = K.koma_discretize(blocks)
     assert m.n_adc == ref_seq.n_adc and m.n_int < ref_seq.n_int
-    ref = oracle_cached(which)
+    ref_raster = oracle_cached(which)
+    ref_min = oracle.simulate(sc, ph, m, mode=oracle.MODE_BLOCK)
     ctx.set_config(prec)
     got = ctx.simulate(sc, ph, m)
     say(f"[minimal grid] {which} {prec}: {m.n_int} vs {ref_seq.n_int} intervals")
-    check(got, ref, prec, f"minimal grid {which} vs raster oracle")
+    check(got, ref_min, prec, f"minimal grid {which} vs oracle on the minimal grid")
+    if prec == "fp64":
+        bound = 64 * np.finfo(float).eps * phase_scale(ref_seq, ph)
+        e = float(np.max(nrmse(got, ref_raster)))
+        say(f"[minimal grid] {which}: NRMSE vs raster oracle {e:.3e} (grid bound {bound:.2e})")
+        assert e < bound
+    else:
+        check(got, ref_raster, prec, f"minimal grid {which} vs raster oracle")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
