@@ -506,6 +506,57 @@ def bench_extras(K, ctx, torch, W, out):
     out["extensions"] = ext
 
 
+PROFILE_WORKLOADS = {"gre64": 1, "epi256": 2, "mrf": 4, "seepi": 5}
+
+
+def profile_workload(K, ctx, torch, W, args):
+    """One workload only, for profiler runs (kernel traces, counters): the
+    named workload's simulation in the chosen forms (``--steps`` pipelined
+    steps after ``--warmup``), the MRF matching of a simulated dictionary
+    (``mrf_match``: ``--steps`` calls), or a plain 1 GiB device copy
+    (``copy``: the reference for scaling byte counters). Prints one JSON line
+    of times; no oracle, no CPU baseline."""
+    out = {"workload": args.workload, "steps": args.steps, "warmup": args.warmup}
+    forms = [f for f in args.forms.split(",") if f]
+    if args.workload == "copy":
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(max(args.steps, 1)):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_bytes_read"] = out["copy_bytes_written"] = a.numel() * 4
+        return out
+    if args.workload == "mrf_match":
+        sc, ph, seq = W.config(4)
+        _, s, _ = run_workload(K, ctx, torch, sc, ph, seq, "mixed", 1, 0)
+        d = s.astype(np.complex64)
+        n_pix = 65536
+        rng = np.random.default_rng(4040)
+        x = d[rng.integers(0, d.shape[0], n_pix)] * np.complex64(0.7 + 0.2j)
+        x = x + (0.02 * rng.normal(size=x.shape) * np.abs(x).max()).astype(np.float32)
+        dd = torch.from_numpy(np.stack([d.real, d.imag], -1)).to("cuda:0").contiguous()
+        xd = torch.from_numpy(np.stack([x.real, x.imag], -1).astype(np.float32)).to("cuda:0").contiguous()
+        best = torch.empty(n_pix, dtype=torch.int32, device="cuda:0")
+        proj = torch.empty((n_pix, 2), dtype=torch.float64, device="cuda:0")
+        for _ in range(args.warmup):
+            ctx.mrf_match(dd, xd, where="device", best=best, proj=proj)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.mrf_match(dd, xd, where="device", best=best, proj=proj)
+        torch.cuda.synchronize()
+        out["call_ms"] = round((time.perf_counter() - t0) / max(args.steps, 1) * 1e3, 4)
+        out.update(pixels=n_pix, entries=int(d.shape[0]), trs=int(d.shape[1]))
+        return out
+    sc, ph, seq = W.config(PROFILE_WORKLOADS[args.workload])
+    out.update(spins=ph.n, intervals=seq.n_int, adc=seq.n_adc)
+    for prec in forms:
+        t, _, _ = run_workload(K, ctx, torch, sc, ph, seq, prec, args.steps, args.warmup, 0, True)
+        out[f"{prec}_ms_per_step"] = round(t * 1e3, 4)
+        log(f"[bench] {args.workload} {prec}: {t * 1e3:.3f} ms/step")
+    return out
+
+
 def gpu_clocks():
     """Shader clock levels of the GPU as the driver reports them (sysfs,
     read-only), to put box-to-box differences in context; None if absent."""
@@ -535,6 +586,9 @@ def main():
     ap.add_argument("--cpu-spins-1t", type=int, default=1024, help="oracle subset on one thread")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration runs)")
+    ap.add_argument("--workload", choices=sorted(PROFILE_WORKLOADS) + ["mrf_match", "copy"], default=None,
+                    help="run only this workload and print its times (for profiler runs)")
+    ap.add_argument("--forms", default="mixed,fp64", help="precision forms of --workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: spins would shard across GPUs with one "
@@ -550,6 +604,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     khash = kernel_source_hash()
     ctx = K.Context(0, "mixed")
+    if args.workload:
+        out = profile_workload(K, ctx, torch, W, args)
+        out["kernel_hash"] = khash
+        ctx.close()
+        print(json.dumps(out), flush=True)
+        return
     out = bench_headline(K, ctx, torch, W, args, khash)
     out["kernel_hash"] = khash
     if not args.no_extra:

@@ -576,8 +576,8 @@ def config(k: int):
 
 
 WORKLOAD_NAMES = {
-    1: "gre64_fp64 (64x64 grid, 64 TR x 1000 int, 4096 ADC)",
-    2: "epi256_mixed (256x256 head, 128x128 EPI, 20374 int)",
+    1: "gre64 (64x64 grid, 64 TR x 1000 int, 4096 ADC)",
+    2: "epi256 (256x256 head, 128x128 EPI, 20374 int)",
     3: "serving_mix (1e3-1e6 spins, GRE/EPI/SE-EPI slice)",
     4: "mrf_fisp (100x100 T1/T2 x 400 iso, 1000 TR)",
     5: "seepi20x500 (5e6 spins, 20 slices, 327680 ADC)",
