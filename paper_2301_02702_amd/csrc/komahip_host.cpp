@@ -2129,7 +2129,7 @@ koma_status koma_mrf_match(koma_ctx *ctx, const float *dict, int64_t n_entries, 
     HIPCHK(ctx, hipSetDevice(ctx->device));
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     koma_status st;
-    const int64_t kp = (2 * n_t + 63) / 64 * 64;  // a multiple of every slice width the kernel may use
+    const int64_t kp = (2 * n_t + 127) / 128 * 128;  // a multiple of every slice width the kernel may use
     const int64_t n_ent_tiles = (n_entries + 127) / 128;
     const int64_t n_ent_pad = n_ent_tiles * 128;
     const int64_t n_pix_pad = (n_pix + 127) / 128 * 128;

@@ -33,6 +33,9 @@ namespace koma {
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+// 16-byte chunks as a native vector (HIP's uint4 is a struct whose copies
+// the compiler routes through private memory here)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMrfWG = 256;
 constexpr int kMrfWaves = 4;
@@ -118,63 +121,83 @@ __device__ __forceinline__ half8 times_i_conj(half8 v) {
 }
 
 // Workgroup tile: 128 pixels x 128 entries, staged through LDS in slices of
-// 32 binary16 values of the contraction axis (16 TR values), double
-// buffered. Wavefront w owns pixels 64 (w & 1) .. +63 and entries
-// 64 (w >> 1) .. +63 of the tile: 2 x 2 blocks of 32 x 32, each with a Re
-// and an Im accumulator (8 MFMA accumulators of 16 floats per lane).
+// kSlice binary16 values of the contraction axis, double buffered. Wavefront
+// w owns entries 64 (w >> 1) .. +63 and pixels 64 (w & 1) .. +63 of the tile:
+// 2 x 2 blocks of 32 x 32 with the entries as the MFMA rows and the pixels as
+// its columns, each with a Re and an Im accumulator (8 accumulators of 16
+// floats per lane). Lane l then holds one pixel (column l % 32) of each pixel
+// block and 16 entries (rows 8 (r / 4) + 4 (l / 32) + r % 4) of each entry
+// block, so its running best is one (score, entry) pair per pixel block: few
+// registers, and two wavefronts per SIMD.
 #ifndef KOMA_MRF_SLICE
-#define KOMA_MRF_SLICE 32
+#define KOMA_MRF_SLICE 64
 #endif
 #ifndef KOMA_MRF_MINW
-#define KOMA_MRF_MINW 1
+#define KOMA_MRF_MINW 2
+#endif
+#ifndef KOMA_MRF_SWIZZLE
+#define KOMA_MRF_SWIZZLE 1
 #endif
 constexpr int kSlice = KOMA_MRF_SLICE;  // halfs of the contraction axis per stage
-constexpr int kLdsRow = kSlice + 8; // padded row (80 bytes) against bank conflicts
+constexpr int kLdsRow = kSlice + 8;     // padded row against bank conflicts
 constexpr int kTileRows = 128;
 
 __global__ __launch_bounds__(kMrfWG, KOMA_MRF_MINW) void k_mrf_match(MrfArgs a) {
-    __shared__ __attribute__((aligned(16))) _Float16 lds[2][2][kTileRows * kLdsRow];  // [stage][A|B]
+    __shared__ __attribute__((aligned(16))) _Float16 lds[2][2][kTileRows * kLdsRow];  // [stage][pixels | entries]
+    __shared__ __attribute__((aligned(16))) float lw[2][kTileRows];  // 1 / ||entry||^2, by tile parity
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
     const int half = lane >> 5;  // k offset 8 * half within a 16-wide MFMA step
     const int col = lane & 31;   // MFMA row (A) / column (B) index of this lane
     const int wp = (wave & 1) * 64, we = (wave >> 1) * 64;
-    const int64_t P0 = (int64_t)blockIdx.x * kPixTile;
+    // Work item w = (pixel tile, split) with the split fastest. Workgroups
+    // are dispatched to the eight XCDs in turn (workgroup L to XCD L % 8), and
+    // each XCD has its own L2: XCD x takes a contiguous range of the work
+    // order, so the workgroups resident on one XCD at a time are a few pixel
+    // tiles times every split and share the fingerprint slices (one pixel
+    // tile, all splits) and the dictionary slices (one split, several pixel
+    // tiles) in their L2.
+    const int64_t L = blockIdx.x, n_wg = gridDim.x;
+#if KOMA_MRF_SWIZZLE
+    const int64_t per = n_wg / 8;
+    const int64_t w = L < 8 * per ? (L % 8) * per + L / 8 : L;
+#else
+    const int64_t w = L;
+#endif
+    const int64_t P0 = (w / a.n_split) * kPixTile;
+    const int64_t split = w % a.n_split;
     const int64_t kp = a.kp;
     const int n_stage = (int)(kp / kSlice);
 
-    // running best per lane: 2 pixel blocks x 16 rows, over the columns this lane has seen
-    float bs[2][16];
-    int32_t bi[2][16];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            bs[i][r] = -1.0f;
-            bi[i][r] = 0x7fffffff;
-        }
+    // running best per lane and pixel block over the entries this lane has seen
+    float bs[2] = {-1.0f, -1.0f};
+    int32_t bi[2] = {0x7fffffff, 0x7fffffff};
 
     // global -> LDS copy of a slice: kNC chunks of 16 bytes per row, kPer chunks
     // per thread and operand (chunk c = tid + 256 u: row c / kNC, part c % kNC)
     constexpr int kNC = kSlice / 8;
     constexpr int kPer = kTileRows * kNC / kMrfWG;
     const int cpart = tid % kNC;
-    const int64_t t0 = (int64_t)blockIdx.y * a.tiles_per_split;
+    const int64_t t0 = split * a.tiles_per_split;
     const int64_t t1 = min(t0 + a.tiles_per_split, a.n_ent_tiles);
     for (int64_t et = t0; et < t1; ++et) {
         const int64_t E0 = et * kTileRows;
-        const uint4 *ga[kPer], *gb[kPer];
-        uint4 ra[kPer], rb[kPer];
+        float *wt = lw[(et - t0) & 1];
+        // read after this tile's last barrier; the buffer was last read in
+        // the epilogue of tile et - 2, before the barriers of tile et - 1
+        if (tid < kTileRows) wt[tid] = a.inv_norm2[E0 + tid];
+        const u32x4 *ga[kPer], *gb[kPer];
+        u32x4 ra[kPer], rb[kPer];
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const int row = (tid + kMrfWG * u) / kNC;
-            ga[u] = reinterpret_cast<const uint4 *>(a.xh + (P0 + row) * kp + 8 * cpart);
-            gb[u] = reinterpret_cast<const uint4 *>(a.dh + (E0 + row) * kp + 8 * cpart);  // binary16 bits
+            ga[u] = reinterpret_cast<const u32x4 *>(a.xh + (P0 + row) * kp + 8 * cpart);
+            gb[u] = reinterpret_cast<const u32x4 *>(a.dh + (E0 + row) * kp + 8 * cpart);  // binary16 bits
             ra[u] = ga[u][0];
             rb[u] = gb[u][0];
         }
-        f32x16 acc[2][2][2];  // [pixel block][entry block][re, im]
+        f32x16 acc[2][2][2];  // [entry block][pixel block][re, im]
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -189,8 +212,8 @@ __global__ __launch_bounds__(kMrfWG, KOMA_MRF_MINW) void k_mrf_match(MrfArgs a) 
 #pragma unroll
             for (int u = 0; u < kPer; ++u) {
                 const int row = (tid + kMrfWG * u) / kNC;
-                *reinterpret_cast<uint4 *>(la + row * kLdsRow + 8 * cpart) = ra[u];
-                *reinterpret_cast<uint4 *>(lb + row * kLdsRow + 8 * cpart) = rb[u];
+                *reinterpret_cast<u32x4 *>(la + row * kLdsRow + 8 * cpart) = ra[u];
+                *reinterpret_cast<u32x4 *>(lb + row * kLdsRow + 8 * cpart) = rb[u];
             }
             __syncthreads();
             if (st + 1 < n_stage) {  // next slice in flight while this one is multiplied
@@ -203,76 +226,70 @@ __global__ __launch_bounds__(kMrfWG, KOMA_MRF_MINW) void k_mrf_match(MrfArgs a) 
             }
 #pragma unroll
             for (int kk = 0; kk < kSlice; kk += 16) {
-                half8 av[2], bv[2], bw[2];
+                half8 dv[2], dw[2], xv[2];
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
-                    av[i] = *reinterpret_cast<const half8 *>(la + (wp + 32 * i + col) * kLdsRow + kk + 8 * half);
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    bv[j] = *reinterpret_cast<const half8 *>(lb + (we + 32 * j + col) * kLdsRow + kk + 8 * half);
-                    bw[j] = times_i_conj(bv[j]);
+                for (int i = 0; i < 2; ++i) {
+                    dv[i] = *reinterpret_cast<const half8 *>(lb + (we + 32 * i + col) * kLdsRow + kk + 8 * half);
+                    dw[i] = times_i_conj(dv[i]);
                 }
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    xv[j] = *reinterpret_cast<const half8 *>(la + (wp + 32 * j + col) * kLdsRow + kk + 8 * half);
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
 #pragma unroll
                     for (int j = 0; j < 2; ++j) {
-                        acc[i][j][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av[i], bv[j], acc[i][j][0], 0, 0, 0);
-                        acc[i][j][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av[i], bw[j], acc[i][j][1], 0, 0, 0);
+                        acc[i][j][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(dv[i], xv[j], acc[i][j][0], 0, 0, 0);
+                        acc[i][j][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(dw[i], xv[j], acc[i][j][1], 0, 0, 0);
                     }
             }
             // the other buffer is written next; one barrier per stage suffices
             // because stage st + 1 writes buffer buf ^ 1, last read in stage st - 1
         }
         __syncthreads();  // all reads of this tile done before the next tile's first write
-        // score: this lane holds columns E0 + we + 32 j + col
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int64_t e = E0 + we + 32 * j + col;
-            const float w = a.inv_norm2[e];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const float re = acc[i][j][0][r], im = acc[i][j][1][r];
-                    const float s = w < 0.0f ? -1.0f : (re * re + im * im) * w;
-                    if (better(s, (int32_t)e, bs[i][r], bi[i][r])) {
-                        bs[i][r] = s;
-                        bi[i][r] = (int32_t)e;
-                    }
-                }
-        }
-    }
-    // best over the 32 columns of each half wave; then one lane per half wave writes
-    // its rows to the partial plane of (split, entry half of the tile)
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            float s = bs[i][r];
-            int32_t id = bi[i][r];
-#pragma unroll
-            for (int m = 1; m < 32; m <<= 1) {
-                const float os = __shfl_xor(s, m, 32);
-                const int32_t oi = __shfl_xor(id, m, 32);
-                if (better(os, oi, s, id)) {
-                    s = os;
-                    id = oi;
-                }
-            }
-            bs[i][r] = s;
-            bi[i][r] = id;
-        }
-    if (col == 0) {
-        const int64_t plane = (int64_t)blockIdx.y * 2 + (wave >> 1);
+        // score: this lane holds entries E0 + we + 32 i + 8 q + 4 half + t
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t p = P0 + wp + 32 * i + 8 * (r >> 2) + 4 * half + (r & 3);
-                const int64_t o = plane * a.n_pix_pad + p;
-                a.part_score[o] = bs[i][r];
-                a.part_idx[o] = bi[i][r];
+            for (int q = 0; q < 4; ++q) {
+                const int eo = we + 32 * i + 8 * q + 4 * half;
+                const float4 w4 = *reinterpret_cast<const float4 *>(wt + eo);
+                const float ww[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int r = 4 * q + t;
+                    const int32_t e = (int32_t)(E0 + eo + t);
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const float re = acc[i][j][0][r], im = acc[i][j][1][r];
+                        const float sc = ww[t] < 0.0f ? -1.0f : (re * re + im * im) * ww[t];
+                        if (better(sc, e, bs[j], bi[j])) {
+                            bs[j] = sc;
+                            bi[j] = e;
+                        }
+                    }
+                }
             }
+    }
+    // the two half waves hold the same pixels (other entry rows); then one lane
+    // per pixel writes the partial plane of (split, entry half of the tile)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const float os = __shfl_xor(bs[j], 32);
+        const int32_t oi = __shfl_xor(bi[j], 32);
+        if (better(os, oi, bs[j], bi[j])) {
+            bs[j] = os;
+            bi[j] = oi;
+        }
+    }
+    if (half == 0) {
+        const int64_t plane = split * 2 + (wave >> 1);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int64_t o = plane * a.n_pix_pad + P0 + wp + 32 * j + col;
+            a.part_score[o] = bs[j];
+            a.part_idx[o] = bi[j];
+        }
     }
 }
 
@@ -344,8 +361,9 @@ int launch_mrf_match(const MrfArgs &a, void *stream) {
     if (a.n_pix_pad % kPixTile || a.n_ent_tiles <= 0 || a.kp % kSlice || a.n_split <= 0 || a.n_split > 65535 ||
         a.n_planes != 2 * a.n_split)
         return -1;
-    dim3 grid((unsigned)(a.n_pix_pad / kPixTile), (unsigned)a.n_split);
-    hipLaunchKernelGGL(k_mrf_match, grid, dim3(kMrfWG), 0, (hipStream_t)stream, a);
+    const int64_t n_wg = a.n_pix_pad / kPixTile * a.n_split;
+    if (n_wg > 0x7fffffff) return -1;
+    hipLaunchKernelGGL(k_mrf_match, dim3((unsigned)n_wg), dim3(kMrfWG), 0, (hipStream_t)stream, a);
     return check_launch();
 }
 
