@@ -198,6 +198,31 @@ koma_status koma_simulate_async(koma_ctx *ctx, const koma_scanner *sc, const kom
                                 const koma_sequence *seq, void *hip_stream, double *sig,
                                 double *m_final, int32_t *status);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * simulation as koma_simulate_async, with the same arguments, semantics and
+ * results, but every buffer beyond the caller's inputs and outputs (packed
+ * event program, validation word, snapshots, signal partials, spin state)
+ * lives in one static device array of koma_noalloc_capacity() bytes
+ * (64 MiB), of which each GPU holds its own copy until the process ends. The
+ * call makes no device or pinned-host allocation: the packed tables go to the
+ * array by hipMemcpyAsync from the context's host plan, which returns once
+ * the host buffer has been read. Inputs and outputs are device-resident
+ * (KOMA_DEVICE); `status` (device int32, or NULL) receives the phantom's
+ * validation bits as for koma_simulate_async. A simulation whose buffers do
+ * not fit (the cross-workgroup partials of one launch are held to half the
+ * array) fails with KOMA_E_BUDGET before any device work, outputs untouched.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * there: calls that overlap on one GPU (other streams, other contexts, other
+ * host threads) race, so the caller orders them, e.g. on one stream. The
+ * context's own scratch is not touched, so other calls on the context need
+ * not wait for this one. */
+koma_status koma_simulate_noalloc(koma_ctx *ctx, const koma_scanner *sc, const koma_phantom *ph,
+                                  const koma_sequence *seq, void *hip_stream, double *sig,
+                                  double *m_final, int32_t *status);
+/* Bytes of the static array koma_simulate_noalloc works in. */
+size_t koma_noalloc_capacity(void);
+
 /* ---- chunked execution with device-resident state (serving) ------------
  * koma_req_open copies the phantom (host or device memory per `where`) and
  * the packed sequence into request-owned device buffers and initialises the

@@ -9,8 +9,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = [os.path.join(HERE, "csrc", f)
        for f in ("komahip_host.cpp", "komahip_discretize.cpp", "komahip_kernels.hip", "komahip_mrf.hip",
-                 "komahip_lowrank.hip")]
-DEPS = SRC + [os.path.join(HERE, "csrc", h) for h in ("komahip_internal.h", "komahip_mrf.h", "komahip_lowrank.h")] + \
+                 "komahip_lowrank.hip", "komahip_scratch.hip")]
+DEPS = SRC + [os.path.join(HERE, "csrc", h) for h in ("komahip_internal.h", "komahip_mrf.h", "komahip_lowrank.h",
+                                                           "komahip_scratch.h")] + \
     [os.path.join(ROOT, "include", "komahip.h")]
 LIB = os.path.join(HERE, "libkomahip.so")
 

@@ -30,6 +30,7 @@
 #include "komahip_internal.h"
 #include "komahip_lowrank.h"
 #include "komahip_mrf.h"
+#include "komahip_scratch.h"
 
 using namespace koma;
 
@@ -135,6 +136,10 @@ struct ProfRec {
 struct koma_ctx {
     int device = 0;
     int n_cu = 256;  // compute units of the device (the planner sizes grids by it)
+    // this device's static scratch (koma_simulate_noalloc), looked up once
+    // per device when the context is created
+    void *nz_scratch = nullptr;
+    hipError_t nz_err = hipSuccess;
     koma_config cfg{};
     hipStream_t stream = nullptr;
     std::string err;
@@ -1470,6 +1475,7 @@ koma_status koma_ctx_create(int device, const koma_config *cfg, koma_ctx **out) 
             ctx->n_cu = cus;
     }
     ctx->cfg = c;
+    ctx->nz_err = noalloc_scratch_attach(device, &ctx->nz_scratch);
     if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess) {
         delete ctx;
         return fail(nullptr, KOMA_E_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
@@ -1591,7 +1597,7 @@ koma_status koma_ctx_kernel_stats(koma_ctx *ctx, int kind, double *total_ms, int
 // async, the validation bits go to `status` (device) and nothing is waited for.
 static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const koma_phantom *ph,
                                     const koma_sequence *seq, koma_mem where, void *hip_stream, double *sig,
-                                    double *m_final, bool async, int32_t *status) {
+                                    double *m_final, bool async, int32_t *status, bool noalloc = false) {
     if (!ctx) return KOMA_E_ARG;
     if (ctx->poisoned) return fail(ctx, KOMA_E_DEVICE, "context poisoned by an earlier device error");
     ctx->err.clear();
@@ -1599,6 +1605,11 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
     if (where != KOMA_HOST && where != KOMA_DEVICE) return fail(ctx, KOMA_E_ARG, "bad koma_mem");
     if (async && where != KOMA_DEVICE)
         return fail(ctx, KOMA_E_ARG, "koma_simulate_async takes device-resident inputs and outputs");
+    if (noalloc && where != KOMA_DEVICE)
+        return fail(ctx, KOMA_E_ARG, "koma_simulate_noalloc takes device-resident inputs and outputs");
+    if (noalloc && !ctx->nz_scratch)
+        return fail(ctx, KOMA_E_DEVICE, "static scratch of device %d unavailable: %s", ctx->device,
+                    hipGetErrorString(ctx->nz_err));
     if ((st = check_scanner(ctx, sc)) != KOMA_OK) return st;
     if ((st = check_phantom_shape(ctx, ph)) != KOMA_OK) return st;
     if ((st = check_sequence(ctx, seq)) != KOMA_OK) return st;
@@ -1612,7 +1623,11 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
     if (ctx->async_pending) HIPCHK(ctx, hipStreamWaitEvent(s, ctx->async_done, 0));
 
     Plan &P = ctx->plan;
-    if ((st = build_plan(ctx, ctx->cfg, sc->gamma, ph, seq, P)) != KOMA_OK) return st;
+    koma_config pcfg = ctx->cfg;
+    // without allocation the cross-workgroup partials of a launch share the
+    // static scratch with the rest: at most half of it
+    if (noalloc) pcfg.partial_budget = std::min(pcfg.partial_budget, kNoallocScratchBytes / 2);
+    if ((st = build_plan(ctx, pcfg, sc->gamma, ph, seq, P)) != KOMA_OK) return st;
     if (ctx->cfg.hbm_budget && plan_footprint(P, fp64, m_final != nullptr, where == KOMA_HOST) > ctx->cfg.hbm_budget)
         return fail(ctx, KOMA_E_BUDGET, "footprint exceeds hbm_budget");
 
@@ -1639,11 +1654,12 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
     // if they are clean, and the host reads the word after the one
     // synchronisation at the end
     const bool dev_check = where == KOMA_DEVICE;
-    int32_t *flag_total = nullptr;
-    if (dev_check) {
-        if ((st = dev_reserve(ctx, ctx->s_vcount, 256)) != KOMA_OK) return st;
-        flag_total = (int32_t *)ctx->s_vcount.p;
-    }
+    const bool store = m_final != nullptr;
+    const size_t n_pad = (size_t)P.n_tiles * kWave;
+    const size_t nsig = (size_t)P.n_sig;
+    const size_t snap_b = (size_t)P.n_slots * n_pad * 2 * r;
+    const size_t pa_b = nsig * (size_t)P.n_rows * P.inl_k.size() * 2 * r;
+    const size_t pb_b = nsig * P.blocks.size() * (size_t)P.max_cols * 16;
 
     // packed tables: one pinned staging buffer, one upload
     struct Part {
@@ -1663,34 +1679,59 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
         pt.off = total;
         total += (pt.bytes + 255) & ~(size_t)255;
     }
-    koma_ctx::StageSlot &sl = ctx->ring[ctx->ring_next];
-    ctx->ring_next = (ctx->ring_next + 1) % koma_ctx::kStageRing;
-    // the host only learns from it that the upload kernel has read the
-    // staging: no memory fence when it is reached (a system-scope fence
-    // writes back and invalidates the caches ahead of the following kernels)
-    if (!sl.copied)
-        HIPCHK(ctx, hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming | hipEventDisableSystemFence));
-    if (sl.pending) HIPCHK(ctx, hipEventSynchronize(sl.copied));  // the host staging is free again
-    if (sl.h && sl.cap < total) {
-        HIPCHK(ctx, hipHostFree(sl.h));
-        sl.h = nullptr;
-        sl.cap = 0;
+    auto a256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    char *tb = nullptr;
+    int32_t *flag_total = nullptr;
+    char *nz = nullptr;  // next free byte of the static scratch
+    if (noalloc) {
+        // layout: validation word, packed tables, snapshots, partials, state
+        const size_t need = 256 + total + a256(snap_b) + a256(pa_b) + a256(pb_b) +
+                            (store ? a256(n_pad * 2 * r) + a256(n_pad * r) : 0);
+        if (need > kNoallocScratchBytes)
+            return fail(ctx, KOMA_E_BUDGET, "the simulation needs %zu bytes of scratch; the static scratch holds %zu",
+                        need, kNoallocScratchBytes);
+        nz = (char *)ctx->nz_scratch;
+        flag_total = (int32_t *)nz;
+        tb = nz + 256;
+        nz = tb + total;
+        for (auto &pt : parts)
+            if (pt.bytes) HIPCHK(ctx, hipMemcpyAsync(tb + pt.off, pt.src, pt.bytes, hipMemcpyHostToDevice, s));
+        // the validation word starts at zero (a kernel, not a memset node)
+        LAUNCH(ctx, K_AUX, 1, s, launch_upload(nullptr, nullptr, 0, flag_total, s));
+    } else {
+        if (dev_check) {
+            if ((st = dev_reserve(ctx, ctx->s_vcount, 256)) != KOMA_OK) return st;
+            flag_total = (int32_t *)ctx->s_vcount.p;
+        }
+        koma_ctx::StageSlot &sl = ctx->ring[ctx->ring_next];
+        ctx->ring_next = (ctx->ring_next + 1) % koma_ctx::kStageRing;
+        // the host only learns from it that the upload kernel has read the
+        // staging: no memory fence when it is reached (a system-scope fence
+        // writes back and invalidates the caches ahead of the following kernels)
+        if (!sl.copied)
+            HIPCHK(ctx, hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming | hipEventDisableSystemFence));
+        if (sl.pending) HIPCHK(ctx, hipEventSynchronize(sl.copied));  // the host staging is free again
+        if (sl.h && sl.cap < total) {
+            HIPCHK(ctx, hipHostFree(sl.h));
+            sl.h = nullptr;
+            sl.cap = 0;
+        }
+        if (!sl.h) {
+            HIPCHK(ctx, hipHostMalloc(&sl.h, total, hipHostMallocDefault));
+            sl.cap = total;
+        }
+        if (!ctx->h_flag) HIPCHK(ctx, hipHostMalloc((void **)&ctx->h_flag, 64, hipHostMallocDefault));
+        for (auto &pt : parts)
+            if (pt.bytes) memcpy((char *)sl.h + pt.off, pt.src, pt.bytes);
+        if ((st = dev_reserve(ctx, sl.d, total)) != KOMA_OK) return st;
+        // copied by a kernel that reads the pinned staging directly (no DMA copy)
+        void *hdev = nullptr;
+        HIPCHK(ctx, hipHostGetDevicePointer(&hdev, sl.h, 0));
+        LAUNCH(ctx, K_AUX, (int64_t)(total / 16), s, launch_upload(hdev, sl.d.p, total, flag_total, s));
+        HIPCHK(ctx, hipEventRecord(sl.copied, s));
+        sl.pending = true;
+        tb = (char *)sl.d.p;
     }
-    if (!sl.h) {
-        HIPCHK(ctx, hipHostMalloc(&sl.h, total, hipHostMallocDefault));
-        sl.cap = total;
-    }
-    if (!ctx->h_flag) HIPCHK(ctx, hipHostMalloc((void **)&ctx->h_flag, 64, hipHostMallocDefault));
-    for (auto &pt : parts)
-        if (pt.bytes) memcpy((char *)sl.h + pt.off, pt.src, pt.bytes);
-    if ((st = dev_reserve(ctx, sl.d, total)) != KOMA_OK) return st;
-    // copied by a kernel that reads the pinned staging directly (no DMA copy)
-    void *hdev = nullptr;
-    HIPCHK(ctx, hipHostGetDevicePointer(&hdev, sl.h, 0));
-    LAUNCH(ctx, K_AUX, (int64_t)(total / 16), s, launch_upload(hdev, sl.d.p, total, flag_total, s));
-    HIPCHK(ctx, hipEventRecord(sl.copied, s));
-    sl.pending = true;
-    char *tb = (char *)sl.d.p;
     B.ev = (const Event *)(tb + parts[0].off);
     B.st = (const Stretch *)(tb + parts[1].off);
     B.tiles = (const Tile *)(tb + parts[2].off);
@@ -1701,23 +1742,34 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
     B.def = (const int32_t *)(tb + parts[7].off);
     B.segs = (const SegEv *)(tb + parts[8].off);
 
-    const size_t n_pad = (size_t)P.n_tiles * kWave;
-    if ((st = dev_reserve(ctx, ctx->s_snap, (size_t)P.n_slots * n_pad * 2 * r)) != KOMA_OK) return st;
-    const size_t nsig = (size_t)P.n_sig;
-    if ((st = dev_reserve(ctx, ctx->s_pa, nsig * (size_t)P.n_rows * P.inl_k.size() * 2 * r)) != KOMA_OK) return st;
-    if ((st = dev_reserve(ctx, ctx->s_pb, nsig * P.blocks.size() * (size_t)P.max_cols * 16)) != KOMA_OK) return st;
-    const bool store = m_final != nullptr;
-    if (store) {
-        if ((st = dev_reserve(ctx, ctx->s_mxy, n_pad * 2 * r)) != KOMA_OK) return st;
-        if ((st = dev_reserve(ctx, ctx->s_mz, n_pad * r)) != KOMA_OK) return st;
-        if ((st = dev_reserve(ctx, ctx->s_mf, (size_t)ph->n * 24)) != KOMA_OK) return st;
+    if (noalloc) {
+        B.snap = nz;
+        nz += a256(snap_b);
+        B.pa = nz;
+        nz += a256(pa_b);
+        B.pb = (double *)nz;
+        nz += a256(pb_b);
+        if (store) {
+            B.mxy = nz;
+            nz += a256(n_pad * 2 * r);
+            B.mz = nz;
+        }
+    } else {
+        if ((st = dev_reserve(ctx, ctx->s_snap, snap_b)) != KOMA_OK) return st;
+        if ((st = dev_reserve(ctx, ctx->s_pa, pa_b)) != KOMA_OK) return st;
+        if ((st = dev_reserve(ctx, ctx->s_pb, pb_b)) != KOMA_OK) return st;
+        if (store) {
+            if ((st = dev_reserve(ctx, ctx->s_mxy, n_pad * 2 * r)) != KOMA_OK) return st;
+            if ((st = dev_reserve(ctx, ctx->s_mz, n_pad * r)) != KOMA_OK) return st;
+            if (!dev_check && (st = dev_reserve(ctx, ctx->s_mf, (size_t)ph->n * 24)) != KOMA_OK) return st;
+        }
+        B.snap = ctx->s_snap.p;
+        B.pa = ctx->s_pa.p;
+        B.pb = (double *)ctx->s_pb.p;
+        B.mxy = ctx->s_mxy.p;
+        B.mz = ctx->s_mz.p;
     }
     const size_t sig_n = nsig * (size_t)P.n_groups * P.n_adc * 2;  // doubles
-    B.snap = ctx->s_snap.p;
-    B.pa = ctx->s_pa.p;
-    B.pb = (double *)ctx->s_pb.p;
-    B.mxy = ctx->s_mxy.p;
-    B.mz = ctx->s_mz.p;
     if (dev_check) {
         // every sample of every signal plane is written by the final sums,
         // straight into the caller's buffer, gated by the validation flag
@@ -1740,6 +1792,11 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
     if (store)
         LAUNCH(ctx, K_AUX, (int64_t)n_pad, s, launch_export(fp64, B.tiles, P.n_tiles, B.mxy, B.mz, mf, B.gate, s));
     if (dev_check) {
+        if (noalloc) {
+            // the context's own scratch is untouched: later calls need not wait for this one
+            if (status) HIPCHK(ctx, hipMemcpyAsync(status, flag_total, 4, hipMemcpyDeviceToDevice, s));
+            return KOMA_OK;
+        }
         if (async) {
             if (status) HIPCHK(ctx, hipMemcpyAsync(status, flag_total, 4, hipMemcpyDeviceToDevice, s));
             // waited for by later calls on other streams (device-side
@@ -1779,6 +1836,14 @@ koma_status koma_simulate_async(koma_ctx *ctx, const koma_scanner *sc, const kom
                                 int32_t *status) {
     return simulate_enqueue(ctx, sc, ph, seq, KOMA_DEVICE, hip_stream, sig, m_final, true, status);
 }
+
+koma_status koma_simulate_noalloc(koma_ctx *ctx, const koma_scanner *sc, const koma_phantom *ph,
+                                  const koma_sequence *seq, void *hip_stream, double *sig, double *m_final,
+                                  int32_t *status) {
+    return simulate_enqueue(ctx, sc, ph, seq, KOMA_DEVICE, hip_stream, sig, m_final, false, status, true);
+}
+
+size_t koma_noalloc_capacity(void) { return kNoallocScratchBytes; }
 
 // ---------------------------------------------------------------- requests
 

@@ -102,6 +102,9 @@ EXPORTS = {
                               POINTER(koma_sequence), c_int, c_void_p, c_void_p, c_void_p]),
     "koma_simulate_async": (c_int, [c_void_p, POINTER(koma_scanner), POINTER(koma_phantom),
                                     POINTER(koma_sequence), c_void_p, c_void_p, c_void_p, c_void_p]),
+    "koma_simulate_noalloc": (c_int, [c_void_p, POINTER(koma_scanner), POINTER(koma_phantom),
+                                      POINTER(koma_sequence), c_void_p, c_void_p, c_void_p, c_void_p]),
+    "koma_noalloc_capacity": (c_size_t, []),
     "koma_req_open": (c_int, [c_void_p, POINTER(koma_scanner), POINTER(koma_phantom),
                               POINTER(koma_sequence), c_int, POINTER(c_void_p)]),
     "koma_req_advance": (c_int, [c_void_p, c_int64, c_void_p]),
@@ -392,7 +395,8 @@ class Context:
             z = z[0]
         return (z, m) if want_m else z
 
-    def bind_async(self, scanner, phantom, seq, sig, stream=None, m_final=None, status=None):
+    def bind_async(self, scanner, phantom, seq, sig, stream=None, m_final=None, status=None,
+                   noalloc: bool = False):
         """koma_simulate_async with its arguments marshalled once: returns a
         function of no arguments that enqueues one whole simulation (host
         packing included) on ``stream`` and returns without waiting. The
@@ -401,7 +405,9 @@ class Context:
         ``m_final`` None or a float64 GPU tensor ``[n, 3]``, ``status`` None or
         an int32 GPU tensor of one element that receives the phantom's
         validation bits (0: valid; otherwise the outputs are left untouched).
-        The tensors and arrays must stay alive until the work has run."""
+        The tensors and arrays must stay alive until the work has run.
+        ``noalloc``: koma_simulate_noalloc instead (the same work in the
+        library's static device scratch, no allocation)."""
         p, s = _PhantomArgs(phantom, True), _SeqArgs(seq)
         sc = make_scanner(scanner)
         if sig.numel() != 2 * p.n_sig * p.n_groups * s.n_adc or not sig.is_contiguous():
@@ -413,7 +419,7 @@ class Context:
         stream_h = None if stream is None else c_void_p(stream if isinstance(stream, int) else stream.cuda_stream)
         args = (self.h, ctypes.byref(sc), ctypes.byref(p.c), ctypes.byref(s.c), stream_h, _ptr(sig),
                 _ptr(m_final), _ptr(status))
-        fn = lib().koma_simulate_async
+        fn = lib().koma_simulate_noalloc if noalloc else lib().koma_simulate_async
         h = self.h
         keep = (p, s, sc, sig, m_final, status)
 
@@ -425,6 +431,11 @@ class Context:
     def simulate_async(self, scanner, phantom, seq, sig, stream=None, m_final=None, status=None):
         """koma_simulate_async once (see ``bind_async``)."""
         return self.bind_async(scanner, phantom, seq, sig, stream, m_final, status)()
+
+    def simulate_noalloc(self, scanner, phantom, seq, sig, stream=None, m_final=None, status=None):
+        """koma_simulate_noalloc once: ``simulate_async`` without any device
+        allocation (see ``bind_async``)."""
+        return self.bind_async(scanner, phantom, seq, sig, stream, m_final, status, noalloc=True)()
 
     def mrf_match(self, dictionary, fingerprints, where: str = "host", stream=None, best=None, proj=None):
         """koma_mrf_match. Host: complex ``[n_entries, n_t]`` and ``[n_pix, n_t]``
