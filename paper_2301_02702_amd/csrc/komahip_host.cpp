@@ -1124,9 +1124,11 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
 
     // ---- sample-parallel layout: blocks of 4*S tiles of one group
     const int64_t n_st = (int64_t)P.st.size();
-    // the matrix-core kernels take kMMStretches stretches per workgroup
+    // the matrix-core kernels take kMMStretches (FP32) or kMMStretches64
+    // (FP64) stretches per workgroup
     const bool mm = cfg.sample_engine == 0;
-    const int64_t st_per_wg = mm ? kMMStretches : 1;
+    const int64_t mm_batch = cfg.precision == KOMA_FP64 ? kMMStretches64 : kMMStretches;
+    const int64_t st_per_wg = mm ? mm_batch : 1;
     auto n_blocks_for = [&](int cand) {
         int64_t nb = 0;
         for (int64_t g = 0; g < P.n_groups; ++g) {
@@ -1147,7 +1149,7 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
         // within 2 % of it the largest (fewest partial rows).
         const int64_t slots =
             (int64_t)(cfg.precision == KOMA_FP64 ? kMMResident64 : kMMResident) * std::max(1, ctx->n_cu);
-        const int64_t batches = (n_st + kMMStretches - 1) / kMMStretches * std::max<int64_t>(1, P.n_coils);
+        const int64_t batches = (n_st + mm_batch - 1) / mm_batch * std::max<int64_t>(1, P.n_coils);
         double eff[17] = {};
         double best_eff = 0.0;
         for (int cand = 1; cand <= 16; ++cand) {
@@ -1188,7 +1190,7 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     // stretches per workgroup: keep >= ~16 workgroups per CU, share spin loads beyond that
     P.per_wg = 1;
     if (mm) {
-        P.per_wg = kMMStretches;
+        P.per_wg = mm_batch;
     } else if (n_st > 0) {
         const int64_t target = 4096;
         const int64_t wgs = n_blocks * n_st;
@@ -2195,10 +2197,11 @@ koma_status koma_mrf_match(koma_ctx *ctx, const float *dict, int64_t n_entries, 
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     koma_status st;
     const int64_t kp = (2 * n_t + 127) / 128 * 128;  // a multiple of every slice width the kernel may use
-    const int64_t n_ent_tiles = (n_entries + 127) / 128;
-    const int64_t n_ent_pad = n_ent_tiles * 128;
-    const int64_t n_pix_pad = (n_pix + 127) / 128 * 128;
-    const int64_t pix_tiles = n_pix_pad / 128;
+    const int64_t pt = mrf_pix_tile(), et = mrf_ent_tile();
+    const int64_t n_ent_tiles = (n_entries + et - 1) / et;
+    const int64_t n_ent_pad = n_ent_tiles * et;
+    const int64_t n_pix_pad = (n_pix + pt - 1) / pt * pt;
+    const int64_t pix_tiles = n_pix_pad / pt;
     // entry splits: enough workgroups to fill the chip several times over
     const int64_t n_split = std::max<int64_t>(1, std::min<int64_t>(n_ent_tiles, (2048 + pix_tiles - 1) / pix_tiles));
     const int64_t tiles_per_split = (n_ent_tiles + n_split - 1) / n_split;
@@ -2217,8 +2220,9 @@ koma_status koma_mrf_match(koma_ctx *ctx, const float *dict, int64_t n_entries, 
     if ((st = dev_reserve(ctx, ctx->m_dexp, (size_t)n_ent_pad * 4)) != KOMA_OK) return st;
     if ((st = dev_reserve(ctx, ctx->m_xexp, (size_t)n_pix_pad * 4)) != KOMA_OK) return st;
     if ((st = dev_reserve(ctx, ctx->m_inv, (size_t)n_ent_pad * 4)) != KOMA_OK) return st;
-    if ((st = dev_reserve(ctx, ctx->m_ps, (size_t)2 * n_split * n_pix_pad * 4)) != KOMA_OK) return st;
-    if ((st = dev_reserve(ctx, ctx->m_pi, (size_t)2 * n_split * n_pix_pad * 4)) != KOMA_OK) return st;
+    const int64_t n_planes = et / 64 * n_split;
+    if ((st = dev_reserve(ctx, ctx->m_ps, (size_t)n_planes * n_pix_pad * 4)) != KOMA_OK) return st;
+    if ((st = dev_reserve(ctx, ctx->m_pi, (size_t)n_planes * n_pix_pad * 4)) != KOMA_OK) return st;
     int32_t *d_best = best;
     double *d_proj = proj;
     if (where == KOMA_HOST) {
@@ -2243,7 +2247,7 @@ koma_status koma_mrf_match(koma_ctx *ctx, const float *dict, int64_t n_entries, 
     a.n_ent_tiles = n_ent_tiles;
     a.n_split = n_split;
     a.tiles_per_split = tiles_per_split;
-    a.n_planes = 2 * n_split;
+    a.n_planes = n_planes;
     a.part_score = (float *)ctx->m_ps.p;
     a.part_idx = (int32_t *)ctx->m_pi.p;
     // work units: complex multiply-adds of the contraction (8 real FLOP each)

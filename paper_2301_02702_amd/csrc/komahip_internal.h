@@ -107,7 +107,11 @@ constexpr int kWG = 256;            // 4 wavefronts
 constexpr int kWavesPerWG = kWG / kWave;
 constexpr int kBatch = 16;          // samples reduced together by the register transpose
 constexpr int kStretchMax = 128;
-constexpr int kMMStretches = 4;     // stretches whose sums one matrix-core workgroup keeps in registers
+#ifndef KOMA_MM_STRETCHES
+#define KOMA_MM_STRETCHES 4
+#endif
+constexpr int kMMStretches = KOMA_MM_STRETCHES;  // stretches whose sums one FP32 matrix-core workgroup keeps in registers
+constexpr int kMMStretches64 = 4;   // the same in FP64
 constexpr int kMMResident = 3;      // matrix-core workgroups resident per CU (LDS 48 KB, 168 VGPRs)
 constexpr int kMMResident64 = 1;    // the same in FP64 (LDS 96 KB)
 

@@ -492,6 +492,9 @@ static_assert(sizeof(Event) % 16 == 0, "Event is copied as 16-byte words");
 struct EvL {  // view of one staged event
     const uint32_t *u;
     __device__ __forceinline__ uint32_t word(int i) const { return u[i]; }
+    // a word every lane of the wavefront reads at the same address, as a
+    // scalar (so that branches and compares on it are scalar)
+    __device__ __forceinline__ uint32_t uword(int i) const { return __builtin_amdgcn_readfirstlane(u[i]); }
     __device__ __forceinline__ int kind() const { return (int)u[0]; }
     __device__ __forceinline__ int a0() const { return (int)u[1]; }
     __device__ __forceinline__ int count() const { return (int)u[2]; }
@@ -588,7 +591,11 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
         mz = reinterpret_cast<const R *>(a.mz)[pidx];
     }
     R eps1 = R(0), eps2 = R(0);
-    double dt_cached = -1.0;  // uniform
+    // bits of the interval length the relaxation factors were formed for, in
+    // the form's precision: the FP32 length (the FP64 one rounded) in the
+    // mixed form, so that lengths which differ only below FP32 resolution
+    // (the rounding of time-point differences) reuse the factors; uniform
+    uint32_t dt_lo = ~0u, dt_hi = ~0u;
     // no spin of this wavefront has off-resonance: zero-gradient excitation
     // intervals are then the same rotation for all of them (precomputed)
     const bool no_offres = __ballot(s.bz0 != R(0)) == 0;
@@ -602,18 +609,22 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
         if (!active) continue;
         for (int k = 0; k < n; ++k) {
             const EvL ev{reinterpret_cast<const uint32_t *>(lds_ev) + k * kEvWords};
-            const int kind = ev.kind();
+            const int kind = (int)ev.uword(0);
             if (kind == EV_RF) {
-                const double dt = ev.d(7);
-                if (dt != dt_cached) {  // uniform: same interval length for every spin
-                    dt_cached = dt;
-                    eps1 = P::one_minus_exp_neg(R(dt) * s.r1);
-                    eps2 = P::one_minus_exp_neg(R(dt) * s.r2);
+                constexpr bool f32 = sizeof(R) == 4;
+                const uint32_t lo = ev.uword(f32 ? 11 : 26), hi = f32 ? 0u : ev.uword(27);
+                if (lo != dt_lo || hi != dt_hi) {  // uniform: same interval length for every spin
+                    dt_lo = lo;
+                    dt_hi = hi;
+                    const R dt = f32 ? R(ev.f(7)) : R(ev.d(7));  // (the FP32 length is the FP64 one rounded)
+                    eps1 = P::one_minus_exp_neg(dt * s.r1);
+                    eps2 = P::one_minus_exp_neg(dt * s.r2);
                 }
-                const int reps = ev.count();  // identical consecutive intervals (uniform)
+                const int reps = (int)ev.uword(2);  // identical consecutive intervals (uniform)
+                const int rot = (int)ev.uword(3);
                 if (reps > 1) {
                     R m[9];
-                    if (ev.rot() >= 0 && no_offres) {
+                    if (rot >= 0 && no_offres) {
                         // the host's coefficients: Mxy_re' = c0 Mz + c1 Mxy_re + c2 Mxy_im, ...
                         const int perm[9] = {1, 2, 0, 5, 4, 3, 7, 8, 6};
 #pragma unroll
@@ -623,7 +634,7 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
 #pragma unroll
                         for (int i = 0; i < 7; ++i) q[i] = sizeof(R) == 4 ? R(ev.f(i)) : R(ev.d(i));
                         R gt[3] = {R(0), R(0), R(0)};
-                        if (MOV && ev.rot() < 0) {
+                        if (MOV && rot < 0) {
 #pragma unroll
                             for (int i = 0; i < 3; ++i) gt[i] = sizeof(R) == 4 ? R(ev.c32(i)) : R(ev.c64(i));
                         }
@@ -637,7 +648,7 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
 #pragma unroll
                     for (int i = 6; i < 9; ++i) m[i] = fma(-eps1, m[i], m[i]);
                     affine_power(m, eps1 * s.pd, reps, mr, mi, mz);
-                } else if (ev.rot() >= 0 && no_offres) {
+                } else if (rot >= 0 && no_offres) {
                     R c[9];
 #pragma unroll
                     for (int i = 0; i < 9; ++i) c[i] = sizeof(R) == 4 ? R(ev.c32(i)) : R(ev.c64(i));
@@ -652,7 +663,7 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
 #pragma unroll
                     for (int i = 0; i < 7; ++i) q[i] = sizeof(R) == 4 ? R(ev.f(i)) : R(ev.d(i));
                     R gt[3] = {R(0), R(0), R(0)};
-                    if (MOV && ev.rot() < 0) {  // (rot >= 0: G and G t are zero on the interval)
+                    if (MOV && rot < 0) {  // (rot >= 0: G and G t are zero on the interval)
 #pragma unroll
                         for (int i = 0; i < 3; ++i) gt[i] = sizeof(R) == 4 ? R(ev.c32(i)) : R(ev.c64(i));
                     }
@@ -684,7 +695,7 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
                 const double k0[4] = {ev.d(0), ev.d(1), ev.d(2), ev.d(3)};
                 const double dk[4] = {ev.d(4), ev.d(5), ev.d(6), ev.d(7)};
                 C2<R> c = cmul(C2<R>{mr, mi}, block_factor<P>(s, block_phase(s, k0), k0[3]));
-                const int cnt = ev.count();
+                const int cnt = (int)ev.uword(2);
                 C2<R> w{R(1), R(0)};
                 if (cnt > 1) w = block_factor<P>(s, block_phase(s, dk), dk[3]);
                 for (int i = 0; i < cnt; ++i) {
@@ -713,9 +724,10 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
 // a precession-block end the rotation by the block phase with the decay
 // over the block. The G lanes of a spin each compose the maps of a
 // contiguous share of a segment's events; the G products are combined by a
-// butterfly over the lanes (the later product after the earlier one, so
-// every lane ends with the same composite), which is applied to the state.
-// The same operators as the one-lane kernel, associated differently.
+// tree over the lanes (the later product after the earlier one), which
+// leaves the segment's composite on the spin's first lane, and that lane
+// applies it to the state it carries. The same operators as the one-lane
+// kernel, associated differently.
 template <class R>
 struct Aff {
     R a[9];  // row-major, on (Mx, My, Mz)
@@ -816,7 +828,10 @@ __device__ __forceinline__ Aff<typename P::R> event_map(const EvL &ev, const Spi
         m.b[2] = fma(-e1, s.pd, s.pd);
         return m;
     }
-    const double dt = ev.d(7);
+    // the factors depend on the interval length in the form's precision: the
+    // FP32 length (the FP64 one rounded) in the mixed form, so that lengths
+    // which differ only below FP32 resolution (time points' rounding) reuse them
+    const double dt = sizeof(R) == 4 ? (double)ev.f(7) : ev.d(7);
     if (dt != dt_cached) {
         dt_cached = dt;
         eps1 = P::one_minus_exp_neg(R(dt) * s.r1);
@@ -935,16 +950,19 @@ __global__ __launch_bounds__(kWave * G) void k_seqg(SeqArgs a) {
         if (L > 0) {  // uniform
             const int lo = (j * L) / G, hi = ((j + 1) * L) / G;
             Aff<R> m = aff_identity<R>();
-            for (int k = lo; k < hi; ++k) {
-                const EvL ev{base + k * kSegStride};
-                const Aff<R> e = event_map<P, MOV>(ev, s, no_offres, dt_cached, eps1, eps2);
-                m = k == lo ? e : aff_then(e, m);
+            if (lo < hi) {
+                m = event_map<P, MOV>(EvL{base + lo * kSegStride}, s, no_offres, dt_cached, eps1, eps2);
+                for (int k = lo + 1; k < hi; ++k) {
+                    const EvL ev{base + k * kSegStride};
+                    m = aff_then(event_map<P, MOV>(ev, s, no_offres, dt_cached, eps1, eps2), m);
+                }
             }
+            // tree over the shares: at step d, share j (a multiple of 2d) takes
+            // share j + d's product after its own, so share 0 ends with the
+            // composite of the segment (the other shares' products are not
+            // used, and share 0 alone carries the spin's state)
 #pragma unroll
-            for (int d = 1; d < G; d <<= 1) {
-                const Aff<R> o = aff_shfl_xor(m, d);
-                m = (j & d) ? aff_then(m, o) : aff_then(o, m);  // the later share after the earlier
-            }
+            for (int d = 1; d < G; d <<= 1) m = aff_then(aff_shfl_xor(m, d), m);
             aff_apply(m, mr, mi, mz);
         }
         if (obs) {  // uniform
@@ -1284,7 +1302,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
     // [wave][stretch of the pair][sample] (16 KB)
     __shared__ __attribute__((aligned(16))) float stage[kWavesPerWG][kWave * kStageFloats];
     static_assert(sizeof(double2) * kWavesPerWG * 2 * kStretchMax <= sizeof(stage), "sums fit in the stage");
-    static_assert(kMMStretches == 4, "two stretch pairs per batch");
+    static_assert(kMMStretches % 2 == 0, "whole stretch pairs per batch");
+    constexpr int NP = kMMStretches / 2;  // stretch pairs per batch
     double2(*red)[2][kStretchMax] = reinterpret_cast<double2(*)[2][kStretchMax]>(&stage[0][0]);
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -1312,9 +1331,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int64_t st1 = min(st0 + a.per_wg, a.s1);
     for (int64_t sb = st0; sb < st1; sb += kMMStretches) {
         const int nb = (int)min<int64_t>(kMMStretches, st1 - sb);  // uniform
-        f32x4 acc[2][3];
+        f32x4 acc[NP][3];
 #pragma unroll
-        for (int p = 0; p < 2; ++p) acc[p][0] = acc[p][1] = acc[p][2] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int p = 0; p < NP; ++p) acc[p][0] = acc[p][1] = acc[p][2] = f32x4{0.f, 0.f, 0.f, 0.f};
         for (int j = 0; j < S; ++j) {
             // the wavefront's tile (uniform: read through the scalar cache)
             const int tl = __builtin_amdgcn_readfirstlane(wave) + kWavesPerWG * j;
@@ -1353,7 +1372,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
                 return cmul(mm, mm_anchor(spn, r2, k0));
             };
 #pragma unroll
-            for (int p = 0; p < 2; ++p) {
+            for (int p = 0; p < NP; ++p) {
                 // a short batch repeats its last stretch (no branch around the
                 // products, so the sums keep their registers); the repeats are
                 // not stored
@@ -1440,9 +1459,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     // the next pair's snapshots arrive during these products
-                    if (p == 0 && pass == passes - 1) {
-                        load_snap(2);
-                        load_snap(3);
+                    if (p + 1 < NP && pass == passes - 1) {
+                        load_snap(2 * p + 2);
+                        load_snap(2 * p + 3);
                     }
                     // the three planes in two halves of 8 spin groups: reads
                     // first (one wait), then the products
@@ -1480,7 +1499,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
         // q = 4 ((l / 16) % 2) + v; column m
         const int half = e_lane >> 5;
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
+        for (int p = 0; p < NP; ++p) {
             if (2 * p >= nb) break;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -1595,7 +1614,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(1))) void k
     // [wave][stretch of the pair][sample]
     __shared__ __attribute__((aligned(16))) double stage[kWavesPerWG][kWave * kStage64];
     static_assert(sizeof(double2) * kWavesPerWG * 2 * kStretchMax <= sizeof(stage), "sums fit in the stage");
-    static_assert(kMMStretches == 4, "two stretch pairs per batch");
+    static_assert(kMMStretches64 == 4, "two stretch pairs per batch");
     double2(*red)[2][kStretchMax] = reinterpret_cast<double2(*)[2][kStretchMax]>(&stage[0][0]);
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -1613,16 +1632,16 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(1))) void k
 
     const int64_t st0 = a.s0 + (int64_t)blockIdx.y * a.per_wg;
     const int64_t st1 = min(st0 + a.per_wg, a.s1);
-    for (int64_t sb = st0; sb < st1; sb += kMMStretches) {
-        const int nb = (int)min<int64_t>(kMMStretches, st1 - sb);  // uniform
+    for (int64_t sb = st0; sb < st1; sb += kMMStretches64) {
+        const int nb = (int)min<int64_t>(kMMStretches64, st1 - sb);  // uniform
         // the batch's stretch parameters, read once into registers (with one
         // wavefront per SIMD a scalar reload per tile would wait in full)
         struct SP {
             double k0[4], dk[4];
             int fam, slot;
-        } sprm[kMMStretches];
+        } sprm[kMMStretches64];
 #pragma unroll
-        for (int i2 = 0; i2 < kMMStretches; ++i2) {
+        for (int i2 = 0; i2 < kMMStretches64; ++i2) {
             const auto &S_ = as_const(a.st)[sb + min(i2, nb - 1)];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -1643,9 +1662,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(1))) void k
             // tile's during this one's products measured no faster
             ParSpin spn{0.f, 0.f, 0.f, 0.f, __builtin_inff()};
             C2<double> sens{1.0, 0.0};
-            double2 snap[kMMStretches];
+            double2 snap[kMMStretches64];
 #pragma unroll
-            for (int i2 = 0; i2 < kMMStretches; ++i2) snap[i2] = make_double2(0.0, 0.0);
+            for (int i2 = 0; i2 < kMMStretches64; ++i2) snap[i2] = make_double2(0.0, 0.0);
             {
                 const auto &T = as_const(a.tiles)[B.tile0 + tl];
                 if (lane < T.count) {
@@ -1654,7 +1673,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(1))) void k
                     spn = ParSpin{a.ph.x[i], a.ph.y[i], a.ph.z[i], a.ph.dw[i], a.ph.t2[i]};
                     if (coils) sens = C2<double>{(double)a.ph.sre[coil * a.ph.n + i], (double)a.ph.sim[coil * a.ph.n + i]};
 #pragma unroll
-                    for (int i2 = 0; i2 < kMMStretches; ++i2)
+                    for (int i2 = 0; i2 < kMMStretches64; ++i2)
                         snap[i2] = reinterpret_cast<const double2 *>(a.snap)[(int64_t)sprm[i2].slot * n_pad + pidx];
                 }
             }

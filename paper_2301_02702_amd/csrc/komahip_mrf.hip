@@ -37,10 +37,18 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // the compiler routes through private memory here)
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kMrfWG = 256;
+constexpr int kMrfWG = 256;  // packing and final kernels
 constexpr int kMrfWaves = 4;
-constexpr int kPixTile = 128;  // pixels per workgroup
-constexpr int kEntTile = 128;  // entries per workgroup tile
+#ifndef KOMA_MRF_PT
+#define KOMA_MRF_PT 256
+#endif
+#ifndef KOMA_MRF_ET
+#define KOMA_MRF_ET 128
+#endif
+constexpr int kPixTile = KOMA_MRF_PT;  // pixels per matching workgroup
+constexpr int kEntTile = KOMA_MRF_ET;  // entries per matching workgroup tile
+constexpr int kPixWaves = kPixTile / 64, kEntWaves = kEntTile / 64;
+constexpr int kMatchWG = 64 * kPixWaves * kEntWaves;  // one 64 x 64 block per wavefront
 
 // ---------------------------------------------------------------- packing
 
@@ -120,9 +128,10 @@ __device__ __forceinline__ half8 times_i_conj(half8 v) {
     return r;
 }
 
-// Workgroup tile: 128 pixels x 128 entries, staged through LDS in slices of
-// kSlice binary16 values of the contraction axis, double buffered. Wavefront
-// w owns entries 64 (w >> 1) .. +63 and pixels 64 (w & 1) .. +63 of the tile:
+// Workgroup tile: kPixTile pixels x kEntTile entries, staged through LDS in
+// slices of kSlice binary16 values of the contraction axis, double buffered.
+// Wavefront w owns pixels 64 (w % kPixWaves) .. +63 and entries
+// 64 (w / kPixWaves) .. +63 of the tile:
 // 2 x 2 blocks of 32 x 32 with the entries as the MFMA rows and the pixels as
 // its columns, each with a Re and an Im accumulator (8 accumulators of 16
 // floats per lane). Lane l then holds one pixel (column l % 32) of each pixel
@@ -140,17 +149,17 @@ __device__ __forceinline__ half8 times_i_conj(half8 v) {
 #endif
 constexpr int kSlice = KOMA_MRF_SLICE;  // halfs of the contraction axis per stage
 constexpr int kLdsRow = kSlice + 8;     // padded row against bank conflicts
-constexpr int kTileRows = 128;
 
-__global__ __launch_bounds__(kMrfWG, KOMA_MRF_MINW) void k_mrf_match(MrfArgs a) {
-    __shared__ __attribute__((aligned(16))) _Float16 lds[2][2][kTileRows * kLdsRow];  // [stage][pixels | entries]
-    __shared__ __attribute__((aligned(16))) float lw[2][kTileRows];  // 1 / ||entry||^2, by tile parity
+__global__ __launch_bounds__(kMatchWG, KOMA_MRF_MINW) void k_mrf_match(MrfArgs a) {
+    __shared__ __attribute__((aligned(16))) _Float16 ldsa[2][kPixTile * kLdsRow];  // [stage] pixels
+    __shared__ __attribute__((aligned(16))) _Float16 ldsb[2][kEntTile * kLdsRow];  // [stage] entries
+    __shared__ __attribute__((aligned(16))) float lw[2][kEntTile];  // 1 / ||entry||^2, by tile parity
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
     const int half = lane >> 5;  // k offset 8 * half within a 16-wide MFMA step
     const int col = lane & 31;   // MFMA row (A) / column (B) index of this lane
-    const int wp = (wave & 1) * 64, we = (wave >> 1) * 64;
+    const int wp = (wave % kPixWaves) * 64, we = (wave / kPixWaves) * 64;
     // Work item w = (pixel tile, split) with the split fastest. Workgroups
     // are dispatched to the eight XCDs in turn (workgroup L to XCD L % 8), and
     // each XCD has its own L2: XCD x takes a contiguous range of the work
@@ -177,24 +186,27 @@ __global__ __launch_bounds__(kMrfWG, KOMA_MRF_MINW) void k_mrf_match(MrfArgs a) 
     // global -> LDS copy of a slice: kNC chunks of 16 bytes per row, kPer chunks
     // per thread and operand (chunk c = tid + 256 u: row c / kNC, part c % kNC)
     constexpr int kNC = kSlice / 8;
-    constexpr int kPer = kTileRows * kNC / kMrfWG;
+    constexpr int kPerA = kPixTile * kNC / kMatchWG, kPerB = kEntTile * kNC / kMatchWG;
+    static_assert(kPerA * kMatchWG == kPixTile * kNC && kPerB * kMatchWG == kEntTile * kNC, "whole chunks per thread");
     const int cpart = tid % kNC;
     const int64_t t0 = split * a.tiles_per_split;
     const int64_t t1 = min(t0 + a.tiles_per_split, a.n_ent_tiles);
     for (int64_t et = t0; et < t1; ++et) {
-        const int64_t E0 = et * kTileRows;
+        const int64_t E0 = et * kEntTile;
         float *wt = lw[(et - t0) & 1];
         // read after this tile's last barrier; the buffer was last read in
         // the epilogue of tile et - 2, before the barriers of tile et - 1
-        if (tid < kTileRows) wt[tid] = a.inv_norm2[E0 + tid];
-        const u32x4 *ga[kPer], *gb[kPer];
-        u32x4 ra[kPer], rb[kPer];
+        if (tid < kEntTile) wt[tid] = a.inv_norm2[E0 + tid];
+        const u32x4 *ga[kPerA], *gb[kPerB];
+        u32x4 ra[kPerA], rb[kPerB];
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int row = (tid + kMrfWG * u) / kNC;
-            ga[u] = reinterpret_cast<const u32x4 *>(a.xh + (P0 + row) * kp + 8 * cpart);
-            gb[u] = reinterpret_cast<const u32x4 *>(a.dh + (E0 + row) * kp + 8 * cpart);  // binary16 bits
+        for (int u = 0; u < kPerA; ++u) {
+            ga[u] = reinterpret_cast<const u32x4 *>(a.xh + (P0 + (tid + kMatchWG * u) / kNC) * kp + 8 * cpart);
             ra[u] = ga[u][0];
+        }
+#pragma unroll
+        for (int u = 0; u < kPerB; ++u) {  // binary16 bits
+            gb[u] = reinterpret_cast<const u32x4 *>(a.dh + (E0 + (tid + kMatchWG * u) / kNC) * kp + 8 * cpart);
             rb[u] = gb[u][0];
         }
         f32x16 acc[2][2][2];  // [entry block][pixel block][re, im]
@@ -207,22 +219,21 @@ __global__ __launch_bounds__(kMrfWG, KOMA_MRF_MINW) void k_mrf_match(MrfArgs a) 
             }
         for (int st = 0; st < n_stage; ++st) {
             const int buf = st & 1;
-            _Float16 *la = lds[buf][0];
-            _Float16 *lb = lds[buf][1];
+            _Float16 *la = ldsa[buf];
+            _Float16 *lb = ldsb[buf];
 #pragma unroll
-            for (int u = 0; u < kPer; ++u) {
-                const int row = (tid + kMrfWG * u) / kNC;
-                *reinterpret_cast<u32x4 *>(la + row * kLdsRow + 8 * cpart) = ra[u];
-                *reinterpret_cast<u32x4 *>(lb + row * kLdsRow + 8 * cpart) = rb[u];
-            }
+            for (int u = 0; u < kPerA; ++u)
+                *reinterpret_cast<u32x4 *>(la + ((tid + kMatchWG * u) / kNC) * kLdsRow + 8 * cpart) = ra[u];
+#pragma unroll
+            for (int u = 0; u < kPerB; ++u)
+                *reinterpret_cast<u32x4 *>(lb + ((tid + kMatchWG * u) / kNC) * kLdsRow + 8 * cpart) = rb[u];
             __syncthreads();
             if (st + 1 < n_stage) {  // next slice in flight while this one is multiplied
                 const int q = (st + 1) * kNC;
 #pragma unroll
-                for (int u = 0; u < kPer; ++u) {
-                    ra[u] = ga[u][q];
-                    rb[u] = gb[u][q];
-                }
+                for (int u = 0; u < kPerA; ++u) ra[u] = ga[u][q];
+#pragma unroll
+                for (int u = 0; u < kPerB; ++u) rb[u] = gb[u][q];
             }
 #pragma unroll
             for (int kk = 0; kk < kSlice; kk += 16) {
@@ -283,7 +294,7 @@ __global__ __launch_bounds__(kMrfWG, KOMA_MRF_MINW) void k_mrf_match(MrfArgs a) 
         }
     }
     if (half == 0) {
-        const int64_t plane = split * 2 + (wave >> 1);
+        const int64_t plane = split * kEntWaves + (wave / kPixWaves);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int64_t o = plane * a.n_pix_pad + P0 + wp + 32 * j + col;
@@ -358,14 +369,17 @@ int launch_mrf_pack(const float2 *src, int64_t n_rows, int64_t n_rows_pad, int64
 }
 
 int launch_mrf_match(const MrfArgs &a, void *stream) {
-    if (a.n_pix_pad % kPixTile || a.n_ent_tiles <= 0 || a.kp % kSlice || a.n_split <= 0 || a.n_split > 65535 ||
-        a.n_planes != 2 * a.n_split)
+    if (a.n_pix_pad % kPixTile || a.n_ent_tiles <= 0 || a.kp % kSlice || a.n_split <= 0 ||
+        a.n_planes != kEntWaves * a.n_split)
         return -1;
     const int64_t n_wg = a.n_pix_pad / kPixTile * a.n_split;
     if (n_wg > 0x7fffffff) return -1;
-    hipLaunchKernelGGL(k_mrf_match, dim3((unsigned)n_wg), dim3(kMrfWG), 0, (hipStream_t)stream, a);
+    hipLaunchKernelGGL(k_mrf_match, dim3((unsigned)n_wg), dim3(kMatchWG), 0, (hipStream_t)stream, a);
     return check_launch();
 }
+
+int mrf_pix_tile() { return kPixTile; }
+int mrf_ent_tile() { return kEntTile; }
 
 int launch_mrf_final(const MrfArgs &a, int32_t *best, double *proj, void *stream) {
     if (a.n_pix <= 0) return 0;
