@@ -50,9 +50,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(files=("komahip_kernels.hip", "komahip_internal.h")) -> str:
     h = hashlib.sha256()
-    for f in ("komahip_kernels.hip", "komahip_internal.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2301_02702_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -134,9 +134,11 @@ def per_launch(st, kind):
     return k["total_ms"] / max(k["launches"], 1), k["launches"] / st["steps"]
 
 
-def rooflines(info, st, prec, n_spins):
+def rooflines(info, st, prec, n_spins, traffic=None):
     """Roofline of every kernel of a step from the live HIP-event timing.
-    Units and per-unit work: the measurement section of the design notes."""
+    Units and per-unit work: the measurement section of the design notes.
+    ``traffic``: stored HBM bytes per launch by kernel (rocprofv3 counters of
+    the same kernels), turned into GB/s with the live launch times."""
     out = {}
     fp64 = prec == "fp64"
     # sample-parallel sums: dense contraction on the matrix cores
@@ -174,6 +176,18 @@ def rooflines(info, st, prec, n_spins):
     if st["reduce"]["launches"]:
         ms, lps = per_launch(st, "reduce")
         out["k_reduce"] = {"bound": "hbm", "avg_launch_ms": round(ms, 5), "launches_per_step": lps}
+    if traffic:
+        for name, r in out.items():
+            key = f"{name}:{prec}"
+            if key in traffic.get("kernels", {}):
+                b = traffic["kernels"][key]["bytes_per_launch"]
+                r["traffic"] = b
+                r["hbm_GBps"] = round(b / (r["avg_launch_ms"] * 1e-3) / 1e9, 2)
+                r["hbm_frac"] = round(r["hbm_GBps"] / PEAK_HBM, 5)
+                r["traffic_source"] = traffic["source"]
+        if "k_reduce" in out and "hbm_GBps" in out["k_reduce"]:
+            out["k_reduce"].update(achieved=out["k_reduce"]["hbm_GBps"], peak=PEAK_HBM, unit="GB/s",
+                                   frac=out["k_reduce"]["hbm_frac"])
     return out
 
 
@@ -249,16 +263,14 @@ def bench_headline(K, ctx, torch, W, args, khash):
     t_64, s_64, st_64 = run_workload(K, ctx, torch, sc, ph, seq, "fp64", args.steps, args.warmup, prof, True)
     log(f"[bench] seepi fp64, pipelined: {t_64 * 1e3:.2f} ms/step")
     events = ph.n * (info["n_rf_events"] + info["n_ends"] + info["n_adc"])
-    rl_mix = rooflines(info, st_mix, "mixed", ph.n)
-    rl_64 = rooflines(info, st_64, "fp64", ph.n)
+    traffic = load_stored("traffic_seepi.json", khash)
+    rl_mix = rooflines(info, st_mix, "mixed", ph.n, traffic)
+    rl_64 = rooflines(info, st_64, "fp64", ph.n, traffic)
     kms = {p: {k: round(v["total_ms"] / st["steps"], 3) for k, v in st.items() if k != "steps"}
            for p, st in (("mixed", st_mix), ("fp64", st_64))}
     dom = max(("k_par_mm", "par"), ("k_seq", "seq"), key=lambda kv: kms["mixed"][kv[1]])[0]
     roofline = dict(rl_mix[dom], kernel=dom)
-    traffic = load_stored(f"traffic_{dom}_seepi.json", khash)
-    roofline["traffic"] = traffic["bytes_per_launch"] if traffic else None
-    if traffic:
-        roofline["traffic_source"] = traffic["source"]
+    roofline.setdefault("traffic", None)
     flops = load_stored("flops_seepi.json", khash)
     out = {
         "metric": METRIC, "value": round(spin_steps / t_mix / 1e9, 3), "unit": "G spin-steps/s",
@@ -339,8 +351,7 @@ def bench_secondary(K, ctx, torch, W, args, out):
                                           "achieved": round(ach_v, 3), "peak": PEAK_FP32_VALU,
                                           "frac": round(ach_v / PEAK_FP32_VALU, 4)},
                              "vs_mfma": err(s_v, s_m)},
-         "error_vs_oracle": {"mixed": err(s_m, ref), "fp64": err(s_6, ref)},
-         "traffic_k_par_mm": load_stored("traffic_k_par_mm_epi256.json", out["kernel_hash"])}
+         "error_vs_oracle": {"mixed": err(s_m, ref), "fp64": err(s_6, ref)}}
     log(f"[bench] epi256: mixed {w['mixed_gsps']}, fp64 {w['fp64_gsps']} G spin-steps/s; vs oracle "
         f"{w['error_vs_oracle']}")
     wl = {"epi256": w}
@@ -350,12 +361,18 @@ def bench_secondary(K, ctx, torch, W, args, out):
         sck, phk, seqk = W.config(k)
         ss = phk.n * seqk.n_int
         infok = K.koma_plan_info(sck, phk, seqk, K.make_config("mixed"))
-        tm, sm, km = run_workload(K, ctx, torch, sck, phk, seqk, "mixed", 3, 1, 3)
-        t6, s6, k6 = run_workload(K, ctx, torch, sck, phk, seqk, "fp64", 3, 1, 3)
+        # a stream of simulations (pipelined) and one call at a time
+        n_pipe = 40 if k == 1 else 10
+        tm, sm, km = run_workload(K, ctx, torch, sck, phk, seqk, "mixed", n_pipe, 2, 3, True)
+        t6, s6, k6 = run_workload(K, ctx, torch, sck, phk, seqk, "fp64", n_pipe, 2, 3, True)
+        tm1, _, _ = run_workload(K, ctx, torch, sck, phk, seqk, "mixed", 5, 1)
+        t61, _, _ = run_workload(K, ctx, torch, sck, phk, seqk, "fp64", 5, 1)
         name = W.WORKLOAD_NAMES[k].split(" ")[0]
         w = {"spins": phk.n, "intervals": seqk.n_int, "spin_steps": ss,
              "mixed_gsps": round(ss / tm / 1e9, 3), "fp64_gsps": round(ss / t6 / 1e9, 3),
              "mixed_ms": round(tm * 1e3, 3), "fp64_ms": round(t6 * 1e3, 3),
+             "mixed_one_call_ms": round(tm1 * 1e3, 3), "fp64_one_call_ms": round(t61 * 1e3, 3),
+             "timing": "ms: pipelined stream of koma_simulate_async calls; one_call_ms: koma_simulate, synchronous",
              "events_per_spin": infok["n_rf_events"] + infok["n_ends"] + infok["n_adc"],
              "kernel_ms": {p: {kk: round(v["total_ms"] / st["steps"], 3) for kk, v in st.items() if kk != "steps"}
                            for p, st in (("mixed", km), ("fp64", k6))},
@@ -421,12 +438,15 @@ def bench_mrf_match(K, ctx, torch, dictionary, no_cpu, n_pix=65536, reps=5):
     flop = 8.0 * n_pix * n_e * n_t
     achieved = flop / (k_ms * 1e-3) / 1e12
     b = best.cpu().numpy()
+    traffic = load_stored("traffic_k_mrf_match.json", kernel_source_hash(("komahip_mrf.hip", "komahip_mrf.h")))
     out = {"pixels": n_pix, "entries": n_e, "trs": n_t, "call_ms": round(t_call * 1e3, 3),
            "kernel_ms": round(k_ms, 4), "flop_per_unit": 8,
            "unit_def": "one complex multiply-add of <d, x> (pixel x entry x TR)",
            "roofline": {"bound": "mfma", "kernel": "k_mrf_match (v_mfma_f32_32x32x16_f16, fused argmax)",
                         "achieved": round(achieved, 2), "peak": PEAK_FP16, "unit": "TFLOP/s",
-                        "frac": round(achieved / PEAK_FP16, 4)},
+                        "frac": round(achieved / PEAK_FP16, 4),
+                        "traffic": traffic["bytes_per_launch"] if traffic else None,
+                        "traffic_source": traffic["source"] if traffic else None},
            "recovered_fraction": float(np.mean(b == truth.cpu().numpy()))}
     if not no_cpu:  # against the FP64 definition on the caller's inputs, a seeded sample of pixels
         from oracle import mrf_match as M

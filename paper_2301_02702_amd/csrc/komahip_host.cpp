@@ -179,6 +179,10 @@ struct koma_ctx {
     // held + pooled total seen since the context was created
     size_t held_bytes = 0;
     size_t mem_peak = 0;
+    // bytes the request being opened has still to take (koma_req_open sets
+    // its footprint, every block taken counts down): a reused cached block
+    // may be larger than asked for, and must still leave room for the rest
+    size_t pool_reserve = 0;
     // scratch reused by koma_simulate (grow-only)
     DevMem s_ev, s_st, s_tiles, s_blocks, s_toff, s_boff, s_inl, s_def, s_snap, s_pa, s_pb, s_sig,
         s_mxy, s_mz, s_flags, s_vcount, s_mf, s_ph[kPhArrays];
@@ -258,10 +262,11 @@ static void dev_free(DevMem &m) {
 // device, which would stall every other request in flight, so blocks of
 // closed requests are kept and reused (smallest fit within 2x). With an HBM
 // budget, the blocks held by open requests plus the cached ones never exceed
-// it: a reused block must fit beside the held ones, and cached blocks are
-// released (largest first) before an allocation that would not fit. Every
-// block is a multiple of 256 bytes; plan_footprint counts the same sizes, so
-// a request whose footprint fits beside the held bytes always gets its memory.
+// it: a reused block must fit beside the held ones and the rest of the
+// request being opened, and cached blocks are released (largest first)
+// before an allocation that would not fit. Every block is a multiple of 256
+// bytes; plan_footprint counts the same sizes, so a request whose footprint
+// fits beside the held bytes always gets its memory.
 static size_t pool_round(size_t bytes) { return (std::max<size_t>(bytes, 16) + 255) & ~(size_t)255; }
 
 static void pool_trim(koma_ctx *ctx) {
@@ -273,19 +278,22 @@ static void pool_trim(koma_ctx *ctx) {
 static koma_status pool_get(koma_ctx *ctx, DevMem &m, size_t bytes) {
     bytes = pool_round(bytes);
     const size_t budget = ctx->cfg.hbm_budget;
+    const size_t rest = ctx->pool_reserve > bytes ? ctx->pool_reserve - bytes : 0;  // after this block
     auto it = ctx->pool.lower_bound(bytes);
-    if (it != ctx->pool.end() && it->first <= 2 * bytes && (!budget || ctx->held_bytes + it->first <= budget)) {
+    if (it != ctx->pool.end() && it->first <= 2 * bytes &&
+        (!budget || ctx->held_bytes + it->first + rest <= budget)) {
         m.p = it->second;
         m.cap = it->first;
         ctx->pool_bytes -= it->first;
         ctx->pool.erase(it);
         ctx->held_bytes += m.cap;
+        ctx->pool_reserve = rest;
         return KOMA_OK;
     }
     if (budget) {
-        if (ctx->held_bytes + bytes > budget)
+        if (ctx->held_bytes + bytes + rest > budget)
             return fail(ctx, KOMA_E_BUDGET, "device memory of open requests would exceed hbm_budget (%zu + %zu > %zu)",
-                        ctx->held_bytes, bytes, budget);
+                        ctx->held_bytes, bytes + rest, budget);
         while (!ctx->pool.empty() && ctx->held_bytes + ctx->pool_bytes + bytes > budget) {
             auto last = std::prev(ctx->pool.end());
             (void)hipFree(last->second);
@@ -306,6 +314,7 @@ static koma_status pool_get(koma_ctx *ctx, DevMem &m, size_t bytes) {
     }
     m.cap = bytes;
     ctx->held_bytes += bytes;
+    ctx->pool_reserve = rest;
     ctx->mem_peak = std::max(ctx->mem_peak, ctx->held_bytes + ctx->pool_bytes);
     return KOMA_OK;
 }
@@ -1907,10 +1916,18 @@ koma_status koma_req_open(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
         return fail(ctx, KOMA_E_BUDGET, "request footprint %zu exceeds hbm_budget %zu", q->footprint,
                     ctx->cfg.hbm_budget);
     }
+    if (ctx->cfg.hbm_budget && ctx->held_bytes + q->footprint > ctx->cfg.hbm_budget) {
+        const size_t held = ctx->held_bytes, need = q->footprint;
+        delete q;
+        return fail(ctx, KOMA_E_BUDGET, "open requests hold %zu bytes; %zu more would exceed hbm_budget %zu", held,
+                    need, ctx->cfg.hbm_budget);
+    }
     hipStream_t s = ctx->stream;
     const size_t r = q->fp64 ? 8 : 4;
     const size_t n_pad = (size_t)P.n_tiles * kWave;
+    ctx->pool_reserve = q->footprint;  // counted down by every block taken below
     auto bail = [&](koma_status e) {
+        ctx->pool_reserve = 0;
         (void)hipStreamSynchronize(s);
         req_free(q);
         delete q;
@@ -1945,6 +1962,7 @@ koma_status koma_req_open(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
         Bufs B = req_bufs(q);
         if ((st = validate_device_phantom(ctx, B.ph, ph->n, ctx->s_flags, s)) != KOMA_OK) return bail(st);
     }
+    ctx->pool_reserve = 0;
     hipError_t e = hipStreamSynchronize(s);  // inputs are copied before the caller's buffers may change
     if (e != hipSuccess) return bail(fail(ctx, KOMA_E_DEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e)));
     *out = q;

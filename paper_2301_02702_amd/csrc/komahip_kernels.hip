@@ -1244,6 +1244,27 @@ __global__ __launch_bounds__(kWG) void k_par_mov(ParArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- work order
+//
+// The matrix-core sample kernels run a grid of (spin block) x (stretch
+// batch) workgroups. Launched in the order x fastest, the batches of one
+// spin block would be a whole row of spin blocks apart, and every batch
+// would fetch the block's spin data again from memory. Workgroups are
+// dispatched to the eight XCDs in turn (workgroup L to XCD L % 8), each with
+// its own L2, so XCD x takes a contiguous range of the order (spin block,
+// then batch): the workgroups resident on one XCD at a time are the batches
+// of a few spin blocks, and share those blocks' data in its L2.
+struct ParWG {
+    int64_t blk, batch;
+};
+__device__ __forceinline__ ParWG par_work_item() {
+    const int64_t nx = gridDim.x, ny = gridDim.y;
+    const int64_t L = (int64_t)blockIdx.x + nx * (int64_t)blockIdx.y;  // dispatch order within a z plane
+    const int64_t per = nx * ny / 8;
+    const int64_t w = L < 8 * per ? (L % 8) * per + L / 8 : L;
+    return {w / ny, w % ny};
+}
+
 // ---------------------------------------------------------------- k_par_mm
 //
 // The mixed-precision sample-parallel kernel on the matrix cores. For one
@@ -1307,7 +1328,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
     double2(*red)[2][kStretchMax] = reinterpret_cast<double2(*)[2][kStretchMax]>(&stage[0][0]);
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const Block B = a.blocks[blockIdx.x];
+    const ParWG wg = par_work_item();
+    const Block B = a.blocks[wg.blk];
     const int64_t n_pad = a.n_tiles * kWave;
     const int64_t coil = blockIdx.z;  // 0 without receive coils
     const bool coils = a.ph.n_coils > 0;
@@ -1327,7 +1349,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int a_wr = 16 * lane, a_sw = (lane >> 1) & 3;
     const int b_wr = 32 * lane, b_sw = lane & 7;
 
-    const int64_t st0 = a.s0 + (int64_t)blockIdx.y * a.per_wg;
+    const int64_t st0 = a.s0 + wg.batch * a.per_wg;
     const int64_t st1 = min(st0 + a.per_wg, a.s1);
     for (int64_t sb = st0; sb < st1; sb += kMMStretches) {
         const int nb = (int)min<int64_t>(kMMStretches, st1 - sb);  // uniform
@@ -1520,7 +1542,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
                         t.x += red[wv][h][k].x;
                         t.y += red[wv][h][k].y;
                     }
-                    reinterpret_cast<double2 *>(a.pb)[(coil * a.n_blocks + (int64_t)blockIdx.x) * a.cols + (d0 - a.col0) + k] = t;
+                    reinterpret_cast<double2 *>(a.pb)[(coil * a.n_blocks + wg.blk) * a.cols + (d0 - a.col0) + k] = t;
                 }
             }
             __syncthreads();
@@ -1618,7 +1640,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(1))) void k
     double2(*red)[2][kStretchMax] = reinterpret_cast<double2(*)[2][kStretchMax]>(&stage[0][0]);
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const Block B = a.blocks[blockIdx.x];
+    const ParWG wg = par_work_item();
+    const Block B = a.blocks[wg.blk];
     const int64_t n_pad = a.n_tiles * kWave;
     const int64_t coil = blockIdx.z;  // 0 without receive coils
     const bool coils = a.ph.n_coils > 0;
@@ -1630,7 +1653,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(1))) void k
     //   8 h + q is A[q] of stretch h of the pair) at 16 s + 2 (c ^ (s & 7)).
     const int m = lane & 15, g = lane >> 4;  // row (A) / column (B) m; spin 4u + g of group u
 
-    const int64_t st0 = a.s0 + (int64_t)blockIdx.y * a.per_wg;
+    const int64_t st0 = a.s0 + wg.batch * a.per_wg;
     const int64_t st1 = min(st0 + a.per_wg, a.s1);
     for (int64_t sb = st0; sb < st1; sb += kMMStretches64) {
         const int nb = (int)min<int64_t>(kMMStretches64, st1 - sb);  // uniform
@@ -1794,7 +1817,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(1))) void k
                         t.x += red[wv][h][k].x;
                         t.y += red[wv][h][k].y;
                     }
-                    reinterpret_cast<double2 *>(a.pb)[(coil * a.n_blocks + (int64_t)blockIdx.x) * a.cols + (d0 - a.col0) + k] = t;
+                    reinterpret_cast<double2 *>(a.pb)[(coil * a.n_blocks + wg.blk) * a.cols + (d0 - a.col0) + k] = t;
                 }
             }
             __syncthreads();

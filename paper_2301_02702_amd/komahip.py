@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkomahip.so")
 
 KOMA_OK = 0
+KOMA_E_BUDGET = -5
 STATUS = {0: "KOMA_OK", -1: "KOMA_E_ARG", -2: "KOMA_E_PHANTOM", -3: "KOMA_E_SEQUENCE",
           -4: "KOMA_E_NOMEM", -5: "KOMA_E_BUDGET", -6: "KOMA_E_DEVICE", -7: "KOMA_E_CANCELLED",
           -8: "KOMA_E_STATE"}

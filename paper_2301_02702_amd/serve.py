@@ -142,8 +142,14 @@ class Server:
                 job.admit = time.perf_counter() - t0
                 try:
                     req = self.ctx.open(job.scanner, job.phantom, job.seq, "host")
-                except K.KomaError as e:  # a bad request fails alone
-                    job.status, job.error = "failed", str(e)
+                except K.KomaError as e:
+                    if e.status == K.KOMA_E_BUDGET and active:
+                        # the device memory the open requests hold (their blocks
+                        # may be larger than their footprints) leaves no room
+                        # now: the request waits for one of them to finish
+                        queue.insert(k, job)
+                        break
+                    job.status, job.error = "failed", str(e)  # a bad request fails alone
                     job.finish = time.perf_counter() - t0
                     done.append(job)
                     continue
