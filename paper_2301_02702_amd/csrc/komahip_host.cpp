@@ -794,6 +794,7 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     // at, its start time and its G t means (moving spins)
     int64_t rf_run_end = -1;
     double rf_run_t0 = 0.0, rf_run_gt[3] = {0, 0, 0};
+    double rf_dt_ref = -1.0;  // reference interval length of the excitation events (Event::dt_ref)
 
     P.def_k.reserve((size_t)q->n_adc);
     const double *__restrict T = q->t;
@@ -1002,6 +1003,8 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
                 e.f[c] = (float)v[c];
             }
             e.b1sq_f32 = (double)e.f[3] * (double)e.f[3] + (double)e.f[4] * (double)e.f[4];
+            if (!(rf_dt_ref > 0.0 && std::fabs(dtr - rf_dt_ref) <= dtr * 0x1p-30)) rf_dt_ref = dtr;
+            e.dt_ref = rf_dt_ref;
             e.rot = -1;
             if (moving) {
                 for (int c = 0; c < 3; ++c) {

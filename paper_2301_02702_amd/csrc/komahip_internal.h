@@ -42,7 +42,13 @@ struct alignas(16) Event {
     double d[8];
     // EV_RF: exact |b1|^2 of the FP32-rounded b1 (f[3], f[4]) for the FP32 kernel.
     double b1sq_f32;
-    double pad2;
+    // EV_RF: a reference interval length within 2^-30 (relative) of d[7], the
+    // same for every such run of lengths (time points' rounding makes
+    // nominally equal lengths differ in their last bits); the FP64 kernel
+    // forms the relaxation factors at it and moves them to d[7] exactly:
+    // 1 - e^-(t + h) r = eps(t) + (1 - eps(t)) (1 - e^-h r), with 1 - e^-h r =
+    // h r to within (h r)^2 / 2
+    double dt_ref;
     // EV_RF with zero gradient (rot >= 0): the interval's rotation for spins
     // without off-resonance (Bz = 0, the same field for all of them), the
     // spinor update of Eq. Rot_exc computed once on the host in FP64:

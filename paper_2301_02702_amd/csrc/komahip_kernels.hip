@@ -506,6 +506,9 @@ struct EvL {  // view of one staged event
     __device__ __forceinline__ double b1sq() const {
         return __builtin_bit_cast(double, ((uint64_t)u[29] << 32) | u[28]);
     }
+    __device__ __forceinline__ double dt_ref() const {
+        return __builtin_bit_cast(double, ((uint64_t)u[31] << 32) | u[30]);
+    }
     __device__ __forceinline__ float c32(int i) const { return __uint_as_float(u[32 + i]); }
     __device__ __forceinline__ double c64(int i) const {
         return __builtin_bit_cast(double, ((uint64_t)u[44 + 2 * i + 1] << 32) | u[44 + 2 * i]);
@@ -552,6 +555,27 @@ __device__ __forceinline__ void inline_sample(const SeqArgs &a, const Tile &T, i
     }
 }
 
+// Relaxation factors eps = 1 - exp(-dt/T) of an excitation event from the
+// factors cached for a key length (eps1c, eps2c). Mixed form: the key is the
+// FP32 length itself, so the cached factors are the event's. FP64 form: the
+// key is the event's reference length (Event::dt_ref, within 2^-30 of dt),
+// and the factors are moved to the event's own length h = dt - dt_ref away:
+// 1 - e^-(t + h) r = eps(t) + (1 - eps(t)) h r, exact to within
+// (1 - eps) (h r)^2 / 2, far below an ulp of eps.
+template <class P>
+__device__ __forceinline__ void event_eps(const EvL &ev, const SpinP<typename P::R> &s, typename P::R eps1c,
+                                          typename P::R eps2c, typename P::R &eps1, typename P::R &eps2) {
+    using R = typename P::R;
+    if constexpr (sizeof(R) == 4) {
+        eps1 = eps1c;
+        eps2 = eps2c;
+    } else {
+        const double h = ev.d(7) - ev.dt_ref();  // exact: the two are within 2^-30 of each other
+        eps1 = fma(h * s.r1, 1.0 - eps1c, eps1c);
+        eps2 = fma(h * s.r2, 1.0 - eps2c, eps2c);
+    }
+}
+
 template <class P, bool MOV>
 __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
     using R = typename P::R;
@@ -590,11 +614,12 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
         mi = m.y;
         mz = reinterpret_cast<const R *>(a.mz)[pidx];
     }
-    R eps1 = R(0), eps2 = R(0);
-    // bits of the interval length the relaxation factors were formed for, in
-    // the form's precision: the FP32 length (the FP64 one rounded) in the
-    // mixed form, so that lengths which differ only below FP32 resolution
-    // (the rounding of time-point differences) reuse the factors; uniform
+    R eps1c = R(0), eps2c = R(0);
+    // bits of the key length the cached relaxation factors were formed for:
+    // the FP32 length (the FP64 one rounded) in the mixed form, so that
+    // lengths which differ only below FP32 resolution (the rounding of
+    // time-point differences) reuse the factors; the event's reference length
+    // in the FP64 form (see event_eps); uniform
     uint32_t dt_lo = ~0u, dt_hi = ~0u;
     // no spin of this wavefront has off-resonance: zero-gradient excitation
     // intervals are then the same rotation for all of them (precomputed)
@@ -612,14 +637,16 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
             const int kind = (int)ev.uword(0);
             if (kind == EV_RF) {
                 constexpr bool f32 = sizeof(R) == 4;
-                const uint32_t lo = ev.uword(f32 ? 11 : 26), hi = f32 ? 0u : ev.uword(27);
-                if (lo != dt_lo || hi != dt_hi) {  // uniform: same interval length for every spin
+                const uint32_t lo = ev.uword(f32 ? 11 : 30), hi = f32 ? 0u : ev.uword(31);
+                if (lo != dt_lo || hi != dt_hi) {  // uniform: same key length for every spin
                     dt_lo = lo;
                     dt_hi = hi;
-                    const R dt = f32 ? R(ev.f(7)) : R(ev.d(7));  // (the FP32 length is the FP64 one rounded)
-                    eps1 = P::one_minus_exp_neg(dt * s.r1);
-                    eps2 = P::one_minus_exp_neg(dt * s.r2);
+                    const R dt = f32 ? R(ev.f(7)) : R(ev.dt_ref());  // (the FP32 length is the FP64 one rounded)
+                    eps1c = P::one_minus_exp_neg(dt * s.r1);
+                    eps2c = P::one_minus_exp_neg(dt * s.r2);
                 }
+                R eps1, eps2;
+                event_eps<P>(ev, s, eps1c, eps2c, eps1, eps2);
                 const int reps = (int)ev.uword(2);  // identical consecutive intervals (uniform)
                 const int rot = (int)ev.uword(3);
                 if (reps > 1) {
@@ -795,12 +822,13 @@ __device__ __forceinline__ Aff<R> aff_shfl_xor(const Aff<R> &m, int d) {
     return o;
 }
 
-// The map of one EV_RF or EV_END event for spin s. eps1/eps2 and dt_cached
-// are the lane's relaxation cache (1 - exp(-dt/T) for the last dt seen).
+// The map of one EV_RF or EV_END event for spin s. eps1c/eps2c and dt_cached
+// are the lane's relaxation cache (1 - exp(-dt/T) for the last key length
+// seen, see event_eps).
 template <class P, bool MOV>
 __device__ __forceinline__ Aff<typename P::R> event_map(const EvL &ev, const SpinP<typename P::R> &s,
                                                         bool no_offres, double &dt_cached,
-                                                        typename P::R &eps1, typename P::R &eps2) {
+                                                        typename P::R &eps1c, typename P::R &eps2c) {
     using R = typename P::R;
     Aff<R> m;
     if (ev.kind() == EV_END) {
@@ -828,15 +856,16 @@ __device__ __forceinline__ Aff<typename P::R> event_map(const EvL &ev, const Spi
         m.b[2] = fma(-e1, s.pd, s.pd);
         return m;
     }
-    // the factors depend on the interval length in the form's precision: the
-    // FP32 length (the FP64 one rounded) in the mixed form, so that lengths
-    // which differ only below FP32 resolution (time points' rounding) reuse them
-    const double dt = sizeof(R) == 4 ? (double)ev.f(7) : ev.d(7);
-    if (dt != dt_cached) {
-        dt_cached = dt;
-        eps1 = P::one_minus_exp_neg(R(dt) * s.r1);
-        eps2 = P::one_minus_exp_neg(R(dt) * s.r2);
+    // the cache key: the FP32 length (the FP64 one rounded) in the mixed
+    // form, the reference length in the FP64 form (see event_eps)
+    const double key = sizeof(R) == 4 ? (double)ev.f(7) : ev.dt_ref();
+    if (key != dt_cached) {
+        dt_cached = key;
+        eps1c = P::one_minus_exp_neg(R(key) * s.r1);
+        eps2c = P::one_minus_exp_neg(R(key) * s.r2);
     }
+    R eps1, eps2;
+    event_eps<P>(ev, s, eps1c, eps2c, eps1, eps2);
     if (ev.rot() >= 0 && no_offres) {
         // the host's coefficients: Mxy_re' = c0 Mz + c1 Mxy_re + c2 Mxy_im, ...
         const int perm[9] = {1, 2, 0, 5, 4, 3, 7, 8, 6};
@@ -901,7 +930,7 @@ __global__ __launch_bounds__(kWave * G) void k_seqg(SeqArgs a) {
         mi = m.y;
         mz = reinterpret_cast<const R *>(a.mz)[pidx];
     }
-    R eps1 = R(0), eps2 = R(0);
+    R eps1c = R(0), eps2c = R(0);  // relaxation cache (see event_eps)
     double dt_cached = -1.0;
     const bool no_offres = __ballot(s.bz0 != R(0)) == 0;  // per wavefront, as in k_seq
     const uint32_t *gev = reinterpret_cast<const uint32_t *>(a.ev);
@@ -951,10 +980,10 @@ __global__ __launch_bounds__(kWave * G) void k_seqg(SeqArgs a) {
             const int lo = (j * L) / G, hi = ((j + 1) * L) / G;
             Aff<R> m = aff_identity<R>();
             if (lo < hi) {
-                m = event_map<P, MOV>(EvL{base + lo * kSegStride}, s, no_offres, dt_cached, eps1, eps2);
+                m = event_map<P, MOV>(EvL{base + lo * kSegStride}, s, no_offres, dt_cached, eps1c, eps2c);
                 for (int k = lo + 1; k < hi; ++k) {
                     const EvL ev{base + k * kSegStride};
-                    m = aff_then(event_map<P, MOV>(ev, s, no_offres, dt_cached, eps1, eps2), m);
+                    m = aff_then(event_map<P, MOV>(ev, s, no_offres, dt_cached, eps1c, eps2c), m);
                 }
             }
             // tree over the shares: at step d, share j (a multiple of 2d) takes
