@@ -129,3 +129,49 @@ def test_small_first_skips_a_request_that_does_not_fit_yet():
     assert all(j.status == "done" for j in done)
     assert s.admit_order[:2] == [0, 2]  # 1 (70) does not fit beside 0 (60); 2 (30) does
     assert s.peak_used <= 100
+
+
+class TightCtx(FakeCtx):
+    """A back end whose device memory per request exceeds the footprint the
+    scheduler counts (cached blocks reused at up to twice their size): it
+    refuses an open with KOMA_E_BUDGET when the real bytes would not fit."""
+
+    def __init__(self, budget):
+        super().__init__()
+        self.budget, self.held, self.refused = budget, 0, 0
+
+    def mem(self):
+        return {"held": self.held, "cached": 0, "peak": self.held}
+
+    def open(self, scanner, phantom, seq, where):
+        real = 2 * phantom.fp
+        if self.held + real > self.budget:
+            self.refused += 1
+            raise K.KomaError(K.KOMA_E_BUDGET, "device memory of open requests would exceed hbm_budget")
+        self.held += real
+        req = FakeReq(self, phantom.n, chunks=phantom.n % 5 + 1)
+        close = req.close
+
+        def release():
+            self.held -= real
+            close()
+        req.close = release
+        return req
+
+
+def test_requests_refused_for_memory_wait_for_it():
+    """When the library refuses an open because the memory the open requests
+    really hold leaves no room, the request waits for one of them to finish
+    (it is not failed), and every request completes."""
+    budget = 100
+    fps = [30, 20, 25, 40, 10, 35, 15, 45]
+    js = []
+    for i, f in enumerate(fps):
+        ph = Ph(10 + i)
+        ph.fp = f
+        js.append(serve.Job(i, 0.0, None, ph, None, footprint=f))
+    ctx = TightCtx(budget)
+    s = serve.Server(max_slots=4, hbm_budget=budget, keep_signal=True, backend=(ctx, FakeStream, FakeEvent))
+    done = s.run(js, realtime=False)
+    assert all(j.status == "done" for j in done) and len(done) == len(fps)
+    assert ctx.refused > 0 and ctx.held == 0
