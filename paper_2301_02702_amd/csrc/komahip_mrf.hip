@@ -17,7 +17,7 @@
 //                buffered) and each wavefront accumulates Re and Im of
 //                <d, x> for 64 x 64 (pixel, entry) pairs with
 //                v_mfma_f32_32x32x16_f16 (FP32 accumulation), then scores
-//                the tile and keeps, per lane and row, the best entry seen
+//                the tile and keeps, per lane and pixel, the best entry seen
 //                (ties: lower index). Re <d, x> = [xr, xi] . [dr, di] and
 //                Im <d, x> = [xr, xi] . [-di, dr]: the second operand is
 //                formed from the first in registers.
@@ -117,7 +117,8 @@ __device__ __forceinline__ bool better(float s, int32_t i, float bs, int32_t bi)
 }
 
 // (Re, Im) pair of binary16 values -> (-Im, Re): rotate the halves of each
-// dword and flip the sign of the new low half.
+// dword and flip the sign of the new low half (2 vector instructions per
+// dword, which the binary16 matrix instructions partly overlap).
 __device__ __forceinline__ half8 times_i_conj(half8 v) {
     uint32_t w[4];
     __builtin_memcpy(w, &v, 16);
@@ -150,10 +151,39 @@ __device__ __forceinline__ half8 times_i_conj(half8 v) {
 constexpr int kSlice = KOMA_MRF_SLICE;  // halfs of the contraction axis per stage
 constexpr int kLdsRow = kSlice + 8;     // padded row against bank conflicts
 
+// One staged slice: kSlice / 16 steps of the 2 x 2 blocks of one wavefront,
+// Re and Im. FIRST: the slice that starts the sums (C operand zero).
+template <bool FIRST>
+__device__ __forceinline__ void mma_slice(f32x16 (&acc)[2][2][2], const _Float16 *la, const _Float16 *lb, int wp,
+                                          int we, int col, int half) {
+#pragma unroll
+    for (int kk = 0; kk < kSlice; kk += 16) {
+        half8 dv[2], dw[2], xv[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            dv[i] = *reinterpret_cast<const half8 *>(lb + (we + 32 * i + col) * kLdsRow + kk + 8 * half);
+            dw[i] = times_i_conj(dv[i]);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            xv[j] = *reinterpret_cast<const half8 *>(la + (wp + 32 * j + col) * kLdsRow + kk + 8 * half);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const bool z = FIRST && kk == 0;
+                acc[i][j][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(dv[i], xv[j], z ? f32x16{} : acc[i][j][0], 0, 0, 0);
+                acc[i][j][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(dw[i], xv[j], z ? f32x16{} : acc[i][j][1], 0, 0, 0);
+            }
+    }
+}
+
 __global__ __launch_bounds__(kMatchWG, KOMA_MRF_MINW) void k_mrf_match(MrfArgs a) {
     __shared__ __attribute__((aligned(16))) _Float16 ldsa[2][kPixTile * kLdsRow];  // [stage] pixels
     __shared__ __attribute__((aligned(16))) _Float16 ldsb[2][kEntTile * kLdsRow];  // [stage] entries
-    __shared__ __attribute__((aligned(16))) float lw[2][kEntTile];  // 1 / ||entry||^2, by tile parity
+    // 1 / ||entry||^2 by tile parity; -inf for padding and all-zero entries, whose
+    // scores 0 * -inf are NaN and never win a comparison
+    __shared__ __attribute__((aligned(16))) float lw[2][kEntTile];
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
@@ -179,7 +209,9 @@ __global__ __launch_bounds__(kMatchWG, KOMA_MRF_MINW) void k_mrf_match(MrfArgs a
     const int64_t kp = a.kp;
     const int n_stage = (int)(kp / kSlice);
 
-    // running best per lane and pixel block over the entries this lane has seen
+    // running best per lane and pixel block over the entries this lane has
+    // seen. A lane sees its entries in increasing order, so a later entry
+    // replaces the best only with a strictly larger score (ties: lower index)
     float bs[2] = {-1.0f, -1.0f};
     int32_t bi[2] = {0x7fffffff, 0x7fffffff};
 
@@ -196,7 +228,10 @@ __global__ __launch_bounds__(kMatchWG, KOMA_MRF_MINW) void k_mrf_match(MrfArgs a
         float *wt = lw[(et - t0) & 1];
         // read after this tile's last barrier; the buffer was last read in
         // the epilogue of tile et - 2, before the barriers of tile et - 1
-        if (tid < kEntTile) wt[tid] = a.inv_norm2[E0 + tid];
+        if (tid < kEntTile) {
+            const float v = a.inv_norm2[E0 + tid];
+            wt[tid] = v < 0.0f ? -__builtin_inff() : v;
+        }
         const u32x4 *ga[kPerA], *gb[kPerB];
         u32x4 ra[kPerA], rb[kPerB];
 #pragma unroll
@@ -210,13 +245,6 @@ __global__ __launch_bounds__(kMatchWG, KOMA_MRF_MINW) void k_mrf_match(MrfArgs a
             rb[u] = gb[u][0];
         }
         f32x16 acc[2][2][2];  // [entry block][pixel block][re, im]
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                acc[i][j][0] = f32x16{};
-                acc[i][j][1] = f32x16{};
-            }
         for (int st = 0; st < n_stage; ++st) {
             const int buf = st & 1;
             _Float16 *la = ldsa[buf];
@@ -235,25 +263,11 @@ __global__ __launch_bounds__(kMatchWG, KOMA_MRF_MINW) void k_mrf_match(MrfArgs a
 #pragma unroll
                 for (int u = 0; u < kPerB; ++u) rb[u] = gb[u][q];
             }
-#pragma unroll
-            for (int kk = 0; kk < kSlice; kk += 16) {
-                half8 dv[2], dw[2], xv[2];
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    dv[i] = *reinterpret_cast<const half8 *>(lb + (we + 32 * i + col) * kLdsRow + kk + 8 * half);
-                    dw[i] = times_i_conj(dv[i]);
-                }
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    xv[j] = *reinterpret_cast<const half8 *>(la + (wp + 32 * j + col) * kLdsRow + kk + 8 * half);
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        acc[i][j][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(dv[i], xv[j], acc[i][j][0], 0, 0, 0);
-                        acc[i][j][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(dw[i], xv[j], acc[i][j][1], 0, 0, 0);
-                    }
-            }
+            // the first stage starts the sums from an inline zero (no register clearing)
+            if (st == 0)
+                mma_slice<true>(acc, la, lb, wp, we, col, half);
+            else
+                mma_slice<false>(acc, la, lb, wp, we, col, half);
             // the other buffer is written next; one barrier per stage suffices
             // because stage st + 1 writes buffer buf ^ 1, last read in stage st - 1
         }
@@ -273,8 +287,8 @@ __global__ __launch_bounds__(kMatchWG, KOMA_MRF_MINW) void k_mrf_match(MrfArgs a
 #pragma unroll
                     for (int j = 0; j < 2; ++j) {
                         const float re = acc[i][j][0][r], im = acc[i][j][1][r];
-                        const float sc = ww[t] < 0.0f ? -1.0f : (re * re + im * im) * ww[t];
-                        if (better(sc, e, bs[j], bi[j])) {
+                        const float sc = (re * re + im * im) * ww[t];
+                        if (sc > bs[j]) {
                             bs[j] = sc;
                             bi[j] = e;
                         }
