@@ -185,6 +185,19 @@ constexpr int DPP_ROR8 = 0x128;
 constexpr int DPP_HALF_MIRROR = 0x141;
 constexpr int DPP_QUAD_1032 = 0xB1;  // quad_perm [1,0,3,2]: lane ^ 1
 constexpr int DPP_QUAD_2301 = 0x4E;  // quad_perm [2,3,0,1]: lane ^ 2
+constexpr int DPP_QUAD_3210 = 0x1B;  // quad_perm [3,2,1,0]: lane ^ 3
+
+// The value of lane ^ D (D = 1, 2, 4 or 8) by data-parallel moves within
+// rows of 16 lanes: ^4 is the half-row mirror (lane ^ 7) then ^3 within quads;
+// ^8 is a rotation of the row by 8.
+template <int D, class R>
+__device__ __forceinline__ R lane_xor(R v) {
+    static_assert(D == 1 || D == 2 || D == 4 || D == 8, "xor distance");
+    if constexpr (D == 1) return dpp<DPP_QUAD_1032>(v);
+    else if constexpr (D == 2) return dpp<DPP_QUAD_2301>(v);
+    else if constexpr (D == 4) return dpp<DPP_QUAD_3210>(dpp<DPP_HALF_MIRROR>(v));
+    else return dpp<DPP_ROR8>(v);
+}
 
 // After the call: a = [a lanes 0-31, b lanes 0-31], b = [a lanes 32-63, b lanes 32-63].
 __device__ __forceinline__ void swap32(float &a, float &b) {
@@ -812,13 +825,13 @@ __device__ __forceinline__ Aff<R> aff_power(Aff<R> p, int k) {
     return r;
 }
 
-template <class R>
-__device__ __forceinline__ Aff<R> aff_shfl_xor(const Aff<R> &m, int d) {
+template <int D, class R>
+__device__ __forceinline__ Aff<R> aff_lane_xor(const Aff<R> &m) {
     Aff<R> o;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) o.a[i] = __shfl_xor(m.a[i], d, kWave);
+    for (int i = 0; i < 9; ++i) o.a[i] = lane_xor<D>(m.a[i]);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) o.b[i] = __shfl_xor(m.b[i], d, kWave);
+    for (int i = 0; i < 3; ++i) o.b[i] = lane_xor<D>(m.b[i]);
     return o;
 }
 
@@ -990,8 +1003,11 @@ __global__ __launch_bounds__(kWave * G) void k_seqg(SeqArgs a) {
             // share j + d's product after its own, so share 0 ends with the
             // composite of the segment (the other shares' products are not
             // used, and share 0 alone carries the spin's state)
-#pragma unroll
-            for (int d = 1; d < G; d <<= 1) m = aff_then(aff_shfl_xor(m, d), m);
+            if constexpr (G > 1) m = aff_then(aff_lane_xor<1>(m), m);
+            if constexpr (G > 2) m = aff_then(aff_lane_xor<2>(m), m);
+            if constexpr (G > 4) m = aff_then(aff_lane_xor<4>(m), m);
+            if constexpr (G > 8) m = aff_then(aff_lane_xor<8>(m), m);
+            static_assert(G <= 16, "at most 16 lanes per spin");
             aff_apply(m, mr, mi, mz);
         }
         if (obs) {  // uniform
