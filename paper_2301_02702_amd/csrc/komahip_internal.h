@@ -118,7 +118,10 @@ constexpr int kStretchMax = 128;
 #endif
 constexpr int kMMStretches = KOMA_MM_STRETCHES;  // stretches whose sums one FP32 matrix-core workgroup keeps in registers
 constexpr int kMMStretches64 = 4;   // the same in FP64
-constexpr int kMMResident = 3;      // matrix-core workgroups resident per CU (LDS 48 KB, 168 VGPRs)
+#ifndef KOMA_MM_RESIDENT
+#define KOMA_MM_RESIDENT 3
+#endif
+constexpr int kMMResident = KOMA_MM_RESIDENT;  // FP32 matrix-core workgroups resident per CU (LDS 48 KB each)
 constexpr int kMMResident64 = 1;    // the same in FP64 (LDS 96 KB)
 
 // A segment of the event program for the several-lanes-per-spin kernel:

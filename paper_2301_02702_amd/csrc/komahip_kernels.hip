@@ -1361,7 +1361,7 @@ __device__ __forceinline__ C2<float> mm_anchor(const ParSpin &s, float r2, const
 
 // Tiles per wavefront: a.spl (a block is 4 a.spl tiles), a run-time value so
 // that the planner can size the grid to whole rounds of resident workgroups.
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k_par_mm(ParArgs a) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMMResident))) void k_par_mm(ParArgs a) {
     const int S = a.spl;
     // per-wavefront stage (12 KB): B operands at a family's start, the three
     // A planes per stretch pair; after the tiles, the FP64 sums
