@@ -611,7 +611,7 @@ def main():
     ap.add_argument("--forms", default="mixed,fp64", help="precision forms of --workload")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: spins would shard across GPUs with one "
+        print(json.dumps({"error": "the benchmark runs on one GPU: spins would shard across GPUs with one "
                                    "final signal sum, which is not implemented; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
