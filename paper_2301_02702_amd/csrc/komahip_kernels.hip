@@ -359,8 +359,9 @@ __device__ __forceinline__ void excite_relax(const SpinP<typename P::R> &s, cons
     if (MOV) bz0 = fma(s.vx, gt[0], fma(s.vy, gt[1], fma(s.vz, gt[2], bz0)));
     const R bz = fma(s.x, gx, fma(s.y, gy, fma(s.z, gz, bz0)));
     const R nb2 = fma(bz, bz, b1sq);
-    // |B| = 0 (possible only if |b1|^2 underflows) leaves the spin unrotated
-    const R inv = nb2 > R(0) ? P::rsq(nb2) : R(0);
+    // |B| = 0 (possible only if |b1|^2 underflows) leaves the spin unrotated:
+    // 1/|B| of the smallest normal number, times |B| = 0, is a zero angle
+    const R inv = P::rsq(fmax(nb2, sizeof(R) == 4 ? R(1.17549435e-38f) : R(2.2250738585072014e-308)));
     const R nb = nb2 * inv;
     R sn, cs;
     P::sincos_turns(hs * nb, sn, cs);  // sin, cos of phi/2
@@ -396,7 +397,7 @@ __device__ __forceinline__ void rot_matrix(const SpinP<typename P::R> &s, const 
     if (MOV) bz0 = fma(s.vx, gt[0], fma(s.vy, gt[1], fma(s.vz, gt[2], bz0)));
     const R bz = fma(s.x, gx, fma(s.y, gy, fma(s.z, gz, bz0)));
     const R nb2 = fma(bz, bz, b1sq);
-    const R inv = nb2 > R(0) ? P::rsq(nb2) : R(0);
+    const R inv = P::rsq(fmax(nb2, sizeof(R) == 4 ? R(1.17549435e-38f) : R(2.2250738585072014e-308)));
     const R nb = nb2 * inv;
     R sn, cs;
     P::sincos_turns(hs * nb, sn, cs);
