@@ -15,6 +15,7 @@
 #include <immintrin.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <array>
 #include <cmath>
 #include <cstdarg>
@@ -1002,6 +1003,12 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
                 e.d[c] = v[c];
                 e.f[c] = (float)v[c];
             }
+            // |b1|^2 at least the smallest normal number of each precision, so
+            // that |B|^2 = Bz^2 + |b1|^2 > 0 and the kernels' 1/|B| is finite
+            // (a zero field then rotates by a zero angle); no non-zero field
+            // of an MRI pulse comes near these values
+            e.d[5] = std::max(e.d[5], DBL_MIN);
+            e.f[5] = std::max(e.f[5], FLT_MIN);
             e.b1sq_f32 = (double)e.f[3] * (double)e.f[3] + (double)e.f[4] * (double)e.f[4];
             if (!(rf_dt_ref > 0.0 && std::fabs(dtr - rf_dt_ref) <= dtr * 0x1p-30)) rf_dt_ref = dtr;
             e.dt_ref = rf_dt_ref;
@@ -1045,6 +1052,23 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     }
     if ((int64_t)P.inl_k.size() + (int64_t)P.def_k.size() != q->n_adc)
         return fail(ctx, KOMA_E_SEQUENCE, "internal: ADC samples lost in packing");
+    // Runs of single excitation intervals: a0 of an EV_RF event is the number
+    // of events from it on that the one-lane kernel takes in one loop, the
+    // event itself and the single intervals (count 1, no precomputed
+    // rotation) right after it whose relaxation keys are the same in both
+    // forms (the FP32 length's bits, the reference length), so that the
+    // factors cached for the first hold for all of them.
+    for (int64_t i = (int64_t)P.ev.size() - 1; i >= 0; --i) {
+        Event &e = P.ev[(size_t)i];
+        if (e.kind != EV_RF) continue;
+        e.a0 = 1;
+        if (i + 1 < (int64_t)P.ev.size()) {
+            const Event &x = P.ev[(size_t)i + 1];
+            if (x.kind == EV_RF && x.count == 1 && x.rot < 0 &&
+                std::memcmp(&x.f[7], &e.f[7], sizeof(float)) == 0 && x.dt_ref == e.dt_ref && x.a0 < (1 << 30))
+                e.a0 = 1 + x.a0;
+        }
+    }
 
     // ---- packed tiles: with no deferred samples the only per-tile sums are
     // the inline ones, so wavefronts may take 64 consecutive spins across

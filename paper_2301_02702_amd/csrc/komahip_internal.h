@@ -28,7 +28,9 @@ enum : int32_t { EV_RF = 0, EV_END = 1, EV_ADC = 2, EV_SNAP = 3 };
 
 struct alignas(16) Event {
     int32_t kind;
-    int32_t a0;     // EV_ADC: first inline sample slot; EV_SNAP: snapshot slot
+    int32_t a0;     // EV_ADC: first inline sample slot; EV_SNAP: snapshot slot;
+                    // EV_RF: events from this one on that form a run of single
+                    // intervals with the same relaxation keys (>= 1)
     int32_t count;  // EV_ADC: number of samples; EV_RF: identical consecutive intervals (>= 1)
     int32_t rot;    // EV_RF: 1 if the rotation for Bz = 0 is precomputed (zero gradient), else -1
     // EV_RF: gx, gy, gz (T/m, interval mean), b1_re, b1_im (T), |b1|^2,
