@@ -13,8 +13,8 @@
 //
 // Kernels:
 //   k_seq   spin-sequential: one lane per spin, every wavefront walks the
-//           shared event program (uniform branches; the events are read with
-//           scalar loads into SGPRs). Excitation intervals, block ends, short
+//           shared event program (uniform branches; the program is staged
+//           through LDS in chunks). Excitation intervals, block ends, short
 //           sample runs (summed per wavefront), snapshots of block-start
 //           states.
 //   k_par_mm sample-parallel, mixed precision, on the matrix cores: a
@@ -37,8 +37,6 @@
 // a device-resident phantom's validation bits into a status word.)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
-
-#include <type_traits>
 
 #include "komahip_internal.h"
 
@@ -500,59 +498,39 @@ __device__ __forceinline__ ConstPtr<T> as_const(const T *p) {
     return (ConstPtr<T>)p;
 }
 
-// The one-lane kernel reads the current event straight from global memory
-// through the constant address space: every field is a scalar load into
-// SGPRs, used as an operand of the vector instructions as it is. The
-// several-lanes kernel stages chunks of events through LDS instead (its
-// lanes read the fields of different events).
+// Events are staged through LDS in chunks: the workgroup copies kChunk
+// events with coalesced 16-byte loads (one round trip to memory for the
+// chunk, however few wavefronts share a SIMD), and every lane then reads the
+// fields of the current event at one LDS address (a broadcast).
+constexpr int kChunk = 64;
 constexpr int kEvWords = (int)(sizeof(Event) / 4);  // 64 dwords
 static_assert(sizeof(Event) % 16 == 0, "Event is copied as 16-byte words");
 
-// View of one event: Ptr is an LDS pointer (a staged event) or a
-// constant-space pointer (the event in global memory). The words of the
-// common steps (excitation interval, block end, samples), words [0, NW),
-// are read at once when the view is made, so that one round trip to the
-// scalar cache serves a whole step; the others on use.
-template <class Ptr, int NW>
-struct EvView {
-    Ptr u;
-    uint32_t w[NW > 0 ? NW : 1];
-    __device__ __forceinline__ explicit EvView(Ptr p) : u(p) {
-#pragma unroll
-        for (int i = 0; i < NW; ++i) w[i] = p[i];
-    }
-    __device__ __forceinline__ uint32_t word(int i) const { return i < NW ? w[i] : u[i]; }
+struct EvL {  // view of one staged event
+    const uint32_t *u;
+    __device__ __forceinline__ uint32_t word(int i) const { return u[i]; }
     // a word every lane of the wavefront reads at the same address, as a
-    // scalar (so that branches and compares on it are scalar); a scalar load
-    // is one already
-    __device__ __forceinline__ uint32_t uword(int i) const {
-        if constexpr (std::is_same_v<Ptr, const uint32_t *>)
-            return __builtin_amdgcn_readfirstlane(u[i]);
-        else
-            return word(i);
-    }
-    __device__ __forceinline__ int kind() const { return (int)word(0); }
-    __device__ __forceinline__ int a0() const { return (int)word(1); }
-    __device__ __forceinline__ int count() const { return (int)word(2); }
-    __device__ __forceinline__ int rot() const { return (int)word(3); }
-    __device__ __forceinline__ float f(int i) const { return __uint_as_float(word(4 + i)); }
+    // scalar (so that branches and compares on it are scalar)
+    __device__ __forceinline__ uint32_t uword(int i) const { return __builtin_amdgcn_readfirstlane(u[i]); }
+    __device__ __forceinline__ int kind() const { return (int)u[0]; }
+    __device__ __forceinline__ int a0() const { return (int)u[1]; }
+    __device__ __forceinline__ int count() const { return (int)u[2]; }
+    __device__ __forceinline__ int rot() const { return (int)u[3]; }
+    __device__ __forceinline__ float f(int i) const { return __uint_as_float(u[4 + i]); }
     __device__ __forceinline__ double d(int i) const {
-        return __builtin_bit_cast(double, ((uint64_t)word(12 + 2 * i + 1) << 32) | word(12 + 2 * i));
+        return __builtin_bit_cast(double, ((uint64_t)u[12 + 2 * i + 1] << 32) | u[12 + 2 * i]);
     }
     __device__ __forceinline__ double b1sq() const {
-        return __builtin_bit_cast(double, ((uint64_t)word(29) << 32) | word(28));
+        return __builtin_bit_cast(double, ((uint64_t)u[29] << 32) | u[28]);
     }
     __device__ __forceinline__ double dt_ref() const {
-        return __builtin_bit_cast(double, ((uint64_t)word(31) << 32) | word(30));
+        return __builtin_bit_cast(double, ((uint64_t)u[31] << 32) | u[30]);
     }
-    __device__ __forceinline__ float c32(int i) const { return __uint_as_float(word(32 + i)); }
+    __device__ __forceinline__ float c32(int i) const { return __uint_as_float(u[32 + i]); }
     __device__ __forceinline__ double c64(int i) const {
-        return __builtin_bit_cast(double, ((uint64_t)word(44 + 2 * i + 1) << 32) | word(44 + 2 * i));
+        return __builtin_bit_cast(double, ((uint64_t)u[44 + 2 * i + 1] << 32) | u[44 + 2 * i]);
     }
 };
-using EvL = EvView<const uint32_t *, 0>;  // staged in LDS
-template <int NW>
-using EvG = EvView<ConstPtr<uint32_t>, NW>;  // in global memory
 
 // The wavefront's sum of v into inline partial row `row` of signal plane k;
 // a tile holding two groups sums lanes [0, split) into its first row and
@@ -622,8 +600,19 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int64_t tile = (int64_t)blockIdx.x * kWavesPerWG + wave;
-    if (tile >= a.n_tiles) return;  // (no barriers below)
-    const Tile T = a.tiles[tile];
+    __shared__ uint4 lds_ev[kChunk * kEvWords / 4];
+    // wavefronts past the last tile still help staging and reach every barrier
+    const bool active = tile < a.n_tiles;
+    Tile T;
+    if (active) {
+        T = a.tiles[tile];
+    } else {
+        T.spin0 = 0;
+        T.count = 0;
+        T.group = 0;
+        T.split = 0;
+        T.seg = 0;
+    }
     const SpinP<R> s = load_spin<R, MOV>(a.ph, T, lane, a.inv_gamma);
     const int64_t n_pad = a.n_tiles * kWave;
     const int64_t pidx = tile * kWave + lane;
@@ -636,7 +625,7 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
     }
 
     R mr = R(0), mi = R(0), mz = s.pd;
-    if (!a.init) {
+    if (active && !a.init) {
         R2 m = reinterpret_cast<const R2 *>(a.mxy)[pidx];
         mr = m.x;
         mi = m.y;
@@ -652,138 +641,165 @@ __global__ __launch_bounds__(kWG) void k_seq(SeqArgs a) {
     // no spin of this wavefront has off-resonance: zero-gradient excitation
     // intervals are then the same rotation for all of them (precomputed)
     const bool no_offres = __ballot(s.bz0 != R(0)) == 0;
-    const ConstPtr<uint32_t> gev = as_const(reinterpret_cast<const uint32_t *>(a.ev));
-
-    // words read at the top of each event: the mixed form's excitation,
-    // block-end and sample fields (header, FP32 values, FP64 moments); the
-    // FP64 form's through the reference length
-    constexpr int NW = sizeof(R) == 4 ? 28 : 32;
+    const uint4 *gev = reinterpret_cast<const uint4 *>(a.ev);
+    const uint32_t *base = reinterpret_cast<const uint32_t *>(lds_ev);
     constexpr bool f32 = sizeof(R) == 4;
-    const ConstPtr<uint32_t> ev0 = gev + a.e0 * kEvWords;
-    const int n_ev = (int)(a.e1 - a.e0);  // (32-bit event indices: scalar compares)
-    for (int e = 0; e < n_ev; ++e) {
-        const EvG<NW> ev{ev0 + e * kEvWords};
-        const int kind = (int)ev.uword(0);
-        if (kind == EV_RF) {
-            const uint32_t lo = ev.uword(f32 ? 11 : 30), hi = f32 ? 0u : ev.uword(31);
-            if (lo != dt_lo || hi != dt_hi) {  // uniform: same key length for every spin
-                dt_lo = lo;
-                dt_hi = hi;
-                const R dt = f32 ? R(ev.f(7)) : R(ev.dt_ref());  // (the FP32 length is the FP64 one rounded)
-                eps1c = P::one_minus_exp_neg(dt * s.r1);
-                eps2c = P::one_minus_exp_neg(dt * s.r2);
-            }
-            R eps1, eps2;
-            event_eps<P>(ev, s, eps1c, eps2c, eps1, eps2);
-            const int reps = (int)ev.uword(2);  // identical consecutive intervals (uniform)
-            const int rot = (int)ev.uword(3);
-            if (reps > 1) {
-                R m[9];
-                if (rot >= 0 && no_offres) {
-                    // the host's coefficients: Mxy_re' = c0 Mz + c1 Mxy_re + c2 Mxy_im, ...
-                    const int perm[9] = {1, 2, 0, 5, 4, 3, 7, 8, 6};
+
+    for (int64_t c0 = a.e0; c0 < a.e1; c0 += kChunk) {
+        const int n = (int)min<int64_t>(kChunk, a.e1 - c0);
+        __syncthreads();  // the previous chunk is no longer read
+        for (int i = threadIdx.x; i < n * (kEvWords / 4); i += kWG) lds_ev[i] = gev[c0 * (kEvWords / 4) + i];
+        __syncthreads();
+        if (!active) continue;
+        for (int e = 0; e < n; ++e) {
+            const EvL ev{base + e * kEvWords};
+            const int kind = (int)ev.uword(0);
+            if (kind == EV_RF) {
+                const uint32_t lo = ev.uword(f32 ? 11 : 30), hi = f32 ? 0u : ev.uword(31);
+                if (lo != dt_lo || hi != dt_hi) {  // uniform: same key length for every spin
+                    dt_lo = lo;
+                    dt_hi = hi;
+                    const R dt = f32 ? R(ev.f(7)) : R(ev.dt_ref());  // (the FP32 length is the FP64 one rounded)
+                    eps1c = P::one_minus_exp_neg(dt * s.r1);
+                    eps2c = P::one_minus_exp_neg(dt * s.r2);
+                }
+                R eps1, eps2;
+                event_eps<P>(ev, s, eps1c, eps2c, eps1, eps2);
+                const int reps = (int)ev.uword(2);  // identical consecutive intervals (uniform)
+                const int rot = (int)ev.uword(3);
+                if (reps > 1) {
+                    R m[9];
+                    if (rot >= 0 && no_offres) {
+                        // the host's coefficients: Mxy_re' = c0 Mz + c1 Mxy_re + c2 Mxy_im, ...
+                        const int perm[9] = {1, 2, 0, 5, 4, 3, 7, 8, 6};
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) m[i] = sizeof(R) == 4 ? R(ev.c32(perm[i])) : R(ev.c64(perm[i]));
+                        for (int i = 0; i < 9; ++i) m[i] = sizeof(R) == 4 ? R(ev.c32(perm[i])) : R(ev.c64(perm[i]));
+                    } else {
+                        R q[7];
+#pragma unroll
+                        for (int i = 0; i < 7; ++i) q[i] = sizeof(R) == 4 ? R(ev.f(i)) : R(ev.d(i));
+                        R gt[3] = {R(0), R(0), R(0)};
+                        if (MOV && rot < 0) {
+#pragma unroll
+                            for (int i = 0; i < 3; ++i) gt[i] = sizeof(R) == 4 ? R(ev.c32(i)) : R(ev.c64(i));
+                        }
+                        const double b1sq = sizeof(R) == 4 ? ev.b1sq() : ev.d(5);
+                        rot_matrix<P, MOV>(s, q, gt, b1sq, m);
+                    }
+                    // the interval's affine map: rotation rows scaled by the
+                    // relaxation factors (m - eps m, never a rounded 1 - eps)
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) m[i] = fma(-eps2, m[i], m[i]);
+#pragma unroll
+                    for (int i = 6; i < 9; ++i) m[i] = fma(-eps1, m[i], m[i]);
+                    affine_power(m, eps1 * s.pd, reps, mr, mi, mz);
+                } else if (rot >= 0 && no_offres) {
+                    R c[9];
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) c[i] = sizeof(R) == 4 ? R(ev.c32(i)) : R(ev.c64(i));
+                    const R nr = fma(c[0], mz, fma(c[1], mr, c[2] * mi));
+                    const R ni = fma(c[3], mz, fma(c[4], mi, c[5] * mr));
+                    const R nz = fma(c[6], mz, fma(c[7], mr, c[8] * mi));
+                    mr = fma(-eps2, nr, nr);
+                    mi = fma(-eps2, ni, ni);
+                    mz = fma(-eps1, nz - s.pd, nz);
                 } else {
-                    R q[7];
+                    // A run of single intervals with the same key length (the
+                    // intervals of a shaped pulse) goes round a loop of its own,
+                    // whose state stays in its registers from one interval to
+                    // the next; the event that ends the run is taken up again
+                    // by the outer loop.
+                    // The run of single intervals that starts here (its length
+                    // from the host: the same relaxation keys throughout; cut at
+                    // the end of the chunk) goes round a loop of its own, which
+                    // keeps the state in its registers and reads each next
+                    // interval's values from LDS during the current one's
+                    // arithmetic.
+                    const int run = min((int)ev.uword(1), n - e);
+                    // two sets of interval values in turn (no copies between
+                    // passes): the values of interval j + 1 are read into one
+                    // while interval j's arithmetic uses the other
+                    struct Iv {
+                        R q[7], gt[3];
+                        double b1sq;
+                        R eps1, eps2;
+                    };
+                    auto read_iv = [&](const EvL &v, Iv &iv, bool first) {
 #pragma unroll
-                    for (int i = 0; i < 7; ++i) q[i] = sizeof(R) == 4 ? R(ev.f(i)) : R(ev.d(i));
-                    R gt[3] = {R(0), R(0), R(0)};
-                    if (MOV && rot < 0) {
+                        for (int i = 0; i < 7; ++i) iv.q[i] = f32 ? R(v.f(i)) : R(v.d(i));
 #pragma unroll
-                        for (int i = 0; i < 3; ++i) gt[i] = sizeof(R) == 4 ? R(ev.c32(i)) : R(ev.c64(i));
+                        for (int i = 0; i < 3; ++i) iv.gt[i] = R(0);
+                        // (rot >= 0: G and G t are zero on the interval; the
+                        // run's later intervals have rot < 0)
+                        if (MOV && (!first || rot < 0)) {
+#pragma unroll
+                            for (int i = 0; i < 3; ++i) iv.gt[i] = f32 ? R(v.c32(i)) : R(v.c64(i));
+                        }
+                        // |b1|^2 of exactly the b1 values the precision uses
+                        iv.b1sq = f32 ? v.b1sq() : v.d(5);
+                        event_eps<P>(v, s, eps1c, eps2c, iv.eps1, iv.eps2);
+                    };
+                    auto step = [&](const Iv &iv) {
+                        excite_relax<P, MOV>(s, iv.q, iv.gt, iv.b1sq, iv.eps1, iv.eps2, mr, mi, mz);
+                    };
+                    Iv ia, ib;
+                    // the scheduler is told to issue the LDS reads of the
+                    // next interval first, then the arithmetic of this one
+                    // (left alone it moves each read next to its first use)
+                    auto reads_first = [] {
+                        __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);  // LDS reads
+                        __builtin_amdgcn_sched_group_barrier(0x002, 200, 0);  // vector ALU
+                    };
+                    read_iv(ev, ia, true);
+                    for (int j = 1;; j += 2) {
+                        read_iv(EvL{base + (e + min(j, run - 1)) * kEvWords}, ib, false);
+                        step(ia);
+                        reads_first();
+                        if (j >= run) break;
+                        read_iv(EvL{base + (e + min(j + 1, run - 1)) * kEvWords}, ia, false);
+                        step(ib);
+                        reads_first();
+                        if (j + 1 >= run) break;
                     }
-                    const double b1sq = sizeof(R) == 4 ? ev.b1sq() : ev.d(5);
-                    rot_matrix<P, MOV>(s, q, gt, b1sq, m);
+                    e += run - 1;
                 }
-                // the interval's affine map: rotation rows scaled by the
-                // relaxation factors (m - eps m, never a rounded 1 - eps)
-#pragma unroll
-                for (int i = 0; i < 6; ++i) m[i] = fma(-eps2, m[i], m[i]);
-#pragma unroll
-                for (int i = 6; i < 9; ++i) m[i] = fma(-eps1, m[i], m[i]);
-                affine_power(m, eps1 * s.pd, reps, mr, mi, mz);
-            } else if (rot >= 0 && no_offres) {
-                R c[9];
-#pragma unroll
-                for (int i = 0; i < 9; ++i) c[i] = sizeof(R) == 4 ? R(ev.c32(i)) : R(ev.c64(i));
-                const R nr = fma(c[0], mz, fma(c[1], mr, c[2] * mi));
-                const R ni = fma(c[3], mz, fma(c[4], mi, c[5] * mr));
-                const R nz = fma(c[6], mz, fma(c[7], mr, c[8] * mi));
-                mr = fma(-eps2, nr, nr);
-                mi = fma(-eps2, ni, ni);
-                mz = fma(-eps1, nz - s.pd, nz);
-            } else {
-                // A run of single intervals with the same key length (the
-                // intervals of a shaped pulse) goes round a loop of its own,
-                // whose state stays in its registers from one interval to
-                // the next; the event that ends the run is taken up again
-                // by the outer loop.
-                // The run of single intervals that starts here (its length
-                // from the host: the same relaxation keys throughout) goes
-                // round a loop of its own, which keeps the state in its
-                // registers and reads each next event during the current
-                // one's arithmetic.
-                using Pre = EvG<f32 ? 12 : 32>;
-                const int run = min((int)ev.uword(1), n_ev - e);
-                Pre cur{ev0 + e * kEvWords};
-                int rot_c = rot;
-                for (int j = 1;; ++j) {
-                    const Pre nx{ev0 + (e + min(j, run - 1)) * kEvWords};
-                    R q[7];
-#pragma unroll
-                    for (int i = 0; i < 7; ++i) q[i] = f32 ? R(cur.f(i)) : R(cur.d(i));
-                    R gt[3] = {R(0), R(0), R(0)};
-                    if (MOV && rot_c < 0) {  // (rot >= 0: G and G t are zero on the interval)
-#pragma unroll
-                        for (int i = 0; i < 3; ++i) gt[i] = f32 ? R(cur.c32(i)) : R(cur.c64(i));
-                    }
-                    // |b1|^2 of exactly the b1 values the precision uses
-                    const double b1sq = f32 ? cur.b1sq() : cur.d(5);
-                    excite_relax<P, MOV>(s, q, gt, b1sq, eps1, eps2, mr, mi, mz);
-                    if (j >= run) break;
-                    cur = nx;
-                    rot_c = -1;
-                    event_eps<P>(cur, s, eps1c, eps2c, eps1, eps2);
+            } else if (kind == EV_END) {
+                const double k4[4] = {ev.d(0), ev.d(1), ev.d(2), ev.d(3)};
+                const double tau = k4[3];
+                double th;
+                if (MOV) {
+                    const double k1[3] = {ev.d(4), ev.d(5), ev.d(6)};
+                    th = block_phase(s, k4, k1);
+                } else {
+                    th = block_phase(s, k4);
                 }
-                e += run - 1;
+                C2<R> f = block_factor<P>(s, th, tau);
+                C2<R> m = cmul(C2<R>{mr, mi}, f);
+                mr = m.re;
+                mi = m.im;
+                mz = s.pd + (mz - s.pd) * P::exp_neg(R(tau) * s.r1);
+            } else if (MOV && kind == EV_ADC) {  // one sample, first moments in c64
+                const double k0[4] = {ev.d(0), ev.d(1), ev.d(2), ev.d(3)};
+                const double k1[3] = {ev.c64(0), ev.c64(1), ev.c64(2)};
+                const C2<R> c = cmul(C2<R>{mr, mi}, block_factor<P>(s, block_phase(s, k0, k1), k0[3]));
+                inline_sample<R, R2>(a, T, lane, ev.a0(), c);
+            } else if (kind == EV_ADC) {
+                const double k0[4] = {ev.d(0), ev.d(1), ev.d(2), ev.d(3)};
+                const double dk[4] = {ev.d(4), ev.d(5), ev.d(6), ev.d(7)};
+                C2<R> c = cmul(C2<R>{mr, mi}, block_factor<P>(s, block_phase(s, k0), k0[3]));
+                const int cnt = (int)ev.uword(2);
+                C2<R> w{R(1), R(0)};
+                if (cnt > 1) w = block_factor<P>(s, block_phase(s, dk), dk[3]);
+                for (int i = 0; i < cnt; ++i) {
+                    inline_sample<R, R2>(a, T, lane, ev.a0() + i, c);
+                    c = cmul(c, w);
+                }
+            } else {  // EV_SNAP
+                reinterpret_cast<R2 *>(a.snap)[(int64_t)ev.a0() * n_pad + pidx] = R2{mr, mi};
             }
-        } else if (kind == EV_END) {
-            const double k4[4] = {ev.d(0), ev.d(1), ev.d(2), ev.d(3)};
-            const double tau = k4[3];
-            double th;
-            if (MOV) {
-                const double k1[3] = {ev.d(4), ev.d(5), ev.d(6)};
-                th = block_phase(s, k4, k1);
-            } else {
-                th = block_phase(s, k4);
-            }
-            C2<R> f = block_factor<P>(s, th, tau);
-            C2<R> m = cmul(C2<R>{mr, mi}, f);
-            mr = m.re;
-            mi = m.im;
-            mz = s.pd + (mz - s.pd) * P::exp_neg(R(tau) * s.r1);
-        } else if (MOV && kind == EV_ADC) {  // one sample, first moments in c64
-            const double k0[4] = {ev.d(0), ev.d(1), ev.d(2), ev.d(3)};
-            const double k1[3] = {ev.c64(0), ev.c64(1), ev.c64(2)};
-            const C2<R> c = cmul(C2<R>{mr, mi}, block_factor<P>(s, block_phase(s, k0, k1), k0[3]));
-            inline_sample<R, R2>(a, T, lane, ev.a0(), c);
-        } else if (kind == EV_ADC) {
-            const double k0[4] = {ev.d(0), ev.d(1), ev.d(2), ev.d(3)};
-            const double dk[4] = {ev.d(4), ev.d(5), ev.d(6), ev.d(7)};
-            C2<R> c = cmul(C2<R>{mr, mi}, block_factor<P>(s, block_phase(s, k0), k0[3]));
-            const int cnt = (int)ev.uword(2);
-            C2<R> w{R(1), R(0)};
-            if (cnt > 1) w = block_factor<P>(s, block_phase(s, dk), dk[3]);
-            for (int i = 0; i < cnt; ++i) {
-                inline_sample<R, R2>(a, T, lane, ev.a0() + i, c);
-                c = cmul(c, w);
-            }
-        } else {  // EV_SNAP
-            reinterpret_cast<R2 *>(a.snap)[(int64_t)ev.a0() * n_pad + pidx] = R2{mr, mi};
         }
     }
-    if (a.store) {
+    if (active && a.store) {
         reinterpret_cast<R2 *>(a.mxy)[pidx] = R2{mr, mi};
         reinterpret_cast<R *>(a.mz)[pidx] = mz;
     }
