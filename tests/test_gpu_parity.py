@@ -273,19 +273,24 @@ def test_device_pointers_match_host(ctx, K):
 
 def test_request_path_equals_simulate(ctx):
     """Chunked execution with device-resident state gives the same bits as
-    one whole simulation, for any chunk length, and survives a checkpoint."""
+    one whole simulation, for any chunk length, and survives a checkpoint.
+    With one lane per spin the chunks also start and end inside the runs of
+    single excitation intervals of the GRE sinc pulses, on both sides of the
+    64-event LDS stage."""
     sc, ph, seq = case("gre")
     ph = ph.subset(np.arange(1000))
     for prec in ("fp64", "mixed"):
-        ctx.set_config(prec)
-        whole = ctx.simulate(sc, ph, seq)
-        for chunk in (1, 97, 100000):
-            r = ctx.open(sc, ph, seq)
-            while not r.done():
-                r.advance(chunk)
-            assert np.array_equal(r.result(), whole)
-            r.close()
-        # checkpoint half way, restore into a fresh request
+        for lanes, chunks in ((1, (1, 63, 64, 65, 97, 100000)), (0, (1, 97, 100000))):
+            ctx.set_config(prec, lanes_per_spin=lanes)
+            whole = ctx.simulate(sc, ph, seq)
+            for chunk in chunks:
+                r = ctx.open(sc, ph, seq)
+                while not r.done():
+                    r.advance(chunk)
+                assert np.array_equal(r.result(), whole), (prec, lanes, chunk)
+                r.close()
+        # checkpoint half way (the planner's lanes per spin, as the last whole
+        # run), restore into a fresh request
         r = ctx.open(sc, ph, seq)
         for _ in range(30):
             r.advance(100)
@@ -297,6 +302,19 @@ def test_request_path_equals_simulate(ctx):
             r2.advance(500)
         assert np.array_equal(r2.result(), whole)
         r2.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_one_lane_per_spin_runs_against_oracle(ctx, prec):
+    """One lane per spin on the SE-EPI subset: the 100- and 200-interval sinc
+    pulses are runs of single intervals longer than the 64-event LDS stage,
+    taken by the run loop in pieces; against the oracle."""
+    say(f"[parity] seepi_subset one lane {prec}")
+    ref = oracle_cached("seepi_subset")
+    ctx.set_config(prec, lanes_per_spin=1)
+    sc, ph, seq = case("seepi_subset")
+    check(ctx.simulate(sc, ph, seq), ref, prec, "seepi subset, one lane per spin")
+    ctx.set_config(prec)
 
 
 def test_invalid_device_phantom_is_rejected(ctx, K):
