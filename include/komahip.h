@@ -264,6 +264,8 @@ typedef struct {
     int64_t n_rows;        /* rows of per-wavefront sample partials (a wavefront holding two
                               groups has two) */
     int64_t lanes_per_spin; /* lanes per spin of the spin-sequential kernel */
+    int64_t max_single_run; /* longest run of single excitation intervals with equal relaxation
+                               keys (the one-lane kernel takes such a run in one loop) */
 } koma_req_info;
 koma_status koma_req_info_get(const koma_req *req, koma_req_info *info);
 /* The same figures for a plan built on the host only (no device work);

@@ -2191,9 +2191,11 @@ static void fill_info(const Plan &P, koma_req_info *info) {
     info->n_rf_in_runs = 0;
     info->n_rows = P.n_rows;
     info->lanes_per_spin = P.lanes;
+    info->max_single_run = 0;
     for (const Event &e : P.ev) {
         if (e.kind == EV_END) ++info->n_ends;
         if (e.kind == EV_RF && e.count > 1) info->n_rf_in_runs += e.count;
+        if (e.kind == EV_RF && e.count == 1) info->max_single_run = std::max<int64_t>(info->max_single_run, e.a0);
     }
 }
 

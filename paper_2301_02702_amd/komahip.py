@@ -61,7 +61,7 @@ class koma_req_info(ctypes.Structure):
         "n_spins", "n_tiles", "n_groups", "n_adc", "n_events", "n_rf", "n_rf_events", "n_runs", "n_inline_adc",
         "n_deferred_adc", "n_stretches", "n_families", "n_snapshots", "n_blocks", "spins_per_lane", "n_chunks",
         "events_done")] + [("footprint", c_size_t), ("n_ends", c_int64), ("n_rf_in_runs", c_int64),
-                           ("n_rows", c_int64), ("lanes_per_spin", c_int64)]
+                           ("n_rows", c_int64), ("lanes_per_spin", c_int64), ("max_single_run", c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

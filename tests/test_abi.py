@@ -101,6 +101,33 @@ def test_runs_of_identical_excitation_intervals_are_one_event(K):
     assert info["n_rf_events"] == 3
 
 
+def test_runs_of_single_intervals_for_the_one_lane_kernel(K):
+    """Consecutive single excitation intervals (distinct fields, as in a
+    shaped pulse under a slice-select gradient) whose relaxation keys are
+    equal form one run of the one-lane kernel: the run ends where the
+    interval length changes by more than the time grid's rounding, and a run
+    of identical intervals (one event with a count) or a sample in between
+    ends it too."""
+    ph = W.random_spins(np.random.default_rng(5), 10)
+    dt = 4e-6
+    b1 = (1e-5 * np.sinc(np.linspace(-3, 3, 100)) + 0j) * np.exp(0.3j * np.arange(100))
+    t = dt * np.arange(101)
+    g = np.zeros((101, 3))
+    g[:, 2] = 10e-3                        # slice select
+    info = K.koma_plan_info(W.Scanner(), ph, W.make_sequence(t, g, b1, []), K.make_config())
+    assert info["n_rf_events"] == 100 and info["max_single_run"] == 100
+    t2 = t.copy()
+    t2[60:] += 1e-9                        # interval 59 longer: runs 0..58, 59, 60..99
+    info = K.koma_plan_info(W.Scanner(), ph, W.make_sequence(t2, g, b1, []), K.make_config())
+    assert info["max_single_run"] == 59
+    b1r = b1.copy()
+    b1r[30:40] = b1r[30]                   # ten identical intervals: one event with a count
+    info = K.koma_plan_info(W.Scanner(), ph, W.make_sequence(t, g, b1r, []), K.make_config())
+    assert info["n_rf_events"] == 91 and info["max_single_run"] == 60
+    info = K.koma_plan_info(W.Scanner(), ph, W.make_sequence(t, g, b1, [45]), K.make_config())
+    assert info["max_single_run"] == 55
+
+
 def test_matrix_core_grid_fills_whole_rounds(K):
     """The matrix-core sample-parallel grids are sized to whole rounds of
     resident workgroups (256 CUs when there is no device): in the mixed form
