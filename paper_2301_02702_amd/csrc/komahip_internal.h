@@ -123,7 +123,7 @@ constexpr int kMMStretches64 = 4;   // the same in FP64
 #ifndef KOMA_MM_RESIDENT
 #define KOMA_MM_RESIDENT 3
 #endif
-constexpr int kMMResident = KOMA_MM_RESIDENT;  // FP32 matrix-core workgroups resident per CU (LDS 48 KB each)
+constexpr int kMMResident = KOMA_MM_RESIDENT;  // FP32 matrix-core workgroups resident per CU (registers; LDS 32 KB each)
 constexpr int kMMResident64 = 1;    // the same in FP64 (LDS 96 KB)
 
 // A segment of the event program for the several-lanes-per-spin kernel:
