@@ -140,13 +140,18 @@ typedef struct {
                               16 (the events between two observations of the state are affine
                               maps; each lane composes a share of them, the lanes' products are
                               combined, the same operators associated differently) */
+    int stretches_per_wg;  /* readout stretches per workgroup of the FP32 matrix-core sample sums:
+                              0 = the planner's choice, 4 or 6 (6 shares each staged operand among
+                              more sums; 4 gives a finer grid). Other engines and KOMA_FP64 ignore
+                              it. */
 } koma_config;
 
 typedef struct koma_ctx koma_ctx;
 typedef struct koma_req koma_req;
 
 /* Defaults: KOMA_MIXED, auto spins per lane, 256, 4096 events, no budget,
- * 1 GiB partials, defer_min_adc 32, stretch_max 128, sample_engine 0. */
+ * 1 GiB partials, defer_min_adc 32, stretch_max 128, sample_engine 0,
+ * tile_packing 1, and the planner's lanes per spin and stretches per workgroup. */
 void koma_config_default(koma_config *cfg);
 
 /* Create a context on HIP device `device` (sets it current). The context
@@ -266,6 +271,8 @@ typedef struct {
     int64_t lanes_per_spin; /* lanes per spin of the spin-sequential kernel */
     int64_t max_single_run; /* longest run of single excitation intervals with equal relaxation
                                keys (the one-lane kernel takes such a run in one loop) */
+    int64_t stretches_per_wg; /* readout stretches one sample-parallel workgroup takes (4 or 6 on the
+                                 FP32 matrix cores, whichever fills the chip's rounds better) */
 } koma_req_info;
 koma_status koma_req_info_get(const koma_req *req, koma_req_info *info);
 /* The same figures for a plan built on the host only (no device work);

@@ -115,10 +115,11 @@ constexpr int kWG = 256;            // 4 wavefronts
 constexpr int kWavesPerWG = kWG / kWave;
 constexpr int kBatch = 16;          // samples reduced together by the register transpose
 constexpr int kStretchMax = 128;
-#ifndef KOMA_MM_STRETCHES
-#define KOMA_MM_STRETCHES 4
-#endif
-constexpr int kMMStretches = KOMA_MM_STRETCHES;  // stretches whose sums one FP32 matrix-core workgroup keeps in registers
+// stretches whose sums one FP32 matrix-core workgroup keeps in registers:
+// 6, or 4 where the larger batches would leave the last round of
+// workgroups short (the planner chooses; the kernel is built for both)
+constexpr int kMMStretches = 6;
+constexpr int kMMStretchesSmall = 4;
 constexpr int kMMStretches64 = 4;   // the same in FP64
 #ifndef KOMA_MM_RESIDENT
 #define KOMA_MM_RESIDENT 3

@@ -1383,7 +1383,8 @@ __device__ __forceinline__ ParWG par_work_item() {
 //
 // B depends on the stretch only through its increments, which the host makes
 // bitwise equal within a family of stretches (all lines of one readout
-// polarity, say). A workgroup takes up to kMMStretches stretches and loops
+// polarity, say). A workgroup takes up to NS stretches (6, or 4 for grids
+// that 6 would leave short: a planner's choice) and loops
 // over its tiles outside them: per tile and family, each lane forms its
 // spin's w^r (r < 16) and w^(16 q) once, and the wavefront turns the B
 // operands round through LDS into registers; per stretch only the anchor c
@@ -1415,6 +1416,7 @@ __device__ __forceinline__ C2<float> mm_anchor(const ParSpin &s, float r2, const
 
 // Tiles per wavefront: a.spl (a block is 4 a.spl tiles), a run-time value so
 // that the planner can size the grid to whole rounds of resident workgroups.
+template <int NS>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMMResident))) void k_par_mm(ParArgs a) {
     const int S = a.spl;
     // per-wavefront stage (8 KB): B operands at a family's start, the two
@@ -1422,8 +1424,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMMResident
     // [wave][stretch of the pair][sample] (16 KB of the workgroup's 32)
     __shared__ __attribute__((aligned(16))) float stage[kWavesPerWG][kWave * kStageFloats];
     static_assert(sizeof(double2) * kWavesPerWG * 2 * kStretchMax <= sizeof(stage), "sums fit in the stage");
-    static_assert(kMMStretches % 2 == 0, "whole stretch pairs per batch");
-    constexpr int NP = kMMStretches / 2;  // stretch pairs per batch
+    static_assert(NS % 2 == 0, "whole stretch pairs per batch");
+    constexpr int NP = NS / 2;  // stretch pairs per batch
     double2(*red)[2][kStretchMax] = reinterpret_cast<double2(*)[2][kStretchMax]>(&stage[0][0]);
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -1450,8 +1452,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMMResident
 
     const int64_t st0 = a.s0 + wg.batch * a.per_wg;
     const int64_t st1 = min(st0 + a.per_wg, a.s1);
-    for (int64_t sb = st0; sb < st1; sb += kMMStretches) {
-        const int nb = (int)min<int64_t>(kMMStretches, st1 - sb);  // uniform
+    for (int64_t sb = st0; sb < st1; sb += NS) {
+        const int nb = (int)min<int64_t>(NS, st1 - sb);  // uniform
         f32x4 acc[NP][3];
 #pragma unroll
         for (int p = 0; p < NP; ++p) acc[p][0] = acc[p][1] = acc[p][2] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -1466,7 +1468,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMMResident
             // and the snapshots of the batch's stretches
             ParSpin spn{0.f, 0.f, 0.f, 0.f, __builtin_inff()};
             C2<float> sens{1.f, 0.f};
-            float2 snap[kMMStretches];
+            float2 snap[NS];
             // snapshots of stretch i2 of the batch (zero for empty lanes)
             auto load_snap = [&](int i2) {
                 snap[i2] = make_float2(0.f, 0.f);
@@ -2068,7 +2070,10 @@ int launch_seq(bool fp64, bool moving, const SeqArgs &a, void *stream) {
 static void par_dispatch_mm(int spl, dim3 grid, const ParArgs &a, hipStream_t st) {
     ParArgs b = a;
     b.spl = spl;
-    hipLaunchKernelGGL(k_par_mm, grid, dim3(kWG), 0, st, b);
+    if (a.per_wg == kMMStretches)
+        hipLaunchKernelGGL(k_par_mm<kMMStretches>, grid, dim3(kWG), 0, st, b);
+    else
+        hipLaunchKernelGGL(k_par_mm<kMMStretchesSmall>, grid, dim3(kWG), 0, st, b);
 }
 
 static void par_dispatch_mm64(int spl, dim3 grid, const ParArgs &a, hipStream_t st) {

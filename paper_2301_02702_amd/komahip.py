@@ -53,7 +53,7 @@ class koma_config(ctypes.Structure):
     _fields_ = [("precision", c_int), ("spins_per_lane", c_int), ("wg_size", c_int),
                 ("chunk_events", c_int64), ("hbm_budget", c_size_t), ("partial_budget", c_size_t),
                 ("defer_min_adc", c_int), ("stretch_max", c_int), ("sample_engine", c_int),
-                ("tile_packing", c_int), ("lanes_per_spin", c_int)]
+                ("tile_packing", c_int), ("lanes_per_spin", c_int), ("stretches_per_wg", c_int)]
 
 
 class koma_req_info(ctypes.Structure):
@@ -61,7 +61,8 @@ class koma_req_info(ctypes.Structure):
         "n_spins", "n_tiles", "n_groups", "n_adc", "n_events", "n_rf", "n_rf_events", "n_runs", "n_inline_adc",
         "n_deferred_adc", "n_stretches", "n_families", "n_snapshots", "n_blocks", "spins_per_lane", "n_chunks",
         "events_done")] + [("footprint", c_size_t), ("n_ends", c_int64), ("n_rf_in_runs", c_int64),
-                           ("n_rows", c_int64), ("lanes_per_spin", c_int64), ("max_single_run", c_int64)]
+                           ("n_rows", c_int64), ("lanes_per_spin", c_int64), ("max_single_run", c_int64),
+                           ("stretches_per_wg", c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

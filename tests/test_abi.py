@@ -130,16 +130,35 @@ def test_runs_of_single_intervals_for_the_one_lane_kernel(K):
 
 def test_matrix_core_grid_fills_whole_rounds(K):
     """The matrix-core sample-parallel grids are sized to whole rounds of
-    resident workgroups (256 CUs when there is no device): in the mixed form
-    (3 per CU) epi256 gets 11 tiles per wavefront, 24 spin blocks x 32
-    batches = 768 workgroups; in FP64 (1 per CU, 96 KB of LDS) every S fills
-    whole rounds and the largest, 16, gives 16 blocks x 32 = 512 (two
-    rounds); the vector-ALU forms keep 1, 2, 4 or 8."""
+    resident workgroups (256 CUs when there is no device). In the mixed form
+    (3 per CU) a workgroup takes 4 or 6 stretches, whichever gives fewer
+    rounds x tiles per wavefront x stretches (6 counted 3.5 % cheaper):
+    epi256 keeps 4, with 11 tiles per wavefront, 24 spin blocks x 32 batches =
+    768 workgroups (6 would need 8 tiles, 32 x 22 = 704 in the one round);
+    a 100k-spin GRE request takes 6, 6 tiles, 66 blocks x 11 batches = 726.
+    In FP64 (1 per CU, 96 KB of LDS) every S fills whole rounds and the
+    largest, 16, gives 16 blocks x 32 = 512 (two rounds); the vector-ALU forms
+    keep 1, 2, 4 or 8. A requested batch size is kept, other values than 0,
+    4 and 6 are rejected."""
     sc, ph, seq = W.config(2)
     i = K.koma_plan_info(sc, ph, seq, K.make_config())
-    assert i["spins_per_lane"] == 11 and i["n_blocks"] == 24
+    assert (i["spins_per_lane"], i["n_blocks"], i["stretches_per_wg"]) == (11, 24, 4)
     i = K.koma_plan_info(sc, ph, seq, K.make_config("fp64"))
-    assert i["spins_per_lane"] == 16 and i["n_blocks"] == 16
+    assert (i["spins_per_lane"], i["n_blocks"], i["stretches_per_wg"]) == (16, 16, 4)
+    r = W.ServingRequest(0, 0.0, 100000, "gre", 77)
+    i = K.koma_plan_info(W.Scanner(), W.serving_phantom(r), W.serving_sequence("gre"), K.make_config())
+    assert (i["spins_per_lane"], i["n_blocks"], i["stretches_per_wg"], i["n_stretches"]) == (6, 66, 6, 64)
+    # a requested S keeps the smaller batch; a requested batch is kept
+    i = K.koma_plan_info(sc, ph, seq, K.make_config(spins_per_lane=3))
+    assert (i["spins_per_lane"], i["stretches_per_wg"]) == (3, 4)
+    i = K.koma_plan_info(sc, ph, seq, K.make_config(stretches_per_wg=6))
+    assert (i["spins_per_lane"], i["n_blocks"], i["stretches_per_wg"]) == (8, 32, 6)
+    i = K.koma_plan_info(sc, ph, seq, K.make_config("fp64", stretches_per_wg=6))
+    assert i["stretches_per_wg"] == 4
+    for bad in (-1, 1, 5, 8):
+        with pytest.raises(K.KomaError) as e:
+            K.koma_plan_info(sc, ph, seq, K.make_config(stretches_per_wg=bad))
+        assert e.value.status == -1
     for cfg in (K.make_config("fp64", sample_engine=1), K.make_config(sample_engine=1)):
         assert K.koma_plan_info(sc, ph, seq, cfg)["spins_per_lane"] in (1, 2, 4, 8)
     assert K.koma_plan_info(sc, W.with_velocity(ph.subset(np.arange(0, ph.n, 8))), seq,

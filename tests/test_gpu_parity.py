@@ -183,7 +183,8 @@ def test_stretch_families_share_operands(ctx, prec):
     mixed order): the matrix-core kernel shares the per-sample operands
     within a family of equal increments; a stretch pair whose stretches
     belong to two families, and a short last batch, take their own paths.
-    Several stretch lengths and tile counts per lane, both sample engines."""
+    Several stretch lengths and tile counts per lane, both sample engines,
+    and on the matrix cores batches of 4 and of 6 stretches per workgroup."""
     import oracle
     rng = np.random.default_rng(21)
     sc = W.Scanner()
@@ -192,13 +193,13 @@ def test_stretch_families_share_operands(ctx, prec):
     ref = oracle.simulate(sc, ph, seq)
     for smax in (128, 16, 7):
         for spl in (1, 2, 8):
-            for eng in (0, 1):
-                ctx.set_config(prec, spins_per_lane=spl, sample_engine=eng, stretch_max=smax)
+            for eng, ns in ((0, 4), (0, 6), (1, 0)):
+                ctx.set_config(prec, spins_per_lane=spl, sample_engine=eng, stretch_max=smax, stretches_per_wg=ns)
                 got = ctx.simulate(sc, ph, seq)
                 e, m, z = errors(got, ref)
-                assert z and e <= TOL[prec] and m <= TOL[prec], (smax, spl, eng, e, m)
+                assert z and e <= TOL[prec] and m <= TOL[prec], (smax, spl, eng, ns, e, m)
     say(f"[parity] stretch families {prec}: ok")
-    ctx.set_config(prec, spins_per_lane=0, sample_engine=0, stretch_max=128)
+    ctx.set_config(prec, spins_per_lane=0, sample_engine=0, stretch_max=128, stretches_per_wg=0)
 
 
 def test_random_readouts_every_engine_and_shape(ctx):
@@ -206,8 +207,8 @@ def test_random_readouts_every_engine_and_shape(ctx):
     stretches of two families and short last batches occur), 8-199 samples
     per line, 1-699 spins in up to three groups, receive coils in some; each
     form on both sample engines with a random number of tiles per lane
-    (1 .. 16, rounded down to 1, 2, 4 or 8 on the vector ALU) and stretch
-    length, against the oracle."""
+    (1 .. 16, rounded down to 1, 2, 4 or 8 on the vector ALU), stretch
+    length and stretches per matrix-core workgroup, against the oracle."""
     import oracle
     rng = np.random.default_rng(777)
     sc = W.Scanner()
@@ -229,13 +230,14 @@ def test_random_readouts_every_engine_and_shape(ctx):
             for eng in (0, 1):
                 spl = int(rng.choice([0, 1, 2, 3, 5, 8, 16]))
                 smax = int(rng.choice([128, 37, 16, 5]))
-                ctx.set_config(prec, sample_engine=eng, spins_per_lane=spl, stretch_max=smax)
+                ns = int(rng.choice([0, 4, 6]))
+                ctx.set_config(prec, sample_engine=eng, spins_per_lane=spl, stretch_max=smax, stretches_per_wg=ns)
                 got = ctx.simulate(sc, ph, seq).reshape(-1, ref.shape[-1])
                 e, m, z = errors(got, r2)
                 assert z, (trial, n, prec, eng)
-                assert e <= TOL[prec] and m <= TOL[prec], (trial, n, prec, eng, spl, smax, e, m)
+                assert e <= TOL[prec] and m <= TOL[prec], (trial, n, prec, eng, spl, smax, ns, e, m)
                 worst[prec] = max(worst[prec], m)
-    ctx.set_config("mixed", sample_engine=0, spins_per_lane=0, stretch_max=128)
+    ctx.set_config("mixed", sample_engine=0, spins_per_lane=0, stretch_max=128, stretches_per_wg=0)
     say(f"[parity] random readouts: worst max sample error fp64 {worst['fp64']:.2e}, mixed {worst['mixed']:.2e}")
 
 
@@ -246,16 +248,16 @@ def test_launch_shape_invariance_and_determinism(ctx, prec):
     ref = oracle_cached("epi_small")
     outs = []
     for spl in (1, 2, 4, 8):
-        for smax in (128, 37):
-            ctx.set_config(prec, spins_per_lane=spl, stretch_max=smax)
+        for smax, ns in ((128, 4), (37, 4), (128, 6), (37, 6)):
+            ctx.set_config(prec, spins_per_lane=spl, stretch_max=smax, stretches_per_wg=ns)
             sc, ph, seq = case("epi_small")
             a = ctx.simulate(sc, ph, seq)
             b = ctx.simulate(sc, ph, seq)
             assert np.array_equal(a, b)
             e, m, _ = errors(a, ref)
-            assert e <= TOL[prec] and m <= TOL[prec], (spl, smax, e, m)
+            assert e <= TOL[prec] and m <= TOL[prec], (spl, smax, ns, e, m)
             outs.append(a)
-    ctx.set_config(prec, spins_per_lane=0, stretch_max=128)
+    ctx.set_config(prec, spins_per_lane=0, stretch_max=128, stretches_per_wg=0)
 
 
 def test_device_pointers_match_host(ctx, K):
