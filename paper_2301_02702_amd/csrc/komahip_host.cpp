@@ -1217,11 +1217,15 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
             // FP32: 6 stretches per workgroup do the same work in about 3.5 %
             // less time than 4 (fewer LDS round trips for the shared
             // operands), unless their coarser grid takes more rounds: compare
-            // rounds x tiles per wavefront x stretches per workgroup
+            // rounds x tiles per wavefront x stretches per workgroup. The
+            // partial sums (device footprint, and the reduction's reads) grow
+            // with the number of spin blocks, which that count leaves out:
+            // 6 only where it does not take more blocks.
             int s6;
             int64_t r6;
             choose(kMMStretches, s6, r6);
-            if ((double)r6 * s6 * kMMStretches * 0.965 < (double)rounds * spl * mm_batch) {
+            if ((double)r6 * s6 * kMMStretches * 0.965 < (double)rounds * spl * mm_batch &&
+                n_blocks_for(s6) <= n_blocks_for(spl)) {
                 mm_batch = kMMStretches;
                 spl = s6;
             }

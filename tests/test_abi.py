@@ -135,7 +135,10 @@ def test_matrix_core_grid_fills_whole_rounds(K):
     rounds x tiles per wavefront x stretches (6 counted 3.5 % cheaper):
     epi256 keeps 4, with 11 tiles per wavefront, 24 spin blocks x 32 batches =
     768 workgroups (6 would need 8 tiles, 32 x 22 = 704 in the one round);
-    a 100k-spin GRE request takes 6, 6 tiles, 66 blocks x 11 batches = 726.
+    a 1e6-spin GRE request takes 6 with 4 tiles, 977 blocks x 11 batches in
+    14 rounds (4 would take 2 tiles, 1,954 x 16 in 41); a 1e5-spin one keeps
+    4 (9 tiles, 44 blocks), since 6 would take more blocks (66) and so more
+    partial sums.
     In FP64 (1 per CU, 96 KB of LDS) every S fills whole rounds and the
     largest, 16, gives 16 blocks x 32 = 512 (two rounds); the vector-ALU forms
     keep 1, 2, 4 or 8. A requested batch size is kept, other values than 0,
@@ -145,9 +148,10 @@ def test_matrix_core_grid_fills_whole_rounds(K):
     assert (i["spins_per_lane"], i["n_blocks"], i["stretches_per_wg"]) == (11, 24, 4)
     i = K.koma_plan_info(sc, ph, seq, K.make_config("fp64"))
     assert (i["spins_per_lane"], i["n_blocks"], i["stretches_per_wg"]) == (16, 16, 4)
-    r = W.ServingRequest(0, 0.0, 100000, "gre", 77)
-    i = K.koma_plan_info(W.Scanner(), W.serving_phantom(r), W.serving_sequence("gre"), K.make_config())
-    assert (i["spins_per_lane"], i["n_blocks"], i["stretches_per_wg"], i["n_stretches"]) == (6, 66, 6, 64)
+    for n, want in ((1000000, (4, 977, 6, 64)), (100000, (9, 44, 4, 64))):
+        r = W.ServingRequest(0, 0.0, n, "gre", 77)
+        i = K.koma_plan_info(W.Scanner(), W.serving_phantom(r), W.serving_sequence("gre"), K.make_config())
+        assert (i["spins_per_lane"], i["n_blocks"], i["stretches_per_wg"], i["n_stretches"]) == want, n
     # a requested S keeps the smaller batch; a requested batch is kept
     i = K.koma_plan_info(sc, ph, seq, K.make_config(spins_per_lane=3))
     assert (i["spins_per_lane"], i["stretches_per_wg"]) == (3, 4)
