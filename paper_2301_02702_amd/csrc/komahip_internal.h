@@ -125,7 +125,7 @@ constexpr int kMMStretches64 = 4;   // the same in FP64
 #define KOMA_MM_RESIDENT 3
 #endif
 constexpr int kMMResident = KOMA_MM_RESIDENT;  // FP32 matrix-core workgroups resident per CU (registers; LDS 32 KB each)
-constexpr int kMMResident64 = 1;    // the same in FP64 (LDS 96 KB)
+constexpr int kMMResident64 = 2;    // the same in FP64 (LDS 64 KB each)
 
 // A segment of the event program for the several-lanes-per-spin kernel:
 // map events (EV_RF, EV_END) [e0, e1), then, if obs, the observation event

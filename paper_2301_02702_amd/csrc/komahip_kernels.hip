@@ -1656,12 +1656,16 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMMResident
 // (lane l: A[l % 16][l / 16], B[l / 16][l % 16]) but returns row 4 v + l / 16
 // of column l % 16 in its element v. Every factor is formed in FP64 (exact
 // FP64 phase, FP64 sincos and exp), the powers by the same shallow product
-// trees. To keep the registers for the FP64 values, the operands stay in LDS
-// as complex numbers (B for the whole family, A per stretch pair) and each
-// product's Re + Im, Im - Re sums are formed as it is read; 32 KB of stage
-// per wavefront (one workgroup per CU, one wavefront per SIMD).
+// trees. The family's B operands (Re B, Im B of spin 4 u + l / 16, column
+// l % 16) are turned round through LDS into 64 registers once per tile and
+// family, Im B - Re B and Re B + Im B formed at each use; the A rows of each
+// stretch pair are staged in LDS as a Re and an Im plane, their sum formed
+// as it is read.
+// 16 KB of stage per wavefront: two workgroups per CU, two wavefronts per
+// SIMD, so that one wavefront's LDS round trips and factors overlap the
+// other's products.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-constexpr int kStage64 = 64;  // doubles per spin: B (16 complex) + A (16 rows, Re and Im planes)
+constexpr int kStage64 = 32;  // doubles per spin: B (16 complex), then A (16 rows, Re and Im planes)
 
 // sin and cos of 2 pi h (h in turns) and exp(-x) for x >= 0 in FP64, shorter
 // than the library routines (which cover every argument with branches):
@@ -1725,11 +1729,11 @@ __device__ __forceinline__ C2<double> mm64_factor(const ParSpin &s, double r2, c
     return {cs * e2, sn * e2};
 }
 
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(1))) void k_par_mm64(ParArgs a) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMMResident64))) void k_par_mm64(ParArgs a) {
     const int S = a.spl;
-    // per-wavefront stage: B operands of the current family (complex, 2048
-    // doubles), then the A rows of the current stretch pair in a Re and an Im
-    // plane (1024 doubles each); after the tiles, the FP64 sums
+    // per-wavefront stage (16 KB): B operands at a family's start, then the
+    // A rows of the current stretch pair in a Re and an Im plane (1024
+    // doubles each); after the tiles, the FP64 sums
     // [wave][stretch of the pair][sample]
     __shared__ __attribute__((aligned(16))) double stage[kWavesPerWG][kWave * kStage64];
     static_assert(sizeof(double2) * kWavesPerWG * 2 * kStretchMax <= sizeof(stage), "sums fit in the stage");
@@ -1746,75 +1750,71 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(1))) void k
     // Stage layouts (doubles), 16-byte chunks XOR-permuted by the spin so
     // that the chunk writes of consecutive lanes fall in distinct banks:
     //   B: spin s, complex r at 32 s + 2 (r ^ (s & 15));
-    //   A plane p (Re A, Im A) at 2048 + 1024 p: spin s, rows 2c, 2c + 1 (row
+    //   A plane p (Re A, Im A) at 1024 p: spin s, rows 2c, 2c + 1 (row
     //   8 h + q is A[q] of stretch h of the pair) at 16 s + 2 (c ^ (s & 7)).
     const int m = lane & 15, g = lane >> 4;  // row (A) / column (B) m; spin 4u + g of group u
+    // operand read positions: B of spin 4u + g at 128 u + b_rd[u % 4], A of
+    // spin 4u + g at 64 u + a_rd[u % 2] (and 1024 further in the Im plane)
+    int b_rd[4], a_rd[2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) b_rd[k] = 32 * g + 2 * (m ^ (4 * k + g));
+#pragma unroll
+    for (int k = 0; k < 2; ++k) a_rd[k] = 16 * g + 2 * ((m >> 1) ^ (4 * k + g)) + (m & 1);
 
     const int64_t st0 = a.s0 + wg.batch * a.per_wg;
     const int64_t st1 = min(st0 + a.per_wg, a.s1);
     for (int64_t sb = st0; sb < st1; sb += kMMStretches64) {
         const int nb = (int)min<int64_t>(kMMStretches64, st1 - sb);  // uniform
-        // the batch's stretch parameters, read once into registers (with one
-        // wavefront per SIMD a scalar reload per tile would wait in full)
-        struct SP {
-            double k0[4], dk[4];
-            int fam, slot;
-        } sprm[kMMStretches64];
-#pragma unroll
-        for (int i2 = 0; i2 < kMMStretches64; ++i2) {
-            const auto &S_ = as_const(a.st)[sb + min(i2, nb - 1)];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                sprm[i2].k0[c] = S_.k0[c];
-                sprm[i2].dk[c] = S_.dk[c];
-                asm volatile("" : "+v"(sprm[i2].k0[c]), "+v"(sprm[i2].dk[c]));
-            }
-            sprm[i2].fam = S_.fam;
-            sprm[i2].slot = S_.slot;
-        }
         f64x4 acc[2][3];
 #pragma unroll
         for (int p = 0; p < 2; ++p) acc[p][0] = acc[p][1] = acc[p][2] = f64x4{0.0, 0.0, 0.0, 0.0};
         for (int j = 0; j < S; ++j) {
             const int tl = __builtin_amdgcn_readfirstlane(wave) + kWavesPerWG * j;
             if (tl >= B.ntiles) break;  // uniform; later slots are empty too
-            // the tile's inputs (zero for empty lanes); loading the next
-            // tile's during this one's products measured no faster
+            const auto &T = as_const(a.tiles)[B.tile0 + tl];
+            const bool valid = lane < T.count;
+            const int64_t pidx = (int64_t)(B.tile0 + tl) * kWave + lane;  // padded spin slot of this lane
+            // the tile's inputs (zero for empty lanes); the second pair's
+            // snapshots arrive during the first pair's products
             ParSpin spn{0.f, 0.f, 0.f, 0.f, __builtin_inff()};
             C2<double> sens{1.0, 0.0};
             double2 snap[kMMStretches64];
-#pragma unroll
-            for (int i2 = 0; i2 < kMMStretches64; ++i2) snap[i2] = make_double2(0.0, 0.0);
-            {
-                const auto &T = as_const(a.tiles)[B.tile0 + tl];
-                if (lane < T.count) {
-                    const int64_t i = T.spin0 + lane;
-                    const int64_t pidx = (int64_t)(B.tile0 + tl) * kWave + lane;
-                    spn = ParSpin{a.ph.x[i], a.ph.y[i], a.ph.z[i], a.ph.dw[i], a.ph.t2[i]};
-                    if (coils) sens = C2<double>{(double)a.ph.sre[coil * a.ph.n + i], (double)a.ph.sim[coil * a.ph.n + i]};
-#pragma unroll
-                    for (int i2 = 0; i2 < kMMStretches64; ++i2)
-                        snap[i2] = reinterpret_cast<const double2 *>(a.snap)[(int64_t)sprm[i2].slot * n_pad + pidx];
-                }
+            auto load_snap = [&](int i2) {
+                snap[i2] = make_double2(0.0, 0.0);
+                if (valid)
+                    snap[i2] = reinterpret_cast<const double2 *>(a.snap)[(int64_t)as_const(a.st)[sb + min(i2, nb - 1)].slot * n_pad + pidx];
+            };
+            if (valid) {
+                const int64_t i = T.spin0 + lane;
+                spn = ParSpin{a.ph.x[i], a.ph.y[i], a.ph.z[i], a.ph.dw[i], a.ph.t2[i]};
+                if (coils) sens = C2<double>{(double)a.ph.sre[coil * a.ph.n + i], (double)a.ph.sim[coil * a.ph.n + i]};
             }
+            load_snap(0);
+            load_snap(1);
             const double r2 = 1.0 / (double)spn.t2;  // +inf -> 0: no decay
-            int32_t fam = -1;  // family of the operands in the stage
-            C2<double> wq[8];  // w^(16 q)
-            auto anchor = [&](const SP &T_, int i2) -> C2<double> {
+            int32_t fam = -1;                         // family of the operands in registers
+            C2<double> w16;                           // w^16
+            double bre[16], bim[16];                  // Re B, Im B (spin 4u + g, column m)
+            auto anchor = [&](const auto &T_, int i2) -> C2<double> {
                 C2<double> mm{snap[i2].x, snap[i2].y};
                 if (coils) mm = cmul(mm, sens);
-                return cmul(mm, mm64_factor(spn, r2, T_.k0));
+                const double k0[4] = {T_.k0[0], T_.k0[1], T_.k0[2], T_.k0[3]};
+                return cmul(mm, mm64_factor(spn, r2, k0));
             };
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
-                const SP &Sa = sprm[2 * p];
-                const SP &Sb = sprm[2 * p + 1];
+                // a short batch repeats its last stretch; the repeats are not stored
+                const auto &Sa = as_const(a.st)[sb + min(2 * p, nb - 1)];
+                const auto &Sb = as_const(a.st)[sb + min(2 * p + 1, nb - 1)];
                 const int passes = Sa.fam == Sb.fam ? 1 : 2;  // uniform
                 for (int pass = 0; pass < passes; ++pass) {
-                    const SP &Sf = pass == 0 ? Sa : Sb;
+                    const auto &Sf = pass == 0 ? Sa : Sb;
                     if (Sf.fam != fam) {  // uniform: the first stretch, or a new family
                         fam = Sf.fam;
-                        const C2<double> w = mm64_factor(spn, r2, Sf.dk);
+                        const double dk[4] = {Sf.dk[0], Sf.dk[1], Sf.dk[2], Sf.dk[3]};
+                        __builtin_amdgcn_sched_barrier(0);
+                        const C2<double> w = mm64_factor(spn, r2, dk);
+                        __builtin_amdgcn_sched_barrier(0);
                         C2<double> pw[16];
                         pw[0] = C2<double>{1.0, 0.0};
                         pw[1] = w;
@@ -1826,68 +1826,90 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(1))) void k
                         pw[8] = cmul(pw[4], pw[4]);
 #pragma unroll
                         for (int r = 9; r < 16; ++r) pw[r] = cmul(pw[8], pw[r - 8]);
-                        wq[0] = C2<double>{1.0, 0.0};
-                        wq[1] = cmul(pw[8], pw[8]);
-                        wq[2] = cmul(wq[1], wq[1]);
-                        wq[3] = cmul(wq[2], wq[1]);
-                        wq[4] = cmul(wq[2], wq[2]);
-#pragma unroll
-                        for (int q = 5; q < 8; ++q) wq[q] = cmul(wq[4], wq[q - 4]);
+                        w16 = cmul(pw[8], pw[8]);
                         // the stage is private to this wavefront, and its LDS
                         // operations complete in program order: only the
                         // compiler must not move LDS accesses across these points
                         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                         __builtin_amdgcn_wave_barrier();
+                        // write positions formed here from an opaque copy of
+                        // the lane (not hoisted out of the loops, where they
+                        // would hold 16 registers)
+                        int ln;
+                        asm volatile("v_mov_b32 %0, %1" : "=v"(ln) : "v"(lane));
+                        double *bw = my + 32 * ln;
 #pragma unroll
                         for (int r = 0; r < 16; ++r)
-                            *reinterpret_cast<double2 *>(my + 32 * lane + 2 * (r ^ (lane & 15))) =
-                                make_double2(pw[r].re, pw[r].im);
+                            *reinterpret_cast<double2 *>(bw + 2 * (r ^ (ln & 15))) = make_double2(pw[r].re, pw[r].im);
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                        for (int u = 0; u < 16; ++u) {
+                            const double2 v = *reinterpret_cast<const double2 *>(my + 128 * u + b_rd[u & 3]);
+                            bre[u] = v.x;
+                            bim[u] = v.y;
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
                     }
+                    __builtin_amdgcn_sched_barrier(0);
                     const C2<double> zero{0.0, 0.0};
                     const C2<double> ca = (passes == 1 || pass == 0) ? anchor(Sa, 2 * p) : zero;
+                    __builtin_amdgcn_sched_barrier(0);
                     const C2<double> cb = (passes == 1 || pass == 1) ? anchor(Sb, 2 * p + 1) : zero;
-                    double *pl = my + 2048 + 16 * lane;
-                    const int sw = lane & 7;
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (p == 0 && pass == passes - 1) {
+                        load_snap(2);
+                        load_snap(3);
+                    }
+                    int ln;
+                    asm volatile("v_mov_b32 %0, %1" : "=v"(ln) : "v"(lane));
+                    double *pl = my + 16 * ln;
+                    const int sw = ln & 7;
+                    // rows 2c, 2c + 1: stretch a (c < 4) or b, q = 2c % 8 and
+                    // 2c % 8 + 1; A[q] = c w^(16 q) by successive products
+                    // with w^16 (the two stretches' chains interleaved; 7
+                    // FP64 roundings at most, far inside the FP64 form's
+                    // error)
+                    C2<double> xa = ca, xb = cb;
 #pragma unroll
-                    for (int c = 0; c < 8; ++c) {
-                        // rows 2c, 2c + 1: stretch a (c < 4) or b, q = 2c % 8 and 2c % 8 + 1
-                        const C2<double> base = c < 4 ? ca : cb;
-                        const int q0 = (2 * c) & 7;
-                        const C2<double> x0 = q0 == 0 ? base : cmul(base, wq[q0]);
-                        const C2<double> x1 = cmul(base, wq[q0 + 1]);
-                        *reinterpret_cast<double2 *>(pl + 2 * (c ^ sw)) = make_double2(x0.re, x1.re);
-                        *reinterpret_cast<double2 *>(pl + 1024 + 2 * (c ^ sw)) = make_double2(x0.im, x1.im);
+                    for (int c = 0; c < 4; ++c) {
+                        const C2<double> ya = cmul(xa, w16), yb = cmul(xb, w16);
+                        *reinterpret_cast<double2 *>(pl + 2 * (c ^ sw)) = make_double2(xa.re, ya.re);
+                        *reinterpret_cast<double2 *>(pl + 1024 + 2 * (c ^ sw)) = make_double2(xa.im, ya.im);
+                        *reinterpret_cast<double2 *>(pl + 2 * ((c + 4) ^ sw)) = make_double2(xb.re, yb.re);
+                        *reinterpret_cast<double2 *>(pl + 1024 + 2 * ((c + 4) ^ sw)) = make_double2(xb.im, yb.im);
+                        if (c < 3) {
+                            xa = cmul(ya, w16);
+                            xb = cmul(yb, w16);
+                        }
                     }
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     // four quarters of 4 spin groups: reads first (one wait),
-                    // then the operand sums and the products
+                    // then Re A + Im A and the products
 #pragma unroll
                     for (int h = 0; h < 4; ++h) {
                         double are[4], aim[4];
-                        double2 bv[4];
 #pragma unroll
                         for (int uu = 0; uu < 4; ++uu) {
-                            const int sp_ = 4 * (4 * h + uu) + g;
-                            const int ai = 2048 + 16 * sp_ + 2 * ((m >> 1) ^ (sp_ & 7)) + (m & 1);
+                            const int ai = 64 * (4 * h + uu) + a_rd[uu & 1];
                             are[uu] = my[ai];
                             aim[uu] = my[ai + 1024];
-                            bv[uu] = *reinterpret_cast<const double2 *>(my + 32 * sp_ + 2 * (m ^ (sp_ & 15)));
                         }
                         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                         for (int uu = 0; uu < 4; ++uu) {
-                            acc[p][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[uu] + aim[uu], bv[uu].x, acc[p][0], 0, 0, 0);
-                            acc[p][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[uu], bv[uu].y - bv[uu].x, acc[p][1], 0, 0, 0);
-                            acc[p][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[uu], bv[uu].x + bv[uu].y, acc[p][2], 0, 0, 0);
+                            const int u = 4 * h + uu;
+                            acc[p][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[uu] + aim[uu], bre[u], acc[p][0], 0, 0, 0);
+                            acc[p][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[uu], bim[u] - bre[u], acc[p][1], 0, 0, 0);
+                            acc[p][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[uu], bre[u] + bim[u], acc[p][2], 0, 0, 0);
                         }
                     }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();  // every wavefront is done with its stage
         // element v of lane l: row 4 v + l / 16 = 8 h + q of column l % 16, so

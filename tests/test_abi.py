@@ -139,8 +139,8 @@ def test_matrix_core_grid_fills_whole_rounds(K):
     14 rounds (4 would take 2 tiles, 1,954 x 16 in 41); a 1e5-spin one keeps
     4 (9 tiles, 44 blocks), since 6 would take more blocks (66) and so more
     partial sums.
-    In FP64 (1 per CU, 96 KB of LDS) every S fills whole rounds and the
-    largest, 16, gives 16 blocks x 32 = 512 (two rounds); the vector-ALU forms
+    In FP64 (2 per CU, 64 KB of LDS each) every S fills whole rounds and the
+    largest, 16, gives 16 blocks x 32 = 512 (one round); the vector-ALU forms
     keep 1, 2, 4 or 8. A requested batch size is kept, other values than 0,
     4 and 6 are rejected."""
     sc, ph, seq = W.config(2)
