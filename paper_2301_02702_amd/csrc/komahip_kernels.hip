@@ -1447,8 +1447,6 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMMResident
     const int a_rd1 = 16 * g + 4 * ((m >> 2) ^ (2 + (g >> 1))) + (m & 3);
     const int b_rd0 = 32 * g + 4 * ((m >> 1) ^ g) + 2 * (m & 1);
     const int b_rd1 = 32 * g + 4 * ((m >> 1) ^ (4 + g)) + 2 * (m & 1);
-    const int a_wr = 16 * lane, a_sw = (lane >> 1) & 3;
-    const int b_wr = 32 * lane, b_sw = lane & 7;
 
     const int64_t st0 = a.s0 + wg.batch * a.per_wg;
     const int64_t st1 = min(st0 + a.per_wg, a.s1);
@@ -1528,9 +1526,15 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMMResident
                         wq[4] = cmul(wq[2], wq[2]);
 #pragma unroll
                         for (int q = 5; q < 8; ++q) wq[q] = cmul(wq[4], wq[q - 4]);
+                        // write positions formed here from an opaque copy of
+                        // the lane, not hoisted out of the loops into registers
+                        int ln_b;
+                        asm volatile("v_mov_b32 %0, %1" : "=v"(ln_b) : "v"(lane));
+                        float *bw = my + 32 * ln_b;
+                        const int bsw = ln_b & 7;
 #pragma unroll
                         for (int c = 0; c < 8; ++c)
-                            *reinterpret_cast<float4 *>(my + b_wr + 4 * (c ^ b_sw)) =
+                            *reinterpret_cast<float4 *>(bw + 4 * (c ^ bsw)) =
                                 make_float4(pw[2 * c].re, pw[2 * c].im, pw[2 * c + 1].re, pw[2 * c + 1].im);
                         // the stage is private to this wavefront, and its LDS
                         // operations complete in program order: only the
@@ -1558,7 +1562,10 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(kMMResident
                         aa[q] = cmul(ca, wq[q]);
                         ab[q] = cmul(cb, wq[q]);
                     }
-                    float *pl = my + a_wr;
+                    int ln_a;
+                    asm volatile("v_mov_b32 %0, %1" : "=v"(ln_a) : "v"(lane));
+                    float *pl = my + 16 * ln_a;
+                    const int a_sw = (ln_a >> 1) & 3;
 #define KOMA_A4(arr, q0, f) make_float4(f(arr[q0]), f(arr[q0 + 1]), f(arr[q0 + 2]), f(arr[q0 + 3]))
 #define KOMA_RE(z) ((z).re)
 #define KOMA_IM(z) ((z).im)
