@@ -69,9 +69,11 @@ struct Plan {
     int64_t n_rows = 0;  // rows of inline partials (tiles, plus one per tile holding two groups)
     bool packed = false; // tiles cross group boundaries (no deferred samples)
     int lanes = 1;       // lanes per spin of the spin-sequential kernel
+    bool half_tiles = false;  // FP64 at 16 lanes: half a tile per workgroup, two inline rows per tile
     std::vector<SegEv> segs;  // segments of the event program (lanes > 1)
     std::vector<Tile> tiles;
     std::vector<int32_t> tile_off;  // [n_groups + 1]
+    std::vector<int32_t> row_off;   // [n_groups + 1]: group g owns inline rows [row_off[g], row_off[g + 1])
     std::vector<Block> blocks;
     std::vector<int32_t> blk_off;   // [n_groups + 1]
     int spl = 1;
@@ -729,6 +731,7 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     P.n_slots = P.n_rf = P.n_rf_events = P.n_runs = 0;
     P.packed = false;
     P.lanes = 1;
+    P.half_tiles = false;
     P.segs.clear();
     P.spl = 1;
     P.per_wg = 1;
@@ -1126,8 +1129,10 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
     // program as one dependent chain; G lanes per spin share every segment of
     // map events (composition of affine maps, then a butterfly over the
     // lanes). The planner takes the largest G in {16, 8, 4, 2} that keeps the
-    // grid within two wavefronts per SIMD (kSeqgWaves), at most 8 in FP64;
-    // packed tiles keep one.
+    // grid within two wavefronts per SIMD (kSeqgWaves); packed tiles keep
+    // one. FP64 maps need twice the registers: at 16 lanes its workgroups take
+    // half a tile (512 lanes), each half summing its inline samples into a
+    // row of its own.
     {
         int G = cfg.lanes_per_spin;
         if (G == 0) {
@@ -1140,9 +1145,8 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
                     }
         }
         if (P.packed) G = 1;
-        // FP64 maps need twice the registers: at most 8 lanes (512-lane workgroups)
-        if (cfg.precision == KOMA_FP64 && G > 8) G = 8;
         P.lanes = G;
+        P.half_tiles = cfg.precision == KOMA_FP64 && G == 16;
         if (G > 1) {
             const int64_t cap = (int64_t)kSegPerLane * G;
             const int64_t ne = (int64_t)P.ev.size();
@@ -1159,6 +1163,13 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
                 P.segs.push_back(g);
             }
         }
+    }
+
+    // inline rows of each group: its tiles (or packed rows), two per tile for half tiles
+    P.row_off = P.tile_off;
+    if (P.half_tiles) {
+        for (int32_t &r : P.row_off) r *= 2;
+        P.n_rows = 2 * P.n_tiles;
     }
 
     // ---- sample-parallel layout: blocks of 4*S tiles of one group
@@ -1303,7 +1314,7 @@ static size_t plan_footprint(const Plan &P, bool fp64, bool with_state, bool wit
     size_t b = 0;
     b += pool_round(P.ev.size() * sizeof(Event)) + pool_round(P.st.size() * sizeof(Stretch));
     b += pool_round(P.tiles.size() * sizeof(Tile)) + pool_round(P.blocks.size() * sizeof(Block));
-    b += pool_round(P.tile_off.size() * 4) + pool_round(P.blk_off.size() * 4);
+    b += pool_round(P.row_off.size() * 4) + pool_round(P.blk_off.size() * 4);
     b += pool_round(P.inl_k.size() * 4) + pool_round(P.def_k.size() * 4);
     b += pool_round(P.segs.size() * sizeof(SegEv));
     b += pool_round((size_t)P.n_slots * n_pad * 2 * r);                         // snapshots
@@ -1403,6 +1414,7 @@ static koma_status run_seq(koma_ctx *ctx, const Plan &P, bool fp64, const Bufs &
     a.n_rows = P.n_rows;
     a.n_inline = (int64_t)P.inl_k.size();
     a.lanes = P.lanes;
+    a.half_tiles = P.half_tiles ? 1 : 0;
     if (P.lanes > 1) {
         // segments that reach into [e0, e1): the first whose events end
         // after e0, up to the first that starts at or after e1
@@ -1738,7 +1750,7 @@ static koma_status simulate_enqueue(koma_ctx *ctx, const koma_scanner *sc, const
                   {P.st.data(), P.st.size() * sizeof(Stretch), 0},
                   {P.tiles.data(), P.tiles.size() * sizeof(Tile), 0},
                   {P.blocks.data(), P.blocks.size() * sizeof(Block), 0},
-                  {P.tile_off.data(), P.tile_off.size() * 4, 0},
+                  {P.row_off.data(), P.row_off.size() * 4, 0},
                   {P.blk_off.data(), P.blk_off.size() * 4, 0},
                   {P.inl_k.data(), P.inl_k.size() * 4, 0},
                   {P.def_k.data(), P.def_k.size() * 4, 0},
@@ -2004,7 +2016,7 @@ koma_status koma_req_open(koma_ctx *ctx, const koma_scanner *sc, const koma_phan
     if ((st = pool_upload(ctx, q->st, P.st, s)) != KOMA_OK) return bail(st);
     if ((st = pool_upload(ctx, q->tiles, P.tiles, s)) != KOMA_OK) return bail(st);
     if ((st = pool_upload(ctx, q->blocks, P.blocks, s)) != KOMA_OK) return bail(st);
-    if ((st = pool_upload(ctx, q->toff, P.tile_off, s)) != KOMA_OK) return bail(st);
+    if ((st = pool_upload(ctx, q->toff, P.row_off, s)) != KOMA_OK) return bail(st);
     if ((st = pool_upload(ctx, q->boff, P.blk_off, s)) != KOMA_OK) return bail(st);
     if ((st = pool_upload(ctx, q->inl, P.inl_k, s)) != KOMA_OK) return bail(st);
     if ((st = pool_upload(ctx, q->def, P.def_k, s)) != KOMA_OK) return bail(st);

@@ -157,6 +157,7 @@ struct SeqArgs {  // spin-sequential kernel
     // several lanes per spin (k_seqg): lanes > 1 splits each segment's map
     // events over `lanes` lanes of a spin; segments [s0, s1) cover [e0, e1)
     int lanes;
+    int half_tiles;  // 1: FP64 at 16 lanes, half a tile per workgroup, inline rows 2 tile + half
     const SegEv *segs;
     int64_t s0, s1;
 };

@@ -964,23 +964,29 @@ __device__ __forceinline__ Aff<typename P::R> event_map(const EvL &ev, const Spi
 // different events of one segment hit different LDS banks).
 constexpr int kSegStride = kEvWords + 1;
 
-// One tile (64 spins) per workgroup of 64 G lanes: lane t holds spin t / G,
-// share t % G of every segment. Segments are staged through LDS, the next
-// one read from memory into registers while the current one is composed.
-template <class P, bool MOV, int G>
-__global__ __launch_bounds__(kWave * G) void k_seqg(SeqArgs a) {
+// SP spins of a tile (all 64, or one half: the FP64 form at 16 lanes, whose
+// registers allow 512-lane workgroups) per workgroup of SP G lanes: lane t
+// holds spin t / G of the workgroup's spins, share t % G of every segment.
+// Segments are staged through LDS, the next one read from memory into
+// registers while the current one is composed. A half tile writes its
+// inline samples to a row of its own (2 tile + half).
+template <class P, bool MOV, int G, int SP>
+__global__ __launch_bounds__(SP * G) void k_seqg(SeqArgs a) {
     using R = typename P::R;
     using R2 = typename P::R2;
-    constexpr int NT = kWave * G;
+    static_assert(SP == kWave || SP == kWave / 2, "a whole tile or one half per workgroup");
+    constexpr int NT = SP * G;
+    constexpr int NW = NT / kWave;  // wavefronts
     constexpr int C = kSegPerLane * G + 1;              // events staged per segment at most
     constexpr int kPre = (C * kEvWords + NT - 1) / NT;  // dwords per thread in flight
     __shared__ uint32_t lds[2][C * kSegStride];
-    __shared__ double red[G][2];
+    __shared__ double red[NW][2];
     const int tid = threadIdx.x;
     const int wave = tid / kWave, lane = tid % kWave;
-    const int sl = tid / G;  // spin slot of the tile
-    const int j = tid % G;   // share of each segment
-    const int64_t tile = blockIdx.x;
+    const int half = SP == kWave ? 0 : (int)(blockIdx.x & 1);
+    const int sl = half * SP + tid / G;  // spin slot of the tile
+    const int j = tid % G;               // share of each segment
+    const int64_t tile = SP == kWave ? (int64_t)blockIdx.x : (int64_t)(blockIdx.x >> 1);
     const Tile T = a.tiles[tile];
     const SpinP<R> s = load_spin<R, MOV>(a.ph, T, sl, a.inv_gamma);
     const int64_t pidx = tile * kWave + sl;
@@ -1067,7 +1073,7 @@ __global__ __launch_bounds__(kWave * G) void k_seqg(SeqArgs a) {
             const int kind = ev.kind();
             if (kind == EV_SNAP) {
                 if (j == 0) reinterpret_cast<R2 *>(a.snap)[(int64_t)ev.a0() * (a.n_tiles * kWave) + pidx] = R2{mr, mi};
-            } else {  // EV_ADC: inline samples, the tile's 64 spins summed once each
+            } else {  // EV_ADC: inline samples, the workgroup's spins summed once each
                 const double k0[4] = {ev.d(0), ev.d(1), ev.d(2), ev.d(3)};
                 C2<R> c, w{R(1), R(0)};
                 int cnt = 1;
@@ -1100,11 +1106,12 @@ __global__ __launch_bounds__(kWave * G) void k_seqg(SeqArgs a) {
                         __syncthreads();
                         if (tid == 0) {
                             double tr = 0.0, ti = 0.0;
-                            for (int q = 0; q < G; ++q) {
+                            for (int q = 0; q < NW; ++q) {
                                 tr += red[q][0];
                                 ti += red[q][1];
                             }
-                            reinterpret_cast<R2 *>(a.pa)[(k * a.n_rows + T.seg) * a.n_inline + ev.a0() + i] = R2{R(tr), R(ti)};
+                            const int64_t row = SP == kWave ? (int64_t)T.seg : 2 * (int64_t)T.seg + half;
+                            reinterpret_cast<R2 *>(a.pa)[(k * a.n_rows + row) * a.n_inline + ev.a0() + i] = R2{R(tr), R(ti)};
                         }
                         __syncthreads();
                     }
@@ -2050,16 +2057,20 @@ template <class P, bool MOV>
 static int launch_seqg(const SeqArgs &a, hipStream_t st) {
     constexpr bool f32 = sizeof(typename P::R) == 4;
     const dim3 grid((unsigned)a.n_tiles);
+    // 16 lanes: whole tiles in FP32 (1,024-lane workgroups); half tiles in
+    // FP64 (512 lanes: two of its wavefronts per SIMD), two rows per tile
+    if (a.half_tiles != (!f32 && a.lanes == 16)) return -1;
     switch (a.lanes) {
-        case 2: hipLaunchKernelGGL((k_seqg<P, MOV, 2>), grid, dim3(kWave * 2), 0, st, a); break;
-        case 4: hipLaunchKernelGGL((k_seqg<P, MOV, 4>), grid, dim3(kWave * 4), 0, st, a); break;
-        case 8: hipLaunchKernelGGL((k_seqg<P, MOV, 8>), grid, dim3(kWave * 8), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_seqg<P, MOV, 2, kWave>), grid, dim3(kWave * 2), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_seqg<P, MOV, 4, kWave>), grid, dim3(kWave * 4), 0, st, a); break;
+        case 8: hipLaunchKernelGGL((k_seqg<P, MOV, 8, kWave>), grid, dim3(kWave * 8), 0, st, a); break;
         case 16:
-            if constexpr (f32) {
-                hipLaunchKernelGGL((k_seqg<P, MOV, 16>), grid, dim3(kWave * 16), 0, st, a);
-                break;
-            }
-            return -1;
+            if constexpr (f32)
+                hipLaunchKernelGGL((k_seqg<P, MOV, 16, kWave>), grid, dim3(kWave * 16), 0, st, a);
+            else
+                hipLaunchKernelGGL((k_seqg<P, MOV, 16, kWave / 2>), dim3(2 * (unsigned)a.n_tiles),
+                                   dim3(kWave / 2 * 16), 0, st, a);
+            break;
         default: return -1;
     }
     return 0;

@@ -345,13 +345,19 @@ def test_packed_tiles_cross_group_boundaries(K):
 
 def test_lanes_per_spin_of_the_planner(K):
     """Several lanes per spin while the tiles fill few wavefronts: the GRE
-    phantom (64 tiles) gets 16 in FP32 and 8 in FP64, the 1024-tile EPI two,
-    the 5e6-spin SE-EPI and the packed MRF batch one; a request for 1 or
-    another valid count is honoured, others are rejected."""
-    def lanes(k, prec="mixed", **kw):
+    phantom (64 tiles) gets 16 in both forms (FP64 in half-tile workgroups,
+    two inline rows per tile), the 1024-tile EPI two, the 5e6-spin SE-EPI
+    and the packed MRF batch one; a request for 1 or another valid count is
+    honoured, others are rejected."""
+    def info(k, prec="mixed", **kw):
         sc, ph, seq = W.config(k)
-        return K.koma_plan_info(sc, ph, seq, K.make_config(prec, **kw))["lanes_per_spin"]
-    assert lanes(1) == 16 and lanes(1, "fp64") == 8
+        return K.koma_plan_info(sc, ph, seq, K.make_config(prec, **kw))
+
+    def lanes(k, prec="mixed", **kw):
+        return info(k, prec, **kw)["lanes_per_spin"]
+    assert lanes(1) == 16 and lanes(1, "fp64") == 16
+    assert info(1)["n_rows"] == 64 and info(1, "fp64")["n_rows"] == 128
+    assert info(1, "fp64", lanes_per_spin=8)["n_rows"] == 64
     assert lanes(2) == 2 and lanes(4) == 1
     assert lanes(1, lanes_per_spin=1) == 1 and lanes(1, lanes_per_spin=4) == 4
     with pytest.raises(K.KomaError):

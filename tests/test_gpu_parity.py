@@ -465,13 +465,14 @@ def test_several_lanes_per_spin_match_oracle(ctx, prec):
     of every segment of excitation intervals and block ends, the lanes'
     products are combined and applied. Every lane count against the oracle
     on the GRE workload (sinc excitations, one lane per spin otherwise
-    latency-bound), random grids with inline samples, coils and moving spins;
-    the chunked request path (chunks end at segment ends) gives the bits of
-    one whole run."""
+    latency-bound), random grids with inline samples, several signal groups,
+    coils and moving spins (FP64 at 16 lanes runs half-tile workgroups, each
+    with its own inline rows); the chunked request path (chunks end at
+    segment ends) gives the bits of one whole run."""
     import oracle
     sc, ph, seq = case("gre")
     ref = oracle_cached("gre")
-    lanes = (1, 2, 4, 8) + ((16,) if prec == "mixed" else ())
+    lanes = (1, 2, 4, 8, 16)
     for g in lanes:
         ctx.set_config(prec, lanes_per_spin=g)
         check(ctx.simulate(sc, ph, seq), ref, prec, f"gre, {g} lanes per spin")
@@ -479,6 +480,8 @@ def test_several_lanes_per_spin_match_oracle(ctx, prec):
     for trial in range(3):
         rseq = W.random_sequence(rng, int(rng.integers(100, 500)), p_rf=0.5, p_adc=0.2)
         sp = W.random_spins(rng, int(rng.integers(1, 200)))
+        if trial == 0 and sp.n >= 3:
+            sp.group_off = np.array([0, sp.n // 3, sp.n // 3, sp.n])  # an empty group among three
         if trial == 1:
             sp = W.with_coils(sp, 2)
         if trial == 2:
