@@ -1148,7 +1148,9 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
         P.lanes = G;
         P.half_tiles = cfg.precision == KOMA_FP64 && G == 16;
         if (G > 1) {
-            const int64_t cap = (int64_t)kSegPerLane * G;
+            // map events per segment: kSegPerLane per lane (half that for
+            // half tiles, as the kernel stages them)
+            const int64_t cap = (int64_t)kSegPerLane * G / (P.half_tiles ? 2 : 1);
             const int64_t ne = (int64_t)P.ev.size();
             int64_t e = 0;
             while (e < ne) {

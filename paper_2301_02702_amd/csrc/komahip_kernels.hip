@@ -977,7 +977,9 @@ __global__ __launch_bounds__(SP * G) void k_seqg(SeqArgs a) {
     static_assert(SP == kWave || SP == kWave / 2, "a whole tile or one half per workgroup");
     constexpr int NT = SP * G;
     constexpr int NW = NT / kWave;  // wavefronts
-    constexpr int C = kSegPerLane * G + 1;              // events staged per segment at most
+    // events staged per segment at most: kSegPerLane per lane, half that for
+    // half tiles (their event prefetch then fits the registers unspilled)
+    constexpr int C = kSegPerLane * G / (kWave / SP) + 1;
     constexpr int kPre = (C * kEvWords + NT - 1) / NT;  // dwords per thread in flight
     __shared__ uint32_t lds[2][C * kSegStride];
     __shared__ double red[NW][2];
