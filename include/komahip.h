@@ -266,8 +266,8 @@ typedef struct {
     size_t footprint;
     int64_t n_ends;        /* precession-block ends every spin evaluates */
     int64_t n_rf_in_runs;  /* excitation intervals inside runs of identical ones */
-    int64_t n_rows;        /* rows of per-wavefront sample partials (a wavefront holding two
-                              groups has two) */
+    int64_t n_rows;        /* rows of inline sample partials: one per tile (a tile holding two
+                              groups has two; in FP64 at 16 lanes per spin, one per half tile) */
     int64_t lanes_per_spin; /* lanes per spin of the spin-sequential kernel */
     int64_t max_single_run; /* longest run of single excitation intervals with equal relaxation
                                keys (the one-lane kernel takes such a run in one loop) */
