@@ -502,3 +502,47 @@ def test_several_lanes_per_spin_match_oracle(ctx, prec):
             assert np.array_equal(r.result(), whole), (g, chunk)
             r.close()
     ctx.set_config(prec, lanes_per_spin=0, defer_min_adc=32)
+
+
+def test_random_configurations_against_oracle(ctx):
+    """Seeded random cases (readout lines or random grids, 1-1,499 spins in
+    up to four groups, receive coils, moving spins) under random settings of
+    every planner knob (sample engine, tiles per wavefront, stretch length,
+    stretches per matrix-core workgroup, lanes per spin, deferral threshold,
+    tile packing), both forms, against the oracle."""
+    import oracle
+    rng = np.random.default_rng(777)
+    sc = W.Scanner()
+    worst = {"fp64": 0.0, "mixed": 0.0}
+    for trial in range(60):
+        if rng.random() < 0.5:
+            amps = list(rng.choice([0.01, -0.01, 0.02, -0.015, 0.005], size=int(rng.integers(1, 12))))
+            seq = W.readout_lines_sequence(amps, n_samples=int(rng.integers(4, 260)))
+        else:
+            seq = W.random_sequence(rng, int(rng.integers(20, 600)), p_rf=float(rng.uniform(0.1, 0.7)),
+                                    p_adc=float(rng.uniform(0.05, 0.5)))
+        n = int(rng.integers(1, 1500))
+        ph = W.random_spins(rng, n)
+        if rng.random() < 0.5 and n >= 3:
+            cuts = np.sort(rng.integers(0, n + 1, int(rng.integers(1, 4))))
+            ph.group_off = np.concatenate([[0], cuts, [n]])
+        if rng.random() < 0.25:
+            ph = W.with_coils(ph, int(rng.integers(1, 4)))
+        if rng.random() < 0.2:
+            ph = W.with_velocity(ph, rng.uniform(-0.3, 0.3, 3), spread=0.2, seed=int(rng.integers(1, 1000)))
+        ref = oracle.simulate(sc, ph, seq)
+        for prec in ("fp64", "mixed"):
+            cfg = dict(sample_engine=int(rng.integers(0, 2)),
+                       spins_per_lane=int(rng.choice([0, 1, 2, 3, 5, 8, 11, 16])),
+                       stretch_max=int(rng.choice([128, 64, 37, 16, 5, 1])),
+                       stretches_per_wg=int(rng.choice([0, 4, 6])),
+                       lanes_per_spin=int(rng.choice([0, 1, 2, 4, 8, 16])),
+                       defer_min_adc=int(rng.choice([-1, 1, 8, 32])),
+                       tile_packing=int(rng.integers(0, 2)))
+            ctx.set_config(prec, **cfg)
+            e, m, z = errors(ctx.simulate(sc, ph, seq), ref)
+            assert z and e <= TOL[prec] and m <= TOL[prec], (trial, n, prec, cfg, e, m)
+            worst[prec] = max(worst[prec], m)
+    ctx.set_config("mixed", sample_engine=0, spins_per_lane=0, stretch_max=128, stretches_per_wg=0,
+                   lanes_per_spin=0, defer_min_adc=32, tile_packing=1)
+    say(f"[parity] random configurations: worst max sample error fp64 {worst['fp64']:.2e}, mixed {worst['mixed']:.2e}")
