@@ -1204,24 +1204,43 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
         // within 2 % of it the largest (fewest partial rows).
         const int64_t slots =
             (int64_t)(cfg.precision == KOMA_FP64 ? kMMResident64 : kMMResident) * std::max(1, ctx->n_cu);
-        // for a batch size: the S, and the rounds of resident workgroups it takes
+        // for a batch size: the S, and the rounds of resident workgroups it
+        // takes. S is searched up to 16 and, in FP32 where that picks 16 for
+        // a grid of at least 32 rounds (there each workgroup's epilogue and
+        // partials weigh more than the last round's tail), up to 32.
         auto choose = [&](int64_t nb_st, int &s_out, int64_t &rounds_out) {
             const int64_t batches = (n_st + nb_st - 1) / nb_st * std::max<int64_t>(1, P.n_coils);
-            double eff[17] = {};
-            int64_t rounds[17] = {};
+            double eff[33] = {};
+            int64_t rounds[33] = {};
             double best_eff = 0.0;
-            for (int cand = 1; cand <= 16; ++cand) {
+            int smax = 16;
+            for (int cand = 1; cand <= smax; ++cand) {
                 const int64_t w = n_blocks_for(cand) * batches;
                 rounds[cand] = (w + slots - 1) / slots;
                 eff[cand] = (double)w / (double)(rounds[cand] * slots);
                 best_eff = std::max(best_eff, eff[cand]);
             }
             s_out = 1;
-            for (int cand = 16; cand >= 1; --cand)
+            for (int cand = smax; cand >= 1; --cand)
                 if (eff[cand] >= best_eff - 0.02) {
                     s_out = cand;
                     break;
                 }
+            if (s_out == 16 && mm32 && rounds[16] >= 32) {
+                smax = 32;
+                best_eff = 0.0;
+                for (int cand = 1; cand <= smax; ++cand) {
+                    const int64_t w = n_blocks_for(cand) * batches;
+                    rounds[cand] = (w + slots - 1) / slots;
+                    eff[cand] = (double)w / (double)(rounds[cand] * slots);
+                    best_eff = std::max(best_eff, eff[cand]);
+                }
+                for (int cand = smax; cand >= 16; --cand)
+                    if (eff[cand] >= best_eff - 0.02) {
+                        s_out = cand;
+                        break;
+                    }
+            }
             rounds_out = rounds[s_out];
         };
         int64_t rounds = 0;

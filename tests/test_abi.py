@@ -138,7 +138,8 @@ def test_matrix_core_grid_fills_whole_rounds(K):
     a 1e6-spin GRE request takes 6 with 4 tiles, 977 blocks x 11 batches in
     14 rounds (4 would take 2 tiles, 1,954 x 16 in 41); a 1e5-spin one keeps
     4 (9 tiles, 44 blocks), since 6 would take more blocks (66) and so more
-    partial sums.
+    partial sums. A grid of 32 or more rounds at 16 tiles per wavefront is
+    searched on up to 32 tiles (SE-EPI).
     In FP64 (2 per CU, 64 KB of LDS each) every S fills whole rounds and the
     largest, 16, gives 16 blocks x 32 = 512 (one round); the vector-ALU forms
     keep 1, 2, 4 or 8. A requested batch size is kept, other values than 0,
@@ -152,6 +153,11 @@ def test_matrix_core_grid_fills_whole_rounds(K):
         r = W.ServingRequest(0, 0.0, n, "gre", 77)
         i = K.koma_plan_info(W.Scanner(), W.serving_phantom(r), W.serving_sequence("gre"), K.make_config())
         assert (i["spins_per_lane"], i["n_blocks"], i["stretches_per_wg"], i["n_stretches"]) == want, n
+    # SE-EPI (1,221 blocks x 72 batches at S = 16: 115 rounds) goes on to
+    # S = 32: 611 blocks x 72 batches, whole rounds to 0.5 %
+    sc5, ph5, seq5 = W.config(5)
+    i = K.koma_plan_info(sc5, ph5, seq5, K.make_config())
+    assert (i["spins_per_lane"], i["n_blocks"], i["stretches_per_wg"]) == (32, 611, 6)
     # a requested S keeps the smaller batch; a requested batch is kept
     i = K.koma_plan_info(sc, ph, seq, K.make_config(spins_per_lane=3))
     assert (i["spins_per_lane"], i["stretches_per_wg"]) == (3, 4)
