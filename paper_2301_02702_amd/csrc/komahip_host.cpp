@@ -1205,9 +1205,9 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
         const int64_t slots =
             (int64_t)(cfg.precision == KOMA_FP64 ? kMMResident64 : kMMResident) * std::max(1, ctx->n_cu);
         // for a batch size: the S, and the rounds of resident workgroups it
-        // takes. S is searched up to 16 and, in FP32 where that picks 16 for
-        // a grid of at least 32 rounds (there each workgroup's epilogue and
-        // partials weigh more than the last round's tail), up to 32.
+        // takes. S is searched up to 16 and, where that picks 16 for a grid
+        // of at least 32 rounds (there each workgroup's epilogue and partials
+        // weigh more than the last round's tail), up to 32.
         auto choose = [&](int64_t nb_st, int &s_out, int64_t &rounds_out) {
             const int64_t batches = (n_st + nb_st - 1) / nb_st * std::max<int64_t>(1, P.n_coils);
             double eff[33] = {};
@@ -1226,7 +1226,7 @@ static koma_status build_plan(koma_ctx *ctx, const koma_config &cfg, double gamm
                     s_out = cand;
                     break;
                 }
-            if (s_out == 16 && mm32 && rounds[16] >= 32) {
+            if (s_out == 16 && rounds[16] >= 32) {
                 smax = 32;
                 best_eff = 0.0;
                 for (int cand = 1; cand <= smax; ++cand) {

@@ -158,6 +158,8 @@ def test_matrix_core_grid_fills_whole_rounds(K):
     sc5, ph5, seq5 = W.config(5)
     i = K.koma_plan_info(sc5, ph5, seq5, K.make_config())
     assert (i["spins_per_lane"], i["n_blocks"], i["stretches_per_wg"]) == (32, 611, 6)
+    i = K.koma_plan_info(sc5, ph5, seq5, K.make_config("fp64"))
+    assert (i["spins_per_lane"], i["n_blocks"], i["stretches_per_wg"]) == (32, 611, 4)
     # a requested S keeps the smaller batch; a requested batch is kept
     i = K.koma_plan_info(sc, ph, seq, K.make_config(spins_per_lane=3))
     assert (i["spins_per_lane"], i["stretches_per_wg"]) == (3, 4)
